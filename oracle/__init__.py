@@ -1,0 +1,269 @@
+"""FP64 CPU oracle for sparse SGGX voxelization and LoD pyramids -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg may
+import this package.  The product path (``paper_2604_13191_amd``) never calls it, and the
+two share no code: the oracle is a separate C++ file built with g++ plus the numpy below.
+
+Functions and the passages they follow:
+
+* ``voxelize_triangles`` / ``voxelize_fibers`` -- Sec. 3.1 (grid transform), Sec. 3.3
+  (gathering every contribution to a leaf voxel), Sec. 3.4 / Sec. 4.1 (one SGGX matrix per
+  voxel).  Exact lattice predicates, FP64 clipped measures and moment sums (``vxo.cpp``).
+* ``build_lod`` -- Sec. 4.3: a coarser voxel aggregates its 2x2x2 children; here as sums
+  (the parent's normalised SGGX is the weight-averaged child SGGX), plus a child mask.
+* ``cluster_pyramid`` -- Sec. 4.4: agglomerative merging of the most similar lobes down to a
+  cap of K per voxel, with the deterministic distance and Lloyd refinement in ``vxo.cpp``.
+
+Pins (tests/test_oracle_*.py): exact-rational brute force (``oracle/brute.py``) on tiny
+grids; conservation of area / length / moment; closed forms for axis-aligned fibers and
+flat triangles; the quadrature identity of the lobe distance; brute-force merge orders.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vxo.cpp")
+_LIB = os.path.join(_HERE, "libvxo.so")
+_lib = None
+
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = False) -> str:
+    """Compile vxo.cpp with g++ (plain C++17, FP contraction off) into oracle/libvxo.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC",
+                               "-pthread", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.vxo_snap.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        L.vxo_morton.restype = ctypes.c_uint64
+        L.vxo_morton.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_int]
+        L.vxo_tri_touch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.vxo_tri_area.restype = ctypes.c_double
+        L.vxo_tri_area.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.vxo_cap_touch.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_int64]
+        L.vxo_seg_length.restype = ctypes.c_double
+        L.vxo_seg_length.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64]
+        L.vxo_voxelize_triangles.restype = ctypes.c_void_p
+        L.vxo_voxelize_triangles.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.vxo_voxelize_fibers.restype = ctypes.c_void_p
+        L.vxo_voxelize_fibers.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.vxo_result_size.restype = ctypes.c_int64
+        L.vxo_result_size.argtypes = [ctypes.c_void_p]
+        L.vxo_result_npairs.restype = ctypes.c_int64
+        L.vxo_result_npairs.argtypes = [ctypes.c_void_p]
+        L.vxo_result_copy.argtypes = [ctypes.c_void_p] * 5
+        L.vxo_result_free.argtypes = [ctypes.c_void_p]
+        L.vxo_cluster_level.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int]
+        L.vxo_lobe_dist.restype = ctypes.c_double
+        L.vxo_lobe_dist.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _grid_args(grid):
+    bmin = (ctypes.c_double * 3)(*[float(x) for x in grid.bmin])
+    return bmin, float(grid.extent), int(grid.log2_res)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _nthreads(n):
+    return int(n) if n else (os.cpu_count() or 1)
+
+
+@dataclass
+class Voxels:
+    """Leaf voxels, sorted by Morton key: FP64 weight and unnormalised SGGX sums."""
+    keys: np.ndarray      # uint64 [n]
+    count: np.ndarray     # uint32 [n]
+    w: np.ndarray         # float64 [n]
+    S: np.ndarray         # float64 [n, 6]  (xx, yy, zz, xy, xz, yz)
+    n_pairs: int = 0
+
+
+def _take(res) -> Voxels:
+    L = lib()
+    n = L.vxo_result_size(res)
+    v = Voxels(np.empty(n, np.uint64), np.empty(n, np.uint32), np.empty(n, np.float64),
+               np.empty((n, 6), np.float64), int(L.vxo_result_npairs(res)))
+    L.vxo_result_copy(res, _ptr(v.keys), _ptr(v.count), _ptr(v.w), _ptr(v.S))
+    L.vxo_result_free(res)
+    return v
+
+
+def _region_arg(region):
+    if region is None:
+        return None, None
+    r = np.ascontiguousarray(np.asarray(region, dtype=np.int64).reshape(6))
+    return r, _ptr(r)
+
+
+def snap(grid, pts) -> np.ndarray:
+    """Sec. 3.1 transform snapped to the 2^-(23 - log2 R) voxel lattice: int64 [n, 3]."""
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float32).reshape(-1, 3))
+    q = np.empty(p.shape, dtype=np.int64)
+    bmin, ext, l2 = _grid_args(grid)
+    st = lib().vxo_snap(bmin, ext, l2, _ptr(p), p.shape[0], _ptr(q))
+    if st:
+        raise OracleError(f"snap failed with status {st}")
+    return q
+
+
+def voxelize_triangles(grid, tris, region=None, nthreads=None) -> Voxels:
+    t = np.ascontiguousarray(np.asarray(tris, dtype=np.float32).reshape(-1, 3, 3))
+    bmin, ext, l2 = _grid_args(grid)
+    r, rp = _region_arg(region)
+    st = ctypes.c_int(0)
+    res = lib().vxo_voxelize_triangles(bmin, ext, l2, _ptr(t), t.shape[0], rp, _nthreads(nthreads),
+                                       ctypes.byref(st))
+    if st.value:
+        raise OracleError(f"voxelize_triangles failed with status {st.value}")
+    return _take(res)
+
+
+def voxelize_fibers(grid, pts, offsets, radius, region=None, nthreads=None) -> Voxels:
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float32).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    bmin, ext, l2 = _grid_args(grid)
+    r, rp = _region_arg(region)
+    st = ctypes.c_int(0)
+    res = lib().vxo_voxelize_fibers(bmin, ext, l2, _ptr(p), p.shape[0], _ptr(o), o.shape[0] - 1,
+                                    float(np.float32(radius)), rp, _nthreads(nthreads), ctypes.byref(st))
+    if st.value:
+        raise OracleError(f"voxelize_fibers failed with status {st.value}")
+    return _take(res)
+
+
+def morton(x, y, z, bits) -> int:
+    return int(lib().vxo_morton(int(x), int(y), int(z), int(bits)))
+
+
+def demorton(keys, bits):
+    """Inverse of the Morton interleave (x at bit 3b, y at 3b+1, z at 3b+2): int64 [n, 3]."""
+    k = np.asarray(keys, dtype=np.uint64)
+    out = np.zeros((k.shape[0], 3), dtype=np.int64)
+    for b in range(bits):
+        for a in range(3):
+            out[:, a] |= ((k >> np.uint64(3 * b + a)) & np.uint64(1)).astype(np.int64) << b
+    return out
+
+
+# --------------------------------------------------------------------------------------------
+# Sec. 4.3: the pyramid of 2x2x2 aggregates (one lobe per voxel).
+# --------------------------------------------------------------------------------------------
+
+@dataclass
+class Level:
+    keys: np.ndarray      # uint64 [n], sorted
+    count: np.ndarray     # uint64 [n]: primitive-voxel pairs under the voxel
+    mask: np.ndarray      # uint8 [n]: bit b set when child (key << 3 | b) exists (0 at the leaf)
+    w: np.ndarray         # float64 [n]
+    S: np.ndarray         # float64 [n, 6]
+    child_start: np.ndarray = field(default=None)   # int64 [n+1] into the level below
+
+
+def build_lod(vox: Voxels, levels: int):
+    """Level 0 is the leaf; level L voxel u sums the voxels v of level L-1 with v >> 3 == u."""
+    out = [Level(vox.keys.copy(), vox.count.astype(np.uint64), np.zeros(len(vox.keys), np.uint8),
+                 vox.w.copy(), vox.S.copy(), None)]
+    for _ in range(1, levels):
+        prev = out[-1]
+        pk = prev.keys >> np.uint64(3)
+        if len(pk) == 0:
+            out.append(Level(pk, pk.astype(np.uint64), np.zeros(0, np.uint8), np.zeros(0), np.zeros((0, 6)),
+                             np.zeros(1, np.int64)))
+            continue
+        starts = np.flatnonzero(np.concatenate([[True], pk[1:] != pk[:-1]]))
+        bits = (np.uint64(1) << (prev.keys & np.uint64(7))).astype(np.uint8)
+        lvl = Level(pk[starts],
+                    np.add.reduceat(prev.count, starts),
+                    np.bitwise_or.reduceat(bits, starts).astype(np.uint8),
+                    np.add.reduceat(prev.w, starts),
+                    np.add.reduceat(prev.S, starts, axis=0),
+                    np.append(starts, len(pk)).astype(np.int64))
+        out.append(lvl)
+    return out
+
+
+# --------------------------------------------------------------------------------------------
+# Sec. 4.4: lobe clustering per coarse voxel.
+# --------------------------------------------------------------------------------------------
+
+@dataclass
+class Lobes:
+    nl: np.ndarray        # int32 [n]
+    w: np.ndarray         # float64 [n, K]
+    S: np.ndarray         # float64 [n, K, 6]
+    gap_rel: np.ndarray   # float64 [n]: least relative margin of a decision taken for the voxel
+    gap_abs: np.ndarray   # float64 [n]: least margin relative to the voxel's weight
+    tie_gap_rel: np.ndarray = None   # least gap_rel over the voxel and all its descendants
+    tie_gap_abs: np.ndarray = None
+
+
+def lobe_dist(A, B) -> float:
+    """D(A, B) = 2 tr(Delta^2) + (tr Delta)^2 for normalised lobes given as (xx, yy, zz, xy, xz, yz)."""
+    a = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(B, dtype=np.float64)
+    return float(lib().vxo_lobe_dist(_ptr(a), _ptr(b)))
+
+
+def cluster_level(child: Lobes, child_start, K: int, iters: int, nthreads=None) -> Lobes:
+    n_par = len(child_start) - 1
+    Kc = child.w.shape[1]
+    out = Lobes(np.zeros(n_par, np.int32), np.zeros((n_par, K)), np.zeros((n_par, K, 6)),
+                np.zeros(n_par), np.zeros(n_par))
+    cs = np.ascontiguousarray(child_start, dtype=np.int64)
+    cnl = np.ascontiguousarray(child.nl, dtype=np.int32)
+    cw = np.ascontiguousarray(child.w, dtype=np.float64)
+    cS = np.ascontiguousarray(child.S, dtype=np.float64)
+    lib().vxo_cluster_level(n_par, _ptr(cs), _ptr(cnl), _ptr(cw), _ptr(cS), Kc, int(K), int(iters),
+                            _ptr(out.nl), _ptr(out.w), _ptr(out.S), _ptr(out.gap_rel), _ptr(out.gap_abs),
+                            _nthreads(nthreads))
+    # decision margins inherited from the subtree
+    seg_min_rel = np.minimum.reduceat(child.tie_gap_rel, cs[:-1]) if n_par else np.zeros(0)
+    seg_min_abs = np.minimum.reduceat(child.tie_gap_abs, cs[:-1]) if n_par else np.zeros(0)
+    out.tie_gap_rel = np.minimum(out.gap_rel, seg_min_rel)
+    out.tie_gap_abs = np.minimum(out.gap_abs, seg_min_abs)
+    return out
+
+
+def cluster_pyramid(lod, K: int, iters: int = 2, nthreads=None):
+    """Per level L >= 1: at most K lobes per voxel, merged from the lobes of its children."""
+    leaf = lod[0]
+    n0 = len(leaf.keys)
+    cur = Lobes((leaf.w > 0).astype(np.int32), leaf.w.reshape(n0, 1).copy(), leaf.S.reshape(n0, 1, 6).copy(),
+                np.full(n0, np.inf), np.full(n0, np.inf), np.full(n0, np.inf), np.full(n0, np.inf))
+    out = [cur]
+    for L in range(1, len(lod)):
+        cur = cluster_level(cur, lod[L].child_start, K, iters, nthreads)
+        out.append(cur)
+    return out
