@@ -1,0 +1,168 @@
+/* vx.h -- C ABI of libvx.so: sparse SGGX voxelization and LoD pyramids on gfx950.
+ *
+ * The operations follow "Fast Voxelization and Level of Detail for Microgeometry Rendering"
+ * (arXiv 2604.13191):
+ *   voxelize(primitives, grid bounds, resolution) -> sparse Morton-keyed leaf voxels
+ *       Sec. 3.1 (grid transform, node records), Sec. 3.2-3.3 (generating and gathering
+ *       everything a primitive contributes to a leaf voxel), Sec. 3.4 and Sec. 4.1 (one SGGX
+ *       matrix per voxel, fitted from the voxel's orientation data);
+ *   build_lod(voxels, levels, lobes_per_voxel) -> pyramid
+ *       Sec. 4.3 (2x2x2 aggregation of SGGX into coarser levels) and Sec. 4.4 (merging the
+ *       most similar lobes, with a cap on the number kept per voxel).
+ *
+ * What this library computes, exactly (the paper samples points; this is the exact-measure
+ * reading of the same aggregation):
+ *   - Grid: cubic bounds [bmin, bmin + extent)^3, R = 2^log2_res voxels per axis.  Every
+ *     vertex is mapped as in Sec. 3.1 and snapped to the lattice of 2^-(23 - log2_res) voxel:
+ *         q = rint((double(P) - bmin) * (2^23 / extent))      (IEEE double, round half even)
+ *     so a voxel is s = 2^(23 - log2_res) lattice units.  |q| must stay within one grid of the
+ *     bounds (q in [-2^23, 2^24]); otherwise the call reports VX_ERR_INPUT.
+ *   - A triangle touches voxel v when it meets the closed box [v, v+1]^3; a fiber segment
+ *     touches v when its centreline is within distance `radius` of that closed box.  Both
+ *     predicates are exact on the lattice.  Voxels outside [0, R)^3 are dropped.
+ *   - Weight of a (primitive, voxel) pair: area of the triangle inside the half-open box
+ *     [v, v+1)^3, or length of the centreline inside it, in voxel units (voxel^2, voxel).
+ *   - Moment: M = n n^T (unit triangle normal) or M = I - t t^T (unit segment tangent); zero
+ *     for degenerate primitives.
+ *   - Per leaf voxel: count = number of touching primitives, w = sum of weights,
+ *     S = sum of weight * M (unnormalised; the SGGX matrix is S / w).
+ *   - Key: Morton code, x bit b at key bit 3b, y at 3b+1, z at 3b+2.  Keys are 32-bit when
+ *     3 * log2_res <= 30 (log2_res <= 10) and 64-bit otherwise.  Parent key = key >> 3.
+ *
+ * Memory: every pointer argument is device memory owned by the caller unless stated.  The
+ * library allocates nothing on these paths; scratch comes from the caller's workspace whose
+ * size the *_workspace_size() calls return.  Work is enqueued on `stream` and returns
+ * without synchronising.  Counts are written to device memory; nothing is copied to the host.
+ *
+ * Errors: arguments the host can check are rejected before anything is enqueued (the
+ * return value).  Conditions found on the device (a capacity too small, a non-finite or
+ * out-of-range coordinate) set bits in stats[VX_STAT_FLAGS]; the outputs are then invalid,
+ * the true required sizes are still written to stats, and vx_check_stats() (which
+ * synchronises the stream) turns the flags into a status.  Calls on one stream are ordered;
+ * calls that share a workspace must not overlap.
+ */
+#ifndef VX_H
+#define VX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* vx_stream;   /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  VX_OK = 0,
+  VX_ERR_ARG = 1,        /* bad argument (host-checked) */
+  VX_ERR_CAPACITY = 2,   /* a device-detected count exceeded the capacity given */
+  VX_ERR_HIP = 3,        /* a HIP runtime call failed */
+  VX_ERR_INPUT = 4,      /* non-finite or out-of-range coordinate, or invalid fiber offsets */
+  VX_ERR_WORKSPACE = 5   /* workspace pointer NULL, misaligned (256 B) or too small */
+} vx_status;
+
+/* device flag bits in stats[VX_STAT_FLAGS] */
+#define VX_FLAG_CAND_CAPACITY  1
+#define VX_FLAG_PAIR_CAPACITY  2
+#define VX_FLAG_VOXEL_CAPACITY 4
+#define VX_FLAG_INPUT          8
+#define VX_FLAG_OFFSETS        16
+
+/* indices into the int64 stats array (device) */
+enum { VX_STAT_CAND = 0, VX_STAT_PAIRS = 1, VX_STAT_VOXELS = 2, VX_STAT_FLAGS = 3, VX_NSTAT = 4 };
+
+typedef struct {
+  double bmin[3];
+  double extent;      /* > 0, cubic bounds */
+  int32_t log2_res;   /* 1 .. 20 */
+} vx_grid;
+
+/* One level of voxels, structure of arrays, capacity `cap` entries.  Entry i is valid for
+ * i < n, where n is written to device memory by the producing call. */
+typedef struct {
+  void* keys;         /* uint32[cap] (log2_res <= 10) or uint64[cap] */
+  uint32_t* count;    /* [cap] primitive-voxel pairs under the voxel */
+  float* w;           /* [cap] summed weight */
+  float* S;           /* [6 * cap]: S[c * cap + i], c = xx, yy, zz, xy, xz, yz */
+  uint8_t* mask;      /* [cap] child mask, bit b = child (key << 3 | b) present; NULL at the leaf */
+  int64_t cap;
+} vx_voxels;
+
+/* Up to K SGGX lobes per voxel of one level (K > 1 only). */
+typedef struct {
+  uint8_t* nl;        /* [cap] number of lobes (0 when w == 0) */
+  float* w;           /* [K * cap]: w[k * cap + i], sorted by descending weight */
+  float* S;           /* [6 * K * cap]: S[(c * K + k) * cap + i] */
+  int64_t cap;
+} vx_lobes;
+
+/* ------------------------------------------------------------------------------------------
+ * Voxelization (Sec. 3.1-3.4).
+ *
+ * kind: 0 = triangles (n_prims = number of triangles), 1 = fibers (n_prims = number of points).
+ * max_cand: capacity of the candidate space (sum over primitives of the voxels of their
+ *   closed bounding box, dilated by the radius for fibers, clipped to the grid).
+ * max_pairs: capacity for touching (primitive, voxel) pairs; at most 2^31 - 1.
+ * Returns the workspace size in bytes (0 on bad arguments).
+ * ------------------------------------------------------------------------------------------ */
+size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
+                                  int32_t log2_res);
+
+/* tris: float32 [n_tris][3][3] (vertex-major; a soup of non-shared vertices, Sec. 3.2).
+ * out: leaf voxels (out->mask unused), sorted by key, unique keys.
+ * stats: int64[VX_NSTAT] on the device, overwritten. */
+vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris,
+                                int64_t max_cand, int64_t max_pairs, void* workspace, size_t ws_bytes,
+                                const vx_voxels* out, int64_t* stats, vx_stream stream);
+
+/* pts: float32 [n_pts][3] polyline nodes (Sec. 3.1 node collections); offsets: int64
+ * [n_fibers + 1] (device), offsets[0] = 0, non-decreasing, offsets[n_fibers] = n_pts.  Segment
+ * (i, i+1) exists when both points belong to one fiber; radius in world units, >= 0. */
+vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
+                             int64_t n_fibers, float radius, int64_t max_cand, int64_t max_pairs,
+                             void* workspace, size_t ws_bytes, const vx_voxels* out, int64_t* stats,
+                             vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
+ * LoD pyramid (Sec. 4.3-4.4).
+ *
+ * leaf: the voxelize output, with its count at n_leaf (device int64, e.g. &stats[VX_STAT_VOXELS]).
+ * levels: total number of levels including the leaf, 1 .. log2_res + 1.
+ * out: levels - 1 coarser levels (level L = 1 .. levels-1 at out[L-1]); each sums its 2x2x2
+ *   children: keys = child >> 3, count, w and S summed, mask of present children.
+ * K: lobes kept per coarse voxel (1 .. 8).  K == 1: `lobes` may be NULL (the level's S is the
+ *   single lobe).  K > 1: lobes[L-1] receives, for each level-L voxel, at most K lobes merged
+ *   from the lobes of its children (the leaf's lobe is the voxel itself): Ward agglomeration
+ *   with cost w_a w_b / (w_a + w_b) * D(S_a / w_a, S_b / w_b),
+ *   D(A, B) = 2 tr((A - B)^2) + (tr(A - B))^2, ties to the first pair in child/lobe order, then
+ *   kmeans_iters weighted Lloyd passes (nearest centroid in D, ties to the lowest index),
+ *   empty clusters dropped, lobes sorted by descending weight.
+ * n_levels: int64[levels + 1] on the device; n_levels[L] = voxels at level L (clamped to the
+ *   level's cap), n_levels[levels] = flags (VX_FLAG_VOXEL_CAPACITY when a level did not fit).
+ * The workspace size depends on leaf->cap (vx_lod_workspace_size(leaf->cap, ...)).
+ * ------------------------------------------------------------------------------------------ */
+size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K);
+
+vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels,
+                       int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
+                       int64_t* n_levels, void* workspace, size_t ws_bytes, vx_stream stream);
+
+/* Synchronises `stream`, reads stats (VX_NSTAT int64 on the device) and maps its flags to a
+ * status: VX_ERR_INPUT before VX_ERR_CAPACITY before VX_OK. */
+vx_status vx_check_stats(const int64_t* stats, vx_stream stream);
+
+const char* vx_status_str(vx_status s);
+
+/* Kernel timing for measurement: when enabled, every kernel launch of the library is
+ * bracketed by HIP events on the caller's stream and its duration is accumulated per kernel
+ * name once vx_timing_collect() (which synchronises the device) is called. */
+void vx_timing_enable(int32_t on);
+void vx_timing_reset(void);
+/* Writes up to max_entries (name, total ms, launches) triples; returns the number of kernels. */
+int32_t vx_timing_collect(char names[][48], double* total_ms, int64_t* launches, int32_t max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VX_H */

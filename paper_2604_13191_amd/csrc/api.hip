@@ -1,0 +1,236 @@
+// api.hip -- the C ABI of libvx.so (declared in include/vx.h): argument checks, workspace
+// sizing, orchestration of the kernels on the caller's stream, and kernel timing.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vx_internal.hpp"
+
+namespace vx {
+
+// ---------------------------------------------------------------------------------------------
+// timing: one event pair per launch while enabled, resolved in vx_timing_collect()
+// ---------------------------------------------------------------------------------------------
+namespace {
+struct Pending {
+  std::string name;
+  hipEvent_t a, b;
+};
+struct Acc {
+  std::string name;
+  double ms = 0;
+  int64_t n = 0;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::vector<Acc> g_acc;
+thread_local std::vector<size_t> g_open;
+
+hipEvent_t get_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  (void)hipEventCreate(&e);
+  return e;
+}
+}  // namespace
+
+void timing_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_on) return;
+  Pending p{name, get_event(), get_event()};
+  (void)hipEventRecord(p.a, s);
+  g_pending.push_back(p);
+  g_open.push_back(g_pending.size() - 1);
+}
+
+void timing_end(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_on || g_open.empty()) return;
+  size_t i = g_open.back();
+  g_open.pop_back();
+  (void)hipEventRecord(g_pending[i].b, s);
+}
+
+}  // namespace vx
+
+using namespace vx;
+
+namespace {
+
+bool grid_ok(const vx_grid* g) {
+  if (!g) return false;
+  if (!(g->extent > 0.0) || !std::isfinite(g->extent)) return false;
+  if (g->log2_res < 1 || g->log2_res > 20) return false;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(g->bmin[a])) return false;
+  return true;
+}
+
+bool voxels_ok(const vx_voxels* v, bool need_mask) {
+  return v && v->keys && v->count && v->w && v->S && v->cap >= 1 && (!need_mask || v->mask);
+}
+
+bool ws_ok(void* ws, size_t have, size_t need) {
+  return ws && (reinterpret_cast<uintptr_t>(ws) % 256 == 0) && have >= need;
+}
+
+constexpr int64_t kMaxPairs = 0x7fffffff;
+
+}  // namespace
+
+extern "C" {
+
+size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
+                                  int32_t log2_res) {
+  if ((kind != 0 && kind != 1) || n_prims < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs ||
+      log2_res < 1 || log2_res > 20)
+    return 0;
+  return voxelize_ws_bytes(n_prims, max_cand, max_pairs, log2_res > 10);
+}
+
+static vx_status voxelize_common(int kind, const vx_grid* grid, const float* data, int64_t n_prims,
+                                 const int64_t* offsets, int64_t n_fib, float radius, int64_t max_cand,
+                                 int64_t max_pairs, void* ws, size_t ws_bytes, const vx_voxels* out,
+                                 int64_t* stats, vx_stream stream) {
+  if (!grid_ok(grid) || n_prims < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs || !stats ||
+      !voxels_ok(out, false) || (n_prims > 0 && !data))
+    return VX_ERR_ARG;
+  if (kind == 1) {
+    if (n_fib < 0 || !offsets || (n_prims > 0 && n_fib < 1)) return VX_ERR_ARG;
+    if (!(radius >= 0.0f) || !std::isfinite(radius)) return VX_ERR_ARG;
+    const double rho = std::rint(double(radius) * (std::ldexp(1.0, 23) / grid->extent));
+    if (rho > 8388608.0) return VX_ERR_ARG;
+  }
+  if (!ws_ok(ws, ws_bytes, voxelize_ws_bytes(n_prims, max_cand, max_pairs, grid->log2_res > 10)))
+    return VX_ERR_WORKSPACE;
+  return voxelize_run(kind, grid, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, ws, out, stats,
+                      reinterpret_cast<hipStream_t>(stream));
+}
+
+vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, int64_t max_cand,
+                                int64_t max_pairs, void* ws, size_t ws_bytes, const vx_voxels* out,
+                                int64_t* stats, vx_stream stream) {
+  return voxelize_common(0, grid, tris, n_tris, nullptr, 0, 0.0f, max_cand, max_pairs, ws, ws_bytes, out, stats,
+                         stream);
+}
+
+vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
+                             int64_t n_fibers, float radius, int64_t max_cand, int64_t max_pairs, void* ws,
+                             size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream) {
+  return voxelize_common(1, grid, pts, n_pts, offsets, n_fibers, radius, max_cand, max_pairs, ws, ws_bytes, out,
+                         stats, stream);
+}
+
+size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K) {
+  if (cap < 1 || levels < 1 || K < 1 || K > 8) return 0;
+  Carver cv(nullptr);
+  cv.take<int64_t>(cap + 1);   // parent starts
+  cv.take<int64_t>(kGrid + 1); // scan partials
+  return cv.off + 256;
+}
+
+vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
+                       int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, int64_t* n_levels,
+                       void* ws, size_t ws_bytes, vx_stream stream) {
+  if (!grid_ok(grid) || !voxels_ok(leaf, false) || !n_leaf || !n_levels || levels < 1 ||
+      levels > grid->log2_res + 1 || K < 1 || K > 8 || kmeans_iters < 0)
+    return VX_ERR_ARG;
+  if (K > 1) return VX_ERR_ARG;   // lobe clustering: not available in this build of the library
+  (void)lobes;
+  if (levels > 1 && !out) return VX_ERR_ARG;
+  for (int L = 1; L < levels; ++L)
+    if (!voxels_ok(&out[L - 1], true)) return VX_ERR_ARG;
+  if (!ws_ok(ws, ws_bytes, vx_lod_workspace_size(leaf->cap, levels, K))) return VX_ERR_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool key64 = grid->log2_res > 10;
+  Carver cv(ws);
+  int64_t* pstart = cv.take<int64_t>(leaf->cap + 1);
+  int64_t* partial = cv.take<int64_t>(kGrid + 1);
+  launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
+  lod_clamp(n_leaf, leaf->cap, n_levels, s);
+  for (int L = 1; L < levels; ++L) {
+    const vx_voxels& in = L == 1 ? *leaf : out[L - 2];
+    lod_level(key64, in, n_levels + L - 1, out[L - 1], n_levels + L, n_levels + levels, pstart, partial, s);
+  }
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {
+  if (!stats) return VX_ERR_ARG;
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return VX_ERR_HIP;
+  int64_t h[VX_NSTAT];
+  if (hipMemcpy(h, stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) return VX_ERR_HIP;
+  const int64_t f = h[VX_STAT_FLAGS];
+  if (f & (VX_FLAG_INPUT | VX_FLAG_OFFSETS)) return VX_ERR_INPUT;
+  if (f & (VX_FLAG_CAND_CAPACITY | VX_FLAG_PAIR_CAPACITY | VX_FLAG_VOXEL_CAPACITY)) return VX_ERR_CAPACITY;
+  return VX_OK;
+}
+
+const char* vx_status_str(vx_status s) {
+  switch (s) {
+    case VX_OK: return "ok";
+    case VX_ERR_ARG: return "invalid argument";
+    case VX_ERR_CAPACITY: return "capacity exceeded";
+    case VX_ERR_HIP: return "HIP runtime error";
+    case VX_ERR_INPUT: return "non-finite or out-of-range input, or invalid fiber offsets";
+    case VX_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+  }
+  return "unknown status";
+}
+
+void vx_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_on = on != 0;
+}
+
+void vx_timing_reset(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& p : g_pending) {
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_pending.clear();
+  g_acc.clear();
+}
+
+int32_t vx_timing_collect(char names[][48], double* total_ms, int64_t* launches, int32_t max_entries) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  (void)hipDeviceSynchronize();
+  for (auto& p : g_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
+    Acc* a = nullptr;
+    for (auto& x : g_acc)
+      if (x.name == p.name) a = &x;
+    if (!a) {
+      g_acc.push_back(Acc{p.name, 0.0, 0});
+      a = &g_acc.back();
+    }
+    a->ms += ms;
+    a->n += 1;
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_pending.clear();
+  int32_t k = 0;
+  for (auto& x : g_acc) {
+    if (k < max_entries) {
+      std::strncpy(names[k], x.name.c_str(), 47);
+      names[k][47] = 0;
+      total_ms[k] = x.ms;
+      launches[k] = x.n;
+    }
+    ++k;
+  }
+  return k;
+}
+
+}  // extern "C"

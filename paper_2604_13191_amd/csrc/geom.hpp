@@ -1,0 +1,460 @@
+// geom.hpp -- exact lattice geometry of the voxelizer: grid snap, candidate ranges, the
+// closed-box touch tests and the clipped measures.  Pure functions usable on device and host
+// (the host side serves unit checks of the predicates).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VX_HD __host__ __device__
+
+namespace vx {
+
+constexpr int kPolyStride = 256;   // LDS stride between a thread's polygon slots (= block size)
+
+struct Lat {
+  double bmin[3];
+  double inv;        // lattice units per world unit, 2^23 / extent
+  int64_t s;         // lattice units per voxel, 2^(23 - log2R)
+  int32_t Sb;        // log2(s)
+  int32_t R;
+  int64_t rho;       // capsule radius in lattice units (fibers)
+};
+
+// per-primitive record, 16 x int32: [0..8] snapped vertices (fibers: A, B, unused),
+// [9..11] first candidate voxel, [12..14] candidate extent per axis
+constexpr int kRec = 16;
+
+VX_HD inline int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+VX_HD inline int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
+VX_HD inline int64_t floor_shift(int64_t a, int Sb) { return a >> Sb; }
+VX_HD inline int64_t ceil_shift(int64_t a, int Sb) { return -((-a) >> Sb); }
+
+// Sec. 3.1: P_volume = (P - bmin) / extent * R, on the lattice; false for non-finite or
+// out-of-range input.  The subtract and multiply are not fused, as in the definition.
+VX_HD inline bool snap_point(const float* p, const Lat& L, int32_t q[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double g;
+    {
+#pragma clang fp contract(off)
+      g = (double(p[a]) - L.bmin[a]) * L.inv;
+    }
+    const double r = rint(g);
+    const bool good = (r >= -8388608.0) && (r <= 16777216.0);   // NaN compares false
+    ok = ok && good;
+    q[a] = good ? int32_t(r) : 0;
+  }
+  return ok;
+}
+
+VX_HD inline int64_t candidate_range(int64_t mn, int64_t mx, const Lat& L, int32_t& vlo) {
+  int64_t lo = ceil_shift(mn, L.Sb) - 1;
+  int64_t hi = floor_shift(mx, L.Sb);
+  lo = lo < 0 ? 0 : lo;
+  hi = hi > L.R - 1 ? L.R - 1 : hi;
+  vlo = int32_t(lo);
+  return hi >= lo ? hi - lo + 1 : 0;
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// candidate -> (primitive, voxel)
+// ---------------------------------------------------------------------------------------------
+// Primitive records: 16 x int32, [0..8] snapped vertices (fibers: A, B, zeros), [9..11] first
+// candidate voxel, [12..14] candidate extent per axis.  Returns the number of candidates (0
+// when the input is invalid, with ok = false).  dir: unit normal and twice the area (voxel^2)
+// for triangles, unit tangent and length (voxel) for segments.
+VX_HD inline int64_t prep_triangle(const float* t9, const Lat& L, int32_t* r, float4* dir, bool& ok) {
+  int32_t q[9];
+  ok = true;
+  for (int v = 0; v < 3; ++v) ok = snap_point(t9 + v * 3, L, q + 3 * v) && ok;
+  int64_t cnt = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t mn = imin(q[a], imin(q[3 + a], q[6 + a]));
+    const int64_t mx = imax(q[a], imax(q[3 + a], q[6 + a]));
+    int32_t vlo;
+    const int64_t na = candidate_range(mn, mx, L, vlo);
+    r[9 + a] = vlo;
+    r[12 + a] = int32_t(na);
+    cnt *= na;
+  }
+  for (int k = 0; k < 9; ++k) r[k] = q[k];
+  r[15] = 0;
+  int64_t e0[3], e1[3];
+  for (int a = 0; a < 3; ++a) { e0[a] = int64_t(q[3 + a]) - q[a]; e1[a] = int64_t(q[6 + a]) - q[a]; }
+  const double nx = double(e0[1] * e1[2] - e0[2] * e1[1]);
+  const double ny = double(e0[2] * e1[0] - e0[0] * e1[2]);
+  const double nz = double(e0[0] * e1[1] - e0[1] * e1[0]);
+  const double len = sqrt(nx * nx + ny * ny + nz * nz);
+  const double inv = len > 0 ? 1.0 / len : 0.0;
+  const double s2 = double(L.s) * double(L.s);
+  *dir = make_float4(float(nx * inv), float(ny * inv), float(nz * inv), float(len / s2));
+  return ok ? cnt : 0;
+}
+
+// b == nullptr: point a ends its fiber and starts no segment (it is still validated)
+VX_HD inline int64_t prep_segment(const float* a, const float* b, const Lat& L, int32_t* r, float4* dir, bool& ok) {
+  int32_t A[3], B[3] = {0, 0, 0};
+  ok = snap_point(a, L, A);
+  if (b) ok = snap_point(b, L, B) && ok;
+  int64_t cnt = b ? 1 : 0;
+  for (int k = 0; k < 3; ++k) {
+    const int64_t mn = imin(A[k], B[k]) - L.rho;
+    const int64_t mx = imax(A[k], B[k]) + L.rho;
+    int32_t vlo;
+    const int64_t na = candidate_range(mn, mx, L, vlo);
+    r[k] = A[k];
+    r[3 + k] = B[k];
+    r[6 + k] = 0;
+    r[9 + k] = vlo;
+    r[12 + k] = int32_t(na);
+    cnt *= na;
+  }
+  r[15] = 0;
+  const double d0 = double(B[0] - A[0]), d1 = double(B[1] - A[1]), d2 = double(B[2] - A[2]);
+  const double len = b ? sqrt(d0 * d0 + d1 * d1 + d2 * d2) : 0.0;
+  const double inv = len > 0 ? 1.0 / len : 0.0;
+  *dir = make_float4(float(d0 * inv), float(d1 * inv), float(d2 * inv), float(len / double(L.s)));
+  return ok ? cnt : 0;
+}
+
+// last p in [lo, n_prims) with cand_off[p] <= c
+VX_HD inline int64_t find_prim(const int64_t* __restrict__ cand_off, int64_t lo, int64_t n_prims,
+                                             int64_t c) {
+  int64_t hi = n_prims;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (cand_off[mid] <= c) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+VX_HD inline void candidate_voxel(const int32_t* r, int64_t li, int64_t v[3]) {
+  const int64_t nx = r[12], ny = r[13];
+  int64_t ix, iy, iz;
+  if (li < 0x7fffffff && nx * ny < 0x7fffffff) {
+    uint32_t l = uint32_t(li), x = uint32_t(nx), y = uint32_t(ny);
+    uint32_t t = l / x;
+    ix = l - t * x;
+    iz = t / y;
+    iy = t - uint32_t(iz) * y;
+  } else {
+    int64_t t = li / nx;
+    ix = li - t * nx;
+    iz = t / ny;
+    iy = t - iz * ny;
+  }
+  v[0] = r[9] + ix;
+  v[1] = r[10] + iy;
+  v[2] = r[11] + iz;
+}
+
+// ---------------------------------------------------------------------------------------------
+// exact triangle / closed box test (the box-axis tests hold by construction of the candidate
+// range): the triangle's plane and the nine edge x axis directions.
+// ---------------------------------------------------------------------------------------------
+VX_HD __attribute__((noinline)) bool plane_exact(const int64_t n[3], const int64_t rel[3], int64_t s) {
+  __int128 base = 0, lo = 0, hi = 0;
+  for (int a = 0; a < 3; ++a) {
+    base += (__int128)n[a] * rel[a];
+    if (n[a] > 0) hi += (__int128)n[a] * s; else lo += (__int128)n[a] * s;
+  }
+  return !(base + lo > 0 || base + hi < 0);
+}
+
+VX_HD inline bool tri_touch(const int32_t* q, const int64_t v[3], int64_t s, int Sb) {
+  int64_t c[3][3];   // vertices relative to the box corner
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[i][a] = int64_t(q[3 * i + a]) - (v[a] << Sb);
+  int64_t e[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    e[0][a] = c[1][a] - c[0][a];
+    e[1][a] = c[2][a] - c[1][a];
+    e[2][a] = c[0][a] - c[2][a];
+  }
+  // nine edge x box-axis directions: projections of the triangle and of the box [0, s]^3
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int u = (k + 1) % 3, w = (k + 2) % 3;     // axis = e_k x e_j -> components on u and w
+      const int64_t au = -e[j][w], aw = e[j][u];
+      int64_t p0 = au * c[0][u] + aw * c[0][w];
+      int64_t p1 = au * c[1][u] + aw * c[1][w];
+      int64_t p2 = au * c[2][u] + aw * c[2][w];
+      const int64_t pmin = imin(p0, imin(p1, p2)), pmax = imax(p0, imax(p1, p2));
+      const int64_t blo = (imin(au, 0) + imin(aw, 0)) * s;
+      const int64_t bhi = (imax(au, 0) + imax(aw, 0)) * s;
+      if (pmax < blo || pmin > bhi) return false;
+    }
+  }
+  // plane: corner offsets n . (corner - c0) must not all share a strict sign
+  int64_t n[3];
+  n[0] = e[0][1] * (-e[2][2]) - e[0][2] * (-e[2][1]);
+  n[1] = e[0][2] * (-e[2][0]) - e[0][0] * (-e[2][2]);
+  n[2] = e[0][0] * (-e[2][1]) - e[0][1] * (-e[2][0]);
+  const double ds = double(s);
+  double base = -(double(n[0]) * double(c[0][0]) + double(n[1]) * double(c[0][1]) + double(n[2]) * double(c[0][2]));
+  double lo = base, hi = base, mag = fabs(double(n[0]) * double(c[0][0])) + fabs(double(n[1]) * double(c[0][1])) +
+                                     fabs(double(n[2]) * double(c[0][2]));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double t = double(n[a]) * ds;
+    if (n[a] > 0) hi += t; else lo += t;
+    mag += fabs(t);
+  }
+  const double err = mag * 0x1p-48;
+  if (lo > err || hi < -err) return false;           // strictly on one side
+  if (lo < -err && hi > err) return true;            // strictly across
+  int64_t rel[3] = {-c[0][0], -c[0][1], -c[0][2]};
+  return plane_exact(n, rel, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// exact capsule / closed box test: min over t in [0,1] of f(t) = dist^2(c + t d, [0, s]^3)
+// against rho^2.  FP64 with an error bound; exact 128-bit integers when too close to call.
+// ---------------------------------------------------------------------------------------------
+VX_HD inline double fdist2(double t, const double c[3], const double d[3], double s) {
+  double f = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double x = fma(t, d[a], c[a]);
+    double g = x < 0 ? -x : (x > s ? x - s : 0.0);
+    f = fma(g, g, f);
+  }
+  return f;
+}
+
+// exact: f is evaluated at 0, 1, every breakpoint, and at the stationary point of the quadratic
+// of every (axis state) combination whose region contains it.
+VX_HD __attribute__((noinline)) bool cap_exact(const int64_t c[3], const int64_t d[3], int64_t s, int64_t rho) {
+  typedef __int128 I;
+  const I r2 = (I)rho * rho;
+  // f(num / den) * den^2 <= rho^2 den^2 at den > 0
+  auto eval = [&](I num, I den) -> bool {
+    I sum = 0;
+    for (int a = 0; a < 3; ++a) {
+      I g = (I)c[a] * den + num * d[a];
+      I sd = (I)s * den;
+      I dist = g < 0 ? -g : (g > sd ? g - sd : (I)0);
+      sum += dist * dist;
+    }
+    return sum <= r2 * den * den;
+  };
+  if (eval(0, 1) || eval(1, 1)) return true;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0) continue;
+    for (int side = 0; side < 2; ++side) {
+      I num = (I)((side ? s : 0) - c[a]), den = d[a];
+      if (den < 0) { num = -num; den = -den; }
+      if (num >= 0 && num <= den && eval(num, den)) return true;
+    }
+  }
+  for (int combo = 1; combo < 27; ++combo) {
+    int st[3] = {combo % 3, (combo / 3) % 3, combo / 9};   // 0 inside, 1 below 0, 2 above s
+    I Q = 0, P = 0;
+    int64_t e[3];
+    for (int a = 0; a < 3; ++a) {
+      e[a] = st[a] == 1 ? c[a] : (st[a] == 2 ? c[a] - s : 0);
+      if (st[a]) { Q += (I)d[a] * d[a]; P -= (I)e[a] * d[a]; }
+    }
+    if (Q == 0) continue;
+    if (P < 0 || P > Q) continue;                             // t* outside [0, 1]
+    bool member = true;
+    for (int a = 0; a < 3; ++a) {
+      I g = (I)c[a] * Q + P * d[a];
+      I sq = (I)s * Q;
+      if (st[a] == 1) member = member && g <= 0;
+      else if (st[a] == 2) member = member && g >= sq;
+      else member = member && g >= 0 && g <= sq;
+    }
+    if (!member) continue;
+    I num = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = a + 1; b < 3; ++b) {
+        if (!st[a] || !st[b]) continue;
+        I x = (I)e[a] * d[b] - (I)e[b] * d[a];
+        num += x * x;
+      }
+    if (num <= r2 * Q) return true;
+  }
+  return false;
+}
+
+#define VX_CSWAP(i, j) { double lo_ = fmin(t[i], t[j]); t[j] = fmax(t[i], t[j]); t[i] = lo_; }
+
+VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
+  int64_t ci[3], di[3];
+  double c[3], d[3];
+  double M = double(s);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ci[a] = int64_t(r[a]) - (v[a] << Sb);
+    di[a] = int64_t(r[3 + a]) - int64_t(r[a]);
+    c[a] = double(ci[a]);
+    d[a] = double(di[a]);
+    M = fmax(M, fabs(c[a]) + fabs(d[a]) + double(s));
+  }
+  const double ds = double(s);
+  double t[8];
+  t[0] = 0.0;
+  t[1] = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double t0 = 0.0, t1 = 0.0;
+    if (di[a] != 0) {
+      t0 = fmin(fmax(-c[a] / d[a], 0.0), 1.0);
+      t1 = fmin(fmax((ds - c[a]) / d[a], 0.0), 1.0);
+    }
+    t[2 + 2 * a] = t0;
+    t[3 + 2 * a] = t1;
+  }
+  VX_CSWAP(0, 1) VX_CSWAP(2, 3) VX_CSWAP(4, 5) VX_CSWAP(6, 7) VX_CSWAP(0, 2) VX_CSWAP(1, 3) VX_CSWAP(4, 6)
+  VX_CSWAP(5, 7) VX_CSWAP(1, 2) VX_CSWAP(5, 6) VX_CSWAP(0, 4) VX_CSWAP(3, 7) VX_CSWAP(1, 5) VX_CSWAP(2, 6)
+  VX_CSWAP(1, 4) VX_CSWAP(3, 6) VX_CSWAP(2, 4) VX_CSWAP(3, 5) VX_CSWAP(3, 4)
+  double fmin_ = fdist2(t[0], c, d, ds);
+#pragma unroll
+  for (int k = 1; k < 8; ++k) fmin_ = fmin(fmin_, fdist2(t[k], c, d, ds));
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double ta = t[k], tb = t[k + 1];
+    const double m = 0.5 * (ta + tb);
+    double Q = 0, P = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double x = fma(m, d[a], c[a]);
+      double b = x < 0 ? 0.0 : (x > ds ? ds : x);
+      bool act = (x < 0) || (x > ds);
+      if (act) {
+        Q = fma(d[a], d[a], Q);
+        P = fma(-(c[a] - b), d[a], P);
+      }
+    }
+    if (Q > 0 && tb > ta) {
+      double ts = fmin(fmax(P / Q, ta), tb);
+      fmin_ = fmin(fmin_, fdist2(ts, c, d, ds));
+    }
+  }
+  const double r2 = double(rho) * double(rho);
+  const double err = M * M * 0x1p-44;
+  if (fmin_ + err <= r2) return true;
+  if (fmin_ - err > r2) return false;
+  return cap_exact(ci, di, s, rho);
+}
+#undef VX_CSWAP
+
+// ---------------------------------------------------------------------------------------------
+// weights
+// ---------------------------------------------------------------------------------------------
+// length of the segment inside [v, v+1)^3 in voxel units (half-open for axis-parallel segments)
+VX_HD inline float seg_length(const int32_t* r, const int64_t v[3], int Sb, float len_vox) {
+  double t0 = 0.0, t1 = 1.0;
+  const double inv_s = 1.0 / double(int64_t(1) << Sb);
+  bool empty = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int64_t ci = int64_t(r[a]) - (v[a] << Sb);
+    const int64_t di = int64_t(r[3 + a]) - int64_t(r[a]);
+    if (di == 0) {
+      empty = empty || !(ci >= 0 && ci < (int64_t(1) << Sb));
+    } else {
+      const double c = double(ci) * inv_s, d = double(di) * inv_s;
+      const double ta = -c / d, tb = (1.0 - c) / d;
+      t0 = fmax(t0, fmin(ta, tb));
+      t1 = fmin(t1, fmax(ta, tb));
+    }
+  }
+  if (empty || !(t1 > t0)) return 0.0f;
+  return float((t1 - t0) * double(len_vox));
+}
+
+constexpr int kPolyMax = 9;
+constexpr size_t kTriEmitLds = size_t(2 * kPolyMax * 2) * kPolyStride * sizeof(double);
+
+// area of the triangle inside [v, v+1)^3 (voxel^2): Sutherland-Hodgman clipping in the
+// triangle's own barycentric plane (l1, l2), FP64, polygons kept in this thread's LDS slots.
+// `poly` points at 2 x 9 x 2 doubles, strided by kPolyStride.
+VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float area2,
+                                          double* poly) {
+  const double inv_s = 1.0 / double(int64_t(1) << Sb);
+  const int64_t s = int64_t(1) << Sb;
+  double cf[3], e0[3], e1[3];
+  bool skip[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int64_t c0 = int64_t(q[a]) - (v[a] << Sb);
+    const int64_t d0 = int64_t(q[3 + a]) - int64_t(q[a]);
+    const int64_t d1 = int64_t(q[6 + a]) - int64_t(q[a]);
+    skip[a] = (d0 == 0 && d1 == 0);
+    if (skip[a] && !(c0 >= 0 && c0 < s)) return 0.0f;   // flat on axis a, owned by another layer
+    cf[a] = double(c0) * inv_s;
+    e0[a] = double(d0) * inv_s;
+    e1[a] = double(d1) * inv_s;
+  }
+#define PX(b, i) poly[((b) * 2 * kPolyMax + (i) * 2) * kPolyStride]
+#define PY(b, i) poly[((b) * 2 * kPolyMax + (i) * 2 + 1) * kPolyStride]
+  int n = 3, cur = 0;
+  PX(0, 0) = 0.0; PY(0, 0) = 0.0;
+  PX(0, 1) = 1.0; PY(0, 1) = 0.0;
+  PX(0, 2) = 0.0; PY(0, 2) = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    if (skip[a]) continue;
+    for (int side = 0; side < 2; ++side) {
+      // f >= 0 with f = x_a (side 0) or 1 - x_a (side 1), x_a = cf + l1 e0 + l2 e1
+      bool all_in = true, all_out = true;
+      for (int i = 0; i < n; ++i) {
+        double x = cf[a] + PX(cur, i) * e0[a] + PY(cur, i) * e1[a];
+        double f = side ? 1.0 - x : x;
+        all_in = all_in && f >= 0.0;
+        all_out = all_out && f < 0.0;
+      }
+      if (all_out) return 0.0f;
+      if (all_in) continue;
+      const int nb = cur ^ 1;
+      int m = 0;
+      double xp = PX(cur, n - 1), yp = PY(cur, n - 1);
+      double fp = cf[a] + xp * e0[a] + yp * e1[a];
+      fp = side ? 1.0 - fp : fp;
+      for (int i = 0; i < n; ++i) {
+        const double xc = PX(cur, i), yc = PY(cur, i);
+        double fc = cf[a] + xc * e0[a] + yc * e1[a];
+        fc = side ? 1.0 - fc : fc;
+        // a convex polygon gains at most one vertex per plane; vertices beyond the 9 slots
+        // (possible only from rounding in degenerate slivers) are dropped
+        if ((fp >= 0.0) != (fc >= 0.0) && m < kPolyMax) {
+          const double t = fp / (fp - fc);
+          PX(nb, m) = xp + t * (xc - xp);
+          PY(nb, m) = yp + t * (yc - yp);
+          ++m;
+        }
+        if (fc >= 0.0 && m < kPolyMax) {
+          PX(nb, m) = xc;
+          PY(nb, m) = yc;
+          ++m;
+        }
+        xp = xc; yp = yc; fp = fc;
+      }
+      n = m;
+      cur = nb;
+      if (n < 3) return 0.0f;
+    }
+  }
+  double acc = 0.0;
+  const double x0 = PX(cur, 0), y0 = PY(cur, 0);
+  for (int i = 1; i + 1 < n; ++i) {
+    const double ux = PX(cur, i) - x0, uy = PY(cur, i) - y0;
+    const double wx = PX(cur, i + 1) - x0, wy = PY(cur, i + 1) - y0;
+    acc += ux * wy - uy * wx;
+  }
+#undef PX
+#undef PY
+  return float(0.5 * fabs(acc) * double(area2));
+}
+
+
+}  // namespace vx

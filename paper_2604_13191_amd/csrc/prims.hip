@@ -1,0 +1,333 @@
+// prims.hip -- per-primitive work of the voxelizer on gfx950:
+//   prep  : Sec. 3.1 grid transform snapped to the lattice, candidate voxel ranges;
+//   test  : exact closed-box touch test per candidate, wave ballot -> 64-bit survivor masks;
+//   emit  : weight (clipped area / length) and Morton key per survivor, written at offsets
+//           from a scan of the mask popcounts (deterministic order, no atomics).
+// The paper generates point samples per primitive and bins them (Sec. 3.2-3.3); here every
+// (primitive, voxel) overlap is found exactly and carries its exact measure instead.
+#include "geom.hpp"
+#include "vx_internal.hpp"
+
+namespace vx {
+
+static_assert(kPolyStride == kBlock, "polygon slots are strided by the block size");
+
+__device__ __forceinline__ void flag_or(int64_t* stats, int64_t bit) {
+  atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)bit);
+}
+
+// ---------------------------------------------------------------------------------------------
+// prep
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ tris, int64_t n, Lat L,
+                                                     int32_t* __restrict__ rec, float4* __restrict__ dirs,
+                                                     int64_t* __restrict__ cand_cnt, int64_t* stats) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    bool ok;
+    cand_cnt[i] = prep_triangle(tris + i * 9, L, rec + i * kRec, dirs + i, ok);
+    if (!ok) flag_or(stats, VX_FLAG_INPUT);
+  }
+}
+
+// One thread per point: point i starts segment (i, i+1) when both belong to the same fiber.
+__global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ pts, int64_t n_pts,
+                                                     const int64_t* __restrict__ offsets, int64_t n_fib, Lat L,
+                                                     int32_t* __restrict__ rec, float4* __restrict__ dirs,
+                                                     int64_t* __restrict__ cand_cnt, int64_t* stats) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_pts; i += int64_t(gridDim.x) * kBlock) {
+    // fiber of point i: the last f with offsets[f] <= i
+    int64_t lo = 0, hi = n_fib;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (offsets[mid] <= i) lo = mid; else hi = mid;
+    }
+    const bool seg = (i + 1 < n_pts) && (i + 1 < offsets[lo + 1]);
+    bool ok;
+    cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, L, rec + i * kRec, dirs + i, ok);
+    if (!ok) flag_or(stats, VX_FLAG_INPUT);
+  }
+}
+
+__global__ void k_check_offsets(const int64_t* __restrict__ offsets, int64_t n_fib, int64_t n_pts, int64_t* stats) {
+  for (int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; f <= n_fib; f += int64_t(gridDim.x) * blockDim.x) {
+    bool bad = false;
+    if (f == 0) bad = offsets[0] != 0;
+    else bad = offsets[f] < offsets[f - 1];
+    if (f == n_fib) bad = bad || offsets[n_fib] != n_pts;
+    if (bad) flag_or(stats, VX_FLAG_OFFSETS);
+  }
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// test: one wave per 64 candidates
+// ---------------------------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec, const int64_t* __restrict__ cand_off,
+                                                 int64_t n_prims, const int64_t* __restrict__ ctl, Lat L,
+                                                 uint64_t* __restrict__ masks, int64_t* __restrict__ chunk_prim) {
+  const int64_t n_cand = ctl[CTL_N_CAND];
+  const int64_t n_chunks = ctl[CTL_N_CHUNKS];
+  const int lane = lane_id();
+  const int64_t w0 = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  const int64_t ws = int64_t(gridDim.x) * kWaves;
+  for (int64_t ch = w0; ch < n_chunks; ch += ws) {
+    const int64_t c0 = ch * 64;
+    int64_t p0 = 0;
+    if (lane == 0) p0 = find_prim(cand_off, 0, n_prims, c0);
+    p0 = __shfl(p0, 0, 64);
+    const int64_t ci = c0 + lane;
+    bool hit = false;
+    if (ci < n_cand) {
+      const int64_t p = find_prim(cand_off, p0, n_prims, ci);
+      const int32_t* r = rec + p * kRec;
+      int64_t v[3];
+      candidate_voxel(r, ci - cand_off[p], v);
+      if (KIND == 0) hit = tri_touch(r, v, L.s, L.Sb);
+      else hit = cap_touch(r, v, L.s, L.Sb, L.rho);
+    }
+    const uint64_t m = __ballot(hit);
+    if (lane == 0) {
+      masks[ch] = m;
+      chunk_prim[ch] = p0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// emit: survivors write (key, weight, primitive) at scan offsets
+// ---------------------------------------------------------------------------------------------
+template <int KIND, class Key>
+__global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec, const float4* __restrict__ dirs,
+                                                 const int64_t* __restrict__ cand_off, int64_t n_prims,
+                                                 const int64_t* __restrict__ ctl, Lat L,
+                                                 const uint64_t* __restrict__ masks,
+                                                 const int64_t* __restrict__ chunk_prim,
+                                                 const int64_t* __restrict__ wave_off, Key* __restrict__ keys,
+                                                 float* __restrict__ wts, uint32_t* __restrict__ prim) {
+  extern __shared__ double lds_poly[];
+  const int64_t n_chunks = ctl[CTL_N_CHUNKS];
+  const int lane = lane_id();
+  const int64_t w0 = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  const int64_t ws = int64_t(gridDim.x) * kWaves;
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  for (int64_t ch = w0; ch < n_chunks; ch += ws) {
+    const uint64_t m = masks[ch];
+    if (!((m >> lane) & 1)) continue;
+    const int64_t pos = wave_off[ch] + __popcll(m & lt);
+    const int64_t ci = ch * 64 + lane;
+    const int64_t p = find_prim(cand_off, chunk_prim[ch], n_prims, ci);
+    const int32_t* r = rec + p * kRec;
+    int64_t v[3];
+    candidate_voxel(r, ci - cand_off[p], v);
+    float wgt;
+    if (KIND == 0) wgt = tri_area(r, v, L.Sb, dirs[p].w, lds_poly + threadIdx.x);
+    else wgt = seg_length(r, v, L.Sb, dirs[p].w);
+    keys[pos] = Key(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])));
+    wts[pos] = wgt;
+    prim[pos] = uint32_t(p);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// scans: candidate offsets, survivor offsets
+// ---------------------------------------------------------------------------------------------
+struct ArrIn {
+  const int64_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i]; }
+};
+struct ArrOut {
+  int64_t* o;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t) const { o[i] = ex; }
+};
+struct CandTotal {
+  int64_t* cand_off;
+  int64_t* ctl;
+  int64_t* stats;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    cand_off[n] = total;
+    stats[VX_STAT_CAND] = total;
+    const bool over = total > cap;
+    if (over) flag_or(stats, VX_FLAG_CAND_CAPACITY);
+    const int64_t eff = over ? 0 : total;
+    ctl[CTL_N_CAND] = eff;
+    ctl[CTL_N_CHUNKS] = (eff + 63) / 64;
+  }
+};
+struct PopIn {
+  const uint64_t* m;
+  __device__ int64_t operator()(int64_t i) const { return __popcll(m[i]); }
+};
+struct PairTotal {
+  int64_t* wave_off;
+  int64_t* ctl;
+  int64_t* stats;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    wave_off[n] = total;
+    stats[VX_STAT_PAIRS] = total;
+    const bool over = total > cap;
+    if (over) {
+      flag_or(stats, VX_FLAG_PAIR_CAPACITY);
+      ctl[CTL_N_CHUNKS] = 0;          // emit nothing
+    }
+    ctl[CTL_N_PAIRS] = over ? 0 : total;
+  }
+};
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
+  int blocks = int((n + 255) / 256);
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_fill_i64, dim3(blocks), dim3(256), 0, s, p, n, v);
+}
+
+// ---------------------------------------------------------------------------------------------
+// the whole voxelize pass
+// ---------------------------------------------------------------------------------------------
+struct VoxWs {
+  int64_t* ctl;
+  int32_t* rec;
+  float4* dirs;
+  int64_t* cand_cnt;
+  int64_t* cand_off;
+  uint64_t* masks;
+  int64_t* chunk_prim;
+  int64_t* wave_off;
+  PairBufs pa, pb;
+  int32_t* hist;
+  int64_t* partial;
+  int64_t* seg_start;
+};
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static size_t voxelize_ws_layout(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, void* base,
+                                 VoxWs* w) {
+  Carver cv(base);
+  const int64_t n_chunks = cdiv(max_cand, 64);
+  const int kb = key64 ? 8 : 4;
+  VoxWs x;
+  x.ctl = cv.take<int64_t>(CTL_SIZE);
+  x.rec = cv.take<int32_t>(n_prims * kRec);
+  x.dirs = cv.take<float4>(n_prims);
+  x.cand_cnt = cv.take<int64_t>(n_prims);
+  x.cand_off = cv.take<int64_t>(n_prims + 1);
+  x.masks = cv.take<uint64_t>(n_chunks);
+  x.chunk_prim = cv.take<int64_t>(n_chunks);
+  x.wave_off = cv.take<int64_t>(n_chunks + 1);
+  for (int k = 0; k < 2; ++k) {
+    PairBufs& p = k ? x.pb : x.pa;
+    p.keys = cv.take<uint8_t>(max_pairs * kb);
+    p.w = cv.take<float>(max_pairs);
+    p.prim = cv.take<uint32_t>(max_pairs);
+  }
+  x.hist = cv.take<int32_t>(int64_t(256) * kGrid);
+  x.partial = cv.take<int64_t>(kGrid + 1);
+  x.seg_start = cv.take<int64_t>(max_pairs + 1);
+  if (w) *w = x;
+  return cv.off + 256;
+}
+
+size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64) {
+  return voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, nullptr, nullptr);
+}
+
+vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                       int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws_ptr,
+                       const vx_voxels* out, int64_t* stats, hipStream_t s) {
+  const bool key64 = g->log2_res > 10;
+  VoxWs w;
+  voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, ws_ptr, &w);
+  Lat L;
+  for (int a = 0; a < 3; ++a) L.bmin[a] = g->bmin[a];
+  L.inv = ldexp(1.0, 23) / g->extent;
+  L.Sb = 23 - g->log2_res;
+  L.s = int64_t(1) << L.Sb;
+  L.R = 1 << g->log2_res;
+  L.rho = kind == 1 ? int64_t(rint(double(radius) * L.inv)) : 0;
+
+  launch_fill_i64(stats, VX_NSTAT, 0, s);
+  launch_fill_i64(w.ctl, CTL_SIZE, 0, s);
+  const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
+  if (kind == 0) {
+    VX_TIMED("prep_tri", s);
+    hipLaunchKernelGGL(k_prep_tri, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, L, w.rec, w.dirs, w.cand_cnt,
+                       stats);
+  } else {
+    {
+      VX_TIMED("check_offsets", s);
+      hipLaunchKernelGGL(k_check_offsets, dim3(int(n_fib / 256 + 1 < 256 ? n_fib / 256 + 1 : 256)), dim3(256), 0,
+                         s, offsets, n_fib, n_prims, stats);
+    }
+    VX_TIMED("prep_fib", s);
+    hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, L, w.rec,
+                       w.dirs, w.cand_cnt, stats);
+  }
+  {
+    VX_TIMED("scan_cand", s);
+    device_scan(ArrIn{w.cand_cnt}, ArrOut{w.cand_off}, CandTotal{w.cand_off, w.ctl, stats, max_cand}, nullptr,
+                n_prims, w.partial, s);
+  }
+  {
+    VX_TIMED(kind == 0 ? "test_tri" : "test_fib", s);
+    if (kind == 0)
+      hipLaunchKernelGGL(k_test<0>, dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims, w.ctl, L,
+                         w.masks, w.chunk_prim);
+    else
+      hipLaunchKernelGGL(k_test<1>, dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims, w.ctl, L,
+                         w.masks, w.chunk_prim);
+  }
+  {
+    VX_TIMED("scan_pairs", s);
+    device_scan(PopIn{w.masks}, ArrOut{w.wave_off}, PairTotal{w.wave_off, w.ctl, stats, max_pairs},
+                w.ctl + CTL_N_CHUNKS, 0, w.partial, s);
+  }
+  {
+    const size_t lds = kind == 0 ? kTriEmitLds : 0;
+    if (kind == 0) {
+      static bool attr_set[2] = {false, false};
+      if (!attr_set[key64]) {
+        if (key64)
+          (void)hipFuncSetAttribute((const void*)k_emit<0, uint64_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(kTriEmitLds));
+        else
+          (void)hipFuncSetAttribute((const void*)k_emit<0, uint32_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(kTriEmitLds));
+        attr_set[key64] = true;
+      }
+    }
+    VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
+    if (kind == 0) {
+      if (key64)
+        hipLaunchKernelGGL((k_emit<0, uint64_t>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off,
+                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint64_t*)w.pa.keys, w.pa.w,
+                           w.pa.prim);
+      else
+        hipLaunchKernelGGL((k_emit<0, uint32_t>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off,
+                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint32_t*)w.pa.keys, w.pa.w,
+                           w.pa.prim);
+    } else {
+      if (key64)
+        hipLaunchKernelGGL((k_emit<1, uint64_t>), dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.dirs, w.cand_off,
+                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint64_t*)w.pa.keys, w.pa.w,
+                           w.pa.prim);
+      else
+        hipLaunchKernelGGL((k_emit<1, uint32_t>), dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.dirs, w.cand_off,
+                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint32_t*)w.pa.keys, w.pa.w,
+                           w.pa.prim);
+    }
+  }
+  const int key_bits = 3 * g->log2_res;
+  const int res = radix_sort_pairs(key64, key_bits, w.pa, w.pb, w.ctl + CTL_N_PAIRS, max_pairs, w.hist, w.partial, s);
+  reduce_pairs(key64, res ? w.pb : w.pa, w.ctl + CTL_N_PAIRS, w.dirs, kind, w.seg_start, w.partial, w.ctl, stats,
+               *out, s);
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+}  // namespace vx

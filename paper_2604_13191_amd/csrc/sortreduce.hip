@@ -1,0 +1,312 @@
+// sortreduce.hip -- ordering the (key, weight, primitive) pairs and aggregating them.
+//   radix sort  : Sec. 3.3 orders the samples by voxel id so that each voxel's samples are
+//                 contiguous; here a stable LSD radix sort (8-bit digits) with wave-level
+//                 ranking in LDS, fixed grid, no atomics on global memory.
+//   reduce      : Sec. 3.3 finds the positions where the id changes (head flags, scanned into
+//                 segment starts); Sec. 3.4 / Sec. 4.1 aggregate each voxel's orientation data
+//                 into one SGGX matrix -- here the weighted second moment S = sum w M.
+//   LoD level   : Sec. 4.3 aggregates 2x2x2 children into a coarser voxel; children of a parent
+//                 are contiguous in Morton order, so this is a segmented sum over key >> 3.
+#include "vx_internal.hpp"
+
+namespace vx {
+
+__device__ __forceinline__ void flag_or_s(int64_t* p, int64_t bit) {
+  atomicOr(reinterpret_cast<unsigned long long*>(p), (unsigned long long)bit);
+}
+
+// ---------------------------------------------------------------------------------------------
+// radix sort
+// ---------------------------------------------------------------------------------------------
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const Key* __restrict__ keys, const int64_t* n_ptr, int shift,
+                                                       int32_t* __restrict__ hist) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = *n_ptr;
+  const int64_t chunk = scan_chunk(n);
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&h[int((keys[i] >> shift) & 255)], 1);
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * kGrid + blockIdx.x] = h[threadIdx.x];
+}
+
+struct I32In {
+  const int32_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i]; }
+};
+struct I32Out {
+  int32_t* o;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t) const { o[i] = int32_t(ex); }
+};
+struct NoTotal {
+  __device__ void operator()(int64_t, int64_t) const {}
+};
+
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict__ kin, const float* __restrict__ win,
+                                                          const uint32_t* __restrict__ pin, Key* __restrict__ kout,
+                                                          float* __restrict__ wout, uint32_t* __restrict__ pout,
+                                                          const int64_t* n_ptr, int shift,
+                                                          const int32_t* __restrict__ hist_off) {
+  __shared__ int32_t run[256];
+  __shared__ int32_t cnt[kWaves][256];
+  __shared__ int32_t pre[kWaves][256];
+  const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+  run[t] = hist_off[int64_t(t) * kGrid + blockIdx.x];
+  const int64_t n = *n_ptr;
+  const int64_t chunk = scan_chunk(n);
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  for (int64_t t0 = b0; t0 < b1; t0 += kBlock) {
+    const int64_t i = t0 + t;
+    const bool valid = i < b1;
+    Key k = 0;
+    float wv = 0.f;
+    uint32_t pv = 0;
+    if (valid) { k = kin[i]; wv = win[i]; pv = pin[i]; }
+    const int d = int((k >> shift) & 255);
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    const int rank = __popcll(peers & lt);
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) cnt[ww][t] = 0;
+    __syncthreads();
+    if (valid && rank == 0) cnt[w][d] = __popcll(peers);
+    __syncthreads();
+    {
+      int32_t acc = run[t];
+#pragma unroll
+      for (int ww = 0; ww < kWaves; ++ww) {
+        pre[ww][t] = acc;
+        acc += cnt[ww][t];
+      }
+      run[t] = acc;
+    }
+    __syncthreads();
+    if (valid) {
+      const int32_t pos = pre[w][d] + rank;
+      kout[pos] = k;
+      wout[pos] = wv;
+      pout[pos] = pv;
+    }
+  }
+}
+
+int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int64_t* n_dev, int64_t cap,
+                     int32_t* hist, int64_t* partial, hipStream_t s) {
+  (void)cap;
+  const int passes = (key_bits + 7) / 8;
+  PairBufs src = a, dst = b;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    {
+      VX_TIMED("radix_hist", s);
+      if (key64)
+        hipLaunchKernelGGL(k_radix_hist<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint64_t*)src.keys, n_dev,
+                           shift, hist);
+      else
+        hipLaunchKernelGGL(k_radix_hist<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint32_t*)src.keys, n_dev,
+                           shift, hist);
+    }
+    {
+      VX_TIMED("radix_scan", s);
+      device_scan(I32In{hist}, I32Out{hist}, NoTotal{}, nullptr, int64_t(256) * kGrid, partial, s);
+    }
+    {
+      VX_TIMED("radix_scatter", s);
+      if (key64)
+        hipLaunchKernelGGL(k_radix_scatter<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint64_t*)src.keys,
+                           src.w, src.prim, (uint64_t*)dst.keys, dst.w, dst.prim, n_dev, shift, hist);
+      else
+        hipLaunchKernelGGL(k_radix_scatter<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint32_t*)src.keys,
+                           src.w, src.prim, (uint32_t*)dst.keys, dst.w, dst.prim, n_dev, shift, hist);
+    }
+    PairBufs tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  return passes & 1;
+}
+
+// ---------------------------------------------------------------------------------------------
+// segmented reduce: leaf voxels
+// ---------------------------------------------------------------------------------------------
+template <class Key, int SHIFT>
+struct HeadIn {
+  const Key* k;
+  __device__ int64_t operator()(int64_t i) const { return i == 0 || (k[i] >> SHIFT) != (k[i - 1] >> SHIFT); }
+};
+struct HeadOut {
+  int64_t* start;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t v) const {
+    if (v) start[ex] = i;
+  }
+};
+struct SegTotal {
+  int64_t* start;
+  int64_t* ctl;
+  int64_t* stats;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    start[total] = n;
+    stats[VX_STAT_VOXELS] = total;
+    const bool over = total > cap;
+    if (over) flag_or_s(stats + VX_STAT_FLAGS, VX_FLAG_VOXEL_CAPACITY);
+    ctl[CTL_N_VOX] = over ? 0 : total;
+  }
+};
+
+// one thread per voxel; the voxel's pairs are summed in sorted (stable, emission) order
+template <class Key, int KIND>
+__global__ void __launch_bounds__(kBlock) k_seg_reduce(const Key* __restrict__ keys, const float* __restrict__ wts,
+                                                       const uint32_t* __restrict__ prim,
+                                                       const float4* __restrict__ dirs,
+                                                       const int64_t* __restrict__ start,
+                                                       const int64_t* __restrict__ n_ptr, vx_voxels out) {
+  const int64_t n = *n_ptr;
+  const int64_t cap = out.cap;
+  Key* okeys = reinterpret_cast<Key*>(out.keys);
+  for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n; v += int64_t(gridDim.x) * kBlock) {
+    const int64_t a = start[v], b = start[v + 1];
+    float W = 0.f, Sxx = 0.f, Syy = 0.f, Szz = 0.f, Sxy = 0.f, Sxz = 0.f, Syz = 0.f;
+    for (int64_t j = a; j < b; ++j) {
+      const float wj = wts[j];
+      const float4 t = dirs[prim[j]];
+      W += wj;
+      if (KIND == 0) {          // surface: n n^T
+        const float ax = wj * t.x, ay = wj * t.y;
+        Sxx = fmaf(ax, t.x, Sxx);
+        Syy = fmaf(ay, t.y, Syy);
+        Szz = fmaf(wj * t.z, t.z, Szz);
+        Sxy = fmaf(ax, t.y, Sxy);
+        Sxz = fmaf(ax, t.z, Sxz);
+        Syz = fmaf(ay, t.z, Syz);
+      } else {                  // fiber: I - t t^T
+        const float ax = wj * t.x, ay = wj * t.y;
+        Sxx += wj - ax * t.x;
+        Syy += wj - ay * t.y;
+        Szz += wj - wj * t.z * t.z;
+        Sxy = fmaf(-ax, t.y, Sxy);
+        Sxz = fmaf(-ax, t.z, Sxz);
+        Syz = fmaf(-ay, t.z, Syz);
+      }
+    }
+    okeys[v] = keys[a];
+    out.count[v] = uint32_t(b - a);
+    out.w[v] = W;
+    out.S[v] = Sxx;
+    out.S[cap + v] = Syy;
+    out.S[2 * cap + v] = Szz;
+    out.S[3 * cap + v] = Sxy;
+    out.S[4 * cap + v] = Sxz;
+    out.S[5 * cap + v] = Syz;
+  }
+}
+
+void reduce_pairs(bool key64, PairBufs p, const int64_t* n_pairs_dev, const float4* dirs, int kind,
+                  int64_t* seg_start, int64_t* partial, int64_t* ctl, int64_t* stats, const vx_voxels& out,
+                  hipStream_t s) {
+  {
+    VX_TIMED("seg_heads", s);
+    if (key64)
+      device_scan(HeadIn<uint64_t, 0>{(const uint64_t*)p.keys}, HeadOut{seg_start},
+                  SegTotal{seg_start, ctl, stats, out.cap}, n_pairs_dev, 0, partial, s);
+    else
+      device_scan(HeadIn<uint32_t, 0>{(const uint32_t*)p.keys}, HeadOut{seg_start},
+                  SegTotal{seg_start, ctl, stats, out.cap}, n_pairs_dev, 0, partial, s);
+  }
+  VX_TIMED("seg_reduce", s);
+#define VX_SEG(K, KD)                                                                                            \
+  hipLaunchKernelGGL((k_seg_reduce<K, KD>), dim3(kGrid), dim3(kBlock), 0, s, (const K*)p.keys, p.w, p.prim, dirs, \
+                     seg_start, ctl + CTL_N_VOX, out)
+  if (key64) {
+    if (kind == 0) VX_SEG(uint64_t, 0); else VX_SEG(uint64_t, 1);
+  } else {
+    if (kind == 0) VX_SEG(uint32_t, 0); else VX_SEG(uint32_t, 1);
+  }
+#undef VX_SEG
+}
+
+// ---------------------------------------------------------------------------------------------
+// LoD: parent = sum of its (<= 8, contiguous) children
+// ---------------------------------------------------------------------------------------------
+struct LodTotal {
+  int64_t* start;
+  int64_t* n_out;     // clamped count of the new level
+  int64_t* flags;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    const bool over = total > cap;
+    if (over) flag_or_s(flags, VX_FLAG_VOXEL_CAPACITY);
+    const int64_t eff = over ? cap : total;
+    start[eff] = n;      // only read up to the clamped count
+    *n_out = eff;
+  }
+};
+
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_lod_reduce(vx_voxels in, const int64_t* __restrict__ start,
+                                                       const int64_t* __restrict__ n_ptr, vx_voxels out) {
+  const int64_t n = *n_ptr;
+  const Key* ikeys = reinterpret_cast<const Key*>(in.keys);
+  Key* okeys = reinterpret_cast<Key*>(out.keys);
+  const int64_t ci = in.cap, co = out.cap;
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n; p += int64_t(gridDim.x) * kBlock) {
+    const int64_t a = start[p], b = start[p + 1];
+    uint32_t c = 0, mask = 0;
+    float W = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t j = a; j < b; ++j) {
+      c += in.count[j];
+      mask |= 1u << uint32_t(ikeys[j] & 7);
+      W += in.w[j];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) S[k] += in.S[k * ci + j];
+    }
+    okeys[p] = ikeys[a] >> 3;
+    out.count[p] = c;
+    out.mask[p] = uint8_t(mask);
+    out.w[p] = W;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out.S[k * co + p] = S[k];
+  }
+}
+
+__global__ void k_clamp_count(const int64_t* src, int64_t cap, int64_t* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t v = *src;
+    *dst = v < 0 ? 0 : (v > cap ? cap : v);
+  }
+}
+
+void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(64), 0, s, src, cap, dst);
+}
+
+void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
+               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s) {
+  {
+    VX_TIMED("lod_heads", s);
+    if (key64)
+      device_scan(HeadIn<uint64_t, 3>{(const uint64_t*)in.keys}, HeadOut{pstart},
+                  LodTotal{pstart, n_out, flags, out.cap}, n_in, 0, partial, s);
+    else
+      device_scan(HeadIn<uint32_t, 3>{(const uint32_t*)in.keys}, HeadOut{pstart},
+                  LodTotal{pstart, n_out, flags, out.cap}, n_in, 0, partial, s);
+  }
+  VX_TIMED("lod_reduce", s);
+  if (key64)
+    hipLaunchKernelGGL(k_lod_reduce<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, in, pstart, n_out, out);
+  else
+    hipLaunchKernelGGL(k_lod_reduce<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, in, pstart, n_out, out);
+}
+
+}  // namespace vx

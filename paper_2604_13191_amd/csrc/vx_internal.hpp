@@ -1,0 +1,223 @@
+// vx_internal.hpp -- device helpers shared by the libvx kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vx.h"
+
+namespace vx {
+
+constexpr int kBlock = 256;          // threads per block: 4 waves of 64
+constexpr int kWaves = kBlock / 64;
+constexpr int kGrid = 1024;          // persistent grid of the streaming kernels: 4 blocks per CU
+
+// ---------------------------------------------------------------------------------------------
+// Kernel timing (measurement only): events around every launch when enabled.
+// ---------------------------------------------------------------------------------------------
+void timing_begin(const char* name, hipStream_t s);
+void timing_end(hipStream_t s);
+
+struct TimedLaunch {
+  hipStream_t s;
+  TimedLaunch(const char* name, hipStream_t st) : s(st) { timing_begin(name, st); }
+  ~TimedLaunch() { timing_end(s); }
+};
+#define VX_CAT2(a, b) a##b
+#define VX_CAT(a, b) VX_CAT2(a, b)
+#define VX_TIMED(name, stream) ::vx::TimedLaunch VX_CAT(vx_timed_, __LINE__)(name, stream)
+
+// ---------------------------------------------------------------------------------------------
+// Morton keys: x bit b -> key bit 3b, y -> 3b+1, z -> 3b+2.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;                       // 21 bits
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+__device__ __forceinline__ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Wave and block scans (wave64).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T u = __shfl_up(v, off, 64);
+    if (l >= off) v += u;
+  }
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Exclusive scan over the block; returns this thread's exclusive prefix and the block total.
+// `tmp` holds kWaves + 1 entries of LDS.  Contains __syncthreads().
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T& total) {
+  const int w = threadIdx.x >> 6;
+  T inc = wave_inclusive_scan(v);
+  if (lane_id() == 63) tmp[w] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    T x = tmp[i];
+    if (i < w) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device-wide exclusive scan with a fixed grid (reduce, scan the partials, apply).
+// The element count may live in device memory (n_ptr), so the launch needs no host sync.
+// In:    int64_t operator()(int64_t i)            value of element i
+// Out:   void operator()(int64_t i, int64_t excl, int64_t v)
+// Total: void operator()(int64_t total, int64_t n)  called once, by one thread
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t scan_n(const int64_t* n_ptr, int64_t n_const) {
+  return n_ptr ? *n_ptr : n_const;
+}
+__device__ __forceinline__ int64_t scan_chunk(int64_t n) {
+  int64_t c = (n + kGrid - 1) / kGrid;
+  return (c + kBlock - 1) / kBlock * kBlock;
+}
+
+template <class In>
+__global__ void __launch_bounds__(kBlock) k_scan_partial(In in, const int64_t* n_ptr, int64_t n_const,
+                                                         int64_t* partial) {
+  __shared__ int64_t red[kWaves];
+  const int64_t n = scan_n(n_ptr, n_const);
+  const int64_t chunk = scan_chunk(n);
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  int64_t acc = 0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) acc += in(i);
+  acc = wave_sum(acc);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int i = 0; i < kWaves; ++i) t += red[i];
+    partial[blockIdx.x] = t;
+  }
+}
+
+// One block of 1024 threads scans kGrid partials in place (exclusive).
+template <class Total>
+__global__ void __launch_bounds__(1024) k_scan_top(int64_t* partial, const int64_t* n_ptr, int64_t n_const,
+                                                   Total total) {
+  __shared__ int64_t tmp[16];
+  const int t = threadIdx.x;
+  int64_t v = t < kGrid ? partial[t] : 0;
+  int64_t inc = wave_inclusive_scan(v);
+  if (lane_id() == 63) tmp[t >> 6] = inc;
+  __syncthreads();
+  int64_t base = 0, tot = 0;
+  for (int i = 0; i < 16; ++i) {
+    if (i < (t >> 6)) base += tmp[i];
+    tot += tmp[i];
+  }
+  if (t < kGrid) partial[t] = base + inc - v;
+  if (t == 0) total(tot, scan_n(n_ptr, n_const));
+}
+
+template <class In, class Out>
+__global__ void __launch_bounds__(kBlock) k_scan_apply(In in, Out out, const int64_t* n_ptr, int64_t n_const,
+                                                       const int64_t* partial) {
+  __shared__ int64_t tmp[kWaves + 1];
+  const int64_t n = scan_n(n_ptr, n_const);
+  const int64_t chunk = scan_chunk(n);
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  int64_t base = partial[blockIdx.x];
+  for (int64_t t0 = b0; t0 < b1; t0 += kBlock) {
+    const int64_t i = t0 + threadIdx.x;
+    const int64_t v = i < b1 ? in(i) : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(v, tmp, tot);
+    if (i < b1) out(i, base + ex, v);
+    base += tot;
+  }
+}
+
+template <class In, class Out, class Total>
+inline void device_scan(In in, Out out, Total total, const int64_t* n_ptr, int64_t n_const, int64_t* partial,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_partial<In>, dim3(kGrid), dim3(kBlock), 0, s, in, n_ptr, n_const, partial);
+  hipLaunchKernelGGL(k_scan_top<Total>, dim3(1), dim3(1024), 0, s, partial, n_ptr, n_const, total);
+  hipLaunchKernelGGL((k_scan_apply<In, Out>), dim3(kGrid), dim3(kBlock), 0, s, in, out, n_ptr, n_const,
+                     partial);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Workspace carving (256-byte aligned sub-buffers).
+// ---------------------------------------------------------------------------------------------
+struct Carver {
+  uintptr_t base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(reinterpret_cast<uintptr_t>(p)) {}
+  template <class T>
+  T* take(int64_t n) {
+    size_t bytes = size_t(n > 0 ? n : 1) * sizeof(T);
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+// internal control block (device): effective counts that later kernels iterate over
+enum { CTL_N_CAND = 0, CTL_N_CHUNKS, CTL_N_PAIRS, CTL_N_VOX, CTL_SIZE = 8 };
+
+// ---------------------------------------------------------------------------------------------
+// launchers implemented in the .hip files
+// ---------------------------------------------------------------------------------------------
+struct PairBufs {
+  void* keys;       // uint32 or uint64
+  float* w;
+  uint32_t* prim;
+};
+
+void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+
+// sort pairs by key (stable LSD radix); returns the buffer index (0 = a, 1 = b) holding the result
+int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int64_t* n_dev, int64_t cap,
+                     int32_t* hist, int64_t* partial, hipStream_t s);
+
+// segmented reduce of sorted pairs into leaf voxels
+void reduce_pairs(bool key64, PairBufs p, const int64_t* n_pairs_dev, const float4* dirs, int kind,
+                  int64_t* seg_start, int64_t* partial, int64_t* ctl, int64_t* stats, const vx_voxels& out,
+                  hipStream_t s);
+
+// one LoD level: parent reduce of `in` (n_in on the device) into `out`; n_out receives the
+// new count clamped to out.cap, and flags the capacity bit when it had to be clamped
+void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
+               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s);
+void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s);
+
+// the voxelize pass (prims.hip)
+size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64);
+vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                       int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws,
+                       const vx_voxels* out, int64_t* stats, hipStream_t s);
+
+}  // namespace vx

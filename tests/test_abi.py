@@ -1,0 +1,62 @@
+"""CPU checks of the C ABI library: it loads, exports every function include/vx.h declares,
+and its host-only calls behave (no kernel is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vx.h")
+LIB = os.path.join(ROOT, "paper_2604_13191_amd", "libvx.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vx_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2604_13191_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_host_only_calls(lib):
+    f = lib.vx_voxelize_workspace_size
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    assert f(0, 100, 1000, 500, 6) > 0
+    assert f(1, 100, 1000, 500, 12) > f(1, 100, 1000, 500, 6)      # 64-bit keys need more room
+    assert f(0, 100, 1000, 1 << 31, 6) == 0                          # pairs beyond 2^31 - 1
+    assert f(3, 100, 1000, 500, 6) == 0 and f(0, -1, 0, 0, 6) == 0 and f(0, 1, 1, 1, 21) == 0
+    g = lib.vx_lod_workspace_size
+    g.restype = ctypes.c_size_t
+    g.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    assert g(1000, 7, 1) > 0 and g(0, 7, 1) == 0 and g(10, 7, 9) == 0
+    s = lib.vx_status_str
+    s.restype = ctypes.c_char_p
+    assert s(0) == b"ok" and s(2) == b"capacity exceeded"
+
+
+def test_argument_errors_before_any_launch(lib):
+    class CGrid(ctypes.Structure):
+        _fields_ = [("bmin", ctypes.c_double * 3), ("extent", ctypes.c_double), ("log2_res", ctypes.c_int32)]
+    f = lib.vx_voxelize_triangles
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(CGrid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    bad = CGrid((ctypes.c_double * 3)(0, 0, 0), 0.0, 4)
+    assert f(ctypes.byref(bad), None, 0, 0, 0, None, 0, None, None, None) == 1
+    good = CGrid((ctypes.c_double * 3)(0, 0, 0), 1.0, 4)
+    assert f(ctypes.byref(good), None, 0, 0, 0, None, 0, None, None, None) == 1     # no outputs
