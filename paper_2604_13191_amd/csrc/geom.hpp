@@ -120,12 +120,28 @@ VX_HD inline int64_t prep_segment(const float* a, const float* b, const Lat& L, 
   return ok ? cnt : 0;
 }
 
-// last p in [lo, n_prims) with cand_off[p] <= c
-VX_HD inline int64_t find_prim(const int64_t* __restrict__ cand_off, int64_t lo, int64_t n_prims,
-                                             int64_t c) {
-  int64_t hi = n_prims;
+// last p in [lo, n_prims) with cand_off[p] <= c, given cand_off[lo] <= c: galloping search from
+// lo (a run of 64 candidates spans few primitives), then bisection
+VX_HD inline int64_t find_prim(const int64_t* __restrict__ cand_off, int64_t lo, int64_t n_prims, int64_t c) {
+  int64_t step = 1, hi = lo + 1;
+  while (hi < n_prims && cand_off[hi] <= c) {
+    lo = hi;
+    step <<= 1;
+    hi = lo + step;
+  }
+  if (hi > n_prims) hi = n_prims;
   while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
+    const int64_t mid = (lo + hi) >> 1;
+    if (cand_off[mid] <= c) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// last p in [0, n_prims) with cand_off[p] <= c, by bisection (cand_off[0] = 0 <= c)
+VX_HD inline int64_t find_prim_bisect(const int64_t* __restrict__ cand_off, int64_t n_prims, int64_t c) {
+  int64_t lo = 0, hi = n_prims;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
     if (cand_off[mid] <= c) lo = mid; else hi = mid;
   }
   return lo;
@@ -216,8 +232,7 @@ VX_HD inline bool tri_touch(const int32_t* q, const int64_t v[3], int64_t s, int
 }
 
 // ---------------------------------------------------------------------------------------------
-// exact capsule / closed box test: min over t in [0,1] of f(t) = dist^2(c + t d, [0, s]^3)
-// against rho^2.  FP64 with an error bound; exact 128-bit integers when too close to call.
+// capsules: is the centreline within rho of the closed box?
 // ---------------------------------------------------------------------------------------------
 VX_HD inline double fdist2(double t, const double c[3], const double d[3], double s) {
   double f = 0;
@@ -286,13 +301,14 @@ VX_HD __attribute__((noinline)) bool cap_exact(const int64_t c[3], const int64_t
   return false;
 }
 
-#define VX_CSWAP(i, j) { double lo_ = fmin(t[i], t[j]); t[j] = fmax(t[i], t[j]); t[i] = lo_; }
-
+// exact capsule / closed box test: min over t in [0,1] of f(t) = dist^2(c + t d, [0, s]^3)
+// against rho^2.  FP64 with an error bound (all inputs are exact integers below 2^26; every
+// rounding of the bracketing, the interpolation and the evaluation stays far inside
+// M^2 2^-44); exact 128-bit integers when too close to call.
 VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
   int64_t ci[3], di[3];
   double c[3], d[3];
   double M = double(s);
-#pragma unroll
   for (int a = 0; a < 3; ++a) {
     ci[a] = int64_t(r[a]) - (v[a] << Sb);
     di[a] = int64_t(r[3 + a]) - int64_t(r[a]);
@@ -301,52 +317,64 @@ VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int
     M = fmax(M, fabs(c[a]) + fabs(d[a]) + double(s));
   }
   const double ds = double(s);
-  double t[8];
-  t[0] = 0.0;
-  t[1] = 1.0;
-#pragma unroll
+  const double r2 = double(rho) * double(rho);
+  const double err = M * M * 0x1p-44;
+  {
+    // the box holds the ball of radius h around its centre and lies in the ball of radius
+    // h sqrt(3): distance from the centre to the segment decides most candidates
+    const double h = 0.5 * ds;
+    double wx = h - c[0], wy = h - c[1], wz = h - c[2];
+    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double tc = dd > 0 ? (wx * d[0] + wy * d[1] + wz * d[2]) / dd : 0.0;
+    tc = fmin(fmax(tc, 0.0), 1.0);
+    wx = fma(-tc, d[0], wx);
+    wy = fma(-tc, d[1], wy);
+    wz = fma(-tc, d[2], wz);
+    const double dc2 = wx * wx + wy * wy + wz * wz;
+    const double rin = h + double(rho);
+    if (dc2 + err <= rin * rin) return true;
+    const double rout = h * 1.7320508075688772 + double(rho);
+    if (dc2 - err > rout * rout * (1.0 + 0x1p-40)) return false;
+  }
+  // f is convex and piecewise quadratic, so f' is monotone and piecewise linear with its
+  // breakpoints where a coordinate crosses 0 or s.  Let t_lo be the largest of {0, 1,
+  // breakpoints} with f' <= 0 and t_hi the smallest with f' >= 0: no breakpoint lies strictly
+  // between them, f' is linear there and its zero is the minimiser.
+  double tb[8];
+  tb[0] = 0.0;
+  tb[1] = 1.0;
   for (int a = 0; a < 3; ++a) {
     double t0 = 0.0, t1 = 0.0;
     if (di[a] != 0) {
-      t0 = fmin(fmax(-c[a] / d[a], 0.0), 1.0);
-      t1 = fmin(fmax((ds - c[a]) / d[a], 0.0), 1.0);
+      const double inv = 1.0 / d[a];
+      t0 = fmin(fmax(-c[a] * inv, 0.0), 1.0);
+      t1 = fmin(fmax((ds - c[a]) * inv, 0.0), 1.0);
     }
-    t[2 + 2 * a] = t0;
-    t[3 + 2 * a] = t1;
+    tb[2 + 2 * a] = t0;
+    tb[3 + 2 * a] = t1;
   }
-  VX_CSWAP(0, 1) VX_CSWAP(2, 3) VX_CSWAP(4, 5) VX_CSWAP(6, 7) VX_CSWAP(0, 2) VX_CSWAP(1, 3) VX_CSWAP(4, 6)
-  VX_CSWAP(5, 7) VX_CSWAP(1, 2) VX_CSWAP(5, 6) VX_CSWAP(0, 4) VX_CSWAP(3, 7) VX_CSWAP(1, 5) VX_CSWAP(2, 6)
-  VX_CSWAP(1, 4) VX_CSWAP(3, 6) VX_CSWAP(2, 4) VX_CSWAP(3, 5) VX_CSWAP(3, 4)
-  double fmin_ = fdist2(t[0], c, d, ds);
-#pragma unroll
-  for (int k = 1; k < 8; ++k) fmin_ = fmin(fmin_, fdist2(t[k], c, d, ds));
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const double ta = t[k], tb = t[k + 1];
-    const double m = 0.5 * (ta + tb);
-    double Q = 0, P = 0;
-#pragma unroll
+  double t_lo = -1.0, g_lo = 0.0, t_hi = 2.0, g_hi = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    const double t = tb[k];
+    double g = 0.0;                         // f'(t) / 2
     for (int a = 0; a < 3; ++a) {
-      double x = fma(m, d[a], c[a]);
-      double b = x < 0 ? 0.0 : (x > ds ? ds : x);
-      bool act = (x < 0) || (x > ds);
-      if (act) {
-        Q = fma(d[a], d[a], Q);
-        P = fma(-(c[a] - b), d[a], P);
-      }
+      const double x = fma(t, d[a], c[a]);
+      const double e = x < 0 ? x : (x > ds ? x - ds : 0.0);
+      g = fma(e, d[a], g);
     }
-    if (Q > 0 && tb > ta) {
-      double ts = fmin(fmax(P / Q, ta), tb);
-      fmin_ = fmin(fmin_, fdist2(ts, c, d, ds));
-    }
+    if (g <= 0.0 && t > t_lo) { t_lo = t; g_lo = g; }
+    if (g >= 0.0 && t < t_hi) { t_hi = t; g_hi = g; }
   }
-  const double r2 = double(rho) * double(rho);
-  const double err = M * M * 0x1p-44;
+  double ts;
+  if (t_lo < 0.0) ts = 0.0;                 // f' > 0 on [0, 1]
+  else if (t_hi > 1.0) ts = 1.0;            // f' < 0 on [0, 1]
+  else if (t_hi <= t_lo || g_hi - g_lo <= 0.0) ts = t_lo;
+  else ts = fmin(fmax(t_lo - g_lo * (t_hi - t_lo) / (g_hi - g_lo), t_lo), t_hi);
+  const double fmin_ = fdist2(ts, c, d, ds);
   if (fmin_ + err <= r2) return true;
   if (fmin_ - err > r2) return false;
   return cap_exact(ci, di, s, rho);
 }
-#undef VX_CSWAP
 
 // ---------------------------------------------------------------------------------------------
 // weights

@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec
   for (int64_t ch = w0; ch < n_chunks; ch += ws) {
     const int64_t c0 = ch * 64;
     int64_t p0 = 0;
-    if (lane == 0) p0 = find_prim(cand_off, 0, n_prims, c0);
+    if (lane == 0) p0 = find_prim_bisect(cand_off, n_prims, c0);
     p0 = __shfl(p0, 0, 64);
     const int64_t ci = c0 + lane;
     bool hit = false;
