@@ -242,6 +242,23 @@ class VoxelizePlan:
         return self.out
 
 
+@dataclass
+class Lobes:
+    """Up to K SGGX lobes per voxel of one level (K > 1)."""
+    nl: object            # uint8 [cap]
+    w: object             # float32 [K, cap], descending weight
+    S: object             # float32 [6, K, cap]
+    n: int = -1
+
+    def cstruct(self) -> CLobes:
+        return CLobes(self.nl.data_ptr(), self.w.data_ptr(), self.S.data_ptr(), int(self.w.shape[1]))
+
+    def numpy(self, n=None):
+        n = self.n if n is None else n
+        return {"nl": self.nl[:n].cpu().numpy(), "w": self.w[:, :n].cpu().numpy().T.copy(),
+                "S": self.S[:, :, :n].cpu().numpy().transpose(2, 1, 0).copy()}
+
+
 class LodPlan:
     """Per-level output buffers for build_lod; level caps default to the leaf's count."""
 
@@ -256,6 +273,13 @@ class LodPlan:
         caps = caps or [base] * (self.levels - 1)
         self.out = [alloc_voxels(c, grid.log2_res, dev, True) for c in caps]
         self._cout = (CVoxels * max(1, len(self.out)))(*[v.cstruct() for v in self.out])
+        self.lobes = []
+        self._clobes = None
+        if self.K > 1:
+            self.lobes = [Lobes(torch.empty(v.cap, dtype=torch.uint8, device=dev),
+                                torch.empty((self.K, v.cap), dtype=torch.float32, device=dev),
+                                torch.empty((6, self.K, v.cap), dtype=torch.float32, device=dev)) for v in self.out]
+            self._clobes = (CLobes * max(1, len(self.lobes)))(*[lb.cstruct() for lb in self.lobes])
         self._cleaf = leaf.cstruct()
         self.n_levels = torch.zeros(self.levels + 1, dtype=torch.int64, device=dev)
         nb = self.L.vx_lod_workspace_size(leaf.cap, self.levels, self.K)
@@ -265,7 +289,7 @@ class LodPlan:
 
     def run(self, stream=None):
         st = self.L.vx_build_lod(ctypes.byref(self.cgrid), ctypes.byref(self._cleaf), _ptr(self.n_leaf_dev),
-                                 self.levels, self.K, self.iters, self._cout, None, _ptr(self.n_levels),
+                                 self.levels, self.K, self.iters, self._cout, self._clobes, _ptr(self.n_levels),
                                  _ptr(self.ws), self.ws.numel(), _stream(stream))
         if st != 0:
             raise VxError(st, "build_lod")
@@ -279,6 +303,8 @@ class LodPlan:
             raise VxError(2, "build_lod")
         for L in range(1, self.levels):
             self.out[L - 1].n = int(h[L])
+            if self.lobes:
+                self.lobes[L - 1].n = int(h[L])
         return [self.leaf] + self.out
 
 
@@ -298,13 +324,16 @@ def voxelize_fibers(pts, offsets, radius, grid, **kw):
     return v
 
 
-def build_lod(grid, leaf: Voxels, levels, K=1, iters=2, n_leaf_dev=None, caps=None):
-    """Leaf voxels -> list [leaf, level 1, ..., level levels-1] (Sec. 4.3)."""
+def build_lod(grid, leaf: Voxels, levels, K=1, iters=2, n_leaf_dev=None, caps=None, return_lobes=False):
+    """Leaf voxels -> list [leaf, level 1, ..., level levels-1] (Sec. 4.3); with K > 1 and
+    return_lobes, also the per-level lobes [level 1, ...] (Sec. 4.4)."""
     import torch
     if n_leaf_dev is None:
         n_leaf_dev = torch.tensor([leaf.n], dtype=torch.int64, device=leaf.w.device)
     p = LodPlan(grid, leaf, n_leaf_dev, levels, K, iters, caps).run()
     out = p.check()
+    if return_lobes:
+        return out, p.lobes
     return out
 
 

@@ -143,11 +143,15 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
   if (!grid_ok(grid) || !voxels_ok(leaf, false) || !n_leaf || !n_levels || levels < 1 ||
       levels > grid->log2_res + 1 || K < 1 || K > 8 || kmeans_iters < 0)
     return VX_ERR_ARG;
-  if (K > 1) return VX_ERR_ARG;   // lobe clustering: not available in this build of the library
-  (void)lobes;
   if (levels > 1 && !out) return VX_ERR_ARG;
-  for (int L = 1; L < levels; ++L)
+  for (int L = 1; L < levels; ++L) {
     if (!voxels_ok(&out[L - 1], true)) return VX_ERR_ARG;
+    if (K > 1) {
+      if (!lobes) return VX_ERR_ARG;
+      const vx_lobes& lb = lobes[L - 1];
+      if (!lb.nl || !lb.w || !lb.S || lb.cap < out[L - 1].cap) return VX_ERR_ARG;
+    }
+  }
   if (!ws_ok(ws, ws_bytes, vx_lod_workspace_size(leaf->cap, levels, K))) return VX_ERR_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool key64 = grid->log2_res > 10;
@@ -159,6 +163,13 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
   for (int L = 1; L < levels; ++L) {
     const vx_voxels& in = L == 1 ? *leaf : out[L - 2];
     lod_level(key64, in, n_levels + L - 1, out[L - 1], n_levels + L, n_levels + levels, pstart, partial, s);
+    if (K > 1) {
+      if (L == 1)
+        cluster_level(pstart, n_levels + 1, leaf->w, leaf->S, nullptr, 1, leaf->cap, K, kmeans_iters, lobes[0], s);
+      else
+        cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
+                      kmeans_iters, lobes[L - 1], s);
+    }
   }
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }

@@ -1,0 +1,249 @@
+// cluster.hip -- Sec. 4.4: per coarse voxel, merge the lobes of its children down to at most K.
+//
+// The paper builds a dendrogram by repeatedly merging the two most similar SGGX lobes of a
+// voxel's set (its similarity compares the distributions, not the parameters).  Here the
+// similarity is the L2 distance between the lobes' projected-area-squared functions,
+// D(A, B) = 2 tr((A - B)^2) + (tr(A - B))^2 for normalised lobes A = S_a / w_a, and merging
+// follows Ward's rule (least w_a w_b / (w_a + w_b) * D, ties to the first pair), then a few
+// weighted Lloyd passes refine the K clusters.  Merging is additive: (w_a + w_b, S_a + S_b).
+//
+// Mapping: a group of G lanes (G = 8 at level 1, 8K rounded up to a power of two above)
+// handles one parent voxel; lane m holds input lobe m; the cluster sums and the pairwise cost
+// matrix live in the group's LDS.  All reductions are fixed butterflies: the result is
+// deterministic.
+#include "vx_internal.hpp"
+
+namespace vx {
+
+__device__ __forceinline__ float lobe_dist(const float* a, float wa, const float* b, float wb) {
+  const float ia = 1.0f / wa, ib = 1.0f / wb;
+  float d[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) d[j] = a[j] * ia - b[j] * ib;
+  const float tr = d[0] + d[1] + d[2];
+  const float t2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0f * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+  return 2.0f * t2 + tr * tr;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int gi) {
+  if (G == 64) return ballot;
+  return (ballot >> (gi * G)) & ((uint64_t(1) << G) - 1);
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+template <int G>
+struct ClusterLds {
+  float lw[64 / G][G];
+  float lS[64 / G][6][G];
+  float cw[64 / G][G];
+  float cS[64 / G][6][G];
+  float mat[64 / G][G][G];
+};
+
+// One level: parents [0, *n_par) with children [pstart[p], pstart[p+1]) of the level below,
+// whose lobes are cw[k * cap_c + c] and cS[(j * Kc + k) * cap_c + c] (cnl == nullptr: one lobe
+// per child, present when its weight is positive).
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
+                                                    const float* __restrict__ cw, const float* __restrict__ cS,
+                                                    const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
+                                                    int iters, vx_lobes out) {
+  __shared__ ClusterLds<G> sm[kWaves];
+  const int lane = lane_id();
+  const int g = lane % G, gi = lane / G;
+  ClusterLds<G>& L = sm[threadIdx.x >> 6];
+  const int64_t n_par = *n_par_ptr;
+  const int64_t cap = out.cap;
+  constexpr int per_wave = 64 / G;
+  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per_wave;
+  const int64_t stride = int64_t(gridDim.x) * kWaves * per_wave;
+  for (int64_t base = w0; base < n_par; base += stride) {
+    const int64_t p = base + gi;
+    const bool live = p < n_par;
+    // ---- gather the children's lobes in canonical order, compacted to lanes 0..n-1
+    float w = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool valid = false;
+    if (live) {
+      const int64_t cs = pstart[p], ce = pstart[p + 1];
+      const int ch = g / Kc, k = g % Kc;
+      if (cs + ch < ce) {
+        const int64_t c = cs + ch;
+        const int nl = cnl ? int(cnl[c]) : 1;
+        if (k < nl) {
+          w = cw[int64_t(k) * cap_c + c];
+          if (w > 0.f) {
+            valid = true;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) S[j] = cS[(int64_t(j) * Kc + k) * cap_c + c];
+          }
+        }
+      }
+    }
+    const uint64_t vm = group_bits<G>(__ballot(valid), gi);
+    const int n = __popcll(vm);
+    if (valid) {
+      const int m = __popcll(vm & ((uint64_t(1) << g) - 1));
+      L.lw[gi][m] = w;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) L.lS[gi][j][m] = S[j];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const bool mine = g < n;
+    float lw = 0.f, lS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (mine) {
+      lw = L.lw[gi][g];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) lS[j] = L.lS[gi][j][g];
+      L.cw[gi][g] = lw;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) L.cS[gi][j][g] = lS[j];
+    }
+    uint64_t act = n == 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (n > K) {
+      // ---- Ward agglomeration: cost matrix, upper triangle, row g written by lane g
+      if (mine) {
+        float a[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a[j] = lS[j];
+        for (int j = g + 1; j < n; ++j) {
+          float b[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) b[t] = L.cS[gi][t][j];
+          const float wb = L.cw[gi][j];
+          L.mat[gi][g][j] = lw * wb / (lw + wb) * lobe_dist(a, lw, b, wb);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int step = n; step > K; --step) {
+        float best = INFINITY;
+        int bj = G;
+        if (mine && ((act >> g) & 1)) {
+          for (int j = g + 1; j < n; ++j) {
+            if (!((act >> j) & 1)) continue;
+            const float c = L.mat[gi][g][j];
+            if (c < best) { best = c; bj = j; }
+          }
+        }
+        int bi = bj < G ? g : G;
+        // group argmin of (cost, i); the row minimum already carries the smallest j
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+          const float oc = __shfl_xor(best, off, G);
+          const int oi = __shfl_xor(bi, off, G);
+          const int oj = __shfl_xor(bj, off, G);
+          if (oc < best || (oc == best && oi < bi)) { best = oc; bi = oi; bj = oj; }
+        }
+        // merge cluster bj into bi
+        if (g == bi) {
+          const float nw = L.cw[gi][bi] + L.cw[gi][bj];
+          L.cw[gi][bi] = nw;
+#pragma unroll
+          for (int t = 0; t < 6; ++t) L.cS[gi][t][bi] = L.cS[gi][t][bi] + L.cS[gi][t][bj];
+        }
+        act &= ~(uint64_t(1) << bj);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (mine && ((act >> g) & 1) && g != bi) {
+          float a[6], b[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) { a[t] = L.cS[gi][t][bi]; b[t] = L.cS[gi][t][g]; }
+          const float wa = L.cw[gi][bi], wb = L.cw[gi][g];
+          const float c = wa * wb / (wa + wb) * lobe_dist(a, wa, b, wb);
+          if (g < bi) L.mat[gi][g][bi] = c; else L.mat[gi][bi][g] = c;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      // ---- weighted Lloyd passes over the original lobes
+      for (int it = 0; it < iters; ++it) {
+        int assign = -1;
+        if (mine) {
+          float bestd = INFINITY;
+          for (int k = 0; k < n; ++k) {
+            if (!((act >> k) & 1)) continue;
+            float b[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) b[t] = L.cS[gi][t][k];
+            const float d = lobe_dist(lS, lw, b, L.cw[gi][k]);
+            if (d < bestd) { bestd = d; assign = k; }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        uint64_t nact = 0;
+        for (int k = 0; k < n; ++k) {
+          if (!((act >> k) & 1)) continue;
+          const bool in = assign == k;
+          const float sw = group_sum<G>(in ? lw : 0.f);
+          float sS[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) sS[t] = group_sum<G>(in ? lS[t] : 0.f);
+          if (sw > 0.f) nact |= uint64_t(1) << k;
+          if (g == 0) {
+            L.cw[gi][k] = sw;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) L.cS[gi][t][k] = sS[t];
+          }
+        }
+        act = nact;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+    }
+    // ---- output: active clusters sorted by descending weight (ties keep cluster order)
+    if (live) {
+      const int nl = __popcll(act);
+      if (g < G && ((act >> g) & 1)) {
+        const float wg = L.cw[gi][g];
+        int rank = 0;
+        for (int k = 0; k < n; ++k) {
+          if (!((act >> k) & 1) || k == g) continue;
+          const float wk = L.cw[gi][k];
+          rank += (wk > wg || (wk == wg && k < g)) ? 1 : 0;
+        }
+        out.w[int64_t(rank) * cap + p] = wg;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + rank) * cap + p] = L.cS[gi][t][g];
+      }
+      if (g >= nl && g < K) {
+        out.w[int64_t(g) * cap + p] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + g) * cap + p] = 0.f;
+      }
+      if (g == 0) out.nl[p] = uint8_t(nl);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+}
+
+void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
+                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, hipStream_t s) {
+  const int need = 8 * Kc;
+  VX_TIMED("lod_cluster", s);
+  if (need <= 8)
+    hipLaunchKernelGGL(k_cluster<8>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+                       iters, out);
+  else if (need <= 16)
+    hipLaunchKernelGGL(k_cluster<16>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+                       iters, out);
+  else if (need <= 32)
+    hipLaunchKernelGGL(k_cluster<32>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+                       iters, out);
+  else
+    hipLaunchKernelGGL(k_cluster<64>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+                       iters, out);
+}
+
+}  // namespace vx

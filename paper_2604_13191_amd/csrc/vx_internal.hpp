@@ -214,6 +214,11 @@ void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_vo
                int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s);
 void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s);
 
+// lobe clustering of one level (cluster.hip): parents [0, *n_par) with children
+// [pstart[p], pstart[p+1]) whose lobes are cw[k * cap_c + c], cS[(j * Kc + k) * cap_c + c]
+void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
+                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, hipStream_t s);
+
 // the voxelize pass (prims.hip)
 size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64);
 vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,

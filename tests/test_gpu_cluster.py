@@ -1,0 +1,101 @@
+"""GPU parity of the Sec. 4.4 lobe clustering (K > 1) against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_lobes, compare_pyramid
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _random_leaf(seed, log2_res, n, families=None):
+    """Distinct random leaf voxels with fiber-like lobes S = w (I - t t^T); with `families`,
+    tangents are drawn near a few directions so that merges are clear."""
+    rng = np.random.default_rng(seed)
+    R = 1 << log2_res
+    coords = rng.choice(R ** 3, size=n, replace=False)
+    x, y, z = coords % R, (coords // R) % R, coords // (R * R)
+    keys = np.array([oracle.morton(a, b, c, log2_res) for a, b, c in zip(x, y, z)], dtype=np.uint64)
+    order = np.argsort(keys)
+    keys = keys[order]
+    w = rng.uniform(0.1, 2.0, n).astype(np.float32)
+    if families is None:
+        t = rng.normal(size=(n, 3))
+    else:
+        base = rng.normal(size=(families, 3))
+        t = base[rng.integers(0, families, n)] + 0.05 * rng.normal(size=(n, 3))
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    M = np.stack([1 - t[:, 0] ** 2, 1 - t[:, 1] ** 2, 1 - t[:, 2] ** 2, -t[:, 0] * t[:, 1], -t[:, 0] * t[:, 2],
+                  -t[:, 1] * t[:, 2]], 1)
+    S = (w[:, None] * M).astype(np.float32)
+    cnt = rng.integers(1, 5, n).astype(np.uint32)
+    return keys, cnt, w, S
+
+
+def _leaf_to_device(vx, keys, cnt, w, S, log2_res):
+    import torch
+    n = len(keys)
+    v = vx.alloc_voxels(n, log2_res, "cuda", False)
+    kd = keys.astype(np.int64) if log2_res > 10 else keys.astype(np.uint32).view(np.int32)
+    v.keys.copy_(torch.as_tensor(kd))
+    v.count.copy_(torch.as_tensor(cnt.view(np.int32)))
+    v.w.copy_(torch.as_tensor(w))
+    v.S.copy_(torch.as_tensor(np.ascontiguousarray(S.T)))
+    v.n = n
+    return v
+
+
+@pytest.mark.parametrize("K,families", [(2, 2), (4, 3), (4, None), (8, 5)])
+def test_cluster_on_given_leaf(vx, K, families):
+    """The clustering alone: the same FP32 leaf goes to the GPU and (as FP64) to the oracle."""
+    log2_res = 5
+    keys, cnt, w, S = _random_leaf(300 + K, log2_res, 6000, families)
+    say(f"case: given leaf, 32^3, K={K}, families={families}")
+    grid = synth.Grid((0.0, 0.0, 0.0), 32.0, log2_res)
+    leaf = _leaf_to_device(vx, keys, cnt, w, S, log2_res)
+    pyr, lobes = vx.build_lod(grid, leaf, log2_res + 1, K=K, iters=2, return_lobes=True)
+    ref = oracle.Voxels(keys, cnt, w.astype(np.float64), S.astype(np.float64), int(cnt.sum()))
+    lod = oracle.build_lod(ref, log2_res + 1)
+    compare_pyramid(pyr, lod, f"given leaf K{K}")
+    olobes = oracle.cluster_pyramid(lod, K, 2)
+    for L in range(1, log2_res + 1):
+        rep = compare_lobes(lobes[L - 1].numpy(), olobes[L], lod[L].w, lod[L].S, K, what=f"K{K} L{L}")
+        say(L, rep)
+
+
+def test_cluster_brushed_metal_window(vx):
+    wl = synth.brushed_metal(window=128)
+    say("case: brushed metal 128x128 window, 4096^3, 13 levels, K=4")
+    import torch
+    leaf = vx.voxelize_triangles(torch.as_tensor(wl.tris).cuda(), wl.grid)
+    pyr, lobes = vx.build_lod(wl.grid, leaf, wl.levels, K=4, iters=2, return_lobes=True)
+    ref = oracle.voxelize_triangles(wl.grid, wl.tris)
+    lod = oracle.build_lod(ref, wl.levels)
+    compare_pyramid(pyr, lod, "brushed128")
+    olobes = oracle.cluster_pyramid(lod, 4, 2)
+    for L in range(1, wl.levels):
+        rep = compare_lobes(lobes[L - 1].numpy(), olobes[L], lod[L].w, lod[L].S, 4, what=f"brushed L{L}")
+        say(L, rep)
+
+
+def test_cluster_weave(vx):
+    wl = synth.plain_weave(n_fibers=128, seed=12)
+    say("case: plain weave 128 fibers, 1024^3, 11 levels, K=4")
+    import torch
+    leaf = vx.voxelize_fibers(torch.as_tensor(wl.pts).cuda(), torch.as_tensor(wl.offsets).cuda(), wl.radius,
+                              wl.grid)
+    pyr, lobes = vx.build_lod(wl.grid, leaf, wl.levels, K=4, iters=2, return_lobes=True)
+    ref = oracle.voxelize_fibers(wl.grid, wl.pts, wl.offsets, wl.radius)
+    lod = oracle.build_lod(ref, wl.levels)
+    olobes = oracle.cluster_pyramid(lod, 4, 2)
+    for L in range(1, wl.levels):
+        rep = compare_lobes(lobes[L - 1].numpy(), olobes[L], lod[L].w, lod[L].S, 4, what=f"weave L{L}")
+        say(L, rep)
