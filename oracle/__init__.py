@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "vxo.cpp")
+_SRCS = [os.path.join(_HERE, "vxo.cpp"), os.path.join(_HERE, "vxo_fit.cpp")]
 _LIB = os.path.join(_HERE, "libvxo.so")
 _lib = None
 
@@ -37,11 +37,11 @@ _c_dp = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force: bool = False) -> str:
-    """Compile vxo.cpp with g++ (plain C++17, FP contraction off) into oracle/libvxo.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile vxo.cpp and vxo_fit.cpp with g++ (plain C++17, FP contraction off) into oracle/libvxo.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC",
-                               "-pthread", _SRC, "-o", tmp])
+                               "-pthread"] + _SRCS + ["-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -267,3 +267,71 @@ def cluster_pyramid(lod, K: int, iters: int = 2, nthreads=None):
         cur = cluster_level(cur, lod[L].child_start, K, iters, nthreads)
         out.append(cur)
     return out
+
+
+# --------------------------------------------------------------------------------------------
+# Differentiable lobe fit (vxo_fit.cpp): loss and analytic gradients in FP64.
+# --------------------------------------------------------------------------------------------
+
+FIT_NDIR = 128
+
+
+def fit_dirs(n=FIT_NDIR):
+    """Fibonacci directions: z = 1 - (2k+1)/n, phi = k pi (3 - sqrt 5)."""
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * k + 1.0) / n
+    phi = k * np.pi * (3.0 - np.sqrt(5.0))
+    r = np.sqrt(1.0 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+
+
+def _fit_lib():
+    L = lib()
+    if not hasattr(L, "_fit_ready"):
+        L.vxo_fit_eval.restype = ctypes.c_double
+        L.vxo_fit_eval.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.vxo_fit_levels.restype = ctypes.c_int
+        L.vxo_fit_levels.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_int]
+        L._fit_ready = True
+    return L
+
+
+def fit_levels(grid, pts, offsets, radius, hi, nthreads=None):
+    """Voxel counts of levels 0..hi of the fibers' pyramid."""
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float32).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    n = np.zeros(hi + 1, dtype=np.int64)
+    bmin, ext, l2 = _grid_args(grid)
+    st = _fit_lib().vxo_fit_levels(bmin, ext, l2, _ptr(p), p.shape[0], _ptr(o), o.shape[0] - 1,
+                                   float(np.float32(radius)), int(hi), _ptr(n), _nthreads(nthreads))
+    if st:
+        raise OracleError(f"fit_levels failed with status {st}")
+    return n
+
+
+def fit_eval(grid, pts_snap, pts_cont, offsets, radius, lo, hi, L_all, grad=True, nthreads=None):
+    """Loss of the two-lobe fit at levels lo..hi and, with grad, d loss / d L and d loss / d points.
+
+    pts_snap (float32) fixes which segment touches which voxel; pts_cont (float64) gives the
+    weights and tangents.  L_all: float64 [sum of level sizes, 12], levels lo..hi in key order."""
+    ps = np.ascontiguousarray(np.asarray(pts_snap, dtype=np.float32).reshape(-1, 3))
+    pc = np.ascontiguousarray(np.asarray(pts_cont, dtype=np.float64).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    La = np.ascontiguousarray(np.asarray(L_all, dtype=np.float64).reshape(-1, 12))
+    lv = np.zeros(La.shape[0])
+    dL = np.zeros_like(La) if grad else None
+    dp = np.zeros_like(pc) if grad else None
+    st = ctypes.c_int(0)
+    bmin, ext, l2 = _grid_args(grid)
+    loss = _fit_lib().vxo_fit_eval(bmin, ext, l2, _ptr(ps), _ptr(pc), ps.shape[0], _ptr(o), o.shape[0] - 1,
+                                   float(np.float32(radius)), int(lo), int(hi), _ptr(La), _ptr(lv),
+                                   _ptr(dL) if grad else None, _ptr(dp) if grad else None, _nthreads(nthreads),
+                                   ctypes.byref(st))
+    if st.value:
+        raise OracleError(f"fit_eval failed with status {st.value}")
+    return loss, lv, dL, dp

@@ -440,29 +440,31 @@ void* vxo_voxelize_triangles(const double* bmin, double extent, int log2R, const
   return reduce_pairs(parts, M);
 }
 
-// Voxelize fibers: pts[m][3] polylines with CSR offsets[F+1]; segment (i, i+1) exists when
-// both points belong to the same fiber, and its primitive id is i.  radius in world units.
-void* vxo_voxelize_fibers(const double* bmin, double extent, int log2R, const float* pts, i64 m,
-                          const i64* offsets, i64 F, double radius, const i64* region, int nthreads,
-                          int* status) {
+}  // extern "C"
+
+namespace {
+// Every (segment, voxel) touch of the fibers, with the weight; M receives the segment moments.
+int fiber_pairs(const double* bmin, double extent, int log2R, const float* pts, i64 m, const i64* offsets, i64 F,
+                double radius, const i64* region, int nthreads, std::vector<std::vector<Pair>>& parts,
+                std::vector<double>& M) {
   Lattice L;
-  if (!make_lattice(bmin, extent, log2R, &L) || m < 0 || F < 0 || !(radius >= 0) ||
-      !std::isfinite(radius)) { *status = E_ARG; return nullptr; }
-  if (offsets[0] != 0 || offsets[F] != m) { *status = E_ARG; return nullptr; }
+  if (!make_lattice(bmin, extent, log2R, &L) || m < 0 || F < 0 || !(radius >= 0) || !std::isfinite(radius))
+    return E_ARG;
+  if (offsets[0] != 0 || offsets[F] != m) return E_ARG;
   for (i64 f = 0; f < F; ++f)
-    if (offsets[f + 1] < offsets[f]) { *status = E_ARG; return nullptr; }
+    if (offsets[f + 1] < offsets[f]) return E_ARG;
   double rr = std::nearbyint(radius * L.inv);
-  if (rr > 8388608.0) { *status = E_ARG; return nullptr; }
+  if (rr > 8388608.0) return E_ARG;
   i64 rho = i64(rr);
   std::vector<i64> Q(size_t(m) * 3);
   for (i64 i = 0; i < m; ++i) {
     int st = snap(L, pts + 3 * i, &Q[size_t(i) * 3]);
-    if (st) { *status = st; return nullptr; }
+    if (st) return st;
   }
   std::vector<char> is_start(size_t(m), 0);
   for (i64 f = 0; f < F; ++f)
     for (i64 i = offsets[f]; i + 1 < offsets[f + 1]; ++i) is_start[size_t(i)] = 1;
-  std::vector<double> M(size_t(m) * 6, 0.0);
+  M.assign(size_t(m) * 6, 0.0);
   for (i64 i = 0; i < m; ++i) {
     if (!is_start[size_t(i)]) continue;
     double d[3];
@@ -474,7 +476,7 @@ void* vxo_voxelize_fibers(const double* bmin, double extent, int log2R, const fl
     mm[3] = -d[0] * d[1] / l2; mm[4] = -d[0] * d[2] / l2; mm[5] = -d[1] * d[2] / l2;
   }
   Region rg = make_region(L, region);
-  std::vector<std::vector<Pair>> parts(std::max(1, nthreads));
+  parts.assign(std::max(1, nthreads), {});
   parallel_for(m, nthreads, [&](int t, i64 a, i64 b) {
     for (i64 i = a; i < b; ++i) {
       if (!is_start[size_t(i)]) continue;
@@ -497,9 +499,51 @@ void* vxo_voxelize_fibers(const double* bmin, double extent, int log2R, const fl
           }
     }
   });
-  *status = OK;
+  return OK;
+}
+
+struct PairList {
+  std::vector<u64> keys;
+  std::vector<i64> prim;
+};
+}  // namespace
+
+extern "C" {
+
+// Voxelize fibers: pts[m][3] polylines with CSR offsets[F+1]; segment (i, i+1) exists when
+// both points belong to the same fiber, and its primitive id is i.  radius in world units.
+void* vxo_voxelize_fibers(const double* bmin, double extent, int log2R, const float* pts, i64 m,
+                          const i64* offsets, i64 F, double radius, const i64* region, int nthreads,
+                          int* status) {
+  std::vector<std::vector<Pair>> parts;
+  std::vector<double> M;
+  *status = fiber_pairs(bmin, extent, log2R, pts, m, offsets, F, radius, region, nthreads, parts, M);
+  if (*status) return nullptr;
   return reduce_pairs(parts, M);
 }
+
+// The touching (segment, voxel) pairs themselves, for the fit oracle.
+void* vxo_voxelize_fibers_pairs(const double* bmin, double extent, int log2R, const float* pts, i64 m,
+                                const i64* offsets, i64 F, double radius, int nthreads, int* status) {
+  std::vector<std::vector<Pair>> parts;
+  std::vector<double> M;
+  *status = fiber_pairs(bmin, extent, log2R, pts, m, offsets, F, radius, nullptr, nthreads, parts, M);
+  if (*status) return nullptr;
+  PairList* r = new PairList;
+  for (auto& part : parts)
+    for (const Pair& p : part) {
+      r->keys.push_back(p.key);
+      r->prim.push_back(p.prim);
+    }
+  return r;
+}
+i64 vxo_pairs_size(void* r) { return i64(static_cast<PairList*>(r)->keys.size()); }
+void vxo_pairs_copy(void* rp, u64* keys, i64* prim) {
+  PairList* r = static_cast<PairList*>(rp);
+  std::memcpy(keys, r->keys.data(), r->keys.size() * sizeof(u64));
+  std::memcpy(prim, r->prim.data(), r->prim.size() * sizeof(i64));
+}
+void vxo_pairs_free(void* r) { delete static_cast<PairList*>(r); }
 
 i64 vxo_result_size(void* r) { return i64(static_cast<Result*>(r)->keys.size()); }
 i64 vxo_result_npairs(void* r) { return static_cast<Result*>(r)->n_pairs; }

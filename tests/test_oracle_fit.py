@@ -1,0 +1,156 @@
+"""Pins of the differentiable lobe fit oracle (FP64): central finite differences of the loss,
+closed-form zero-loss case, and the clipped-length gradient away from clip-plane kinks."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _lattice_points(grid, pts):
+    """Points moved onto the snapping lattice (exact in float32), so snapped = continuous."""
+    q = oracle.snap(grid, pts).astype(np.float64)
+    return (np.asarray(grid.bmin) + q * (grid.extent / 2.0 ** 23)).astype(np.float32)
+
+
+def _init_L(grid, pts, offsets, radius, lo, hi, seed):
+    """0.5 chol(S/w + 0.05 I) + N(0, 0.01) per voxel and lobe, from the oracle's own pyramid."""
+    rng = np.random.default_rng(seed)
+    v = oracle.voxelize_fibers(grid, pts, offsets, radius)
+    lod = oracle.build_lod(v, hi + 1)
+    out = []
+    for L in range(lo, hi + 1):
+        lv = lod[L]
+        for i in range(len(lv.keys)):
+            if lv.w[i] > 0:
+                S = lv.S[i] / lv.w[i]
+                M = np.array([[S[0], S[3], S[4]], [S[3], S[1], S[5]], [S[4], S[5], S[2]]]) + 0.05 * np.eye(3)
+                C = 0.5 * np.linalg.cholesky(M)
+            else:
+                C = np.zeros((3, 3))
+            row = []
+            for j in range(2):
+                row += [C[0, 0], C[1, 0], C[1, 1], C[2, 0], C[2, 1], C[2, 2]]
+            out.append(np.array(row) + rng.normal(0, 0.01, 12))
+    return np.array(out)
+
+
+def _small_fabric():
+    wl = synth.plain_weave(n_fibers=16, n_points=33, res=128, seed=41)
+    pts = _lattice_points(wl.grid, wl.pts)
+    return wl, pts
+
+
+def _lb_state(A, B, lo):
+    """Which constraints fix the clipped interval of segment A-B in [lo, lo+1)^3 (kink detector)."""
+    d = B - A
+    t0, t1, e0, e1 = 0.0, 1.0, -1, -1
+    for a in range(3):
+        if d[a] == 0:
+            if not (lo[a] <= A[a] < lo[a] + 1):
+                return ("empty",)
+            continue
+        ta, tb = (lo[a] - A[a]) / d[a], (lo[a] + 1 - A[a]) / d[a]
+        tin, tout = min(ta, tb), max(ta, tb)
+        if tin > t0:
+            t0, e0 = tin, a
+        if tout < t1:
+            t1, e1 = tout, a
+    return ("empty",) if t1 <= t0 else (e0, e1)
+
+
+def _crosses(pts_c, i, offsets, grid, delta):
+    """Does moving point i by +-delta change the clipping structure of one of its segments?"""
+    vs = grid.res / grid.extent
+    segs = [j for j in (i - 1, i) if j >= 0 and j + 1 < len(pts_c)
+            and np.searchsorted(offsets, j, "right") == np.searchsorted(offsets, j + 1, "right")]
+    for j in segs:
+        states = []
+        for sgn in (0.0, 1.0, -1.0):
+            P = pts_c.copy()
+            P[i] += sgn * delta
+            A, B = P[j] * vs, P[j + 1] * vs
+            lo = np.floor(np.minimum(A, B)) - 1
+            hi = np.floor(np.maximum(A, B)) + 1
+            st = {}
+            for x in range(int(lo[0]), int(hi[0]) + 1):
+                for y in range(int(lo[1]), int(hi[1]) + 1):
+                    for z in range(int(lo[2]), int(hi[2]) + 1):
+                        st[(x, y, z)] = _lb_state(A, B, np.array([x, y, z], float))
+            states.append(st)
+        if states[0] != states[1] or states[0] != states[2]:
+            return True
+    return False
+
+
+def test_fit_gradient_matches_central_differences():
+    wl, pts = _small_fabric()
+    lo, hi = 1, 5
+    L0 = _init_L(wl.grid, pts, wl.offsets, wl.radius, lo, hi, 4)
+    pc = pts.astype(np.float64)
+    loss, lv, dL, dp = oracle.fit_eval(wl.grid, pts, pc, wl.offsets, wl.radius, lo, hi, L0)
+    assert loss > 0 and np.isfinite(dp).all() and np.abs(dp).max() > 0
+    h = 1e-3
+    rng = np.random.default_rng(42)
+    fd, an, kinks = [], [], 0
+    tried = 0
+    while len(fd) < 40 and tried < 400:
+        tried += 1
+        i = int(rng.integers(0, len(pts)))
+        a = int(rng.integers(0, 3))
+        delta = np.zeros(3)
+        delta[a] = h
+        if _crosses(pc, i, wl.offsets, wl.grid, delta):
+            kinks += 1
+            continue
+        def cd(step):
+            P1, P2 = pc.copy(), pc.copy()
+            P1[i, a] += step
+            P2[i, a] -= step
+            _, l1, _, _ = oracle.fit_eval(wl.grid, pts, P1, wl.offsets, wl.radius, lo, hi, L0, grad=False)
+            _, l2, _, _ = oracle.fit_eval(wl.grid, pts, P2, wl.offsets, wl.radius, lo, hi, L0, grad=False)
+            return (l1 - l2).sum() / (2 * step)      # per-voxel differences: no cancellation
+        # central differences at h and h/2, Richardson-extrapolated (the h^2 term cancels)
+        fd.append((4.0 * cd(h / 2) - cd(h)) / 3.0)
+        an.append(dp[i, a])
+    fd, an = np.array(fd), np.array(an)
+    assert len(fd) >= 30, (len(fd), kinks)
+    assert np.linalg.norm(fd - an) <= 1e-5 * np.linalg.norm(an), (np.abs(fd - an).max(), np.linalg.norm(an))
+    # lobe parameters: smooth wherever no lobe has L^T w = 0
+    live = np.flatnonzero(np.abs(dL).sum(1) > 0)
+    for r, c in [(int(r), c) for r in rng.choice(live, 4, replace=False) for c in range(12)]:
+        L1, L2 = L0.copy(), L0.copy()
+        L1[r, c] += 1e-5
+        L2[r, c] -= 1e-5
+        _, a1, _, _ = oracle.fit_eval(wl.grid, pts, pc, wl.offsets, wl.radius, lo, hi, L1, grad=False)
+        _, a2, _, _ = oracle.fit_eval(wl.grid, pts, pc, wl.offsets, wl.radius, lo, hi, L2, grad=False)
+        g = (a1 - a2).sum() / 2e-5
+        assert abs(g - dL[r, c]) <= 1e-6 * max(1.0, abs(dL[r, c])), (r, c, g, dL[r, c])
+
+
+def test_fit_zero_loss_at_exact_single_child_lobe():
+    """One straight fiber inside one level-1 parent's single child: L1 L1^T = S/w, L2 = 0 gives
+    f = tau in every direction, so the loss and the lobe gradient vanish."""
+    grid = synth.Grid((0.0, 0.0, 0.0), 8.0, 3)
+    pts = np.array([[2.25, 2.5, 2.375], [2.75, 2.625, 2.5]], dtype=np.float32)   # inside voxel (2, 2, 2)
+    off = np.array([0, 2])
+    v = oracle.voxelize_fibers(grid, pts, off, 0.0)
+    lod = oracle.build_lod(v, 2)
+    n1 = oracle.fit_levels(grid, pts, off, 0.0, 1)
+    assert n1[1] == 1
+    S = lod[1].S[0] / lod[1].w[0]
+    M = np.array([[S[0], S[3], S[4]], [S[3], S[1], S[5]], [S[4], S[5], S[2]]])
+    ev, evec = np.linalg.eigh(M)
+    # a lower-triangular factor of the PSD (rank-2) matrix through its LDL^T / QR of a root
+    R = evec @ np.diag(np.sqrt(np.maximum(ev, 0)))
+    q, r = np.linalg.qr(R.T)
+    Lf = r.T                                            # M = R R^T = r^T r, r^T lower triangular
+    row = [Lf[0, 0], Lf[1, 0], Lf[1, 1], Lf[2, 0], Lf[2, 1], Lf[2, 2]] + [0.0] * 6
+    loss, lv, dL, dp = oracle.fit_eval(grid, pts, pts.astype(np.float64), off, 0.0, 1, 1, np.array([row]))
+    assert loss < 1e-24 and np.abs(dL).max() < 1e-12
+
+
+def test_fit_directions_cover_the_sphere_evenly():
+    W = oracle.fit_dirs()
+    assert W.shape == (128, 3) and np.allclose(np.linalg.norm(W, axis=1), 1.0)
+    assert np.allclose(W.T @ W / 128, np.eye(3) / 3, atol=2e-3)
