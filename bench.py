@@ -53,6 +53,33 @@ def cpu_baseline(wl, nthreads):
                       f"{ref.n_pairs} pairs) in {dt:.2f} s on {nthreads} host threads"}
 
 
+def fit_timing(vx, wl, pts, offs, args, plain_ms):
+    """Differentiable two-lobe fit (levels 1..6, 128 directions) on the same fabric: one forward
+    (voxelize + 7-level pyramid + fit loss) plus one backward (lobe and control-point gradients)."""
+    import torch
+    plan = vx.FitPlan(wl.grid, pts, offs, wl.radius, 1, 6)
+    params = vx.fit_init(plan, seed=4)
+    one = torch.ones(1, device=pts.device)
+    for _ in range(max(1, args.warmup)):
+        plan.forward(pts, params)
+        plan.backward(one, params)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for a, b, c in ev:
+        a.record()
+        plan.forward(pts, params)
+        b.record()
+        plan.backward(one, params)
+        c.record()
+    torch.cuda.synchronize()
+    plan.check()
+    fwd = sum(a.elapsed_time(b) for a, b, _ in ev) / args.steps
+    bwd = sum(b.elapsed_time(c) for _, b, c in ev) / args.steps
+    return {"levels": "1-6", "lobes": 2, "directions": 128, "fwd_ms": fwd, "bwd_ms": bwd, "fwd_bwd_ms": fwd + bwd,
+            "plain_path_ms": plain_ms, "fwd_bwd_over_plain": (fwd + bwd) / plain_ms,
+            "fitted_voxels": int(sum(plan.counts[1:7]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +163,7 @@ def main():
                      "algorithmic_bytes_per_launch": dom_b, "avg_launch_ms": dom_avg},
         "kernels": kernels,
     }
+    out["fit"] = fit_timing(vx, wl, pts, offs, args, ms_step)
     if not args.no_cpu_baseline:
         nth = max(1, min(16, os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(wl, nth)

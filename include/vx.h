@@ -148,6 +148,50 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
                        int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
                        int64_t* n_levels, void* workspace, size_t ws_bytes, vx_stream stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Differentiable two-lobe fit (extension; the projected area of an SGGX lobe is Sec. 4.1's
+ * sigma(omega) = sqrt(omega^T S omega)).
+ *
+ * For every voxel u of levels lo..hi (1 <= lo <= hi, hi <= 20) with w_u > 0, two lobes given by
+ * lower-triangular 3x3 matrices L_1, L_2 (12 floats per voxel: L00 L10 L11 L20 L21 L22 of L_1,
+ * then of L_2; L L^T is the lobe's SGGX matrix, PSD for any parameters) are fitted to u's
+ * children:
+ *   f_u(omega)   = |L_1^T omega| + |L_2^T omega|
+ *   tau_u(omega) = sum_c sqrt(w_c omega^T S_c omega) / sum_c w_c   (children with w_c > 0)
+ *   loss         = sum_{levels lo..hi} sum_u (1/ndir) sum_k (f_u(omega_k) - tau_u(omega_k))^2
+ * levels: host array of hi + 1 level descriptors (leaf, then levels 1..hi of vx_build_lod with
+ * K = 1); n_levels: their counts (device); params / dparams: host arrays of hi - lo + 1 device
+ * pointers, level L at index L - lo, each [cap_L][12]; dirs: device float [ndir][3] unit
+ * directions, 1 <= ndir <= 256; caps: host int64 [hi + 1], the capacities of levels 0..hi.
+ * The gradient to the control points flows through the leaf sums: the clipped centreline
+ * lengths (weights) and the tangents (moments I - t t^T) of the segments, evaluated at the
+ * lattice-snapped points; the voxel sets are held fixed (the loss is piecewise smooth).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  const float* pts;          /* device float [n_pts][3] */
+  int64_t n_pts;
+  const int64_t* offsets;    /* device int64 [n_fibers + 1] */
+  int64_t n_fibers;
+  float radius;
+} vx_fibers;
+
+size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int32_t hi,
+                             int32_t log2_res);
+
+/* loss: device float [1], overwritten. */
+vx_status vx_fit_forward(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int32_t lo,
+                         int32_t hi, const float* const* params, const float* dirs, int32_t ndir, float* loss,
+                         const int64_t* caps, void* workspace, size_t ws_bytes, vx_stream stream);
+
+/* dloss: device float [1] (upstream gradient); dpts: device float [n_pts][3], overwritten;
+ * stats: device int64 [VX_NSTAT] for the re-emitted pairs (max_cand / max_pairs as for
+ * vx_voxelize_fibers on the same fibers). */
+vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fibers, int64_t max_cand, int64_t max_pairs,
+                          const vx_voxels* levels, const int64_t* n_levels, int32_t lo, int32_t hi,
+                          const float* const* params, const float* dirs, int32_t ndir, const float* dloss,
+                          float* const* dparams, float* dpts, int64_t* stats, const int64_t* caps, void* workspace,
+                          size_t ws_bytes, vx_stream stream);
+
 /* Synchronises `stream`, reads stats (VX_NSTAT int64 on the device) and maps its flags to a
  * status: VX_ERR_INPUT before VX_ERR_CAPACITY before VX_OK. */
 vx_status vx_check_stats(const int64_t* stats, vx_stream stream);

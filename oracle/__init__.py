@@ -293,6 +293,14 @@ def _fit_lib():
                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.vxo_voxelize_fibers_pairs.restype = ctypes.c_void_p
+        L.vxo_voxelize_fibers_pairs.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int)]
+        L.vxo_pairs_size.restype = ctypes.c_int64
+        L.vxo_pairs_size.argtypes = [ctypes.c_void_p]
+        L.vxo_pairs_copy.argtypes = [ctypes.c_void_p] * 3
+        L.vxo_pairs_free.argtypes = [ctypes.c_void_p]
         L.vxo_fit_levels.restype = ctypes.c_int
         L.vxo_fit_levels.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
@@ -335,3 +343,54 @@ def fit_eval(grid, pts_snap, pts_cont, offsets, radius, lo, hi, L_all, grad=True
     if st.value:
         raise OracleError(f"fit_eval failed with status {st.value}")
     return loss, lv, dL, dp
+
+
+def fiber_pairs(grid, pts, offsets, radius, nthreads=None):
+    """Every touching (segment, leaf voxel) pair: Morton keys and segment ids (first point)."""
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float32).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    st = ctypes.c_int(0)
+    bmin, ext, l2 = _grid_args(grid)
+    L = _fit_lib()
+    r = L.vxo_voxelize_fibers_pairs(bmin, ext, l2, _ptr(p), p.shape[0], _ptr(o), o.shape[0] - 1,
+                                    float(np.float32(radius)), _nthreads(nthreads), ctypes.byref(st))
+    if st.value:
+        raise OracleError(f"fiber_pairs failed with status {st.value}")
+    n = L.vxo_pairs_size(r)
+    keys = np.zeros(n, np.uint64)
+    prim = np.zeros(n, np.int64)
+    L.vxo_pairs_copy(r, _ptr(keys), _ptr(prim))
+    L.vxo_pairs_free(r)
+    return keys, prim
+
+
+def fit_conditioning(grid, pts, offsets, radius, hi):
+    """Per control point: the least normalised projected area squared, min over directions of
+    w^T (S / w) w, over every voxel whose sums feed a fitted target and that a segment of the
+    point touches (the voxel itself and its ancestors up to level hi - 1).  The target's
+    sqrt is ill-conditioned where this is small: its derivative scales as 1 / sqrt of it."""
+    v = voxelize_fibers(grid, pts, offsets, radius)
+    lod = build_lod(v, hi + 1)
+    W = fit_dirs()
+    mins = []
+    for L in range(hi):
+        lv = lod[L]
+        m = lv.w > 0
+        S = lv.S[m] / lv.w[m, None]
+        q = (S[:, 0, None] * W[:, 0] ** 2 + S[:, 1, None] * W[:, 1] ** 2 + S[:, 2, None] * W[:, 2] ** 2
+             + 2 * (S[:, 3, None] * W[:, 0] * W[:, 1] + S[:, 4, None] * W[:, 0] * W[:, 2]
+                    + S[:, 5, None] * W[:, 1] * W[:, 2]))
+        out = np.full(len(lv.w), np.inf)
+        out[m] = q.min(1)
+        mins.append(out)
+    leafk = lod[0].keys
+    cond_leaf = np.full(len(leafk), np.inf)
+    for L in range(hi):
+        idx = np.searchsorted(lod[L].keys, leafk >> np.uint64(3 * L))
+        cond_leaf = np.minimum(cond_leaf, mins[L][idx])
+    pk, pp = fiber_pairs(grid, pts, offsets, radius)
+    vi = np.searchsorted(leafk, pk)
+    cond = np.full(len(np.asarray(pts).reshape(-1, 3)), np.inf)
+    np.minimum.at(cond, pp, cond_leaf[vi])
+    np.minimum.at(cond, pp + 1, cond_leaf[vi])
+    return cond

@@ -47,6 +47,11 @@ class CLobes(ctypes.Structure):
     _fields_ = [("nl", ctypes.c_void_p), ("w", ctypes.c_void_p), ("S", ctypes.c_void_p), ("cap", ctypes.c_int64)]
 
 
+class CFibers(ctypes.Structure):
+    _fields_ = [("pts", ctypes.c_void_p), ("n_pts", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("n_fibers", ctypes.c_int64), ("radius", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -79,6 +84,14 @@ def load():
     L.vx_check_stats.argtypes = [vp, vp]
     L.vx_status_str.restype = ctypes.c_char_p
     L.vx_status_str.argtypes = [ctypes.c_int]
+    L.vx_fit_workspace_size.restype = sz
+    L.vx_fit_workspace_size.argtypes = [i64, i64, i64, vp, i32, i32]
+    L.vx_fit_forward.restype = ctypes.c_int
+    L.vx_fit_forward.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, vp, vp, i32, vp, vp,
+                                 vp, sz, vp]
+    L.vx_fit_backward.restype = ctypes.c_int
+    L.vx_fit_backward.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CFibers), i64, i64, ctypes.POINTER(CVoxels),
+                                  vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.vx_timing_enable.argtypes = [i32]
     L.vx_timing_reset.argtypes = []
     L.vx_timing_collect.restype = i32
@@ -354,3 +367,164 @@ def timing_collect():
     cnt = (ctypes.c_int64 * n)()
     k = L.vx_timing_collect(names, ms, cnt, n)
     return {bytes(names[i]).split(b"\0")[0].decode(): (ms[i], cnt[i]) for i in range(min(k, n))}
+
+
+# ------------------------------------------------------------------------------------------------
+# Differentiable two-lobe fit (vx_fit_forward / vx_fit_backward)
+# ------------------------------------------------------------------------------------------------
+
+def fit_dirs(ndir=128, device="cuda"):
+    """Fibonacci directions on the sphere: z = 1 - (2k+1)/n, phi = k pi (3 - sqrt 5)."""
+    import torch
+    k = torch.arange(ndir, dtype=torch.float64)
+    z = 1.0 - (2.0 * k + 1.0) / ndir
+    phi = k * (np.pi * (3.0 - np.sqrt(5.0)))
+    r = torch.sqrt(1.0 - z * z)
+    return torch.stack([r * torch.cos(phi), r * torch.sin(phi), z], 1).to(torch.float32).to(device).contiguous()
+
+
+class FitPlan:
+    """Voxelize + K = 1 pyramid + two-lobe fit at levels lo..hi for one fiber set.
+
+    Buffers are sized from a calibration run with 25 % slack, so control points may move
+    during an optimisation; a run that outgrows them reports VX_ERR_CAPACITY."""
+
+    def __init__(self, grid, pts, offsets, radius, lo=1, hi=6, ndir=128, slack=1.25):
+        import torch
+        self.L = load()
+        self.grid, self.cgrid, self.lo, self.hi = grid, _cgrid(grid), int(lo), int(hi)
+        self.pts = pts.detach().contiguous().clone()
+        self.offsets = offsets.to(device=self.pts.device, dtype=torch.int64).contiguous()
+        self.radius = float(radius)
+        cal = VoxelizePlan(1, grid, self.pts, offsets=self.offsets, radius=radius)
+        mc = int(cal.max_cand * slack) + 64
+        mp = int(cal.max_pairs * slack) + 64
+        self.vox = VoxelizePlan(1, grid, self.pts, offsets=self.offsets, radius=radius, max_cand=mc, max_pairs=mp)
+        self.vox.run()
+        leaf = self.vox.check()
+        lodc = LodPlan(grid, leaf, self.vox.stats[2:3], self.hi + 1).run()
+        counts = [v.n for v in lodc.check()]
+        del lodc
+        self.lod = LodPlan(grid, leaf, self.vox.stats[2:3], self.hi + 1,
+                           caps=[int(max(c, 1) * slack) + 64 for c in counts[1:]])
+        self.counts = counts                                    # voxels per level at calibration
+        self.lod.run()
+        self.lod.check()
+        self.levels = [leaf] + self.lod.out
+        self._clevels = (CVoxels * (self.hi + 1))(*[v.cstruct() for v in self.levels])
+        self._caps = (ctypes.c_int64 * (self.hi + 1))(*[v.cap for v in self.levels])
+        self.dirs = fit_dirs(ndir, self.pts.device)
+        self.ndir = int(ndir)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.pts.device)
+        self.bstats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.pts.device)
+        nb = self.L.vx_fit_workspace_size(int(self.pts.shape[0]), mc, mp, self._caps, self.hi, int(grid.log2_res))
+        if nb == 0:
+            raise VxError(1, "vx_fit_workspace_size")
+        self.ws = _ws(nb, self.pts.device)
+        self.max_cand, self.max_pairs = mc, mp
+        self.dpts = torch.zeros_like(self.pts)
+
+    def param_shapes(self):
+        return [(self.counts[L], 12) for L in range(self.lo, self.hi + 1)]
+
+    def _ptrs(self, tensors):
+        return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+    def forward(self, pts, params, stream=None):
+        """Voxelize the (possibly moved) points, build the pyramid, evaluate the fit loss."""
+        self.pts.copy_(pts.detach())
+        self.vox.run(stream)
+        self.lod.run(stream)
+        params = [p.contiguous() for p in params]
+        st = self.L.vx_fit_forward(ctypes.byref(self.cgrid), self._clevels, _ptr(self.lod.n_levels), self.lo, self.hi,
+                                   self._ptrs(params), _ptr(self.dirs), self.ndir, _ptr(self.loss), self._caps,
+                                   _ptr(self.ws), self.ws.numel(), _stream(stream))
+        if st != 0:
+            raise VxError(st, "vx_fit_forward")
+        return self.loss
+
+    def backward(self, dloss, params, stream=None):
+        import torch
+        params = [p.contiguous() for p in params]
+        dparams = [torch.empty_like(p) for p in params]
+        fib = CFibers(self.pts.data_ptr(), int(self.pts.shape[0]), self.offsets.data_ptr(),
+                      int(self.offsets.numel() - 1), self.radius)
+        st = self.L.vx_fit_backward(ctypes.byref(self.cgrid), ctypes.byref(fib), self.max_cand, self.max_pairs,
+                                    self._clevels, _ptr(self.lod.n_levels), self.lo, self.hi, self._ptrs(params),
+                                    _ptr(self.dirs), self.ndir, _ptr(dloss), self._ptrs(dparams), _ptr(self.dpts),
+                                    _ptr(self.bstats), self._caps, _ptr(self.ws), self.ws.numel(), _stream(stream))
+        if st != 0:
+            raise VxError(st, "vx_fit_backward")
+        return self.dpts.clone(), dparams
+
+    def check(self):
+        """Synchronise and raise if a buffer was outgrown."""
+        self.vox.check()
+        self.lod.check()
+        st = self.L.vx_check_stats(_ptr(self.bstats), _stream())
+        if st != 0:
+            raise VxError(st, "vx_fit_backward")
+
+
+def _make_lobe_fit():
+    import torch
+
+    class LobeFit(torch.autograd.Function):
+        """loss = LobeFit.apply(plan, pts, *params): the two-lobe fit loss with hand-written
+        backward kernels for the lobes (params, one [n_L, 12] tensor per level) and the control
+        points."""
+
+        @staticmethod
+        def forward(ctx, plan, pts, *params):
+            loss = plan.forward(pts, params)
+            ctx.plan = plan
+            ctx.save_for_backward(*params)
+            return loss[0].clone()
+
+        @staticmethod
+        def backward(ctx, gloss):
+            params = ctx.saved_tensors
+            g = gloss.reshape(1).to(torch.float32).contiguous()
+            dpts, dparams = ctx.plan.backward(g, params)
+            return (None, dpts, *dparams)
+
+    return LobeFit
+
+
+_LobeFit = None
+
+
+def lobe_fit(plan, pts, params):
+    """Differentiable fit loss (a torch scalar on the GPU)."""
+    global _LobeFit
+    if _LobeFit is None:
+        _LobeFit = _make_lobe_fit()
+    return _LobeFit.apply(plan, pts, *params)
+
+
+def fit_init(plan, seed=4, noise=0.01):
+    """Initial lobes per fitted voxel: 0.5 chol(S/w + 0.05 I) + N(0, noise^2) for both lobes
+    (zeros where w = 0), computed on the GPU from the plan's current pyramid."""
+    import torch
+    g = torch.Generator(device=plan.pts.device)
+    g.manual_seed(seed)
+    out = []
+    for L in range(plan.lo, plan.hi + 1):
+        v = plan.levels[L]
+        n = plan.counts[L]
+        w = v.w[:n].double()
+        S = v.S[:, :n].double()
+        Sb = torch.where(w > 0, S / w.clamp_min(1e-30), torch.zeros_like(S))
+        M = torch.zeros((n, 3, 3), dtype=torch.float64, device=w.device)
+        idx = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+        for c, (i, j) in enumerate(idx):
+            M[:, i, j] = Sb[c]
+            M[:, j, i] = Sb[c]
+        M = M + 0.05 * torch.eye(3, dtype=torch.float64, device=w.device)
+        C = 0.5 * torch.linalg.cholesky(M)
+        row = torch.stack([C[:, 0, 0], C[:, 1, 0], C[:, 1, 1], C[:, 2, 0], C[:, 2, 1], C[:, 2, 2]], 1)
+        row = torch.where((w > 0)[:, None], row, torch.zeros_like(row))
+        P = torch.cat([row, row], 1)
+        P = P + noise * torch.randn(P.shape, generator=g, device=w.device, dtype=torch.float64)
+        out.append(P.to(torch.float32).contiguous())
+    return out

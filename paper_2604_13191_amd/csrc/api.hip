@@ -174,6 +174,57 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
 
+size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int32_t hi,
+                             int32_t log2_res) {
+  if (n_pts < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs || !caps || hi < 1 || hi > 20 ||
+      log2_res < 1 || log2_res > 20)
+    return 0;
+  for (int L = 0; L <= hi; ++L)
+    if (caps[L] < 1) return 0;
+  return fit_ws_bytes(n_pts, max_cand, max_pairs, caps, hi, log2_res > 10);
+}
+
+static bool fit_args_ok(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
+                        const float* const* params, const float* dirs, int ndir, const int64_t* caps) {
+  if (!grid_ok(grid) || !levels || !n_levels || lo < 1 || hi < lo || hi > 20 || hi > grid->log2_res || !params ||
+      !dirs || ndir < 1 || ndir > 256 || !caps)
+    return false;
+  for (int L = 0; L <= hi; ++L)
+    if (!voxels_ok(&levels[L], false) || caps[L] < levels[L].cap) return false;
+  for (int L = lo; L <= hi; ++L)
+    if (!params[L - lo]) return false;
+  return true;
+}
+
+vx_status vx_fit_forward(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int32_t lo,
+                         int32_t hi, const float* const* params, const float* dirs, int32_t ndir, float* loss,
+                         const int64_t* caps, void* ws, size_t ws_bytes, vx_stream stream) {
+  if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, dirs, ndir, caps) || !loss) return VX_ERR_ARG;
+  if (!ws_ok(ws, ws_bytes, fit_ws_bytes(0, 0, 0, caps, hi, grid->log2_res > 10))) return VX_ERR_WORKSPACE;
+  return fit_forward_run(grid, levels, n_levels, lo, hi, params, dirs, ndir, loss, ws, caps,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fib, int64_t max_cand, int64_t max_pairs,
+                          const vx_voxels* levels, const int64_t* n_levels, int32_t lo, int32_t hi,
+                          const float* const* params, const float* dirs, int32_t ndir, const float* dloss,
+                          float* const* dparams, float* dpts, int64_t* stats, const int64_t* caps, void* ws,
+                          size_t ws_bytes, vx_stream stream) {
+  if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, dirs, ndir, caps) || !fib || !dloss || !dparams ||
+      !dpts || !stats || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs)
+    return VX_ERR_ARG;
+  if (fib->n_pts < 0 || fib->n_fibers < 0 || !fib->offsets || (fib->n_pts > 0 && (!fib->pts || fib->n_fibers < 1)))
+    return VX_ERR_ARG;
+  if (!(fib->radius >= 0.0f) || !std::isfinite(fib->radius)) return VX_ERR_ARG;
+  for (int L = lo; L <= hi; ++L)
+    if (!dparams[L - lo]) return VX_ERR_ARG;
+  if (!ws_ok(ws, ws_bytes, fit_ws_bytes(fib->n_pts, max_cand, max_pairs, caps, hi, grid->log2_res > 10)))
+    return VX_ERR_WORKSPACE;
+  return fit_backward_run(grid, fib->pts, fib->n_pts, fib->offsets, fib->n_fibers, fib->radius, max_cand, max_pairs,
+                          levels, n_levels, lo, hi, params, dirs, ndir, dloss, dparams, dpts, stats, ws, caps,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
 vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {
   if (!stats) return VX_ERR_ARG;
   if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return VX_ERR_HIP;

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vx.h"
+
 #define VX_HD __host__ __device__
 
 namespace vx {
@@ -171,7 +173,7 @@ VX_HD inline void candidate_voxel(const int32_t* r, int64_t li, int64_t v[3]) {
 // exact triangle / closed box test (the box-axis tests hold by construction of the candidate
 // range): the triangle's plane and the nine edge x axis directions.
 // ---------------------------------------------------------------------------------------------
-VX_HD __attribute__((noinline)) bool plane_exact(const int64_t n[3], const int64_t rel[3], int64_t s) {
+VX_HD inline __attribute__((noinline)) bool plane_exact(const int64_t n[3], const int64_t rel[3], int64_t s) {
   __int128 base = 0, lo = 0, hi = 0;
   for (int a = 0; a < 3; ++a) {
     base += (__int128)n[a] * rel[a];
@@ -247,7 +249,7 @@ VX_HD inline double fdist2(double t, const double c[3], const double d[3], doubl
 
 // exact: f is evaluated at 0, 1, every breakpoint, and at the stationary point of the quadratic
 // of every (axis state) combination whose region contains it.
-VX_HD __attribute__((noinline)) bool cap_exact(const int64_t c[3], const int64_t d[3], int64_t s, int64_t rho) {
+VX_HD inline __attribute__((noinline)) bool cap_exact(const int64_t c[3], const int64_t d[3], int64_t s, int64_t rho) {
   typedef __int128 I;
   const I r2 = (I)rho * rho;
   // f(num / den) * den^2 <= rho^2 den^2 at den > 0
@@ -399,6 +401,55 @@ VX_HD inline float seg_length(const int32_t* r, const int64_t v[3], int Sb, floa
   }
   if (empty || !(t1 > t0)) return 0.0f;
   return float((t1 - t0) * double(len_vox));
+}
+
+// Length (voxel units) of the segment A-B inside [lo, lo+1)^3 and its derivatives with respect
+// to both ends, FP64 voxel coordinates.  A clipped end slides inside its clipping plane when an
+// end point moves: its velocity is the end point's velocity projected along d onto that plane.
+VX_HD inline double seg_length_grad(const double A[3], const double B[3], const double lo[3], double gA[3],
+                                    double gB[3]) {
+  double d[3];
+  double t_in = 0.0, t_out = 1.0;
+  int ax_in = -1, ax_out = -1;
+  for (int a = 0; a < 3; ++a) {
+    gA[a] = 0.0;
+    gB[a] = 0.0;
+    d[a] = B[a] - A[a];
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) {
+      if (!(A[a] >= lo[a] && A[a] < lo[a] + 1.0)) return 0.0;
+      continue;
+    }
+    const double t0 = (lo[a] - A[a]) / d[a], t1 = (lo[a] + 1.0 - A[a]) / d[a];
+    const double lo_t = t0 < t1 ? t0 : t1, hi_t = t0 < t1 ? t1 : t0;
+    if (lo_t > t_in) { t_in = lo_t; ax_in = a; }
+    if (hi_t < t_out) { t_out = hi_t; ax_out = a; }
+  }
+  if (!(t_out > t_in)) return 0.0;
+  const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  // length = u . (exit - entry), u = d / len; a free end moves with its point, a clipped end
+  // with that motion minus its component that leaves the plane along d
+  double ue[3], ui[3];
+  for (int a = 0; a < 3; ++a) { ue[a] = d[a] / len; ui[a] = d[a] / len; }
+  if (ax_out >= 0) ue[ax_out] -= len / d[ax_out];
+  if (ax_in >= 0) ui[ax_in] -= len / d[ax_in];
+  for (int a = 0; a < 3; ++a) {
+    gA[a] = ue[a] * (1.0 - t_out) - ui[a] * (1.0 - t_in);
+    gB[a] = ue[a] * t_out - ui[a] * t_in;
+  }
+  return (t_out - t_in) * len;
+}
+
+VX_HD inline Lat make_lat(const vx_grid* g, int kind, float radius) {
+  Lat L;
+  for (int a = 0; a < 3; ++a) L.bmin[a] = g->bmin[a];
+  L.inv = ldexp(1.0, 23) / g->extent;
+  L.Sb = 23 - g->log2_res;
+  L.s = int64_t(1) << L.Sb;
+  L.R = 1 << g->log2_res;
+  L.rho = kind == 1 ? int64_t(rint(double(radius) * L.inv)) : 0;
+  return L;
 }
 
 constexpr int kPolyMax = 9;

@@ -190,29 +190,11 @@ void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 // the whole voxelize pass
 // ---------------------------------------------------------------------------------------------
-struct VoxWs {
-  int64_t* ctl;
-  int32_t* rec;
-  float4* dirs;
-  int64_t* cand_cnt;
-  int64_t* cand_off;
-  uint64_t* masks;
-  int64_t* chunk_prim;
-  int64_t* wave_off;
-  PairBufs pa, pb;
-  int32_t* hist;
-  int64_t* partial;
-  int64_t* seg_start;
-};
-
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-static size_t voxelize_ws_layout(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, void* base,
-                                 VoxWs* w) {
-  Carver cv(base);
+void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, FrontWs* f) {
   const int64_t n_chunks = cdiv(max_cand, 64);
-  const int kb = key64 ? 8 : 4;
-  VoxWs x;
+  FrontWs x;
   x.ctl = cv.take<int64_t>(CTL_SIZE);
   x.rec = cv.take<int32_t>(n_prims * kRec);
   x.dirs = cv.take<float4>(n_prims);
@@ -221,14 +203,29 @@ static size_t voxelize_ws_layout(int64_t n_prims, int64_t max_cand, int64_t max_
   x.masks = cv.take<uint64_t>(n_chunks);
   x.chunk_prim = cv.take<int64_t>(n_chunks);
   x.wave_off = cv.take<int64_t>(n_chunks + 1);
-  for (int k = 0; k < 2; ++k) {
-    PairBufs& p = k ? x.pb : x.pa;
-    p.keys = cv.take<uint8_t>(max_pairs * kb);
-    p.w = cv.take<float>(max_pairs);
-    p.prim = cv.take<uint32_t>(max_pairs);
-  }
-  x.hist = cv.take<int32_t>(int64_t(256) * kGrid);
+  x.pa.keys = cv.take<uint8_t>(max_pairs * (key64 ? 8 : 4));
+  x.pa.w = cv.take<float>(max_pairs);
+  x.pa.prim = cv.take<uint32_t>(max_pairs);
   x.partial = cv.take<int64_t>(kGrid + 1);
+  if (f) *f = x;
+}
+
+struct VoxWs {
+  FrontWs f;
+  PairBufs pb;
+  int32_t* hist;
+  int64_t* seg_start;
+};
+
+static size_t voxelize_ws_layout(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, void* base,
+                                 VoxWs* w) {
+  Carver cv(base);
+  VoxWs x;
+  front_ws_carve(cv, n_prims, max_cand, max_pairs, key64, &x.f);
+  x.pb.keys = cv.take<uint8_t>(max_pairs * (key64 ? 8 : 4));
+  x.pb.w = cv.take<float>(max_pairs);
+  x.pb.prim = cv.take<uint32_t>(max_pairs);
+  x.hist = cv.take<int32_t>(int64_t(256) * kGrid);
   x.seg_start = cv.take<int64_t>(max_pairs + 1);
   if (w) *w = x;
   return cv.off + 256;
@@ -238,20 +235,13 @@ size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, b
   return voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, nullptr, nullptr);
 }
 
-vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
-                       int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws_ptr,
-                       const vx_voxels* out, int64_t* stats, hipStream_t s) {
-  const bool key64 = g->log2_res > 10;
-  VoxWs w;
-  voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, ws_ptr, &w);
-  Lat L;
-  for (int a = 0; a < 3; ++a) L.bmin[a] = g->bmin[a];
-  L.inv = ldexp(1.0, 23) / g->extent;
-  L.Sb = 23 - g->log2_res;
-  L.s = int64_t(1) << L.Sb;
-  L.R = 1 << g->log2_res;
-  L.rho = kind == 1 ? int64_t(rint(double(radius) * L.inv)) : 0;
 
+// prep -> candidate scan -> exact test -> pair scan -> emit: pairs in emission order in f.pa
+void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                    int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
+                    int64_t* stats, hipStream_t s) {
+  const bool key64 = g->log2_res > 10;
+  const Lat L = make_lat(g, kind, radius);
   launch_fill_i64(stats, VX_NSTAT, 0, s);
   launch_fill_i64(w.ctl, CTL_SIZE, 0, s);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
@@ -288,45 +278,43 @@ vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_
     device_scan(PopIn{w.masks}, ArrOut{w.wave_off}, PairTotal{w.wave_off, w.ctl, stats, max_pairs},
                 w.ctl + CTL_N_CHUNKS, 0, w.partial, s);
   }
-  {
-    const size_t lds = kind == 0 ? kTriEmitLds : 0;
-    if (kind == 0) {
-      static bool attr_set[2] = {false, false};
-      if (!attr_set[key64]) {
-        if (key64)
-          (void)hipFuncSetAttribute((const void*)k_emit<0, uint64_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    int(kTriEmitLds));
-        else
-          (void)hipFuncSetAttribute((const void*)k_emit<0, uint32_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    int(kTriEmitLds));
-        attr_set[key64] = true;
-      }
-    }
-    VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
-    if (kind == 0) {
+  const size_t lds = kind == 0 ? kTriEmitLds : 0;
+  if (kind == 0) {
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[key64]) {
       if (key64)
-        hipLaunchKernelGGL((k_emit<0, uint64_t>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off,
-                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint64_t*)w.pa.keys, w.pa.w,
-                           w.pa.prim);
+        (void)hipFuncSetAttribute((const void*)k_emit<0, uint64_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(kTriEmitLds));
       else
-        hipLaunchKernelGGL((k_emit<0, uint32_t>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off,
-                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint32_t*)w.pa.keys, w.pa.w,
-                           w.pa.prim);
-    } else {
-      if (key64)
-        hipLaunchKernelGGL((k_emit<1, uint64_t>), dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.dirs, w.cand_off,
-                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint64_t*)w.pa.keys, w.pa.w,
-                           w.pa.prim);
-      else
-        hipLaunchKernelGGL((k_emit<1, uint32_t>), dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.dirs, w.cand_off,
-                           n_prims, w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (uint32_t*)w.pa.keys, w.pa.w,
-                           w.pa.prim);
+        (void)hipFuncSetAttribute((const void*)k_emit<0, uint32_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(kTriEmitLds));
+      attr_set[key64] = true;
     }
   }
+  VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
+#define VX_EMIT(KD, K)                                                                                        \
+  hipLaunchKernelGGL((k_emit<KD, K>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off, n_prims, \
+                     w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim)
+  if (kind == 0) {
+    if (key64) VX_EMIT(0, uint64_t); else VX_EMIT(0, uint32_t);
+  } else {
+    if (key64) VX_EMIT(1, uint64_t); else VX_EMIT(1, uint32_t);
+  }
+#undef VX_EMIT
+}
+
+vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                       int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws_ptr,
+                       const vx_voxels* out, int64_t* stats, hipStream_t s) {
+  const bool key64 = g->log2_res > 10;
+  VoxWs w;
+  voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, ws_ptr, &w);
+  voxelize_front(kind, g, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s);
   const int key_bits = 3 * g->log2_res;
-  const int res = radix_sort_pairs(key64, key_bits, w.pa, w.pb, w.ctl + CTL_N_PAIRS, max_pairs, w.hist, w.partial, s);
-  reduce_pairs(key64, res ? w.pb : w.pa, w.ctl + CTL_N_PAIRS, w.dirs, kind, w.seg_start, w.partial, w.ctl, stats,
-               *out, s);
+  const int res = radix_sort_pairs(key64, key_bits, w.f.pa, w.pb, w.f.ctl + CTL_N_PAIRS, max_pairs, w.hist,
+                                   w.f.partial, s);
+  reduce_pairs(key64, res ? w.pb : w.f.pa, w.f.ctl + CTL_N_PAIRS, w.f.dirs, kind, w.seg_start, w.f.partial, w.f.ctl,
+               stats, *out, s);
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
 

@@ -219,6 +219,35 @@ void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s);
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
                    int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, hipStream_t s);
 
+// the front half of voxelize (prims.hip): pairs in emission order (by primitive, then candidate)
+struct FrontWs {
+  int64_t* ctl;
+  int32_t* rec;
+  float4* dirs;
+  int64_t* cand_cnt;
+  int64_t* cand_off;
+  uint64_t* masks;
+  int64_t* chunk_prim;
+  int64_t* wave_off;
+  PairBufs pa;
+  int64_t* partial;
+};
+void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, FrontWs* f);
+void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                    int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
+                    int64_t* stats, hipStream_t s);
+
+// the differentiable two-lobe fit (fit.hip)
+size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, bool key64);
+vx_status fit_forward_run(const vx_grid* g, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
+                          const float* const* params, const float* dirs, int ndir, float* loss, void* ws,
+                          const int64_t* caps, hipStream_t s);
+vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, const int64_t* offsets, int64_t n_fib,
+                           float radius, int64_t max_cand, int64_t max_pairs, const vx_voxels* levels,
+                           const int64_t* n_levels, int lo, int hi, const float* const* params, const float* dirs,
+                           int ndir, const float* dloss, float* const* dparams, float* dpts, int64_t* stats,
+                           void* ws, const int64_t* caps, hipStream_t s);
+
 // the voxelize pass (prims.hip)
 size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64);
 vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
