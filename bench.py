@@ -80,12 +80,90 @@ def fit_timing(vx, wl, pts, offs, args, plain_ms):
             "fitted_voxels": int(sum(plan.counts[1:7]))}
 
 
+def _single_build(vx, wl, K):
+    """Single-instance plain path for one fiber set: voxelize + full pyramid with K lobes."""
+    import torch
+    pts = torch.as_tensor(wl.pts).cuda()
+    offs = torch.as_tensor(wl.offsets).cuda()
+    plan = vx.VoxelizePlan(1, wl.grid, pts, offsets=offs, radius=wl.radius)
+    plan.run()
+    leaf = plan.check()
+    levels = wl.grid.log2_res + 1
+    cal = vx.LodPlan(wl.grid, leaf, plan.stats[2:3], levels).run()
+    caps = [max(v.n, 1) for v in cal.check()[1:]]
+    del cal
+    lod = vx.LodPlan(wl.grid, leaf, plan.stats[2:3], levels, K=K, iters=2, caps=caps)
+    return plan, lod
+
+
+def batch_timing(vx, args):
+    """Uneven batch: 64 weave patches (fiber counts log-uniform in [100, 20000], grids 256^3 ..
+    2048^3, full pyramids, K = 4): one replay of the captured batched build against the 64
+    single-instance builds of the same patches, each timed on its own."""
+    import torch
+    import synth
+    from paper_2604_13191_amd import autotune
+    wls = synth.weave_patches()
+    default = vx.get_launch_grids()
+    grids = autotune.apply("weave_patches")
+    stream = torch.cuda.Stream()
+    plan = vx.BatchPlan([vx.Patch(w.grid, torch.as_tensor(w.pts).cuda(), torch.as_tensor(w.offsets), w.radius)
+                         for w in wls], K=4, iters=2)
+    plan.run(stream)
+    plan.check(stream)
+    torch.cuda.synchronize()
+    g = plan.capture(stream)
+    for _ in range(max(1, args.warmup)):
+        g.replay()
+    stream.synchronize()
+    steps = max(1, min(args.steps, 10))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        g.replay()
+        b.record(stream)
+    stream.synchronize()
+    plan.check(stream)
+    batch_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    n_pairs, levels_n = plan.n_pairs, [v.n for v in plan.out]
+    del g, plan
+    torch.cuda.empty_cache()
+    single_ms, single_pairs = 0.0, 0
+    for wl in wls:
+        sp, sl = _single_build(vx, wl, 4)
+        sp.run()
+        sl.run()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for a, b in ev:
+            a.record()
+            sp.run()
+            sl.run()
+            b.record()
+        torch.cuda.synchronize()
+        sp.check()
+        sl.check()
+        single_ms += sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+        single_pairs += sp.n_pairs
+        del sp, sl
+    torch.cuda.empty_cache()
+    vx.set_launch_grids(default)
+    assert single_pairs == n_pairs, (single_pairs, n_pairs)
+    return {"workload": "64 weave patches, 100-20,000 fibers x 256 segments, 256^3-2048^3, full pyramids, K=4",
+            "fibers": int(sum(len(w.offsets) - 1 for w in wls)), "pairs": n_pairs, "voxels_per_level": levels_n,
+            "graph_replay_ms": batch_ms, "pairs_per_s": n_pairs / (batch_ms * 1e-3),
+            "single_instance_sum_ms": single_ms, "speedup_vs_single": single_ms / batch_ms,
+            "launch_grids": grids if grids is not None else "default (1024)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-fit", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design note, "
@@ -163,7 +241,12 @@ def main():
                      "algorithmic_bytes_per_launch": dom_b, "avg_launch_ms": dom_avg},
         "kernels": kernels,
     }
-    out["fit"] = fit_timing(vx, wl, pts, offs, args, ms_step)
+    if not args.no_fit:
+        out["fit"] = fit_timing(vx, wl, pts, offs, args, ms_step)
+    if not args.no_batch:
+        del plan, lod
+        torch.cuda.empty_cache()
+        out["batched"] = batch_timing(vx, args)
     if not args.no_cpu_baseline:
         nth = max(1, min(16, os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(wl, nth)

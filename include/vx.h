@@ -192,6 +192,58 @@ vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fibers, int64_t 
                           float* const* dparams, float* dpts, int64_t* stats, const int64_t* caps, void* workspace,
                           size_t ws_bytes, vx_stream stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched fiber patches (extension): many patches of uneven size and resolution voxelized and
+ * LoD-built together, by the same kernels as one instance, with one pass over all primitives.
+ *
+ * Every patch has its own cubic grid (log2_res <= 11) and radius; its points are the range
+ * [pt_begin, pt_end) of the shared point array and its fibers must not cross that range.  Keys
+ * are 64-bit: (patch << 33) | Morton code, and a parent keeps its patch bits:
+ * parent(k) = (k & ~(2^33 - 1)) | ((k & (2^33 - 1)) >> 3).  Patch p's voxels of a level are the
+ * contiguous range [patch_table[L][p], patch_table[L][p + 1]).  A patch whose own pyramid is
+ * shorter than `levels` keeps its root voxel on the levels above it.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  vx_grid grid;
+  int64_t pt_begin;
+  int64_t pt_end;
+  float radius;
+  int32_t reserved;
+} vx_patch;
+
+size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_cand, int64_t max_pairs,
+                               int64_t leaf_cap);
+
+/* patches: host array (validated) and the same array in device memory (read by the kernels);
+ * pts / offsets: device, all patches concatenated (offsets global over all fibers);
+ * out: host array of `levels` level descriptors, leaf first (out[0].mask may be NULL);
+ * lobes: host array of levels - 1 descriptors when K > 1, else NULL;
+ * n_levels: device int64 [levels + 1] (counts, then flags); patch_table: device int64
+ * [levels][n_patches + 1]; stats: device int64 [VX_NSTAT] (pair and leaf totals, flags). */
+vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, int32_t n_patches, const float* pts,
+                         int64_t n_pts, const int64_t* offsets, int64_t n_fibers, int32_t levels, int32_t K,
+                         int32_t kmeans_iters, int64_t max_cand, int64_t max_pairs, const vx_voxels* out,
+                         const vx_lobes* lobes, int64_t* n_levels, int64_t* patch_table, int64_t* stats,
+                         void* workspace, size_t ws_bytes, vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Graph capture of a whole call (no host work inside, so it replays as one launch).  `stream`
+ * must not be the null stream.  Between begin and end, enqueue library calls on `stream`;
+ * vx_graph_launch replays them (with the buffers and sizes of the capture).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct vx_graph_s* vx_graph;
+vx_status vx_graph_begin(vx_stream stream);
+vx_status vx_graph_end(vx_stream stream, vx_graph* graph);
+vx_status vx_graph_launch(vx_graph graph, vx_stream stream);
+void vx_graph_destroy(vx_graph graph);
+
+/* Launch geometry (set by the autotuner): grid sizes of the persistent kernels for the exact
+ * test, the emission, the leaf reduce, the parent reduce and the lobe clustering, in that
+ * order; each 64 .. 16384 blocks of 256 threads. */
+#define VX_TUNE_COUNT 5
+vx_status vx_set_launch_grids(const int32_t* grids, int32_t n);
+void vx_get_launch_grids(int32_t* grids, int32_t n);
+
 /* Synchronises `stream`, reads stats (VX_NSTAT int64 on the device) and maps its flags to a
  * status: VX_ERR_INPUT before VX_ERR_CAPACITY before VX_OK. */
 vx_status vx_check_stats(const int64_t* stats, vx_stream stream);

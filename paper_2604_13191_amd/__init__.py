@@ -47,6 +47,11 @@ class CLobes(ctypes.Structure):
     _fields_ = [("nl", ctypes.c_void_p), ("w", ctypes.c_void_p), ("S", ctypes.c_void_p), ("cap", ctypes.c_int64)]
 
 
+class CPatch(ctypes.Structure):
+    _fields_ = [("grid", CGrid), ("pt_begin", ctypes.c_int64), ("pt_end", ctypes.c_int64),
+                ("radius", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
 class CFibers(ctypes.Structure):
     _fields_ = [("pts", ctypes.c_void_p), ("n_pts", ctypes.c_int64), ("offsets", ctypes.c_void_p),
                 ("n_fibers", ctypes.c_int64), ("radius", ctypes.c_float)]
@@ -92,6 +97,23 @@ def load():
     L.vx_fit_backward.restype = ctypes.c_int
     L.vx_fit_backward.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CFibers), i64, i64, ctypes.POINTER(CVoxels),
                                   vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.vx_batch_workspace_size.restype = sz
+    L.vx_batch_workspace_size.argtypes = [i32, i64, i64, i64, i64]
+    L.vx_batch_build.restype = ctypes.c_int
+    L.vx_batch_build.argtypes = [ctypes.POINTER(CPatch), vp, i32, vp, i64, vp, i64, i32, i32, i32, i64, i64,
+                                 ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp, vp, vp, sz, vp]
+    L.vx_graph_begin.restype = ctypes.c_int
+    L.vx_graph_begin.argtypes = [vp]
+    L.vx_graph_end.restype = ctypes.c_int
+    L.vx_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
+    L.vx_graph_launch.restype = ctypes.c_int
+    L.vx_graph_launch.argtypes = [vp, vp]
+    L.vx_graph_destroy.restype = None
+    L.vx_graph_destroy.argtypes = [vp]
+    L.vx_set_launch_grids.restype = ctypes.c_int
+    L.vx_set_launch_grids.argtypes = [ctypes.POINTER(i32), i32]
+    L.vx_get_launch_grids.restype = None
+    L.vx_get_launch_grids.argtypes = [ctypes.POINTER(i32), i32]
     L.vx_timing_enable.argtypes = [i32]
     L.vx_timing_reset.argtypes = []
     L.vx_timing_collect.restype = i32
@@ -528,3 +550,227 @@ def fit_init(plan, seed=4, noise=0.01):
         P = P + noise * torch.randn(P.shape, generator=g, device=w.device, dtype=torch.float64)
         out.append(P.to(torch.float32).contiguous())
     return out
+
+
+# ------------------------------------------------------------------------------------------------
+# Launch geometry and graphs
+# ------------------------------------------------------------------------------------------------
+
+TUNE_KERNELS = ("test_fib", "emit_fib", "seg_reduce", "lod_reduce", "lod_cluster")
+
+
+def get_launch_grids():
+    """Grid sizes (blocks) of the persistent kernels, in the order of TUNE_KERNELS."""
+    arr = (ctypes.c_int32 * len(TUNE_KERNELS))()
+    load().vx_get_launch_grids(arr, len(TUNE_KERNELS))
+    return list(arr)
+
+
+def set_launch_grids(grids):
+    grids = [int(g) for g in grids]
+    arr = (ctypes.c_int32 * len(grids))(*grids)
+    st = load().vx_set_launch_grids(arr, len(grids))
+    if st != 0:
+        raise VxError(st, f"vx_set_launch_grids({grids})")
+
+
+class Graph:
+    """A captured sequence of library calls on one (non-null) stream, replayed as one launch."""
+
+    def __init__(self, handle, stream):
+        self.handle, self.stream = handle, stream
+
+    def replay(self, stream=None):
+        st = load().vx_graph_launch(self.handle, _stream(stream if stream is not None else self.stream))
+        if st != 0:
+            raise VxError(st, "vx_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vx_graph_destroy(self.handle)
+            self.handle = None
+
+
+def capture(fn, stream):
+    """Capture everything ``fn(stream)`` enqueues on ``stream`` into a Graph.  Kernel timing must
+    be off; the buffers used by ``fn`` must stay alive as long as the graph."""
+    L = load()
+    cs = _stream(stream)
+    st = L.vx_graph_begin(cs)
+    if st != 0:
+        raise VxError(st, "vx_graph_begin")
+    try:
+        fn(stream)
+    finally:
+        h = ctypes.c_void_p()
+        st2 = L.vx_graph_end(cs, ctypes.byref(h))
+    if st2 != 0:
+        raise VxError(st2, "vx_graph_end")
+    return Graph(h, stream)
+
+
+# ------------------------------------------------------------------------------------------------
+# Batched patches (vx_batch_build)
+# ------------------------------------------------------------------------------------------------
+
+PATCH_SHIFT = 33
+
+
+@dataclass
+class Patch:
+    """One fiber patch of a batch: its own grid, points [n, 3] (float32, GPU), local CSR
+    offsets [F + 1] and radius."""
+    grid: object
+    pts: object
+    offsets: object
+    radius: float
+
+
+class BatchPlan:
+    """Many fiber patches voxelized and LoD-built by one batched call (one pass of every kernel
+    over all patches' primitives), optionally captured into a graph.
+
+    ``levels`` defaults to the deepest patch's full pyramid; a shallower patch keeps its root
+    voxel on the levels above it.  Capacities come from counting calls of the same entry point
+    (candidates, pairs, leaf voxels, then per-level counts), synchronising once per call."""
+
+    def __init__(self, patches, K=4, iters=2, levels=None, device=None):
+        import torch
+        self.L = load()
+        self.patches = list(patches)
+        self.n_patches = len(self.patches)
+        if self.n_patches < 1:
+            raise ValueError("a batch needs at least one patch")
+        dev = device if device is not None else self.patches[0].pts.device
+        self.device = torch.device(dev)
+        pts, offs, cp = [], [], (CPatch * self.n_patches)()
+        base_pt, base_fib = 0, 0
+        for i, P in enumerate(self.patches):
+            p = P.pts.to(device=self.device, dtype=torch.float32).reshape(-1, 3)
+            o = torch.as_tensor(P.offsets).to(device=self.device, dtype=torch.int64).reshape(-1)
+            n = int(p.shape[0])
+            pts.append(p)
+            offs.append(o[1:] + base_pt if i else o + base_pt)
+            cp[i].grid = _cgrid(P.grid)
+            cp[i].pt_begin, cp[i].pt_end = base_pt, base_pt + n
+            cp[i].radius = float(P.radius)
+            base_pt += n
+            base_fib += int(o.numel() - 1)
+        self.pts = torch.cat(pts).contiguous()
+        self.offsets = torch.cat(offs).contiguous()
+        self.n_pts, self.n_fib = int(self.pts.shape[0]), int(self.offsets.numel() - 1)
+        self._cp = cp
+        self.patches_dev = torch.frombuffer(bytearray(bytes(cp)), dtype=torch.uint8).to(self.device)
+        self.levels = int(levels) if levels is not None else max(P.grid.log2_res for P in self.patches) + 1
+        self.K, self.iters = int(K), int(iters)
+        self.stats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.device)
+        self.n_levels = torch.zeros(self.levels + 1, dtype=torch.int64, device=self.device)
+        self.patch_table = torch.zeros((self.levels, self.n_patches + 1), dtype=torch.int64, device=self.device)
+        self._plan_capacities()
+
+    # -- one call of the entry point ------------------------------------------------------------
+    def _call(self, levels, K, max_cand, max_pairs, cout, clobes, ws, stream):
+        st = self.L.vx_batch_build(self._cp, _ptr(self.patches_dev), self.n_patches, _ptr(self.pts), self.n_pts,
+                                   _ptr(self.offsets), self.n_fib, levels, K, self.iters, max_cand, max_pairs, cout,
+                                   clobes, _ptr(self.n_levels), _ptr(self.patch_table), _ptr(self.stats), _ptr(ws),
+                                   ws.numel(), stream)
+        if st != 0:
+            raise VxError(st, "vx_batch_build")
+
+    def _ws_for(self, max_cand, max_pairs, leaf_cap):
+        nb = self.L.vx_batch_workspace_size(self.n_patches, self.n_pts, max_cand, max_pairs, leaf_cap)
+        if nb == 0:
+            raise VxError(1, "vx_batch_workspace_size")
+        return _ws(nb, self.device)
+
+    def _stats(self, s):
+        self.L.vx_check_stats(_ptr(self.stats), s)
+        h = self.stats.cpu().numpy()
+        if h[STAT_FLAGS] & (FLAG_INPUT | FLAG_OFFSETS):
+            raise VxError(4, "vx_batch_build")
+        return h
+
+    def _plan_capacities(self):
+        import torch
+        s = _stream()
+        one = alloc_voxels(1, 11, self.device, False)
+        c1 = (CVoxels * 1)(one.cstruct())
+        ws = self._ws_for(0, 0, 1)
+        self._call(1, 1, 0, 0, c1, None, ws, s)
+        n_cand = int(self._stats(s)[STAT_CAND])
+        ws = self._ws_for(n_cand, 0, 1)
+        self._call(1, 1, n_cand, 0, c1, None, ws, s)
+        n_pairs = int(self._stats(s)[STAT_PAIRS])
+        del ws
+        ws = self._ws_for(n_cand, n_pairs, 1)
+        self._call(1, 1, n_cand, n_pairs, c1, None, ws, s)
+        n_leaf = max(1, int(self._stats(s)[STAT_VOXELS]))
+        del ws
+        # per-level counts: K = 1, two level buffers of the leaf's size used in turn
+        leaf = alloc_voxels(n_leaf, 11, self.device, False)
+        ping = [alloc_voxels(n_leaf, 11, self.device, True) for _ in range(min(2, self.levels - 1))]
+        cl = [leaf] + [ping[(L - 1) % 2] for L in range(1, self.levels)]
+        cout = (CVoxels * self.levels)(*[v.cstruct() for v in cl])
+        ws = self._ws_for(n_cand, n_pairs, n_leaf)
+        self._call(self.levels, 1, n_cand, n_pairs, cout, None, ws, s)
+        self._stats(s)
+        torch.cuda.synchronize()
+        counts = [int(x) for x in self.n_levels[:self.levels].cpu()]
+        del leaf, ping, cl, cout
+        self.max_cand, self.max_pairs, self.counts = n_cand, n_pairs, counts
+        self.out = [alloc_voxels(max(c, 1), 11, self.device, L > 0) for L, c in enumerate(counts)]
+        self._cout = (CVoxels * self.levels)(*[v.cstruct() for v in self.out])
+        self.lobes, self._clobes = [], None
+        if self.K > 1 and self.levels > 1:
+            self.lobes = [Lobes(torch.empty(v.cap, dtype=torch.uint8, device=self.device),
+                                torch.empty((self.K, v.cap), dtype=torch.float32, device=self.device),
+                                torch.empty((6, self.K, v.cap), dtype=torch.float32, device=self.device))
+                          for v in self.out[1:]]
+            self._clobes = (CLobes * len(self.lobes))(*[lb.cstruct() for lb in self.lobes])
+        self.ws = self._ws_for(n_cand, n_pairs, self.out[0].cap)
+
+    # -- hot path -------------------------------------------------------------------------------
+    def run(self, stream=None):
+        self._call(self.levels, self.K, self.max_cand, self.max_pairs, self._cout, self._clobes, self.ws,
+                   _stream(stream))
+        return self
+
+    def capture(self, stream):
+        """Graph of one whole batched build on ``stream`` (a torch.cuda.Stream, not the default)."""
+        return capture(lambda st: self.run(st), stream)
+
+    def check(self, stream=None):
+        """Synchronise, raise on a capacity or input flag, and fetch counts and patch tables."""
+        import torch
+        st = self.L.vx_check_stats(_ptr(self.stats), _stream(stream))
+        h = self.stats.cpu().numpy()
+        if st != 0:
+            raise VxError(st, f"vx_batch_build (stats {h.tolist()})")
+        torch.cuda.synchronize()
+        nl = self.n_levels.cpu().numpy()
+        if nl[self.levels] & FLAG_VOXEL_CAPACITY:
+            raise VxError(2, "vx_batch_build")
+        for L in range(self.levels):
+            self.out[L].n = int(nl[L])
+            if L > 0 and self.lobes:
+                self.lobes[L - 1].n = int(nl[L])
+        self.n_pairs, self.n_cand = int(h[STAT_PAIRS]), int(h[STAT_CAND])
+        self.table = self.patch_table.cpu().numpy()
+        return self
+
+    def patch_level(self, p, L):
+        """Host copy of patch p's voxels at level L (keys without the patch bits; with K > 1 and
+        L > 0 also 'nl', 'lw', 'lS' lobes)."""
+        a, b = int(self.table[L, p]), int(self.table[L, p + 1])
+        v = self.out[L]
+        k = v.keys[a:b].cpu().numpy().view(np.uint64) & np.uint64((1 << PATCH_SHIFT) - 1)
+        out = {"keys": k, "count": v.count[a:b].cpu().numpy().view(np.uint32), "w": v.w[a:b].cpu().numpy(),
+               "S": v.S[:, a:b].cpu().numpy().T.copy()}
+        if v.mask is not None:
+            out["mask"] = v.mask[a:b].cpu().numpy()
+        if L > 0 and self.lobes:
+            lb = self.lobes[L - 1]
+            out["nl"] = lb.nl[a:b].cpu().numpy()
+            out["lw"] = lb.w[:, a:b].cpu().numpy().T.copy()
+            out["lS"] = lb.S[:, :, a:b].cpu().numpy().transpose(2, 1, 0).copy()
+        return out

@@ -1,11 +1,13 @@
 // api.hip -- the C ABI of libvx.so (declared in include/vx.h): argument checks, workspace
 // sizing, orchestration of the kernels on the caller's stream, and kernel timing.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "geom.hpp"
 #include "vx_internal.hpp"
 
 namespace vx {
@@ -59,7 +61,42 @@ void timing_end(hipStream_t s) {
   (void)hipEventRecord(g_pending[i].b, s);
 }
 
+int g_grids[kTuneCount] = {kGrid, kGrid, kGrid, kGrid, kGrid};
+int tuned_grid(int which) { return g_grids[which]; }
+
+// batched patches: device lattice table and point ranges from the caller's device patch array
+__global__ void k_batch_setup(const vx_patch* __restrict__ patches, int n, Lat* __restrict__ lats,
+                              int64_t* __restrict__ pt_begin) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    lats[p] = make_lat(&patches[p].grid, 1, patches[p].radius);
+    pt_begin[p] = patches[p].pt_begin;
+    if (p == n - 1) pt_begin[n] = patches[p].pt_end;
+  }
+}
+
+// start of every patch's voxels in a level: lower bound of (p << 33) in the sorted keys
+__global__ void k_patch_table(const uint64_t* __restrict__ keys, const int64_t* n_ptr, int n_patches,
+                              int64_t* __restrict__ table) {
+  const int64_t n = *n_ptr;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p <= n_patches; p += gridDim.x * blockDim.x) {
+    const uint64_t k = uint64_t(p) << kPatchShift;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (keys[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    table[p] = p == n_patches ? n : lo;
+  }
+}
+
+struct vx_graph_impl {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 }  // namespace vx
+
+struct vx_graph_s : vx::vx_graph_impl {};
 
 using namespace vx;
 
@@ -223,6 +260,130 @@ vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fib, int64_t max
   return fit_backward_run(grid, fib->pts, fib->n_pts, fib->offsets, fib->n_fibers, fib->radius, max_cand, max_pairs,
                           levels, n_levels, lo, hi, params, dirs, ndir, dloss, dparams, dpts, stats, ws, caps,
                           reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_cand, int64_t max_pairs,
+                               int64_t leaf_cap) {
+  if (n_patches < 1 || n_patches > 65536 || n_pts < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs ||
+      leaf_cap < 1)
+    return 0;
+  // batch tables + the voxelize workspace with 64-bit keys + the pyramid's parent starts
+  Carver cv(nullptr);
+  cv.take<Lat>(n_patches);
+  cv.take<int64_t>(n_patches + 1);
+  cv.take<int64_t>(leaf_cap + 1);
+  cv.take<int64_t>(kGrid + 1);
+  return cv.off + voxelize_ws_bytes(n_pts, max_cand, max_pairs, true) + 512;
+}
+
+vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, int32_t n_patches, const float* pts,
+                         int64_t n_pts, const int64_t* offsets, int64_t n_fibers, int32_t levels, int32_t K,
+                         int32_t kmeans_iters, int64_t max_cand, int64_t max_pairs, const vx_voxels* out,
+                         const vx_lobes* lobes, int64_t* n_levels, int64_t* patch_table, int64_t* stats, void* ws,
+                         size_t ws_bytes, vx_stream stream) {
+  if (!patches || !patches_dev || n_patches < 1 || n_patches > 65536 || n_pts < 0 || !offsets || n_fibers < 0 ||
+      (n_pts > 0 && (!pts || n_fibers < 1)) || levels < 1 || K < 1 || K > 8 || kmeans_iters < 0 || max_cand < 0 ||
+      max_pairs < 0 || max_pairs > kMaxPairs || !out || !n_levels || !patch_table || !stats)
+    return VX_ERR_ARG;
+  int max_levels = 0;
+  for (int p = 0; p < n_patches; ++p) {
+    const vx_patch& P = patches[p];
+    if (!grid_ok(&P.grid) || P.grid.log2_res > 11) return VX_ERR_ARG;
+    if (!(P.radius >= 0.0f) || !std::isfinite(P.radius)) return VX_ERR_ARG;
+    if (std::rint(double(P.radius) * (std::ldexp(1.0, 23) / P.grid.extent)) > 8388608.0) return VX_ERR_ARG;
+    if (P.pt_begin != (p == 0 ? 0 : patches[p - 1].pt_end) || P.pt_end < P.pt_begin) return VX_ERR_ARG;
+    max_levels = std::max(max_levels, P.grid.log2_res + 1);
+  }
+  if (patches[n_patches - 1].pt_end != n_pts || levels > max_levels) return VX_ERR_ARG;
+  if (!voxels_ok(&out[0], false)) return VX_ERR_ARG;
+  for (int L = 1; L < levels; ++L) {
+    if (!voxels_ok(&out[L], true)) return VX_ERR_ARG;
+    if (K > 1 && (!lobes || !lobes[L - 1].nl || !lobes[L - 1].w || !lobes[L - 1].S || lobes[L - 1].cap < out[L].cap))
+      return VX_ERR_ARG;
+  }
+  const int64_t leaf_cap = out[0].cap;
+  if (!ws_ok(ws, ws_bytes, vx_batch_workspace_size(n_patches, n_pts, max_cand, max_pairs, leaf_cap)))
+    return VX_ERR_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Carver cv(ws);
+  Lat* lats = cv.take<Lat>(n_patches);
+  int64_t* pt_begin = cv.take<int64_t>(n_patches + 1);
+  int64_t* pstart = cv.take<int64_t>(leaf_cap + 1);
+  int64_t* partial = cv.take<int64_t>(kGrid + 1);
+  void* vws = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(ws) + cv.off + 255) & ~uintptr_t(255));
+  hipLaunchKernelGGL(k_batch_setup, dim3((n_patches + 255) / 256), dim3(256), 0, s, patches_dev, n_patches, lats,
+                     pt_begin);
+  BatchLattice bl{lats, pt_begin, n_patches};
+  int patch_bits = 1;
+  while ((1 << patch_bits) < n_patches) ++patch_bits;
+  vx_status st = voxelize_batch_run(&patches[0].grid, pts, n_pts, offsets, n_fibers, max_cand, max_pairs, vws,
+                                    &out[0], stats, s, bl, kPatchShift + patch_bits);
+  if (st != VX_OK) return st;
+  // the pyramid, with the patch-preserving parent
+  launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
+  lod_clamp(stats + VX_STAT_VOXELS, leaf_cap, n_levels, s);
+  for (int L = 1; L < levels; ++L) {
+    lod_level(true, out[L - 1], n_levels + L - 1, out[L], n_levels + L, n_levels + levels, pstart, partial, s,
+              true);
+    if (K > 1) {
+      if (L == 1)
+        cluster_level(pstart, n_levels + 1, out[0].w, out[0].S, nullptr, 1, out[0].cap, K, kmeans_iters, lobes[0], s);
+      else
+        cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
+                      kmeans_iters, lobes[L - 1], s);
+    }
+  }
+  for (int L = 0; L < levels; ++L)
+    hipLaunchKernelGGL(k_patch_table, dim3((n_patches + 256) / 256), dim3(256), 0, s, (const uint64_t*)out[L].keys,
+                       n_levels + L, n_patches, patch_table + int64_t(L) * (n_patches + 1));
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+vx_status vx_graph_begin(vx_stream stream) {
+  if (!stream) return VX_ERR_ARG;
+  return hipStreamBeginCapture(reinterpret_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal) == hipSuccess
+             ? VX_OK
+             : VX_ERR_HIP;
+}
+
+vx_status vx_graph_end(vx_stream stream, vx_graph* graph) {
+  if (!stream || !graph) return VX_ERR_ARG;
+  vx_graph g = new vx_graph_s;
+  if (hipStreamEndCapture(reinterpret_cast<hipStream_t>(stream), &g->graph) != hipSuccess) {
+    delete g;
+    return VX_ERR_HIP;
+  }
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return VX_ERR_HIP;
+  }
+  *graph = g;
+  return VX_OK;
+}
+
+vx_status vx_graph_launch(vx_graph graph, vx_stream stream) {
+  if (!graph) return VX_ERR_ARG;
+  return hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+void vx_graph_destroy(vx_graph graph) {
+  if (!graph) return;
+  (void)hipGraphExecDestroy(graph->exec);
+  (void)hipGraphDestroy(graph->graph);
+  delete graph;
+}
+
+vx_status vx_set_launch_grids(const int32_t* grids, int32_t n) {
+  if (!grids || n < 1 || n > kTuneCount) return VX_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (grids[i] < 64 || grids[i] > 16384) return VX_ERR_ARG;
+  for (int i = 0; i < n; ++i) g_grids[i] = grids[i];
+  return VX_OK;
+}
+
+void vx_get_launch_grids(int32_t* grids, int32_t n) {
+  for (int i = 0; i < n && i < kTuneCount; ++i) grids[i] = g_grids[i];
 }
 
 vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {

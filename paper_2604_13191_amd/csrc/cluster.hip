@@ -233,16 +233,16 @@ void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw,
   const int need = 8 * Kc;
   VX_TIMED("lod_cluster", s);
   if (need <= 8)
-    hipLaunchKernelGGL(k_cluster<8>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+    hipLaunchKernelGGL(k_cluster<8>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
   else if (need <= 16)
-    hipLaunchKernelGGL(k_cluster<16>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+    hipLaunchKernelGGL(k_cluster<16>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
   else if (need <= 32)
-    hipLaunchKernelGGL(k_cluster<32>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+    hipLaunchKernelGGL(k_cluster<32>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
   else
-    hipLaunchKernelGGL(k_cluster<64>, dim3(kGrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+    hipLaunchKernelGGL(k_cluster<64>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
 }
 

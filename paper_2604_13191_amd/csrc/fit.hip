@@ -444,7 +444,7 @@ vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, co
                          caps[L], levels[L + 1], n_levels + L + 1, w.g[L + 1], caps[L + 1]);
   }
   // re-emit the pairs in primitive order, then the chain rule per segment and per point
-  voxelize_front(1, g, pts, n_pts, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s);
+  voxelize_front(1, g, pts, n_pts, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s, nullptr);
   const Lat lat = make_lat(g, 1, radius);
   const double vs = double(int64_t(1) << g->log2_res) / g->extent;
   {

@@ -48,6 +48,35 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ p
   }
 }
 
+// Batched fibers: patch p owns points [pt_begin[p], pt_begin[p+1]) and is snapped to its own
+// lattice; the record keeps the patch id in its last slot.
+__global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restrict__ pts, int64_t n_pts,
+                                                           const int64_t* __restrict__ offsets, int64_t n_fib,
+                                                           const Lat* __restrict__ lats,
+                                                           const int64_t* __restrict__ pt_begin, int n_patches,
+                                                           int32_t* __restrict__ rec, float4* __restrict__ dirs,
+                                                           int64_t* __restrict__ cand_cnt, int64_t* stats) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_pts; i += int64_t(gridDim.x) * kBlock) {
+    int lo = 0, hi = n_patches;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pt_begin[mid] <= i) lo = mid; else hi = mid;
+    }
+    const int patch = lo;
+    int64_t flo = 0, fhi = n_fib;
+    while (fhi - flo > 1) {
+      const int64_t mid = (flo + fhi) >> 1;
+      if (offsets[mid] <= i) flo = mid; else fhi = mid;
+    }
+    const bool seg = (i + 1 < n_pts) && (i + 1 < offsets[flo + 1]) && (i + 1 < pt_begin[patch + 1]);
+    bool ok;
+    cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, lats[patch], rec + i * kRec, dirs + i,
+                               ok);
+    rec[i * kRec + 15] = patch;
+    if (!ok) flag_or(stats, VX_FLAG_INPUT);
+  }
+}
+
 __global__ void k_check_offsets(const int64_t* __restrict__ offsets, int64_t n_fib, int64_t n_pts, int64_t* stats) {
   for (int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; f <= n_fib; f += int64_t(gridDim.x) * blockDim.x) {
     bool bad = false;
@@ -65,7 +94,8 @@ __global__ void k_check_offsets(const int64_t* __restrict__ offsets, int64_t n_f
 template <int KIND>
 __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec, const int64_t* __restrict__ cand_off,
                                                  int64_t n_prims, const int64_t* __restrict__ ctl, Lat L,
-                                                 uint64_t* __restrict__ masks, int64_t* __restrict__ chunk_prim) {
+                                                 const Lat* __restrict__ lats, uint64_t* __restrict__ masks,
+                                                 int64_t* __restrict__ chunk_prim) {
   const int64_t n_cand = ctl[CTL_N_CAND];
   const int64_t n_chunks = ctl[CTL_N_CHUNKS];
   const int lane = lane_id();
@@ -83,8 +113,9 @@ __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec
       const int32_t* r = rec + p * kRec;
       int64_t v[3];
       candidate_voxel(r, ci - cand_off[p], v);
-      if (KIND == 0) hit = tri_touch(r, v, L.s, L.Sb);
-      else hit = cap_touch(r, v, L.s, L.Sb, L.rho);
+      const Lat& Lp = lats ? lats[r[15]] : L;        // batched patches: the primitive's own lattice
+      if (KIND == 0) hit = tri_touch(r, v, Lp.s, Lp.Sb);
+      else hit = cap_touch(r, v, Lp.s, Lp.Sb, Lp.rho);
     }
     const uint64_t m = __ballot(hit);
     if (lane == 0) {
@@ -100,7 +131,7 @@ __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec
 template <int KIND, class Key>
 __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec, const float4* __restrict__ dirs,
                                                  const int64_t* __restrict__ cand_off, int64_t n_prims,
-                                                 const int64_t* __restrict__ ctl, Lat L,
+                                                 const int64_t* __restrict__ ctl, Lat L, const Lat* __restrict__ lats,
                                                  const uint64_t* __restrict__ masks,
                                                  const int64_t* __restrict__ chunk_prim,
                                                  const int64_t* __restrict__ wave_off, Key* __restrict__ keys,
@@ -121,9 +152,12 @@ __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec
     int64_t v[3];
     candidate_voxel(r, ci - cand_off[p], v);
     float wgt;
-    if (KIND == 0) wgt = tri_area(r, v, L.Sb, dirs[p].w, lds_poly + threadIdx.x);
-    else wgt = seg_length(r, v, L.Sb, dirs[p].w);
-    keys[pos] = Key(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])));
+    const int Sb = lats ? lats[r[15]].Sb : L.Sb;
+    if (KIND == 0) wgt = tri_area(r, v, Sb, dirs[p].w, lds_poly + threadIdx.x);
+    else wgt = seg_length(r, v, Sb, dirs[p].w);
+    Key key = Key(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])));
+    if (lats) key |= Key(uint64_t(uint32_t(r[15])) << kPatchShift);
+    keys[pos] = key;
     wts[pos] = wgt;
     prim[pos] = uint32_t(p);
   }
@@ -239,9 +273,10 @@ size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, b
 // prep -> candidate scan -> exact test -> pair scan -> emit: pairs in emission order in f.pa
 void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                     int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
-                    int64_t* stats, hipStream_t s) {
-  const bool key64 = g->log2_res > 10;
+                    int64_t* stats, hipStream_t s, const BatchLattice* batch) {
+  const bool key64 = batch || g->log2_res > 10;
   const Lat L = make_lat(g, kind, radius);
+  const Lat* lats = batch ? batch->lats : nullptr;
   launch_fill_i64(stats, VX_NSTAT, 0, s);
   launch_fill_i64(w.ctl, CTL_SIZE, 0, s);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
@@ -256,8 +291,12 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
                          s, offsets, n_fib, n_prims, stats);
     }
     VX_TIMED("prep_fib", s);
-    hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, L, w.rec,
-                       w.dirs, w.cand_cnt, stats);
+    if (batch)
+      hipLaunchKernelGGL(k_prep_fib_batch, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, batch->lats,
+                         batch->pt_begin, batch->n_patches, w.rec, w.dirs, w.cand_cnt, stats);
+    else
+      hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, L, w.rec,
+                         w.dirs, w.cand_cnt, stats);
   }
   {
     VX_TIMED("scan_cand", s);
@@ -267,11 +306,11 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
   {
     VX_TIMED(kind == 0 ? "test_tri" : "test_fib", s);
     if (kind == 0)
-      hipLaunchKernelGGL(k_test<0>, dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims, w.ctl, L,
-                         w.masks, w.chunk_prim);
+      hipLaunchKernelGGL(k_test<0>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims,
+                         w.ctl, L, lats, w.masks, w.chunk_prim);
     else
-      hipLaunchKernelGGL(k_test<1>, dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims, w.ctl, L,
-                         w.masks, w.chunk_prim);
+      hipLaunchKernelGGL(k_test<1>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims,
+                         w.ctl, L, lats, w.masks, w.chunk_prim);
   }
   {
     VX_TIMED("scan_pairs", s);
@@ -293,8 +332,8 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
   }
   VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
 #define VX_EMIT(KD, K)                                                                                        \
-  hipLaunchKernelGGL((k_emit<KD, K>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off, n_prims, \
-                     w.ctl, L, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim)
+  hipLaunchKernelGGL((k_emit<KD, K>), dim3(tuned_grid(kTuneEmit)), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off, \
+                     n_prims, w.ctl, L, lats, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim)
   if (kind == 0) {
     if (key64) VX_EMIT(0, uint64_t); else VX_EMIT(0, uint32_t);
   } else {
@@ -309,11 +348,25 @@ vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_
   const bool key64 = g->log2_res > 10;
   VoxWs w;
   voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, ws_ptr, &w);
-  voxelize_front(kind, g, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s);
+  voxelize_front(kind, g, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s, nullptr);
   const int key_bits = 3 * g->log2_res;
   const int res = radix_sort_pairs(key64, key_bits, w.f.pa, w.pb, w.f.ctl + CTL_N_PAIRS, max_pairs, w.hist,
                                    w.f.partial, s);
   reduce_pairs(key64, res ? w.pb : w.f.pa, w.f.ctl + CTL_N_PAIRS, w.f.dirs, kind, w.seg_start, w.f.partial, w.f.ctl,
+               stats, *out, s);
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+// batched fiber patches: 64-bit keys (patch << 33 | Morton), each primitive on its patch's lattice
+vx_status voxelize_batch_run(const vx_grid* g0, const float* pts, int64_t n_pts, const int64_t* offsets,
+                             int64_t n_fib, int64_t max_cand, int64_t max_pairs, void* ws_ptr, const vx_voxels* out,
+                             int64_t* stats, hipStream_t s, const BatchLattice& bl, int key_bits) {
+  VoxWs w;
+  voxelize_ws_layout(n_pts, max_cand, max_pairs, true, ws_ptr, &w);
+  voxelize_front(1, g0, pts, n_pts, offsets, n_fib, 0.0f, max_cand, max_pairs, w.f, stats, s, &bl);
+  const int res = radix_sort_pairs(true, key_bits, w.f.pa, w.pb, w.f.ctl + CTL_N_PAIRS, max_pairs, w.hist,
+                                   w.f.partial, s);
+  reduce_pairs(true, res ? w.pb : w.f.pa, w.f.ctl + CTL_N_PAIRS, w.f.dirs, 1, w.seg_start, w.f.partial, w.f.ctl,
                stats, *out, s);
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }

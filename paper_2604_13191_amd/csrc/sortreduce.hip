@@ -140,10 +140,22 @@ int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int
 // ---------------------------------------------------------------------------------------------
 // segmented reduce: leaf voxels
 // ---------------------------------------------------------------------------------------------
-template <class Key, int SHIFT>
+// parent key: the Morton code shifted by one level; batched keys keep their patch id above
+// bit kPatchShift
+template <bool BATCH, class Key>
+__device__ __forceinline__ Key parent_key(Key k) {
+  if (!BATCH) return k >> 3;
+  const Key lowmask = (Key(1) << kPatchShift) - 1;
+  return (k & ~lowmask) | ((k & lowmask) >> 3);
+}
+
+template <class Key, int SHIFT, bool BATCH = false>
 struct HeadIn {
   const Key* k;
-  __device__ int64_t operator()(int64_t i) const { return i == 0 || (k[i] >> SHIFT) != (k[i - 1] >> SHIFT); }
+  __device__ int64_t operator()(int64_t i) const {
+    if (SHIFT == 0) return i == 0 || k[i] != k[i - 1];
+    return i == 0 || parent_key<BATCH>(k[i]) != parent_key<BATCH>(k[i - 1]);
+  }
 };
 struct HeadOut {
   int64_t* start;
@@ -226,7 +238,7 @@ void reduce_pairs(bool key64, PairBufs p, const int64_t* n_pairs_dev, const floa
   }
   VX_TIMED("seg_reduce", s);
 #define VX_SEG(K, KD)                                                                                            \
-  hipLaunchKernelGGL((k_seg_reduce<K, KD>), dim3(kGrid), dim3(kBlock), 0, s, (const K*)p.keys, p.w, p.prim, dirs, \
+  hipLaunchKernelGGL((k_seg_reduce<K, KD>), dim3(tuned_grid(kTuneReduce)), dim3(kBlock), 0, s, (const K*)p.keys, p.w, p.prim, dirs, \
                      seg_start, ctl + CTL_N_VOX, out)
   if (key64) {
     if (kind == 0) VX_SEG(uint64_t, 0); else VX_SEG(uint64_t, 1);
@@ -253,7 +265,7 @@ struct LodTotal {
   }
 };
 
-template <class Key>
+template <class Key, bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_lod_reduce(vx_voxels in, const int64_t* __restrict__ start,
                                                        const int64_t* __restrict__ n_ptr, vx_voxels out) {
   const int64_t n = *n_ptr;
@@ -271,7 +283,7 @@ __global__ void __launch_bounds__(kBlock) k_lod_reduce(vx_voxels in, const int64
 #pragma unroll
       for (int k = 0; k < 6; ++k) S[k] += in.S[k * ci + j];
     }
-    okeys[p] = ikeys[a] >> 3;
+    okeys[p] = parent_key<BATCH>(ikeys[a]);
     out.count[p] = c;
     out.mask[p] = uint8_t(mask);
     out.w[p] = W;
@@ -292,10 +304,13 @@ void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s) {
 }
 
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
-               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s) {
+               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s, bool batch) {
   {
     VX_TIMED("lod_heads", s);
-    if (key64)
+    if (batch)
+      device_scan(HeadIn<uint64_t, 3, true>{(const uint64_t*)in.keys}, HeadOut{pstart},
+                  LodTotal{pstart, n_out, flags, out.cap}, n_in, 0, partial, s);
+    else if (key64)
       device_scan(HeadIn<uint64_t, 3>{(const uint64_t*)in.keys}, HeadOut{pstart},
                   LodTotal{pstart, n_out, flags, out.cap}, n_in, 0, partial, s);
     else
@@ -303,10 +318,13 @@ void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_vo
                   LodTotal{pstart, n_out, flags, out.cap}, n_in, 0, partial, s);
   }
   VX_TIMED("lod_reduce", s);
-  if (key64)
-    hipLaunchKernelGGL(k_lod_reduce<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, in, pstart, n_out, out);
+  const dim3 grid(tuned_grid(kTuneLod));
+  if (batch)
+    hipLaunchKernelGGL((k_lod_reduce<uint64_t, true>), grid, dim3(kBlock), 0, s, in, pstart, n_out, out);
+  else if (key64)
+    hipLaunchKernelGGL((k_lod_reduce<uint64_t, false>), grid, dim3(kBlock), 0, s, in, pstart, n_out, out);
   else
-    hipLaunchKernelGGL(k_lod_reduce<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, in, pstart, n_out, out);
+    hipLaunchKernelGGL((k_lod_reduce<uint32_t, false>), grid, dim3(kBlock), 0, s, in, pstart, n_out, out);
 }
 
 }  // namespace vx

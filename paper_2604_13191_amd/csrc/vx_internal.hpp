@@ -11,6 +11,7 @@ namespace vx {
 constexpr int kBlock = 256;          // threads per block: 4 waves of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kGrid = 1024;          // persistent grid of the streaming kernels: 4 blocks per CU
+constexpr int kPatchShift = 33;      // batched keys: patch id above a 33-bit Morton code (R <= 2048)
 
 // ---------------------------------------------------------------------------------------------
 // Kernel timing (measurement only): events around every launch when enabled.
@@ -169,6 +170,12 @@ inline void device_scan(In in, Out out, Total total, const int64_t* n_ptr, int64
 }
 
 // ---------------------------------------------------------------------------------------------
+// Launch geometry chosen by the autotuner: grid sizes of the persistent streaming kernels.
+// ---------------------------------------------------------------------------------------------
+enum { kTuneTest = 0, kTuneEmit, kTuneReduce, kTuneLod, kTuneCluster, kTuneCount };
+int tuned_grid(int which);
+
+// ---------------------------------------------------------------------------------------------
 // Workspace carving (256-byte aligned sub-buffers).
 // ---------------------------------------------------------------------------------------------
 struct Carver {
@@ -211,7 +218,7 @@ void reduce_pairs(bool key64, PairBufs p, const int64_t* n_pairs_dev, const floa
 // one LoD level: parent reduce of `in` (n_in on the device) into `out`; n_out receives the
 // new count clamped to out.cap, and flags the capacity bit when it had to be clamped
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
-               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s);
+               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s, bool batch = false);
 void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s);
 
 // lobe clustering of one level (cluster.hip): parents [0, *n_par) with children
@@ -233,9 +240,17 @@ struct FrontWs {
   int64_t* partial;
 };
 void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, FrontWs* f);
+struct Lat;
+// batched patches: per-patch lattices and point ranges (device), keys carry the patch id above
+// bit kPatchShift
+struct BatchLattice {
+  const Lat* lats;
+  const int64_t* pt_begin;   // [n_patches + 1]
+  int n_patches;
+};
 void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                     int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
-                    int64_t* stats, hipStream_t s);
+                    int64_t* stats, hipStream_t s, const BatchLattice* batch);
 
 // the differentiable two-lobe fit (fit.hip)
 size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, bool key64);
@@ -253,5 +268,8 @@ size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, b
 vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                        int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws,
                        const vx_voxels* out, int64_t* stats, hipStream_t s);
+vx_status voxelize_batch_run(const vx_grid* g0, const float* pts, int64_t n_pts, const int64_t* offsets,
+                             int64_t n_fib, int64_t max_cand, int64_t max_pairs, void* ws, const vx_voxels* out,
+                             int64_t* stats, hipStream_t s, const BatchLattice& bl, int key_bits);
 
 }  // namespace vx

@@ -16,6 +16,9 @@ Workloads (sizes and recipes are stated once here and in the design notes):
 * ``plain_weave``    -- 2,000 fibers x 257 points (256 segments), warp along x and weft
   along y, sinusoidal crimp (period 64 voxels, amplitude 4), helix twist U(-5, 5) deg,
   N(0, 0.3^2) per-point jitter, radius 0.5 voxel, bounds [0, 1024]^3 at 1024^3.
+* ``weave_patches``  -- 64 plain-weave patches of uneven size: fiber counts log-uniform in
+  [100, 20000], grids 2^(8..11), the plain-weave recipe in voxel units with R/32 yarns per
+  direction and 256 segments per fiber (a batched workload of many small and large jobs).
 * ``brushed_metal``  -- height field, two triangles per cell, ridge wavelength about 8
   cells along x and about 256 along y, amplitude 2 voxels, 4096^3 (a window of it for tests).
 """
@@ -159,6 +162,55 @@ def plain_weave(n_fibers: int = 2000, n_points: int = 257, res: int = 1024, seed
     return FiberWorkload("plain_weave", Grid((0.0, 0.0, 0.0), float(res), log2_res),
                          pts.reshape(-1, 3).astype(np.float32), offsets, radius,
                          levels if levels is not None else log2_res + 1, 1)
+
+
+def weave_fibers(rng, n_fibers: int, res: int, n_points: int = 257, pitch: float = 32.0,
+                 ellipse=(10.0, 2.5), crimp_amp: float = 4.0, twist_deg: float = 5.0,
+                 jitter: float = 0.3):
+    """The plain-weave recipe (see ``plain_weave``) drawn for all fibers at once: per-fiber
+    (r, alpha0, theta) as three vectors, then the point jitter as one [F, n_points, 3] draw.
+    Returns float64 points [F, n_points, 3]."""
+    n_yarn = max(1, int(round(res / pitch)))
+    half = n_fibers // 2
+    f = np.arange(n_fibers)
+    j = (f % n_yarn)[:, None]
+    centre = pitch / 2.0 + pitch * j
+    r = np.sqrt(rng.uniform(size=n_fibers))[:, None]
+    alpha0 = rng.uniform(0.0, 2.0 * math.pi, size=n_fibers)[:, None]
+    theta = np.radians(rng.uniform(-twist_deg, twist_deg, size=n_fibers))[:, None]
+    a_in, a_z = ellipse
+    s = (2.0 + (res - 4.0) * np.arange(n_points, dtype=np.float64) / (n_points - 1))[None, :]
+    rho = np.hypot(a_in * r * np.cos(alpha0), a_z * r * np.sin(alpha0))
+    alpha = alpha0 + s * np.tan(theta) / np.maximum(rho, 1.0)
+    off_in = a_in * r * np.cos(alpha)
+    off_z = a_z * r * np.sin(alpha)
+    phase = math.pi * (s - pitch / 2.0) / pitch + math.pi * j
+    warp = (f < half)[:, None]
+    mid = res / 2.0
+    pts = np.empty((n_fibers, n_points, 3), dtype=np.float64)
+    pts[:, :, 0] = np.where(warp, s, centre + off_in)
+    pts[:, :, 1] = np.where(warp, centre + off_in, s)
+    pts[:, :, 2] = mid + np.where(warp, 1.0, -1.0) * crimp_amp * np.cos(phase) + off_z
+    pts += rng.normal(0.0, jitter, size=pts.shape)
+    return pts
+
+
+def weave_patches(n_patches: int = 64, seed: int = 3, fibers=(100, 20000), log2_res=(8, 11),
+                  n_points: int = 257, radius: float = 0.5, K: int = 4) -> list:
+    """Uneven batch: patch p has n_p = round(exp U(ln lo, ln hi)) fibers on a 2^l grid with
+    l ~ U{log2_res[0] .. log2_res[1]}, each patch drawn with ``weave_fibers`` in its own voxel
+    units (bounds [0, R)^3), full pyramid per patch, K lobes per coarse voxel."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(n_patches):
+        n = int(round(math.exp(rng.uniform(math.log(fibers[0]), math.log(fibers[1])))))
+        l2 = int(rng.integers(log2_res[0], log2_res[1] + 1))
+        res = 1 << l2
+        pts = weave_fibers(rng, n, res, n_points=n_points)
+        offsets = np.arange(0, n * n_points + 1, n_points, dtype=np.int64)
+        out.append(FiberWorkload(f"weave_patch_{p}", Grid((0.0, 0.0, 0.0), float(res), l2),
+                                 pts.reshape(-1, 3).astype(np.float32), offsets, radius, l2 + 1, K))
+    return out
 
 
 # ----------------------------------------------------------------------------------------------

@@ -60,3 +60,40 @@ def test_argument_errors_before_any_launch(lib):
     assert f(ctypes.byref(bad), None, 0, 0, 0, None, 0, None, None, None) == 1
     good = CGrid((ctypes.c_double * 3)(0, 0, 0), 1.0, 4)
     assert f(ctypes.byref(good), None, 0, 0, 0, None, 0, None, None, None) == 1     # no outputs
+
+
+def test_batch_graph_and_grid_calls_host_side(lib):
+    ws = lib.vx_batch_workspace_size
+    ws.restype = ctypes.c_size_t
+    ws.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    assert ws(1000, 1000, 5000, 4000, 4000) > ws(1, 1000, 5000, 4000, 4000) > 0
+    assert ws(0, 1, 1, 1, 1) == 0 and ws(70000, 1, 1, 1, 1) == 0 and ws(2, 1, 1, 1 << 31, 1) == 0
+    assert ws(2, 1, 1, 1, 0) == 0
+    b = lib.vx_batch_build
+    b.restype = ctypes.c_int
+    assert b(None, None, 1, None, 0, None, 0, 1, 1, 0, 0, 0, None, None, None, None, None, None, 0, None) == 1
+    gb = lib.vx_graph_begin
+    gb.restype = ctypes.c_int
+    gb.argtypes = [ctypes.c_void_p]
+    assert gb(None) == 1                       # the null stream cannot be captured
+    gl = lib.vx_graph_launch
+    gl.restype = ctypes.c_int
+    gl.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert gl(None, None) == 1
+    lib.vx_graph_destroy.argtypes = [ctypes.c_void_p]
+    lib.vx_graph_destroy(None)
+    sg, gg = lib.vx_set_launch_grids, lib.vx_get_launch_grids
+    sg.restype = ctypes.c_int
+    arr = (ctypes.c_int32 * 5)()
+    gg(arr, 5)
+    default = list(arr)
+    assert default == [1024] * 5
+    assert sg((ctypes.c_int32 * 5)(64, 128, 256, 512, 16384), 5) == 0
+    gg(arr, 5)
+    assert list(arr) == [64, 128, 256, 512, 16384]
+    assert sg((ctypes.c_int32 * 5)(63, 128, 256, 512, 1024), 5) == 1
+    assert sg((ctypes.c_int32 * 5)(64, 128, 256, 512, 16385), 5) == 1
+    assert sg((ctypes.c_int32 * 6)(*([1024] * 6)), 6) == 1
+    gg(arr, 5)
+    assert list(arr) == [64, 128, 256, 512, 16384]      # a rejected call changes nothing
+    assert sg((ctypes.c_int32 * 5)(*default), 5) == 0
