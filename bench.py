@@ -26,20 +26,48 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_bytes(name, c):
-    """Algorithmic bytes one launch of `name` must move (counted once), from the run's counts."""
-    kb, P, Nc, Np, V, F = c["key_bytes"], c["n_pairs"], c["n_cand"], c["n_prims"], c["n_vox"], c["n_fib"]
-    chunks = (Nc + 63) // 64
+    """Algorithmic bytes one launch of `name` must move (counted once), from the run's counts:
+    P pairs, C candidates, N primitives, V leaf voxels, F fibers, T records, U units."""
+    kb, P, N, V, F = c["key_bytes"], c["n_pairs"], c["n_prims"], c["n_vox"], c["n_fib"]
+    T, U = c["n_records"], c["n_units"]
     rec = 64   # per-primitive record
     table = {
-        "prep_fib": 12 * Np + 8 * (F + 1) + rec * Np + 16 * Np + 8 * Np,
+        "prep_fib": 12 * N + 8 * (F + 1) + rec * N + 16 * N + 8 * N,
         "check_offsets": 8 * (F + 1),
-        "test_fib": rec * Np + 8 * (Np + 1) + 16 * chunks,
-        "emit_fib": 24 * chunks + rec * Np + 16 * Np + (kb + 8) * P,
-        "radix_hist": kb * P,
-        "radix_scatter": 2 * (kb + 8) * P,
-        "seg_reduce": (kb + 8) * P + 16 * P + 8 * (V + 1) + (kb + 4 + 4 + 24) * V,
+        # per unit: its records (primitive id + record), per pair the primitive's direction,
+        # per voxel the staged key, count, w and S
+        "unit_fib": 4 * T + rec * T + 16 * P + 40 * V + 32 * U,
+        "unit_compact": 2 * 40 * V + 24 * U,
+        "radix_scatter": 2 * (kb + 8) * T,
+        "radix_hist": kb * T,
     }
     return table.get(name)
+
+
+def source_digest():
+    """Digest of the HIP sources: counter figures taken from another build are not reused."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_13191_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy of known size), or None when absent or taken from
+    other sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_plain_weave.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    k = t.get("kernels", {}).get(kernel)
+    if not k or t.get("source_digest") != source_digest():
+        return None
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
 def cpu_baseline(wl, nthreads):
@@ -191,10 +219,34 @@ def main():
         plan.run()
         lod.run()
     torch.cuda.synchronize()
+    counts = {"key_bytes": 4 if wl.grid.log2_res <= 10 else 8, "n_pairs": plan.n_pairs, "n_cand": plan.n_cand,
+              "n_prims": plan.n_prims, "n_vox": leaf.n, "n_fib": plan.n_fib, "n_records": plan.n_records,
+              "n_units": plan.n_units}
 
+    # kernel breakdown: a few untimed steps with events around every launch
+    prof_steps = 5
+    vx.timing_reset()
+    vx.timing_filter(None)
+    vx.timing_enable(True)
+    for _ in range(prof_steps):
+        plan.run()
+        lod.run()
+    vx.timing_enable(False)
+    kt = vx.timing_collect()
+    kernels = {}
+    for name, (ms, n) in sorted(kt.items(), key=lambda x: -x[1][0]):
+        avg = ms / max(n, 1)
+        b = kernel_bytes(name, counts)
+        kernels[name] = {"ms_per_step": round(ms / prof_steps, 4), "launches_per_step": n // prof_steps,
+                         "avg_ms": round(avg, 4),
+                         "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b is not None and avg > 0 else None}
+    dom = next(iter(kernels))                       # largest share of the step
+
+    # timed region: K whole steps; events only around the dominant kernel's launches
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     vx.timing_reset()
+    vx.timing_filter(dom)
     vx.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -207,38 +259,62 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     vx.timing_enable(False)
-    kt = vx.timing_collect()
+    kd = vx.timing_collect()
+    vx.timing_filter(None)
     plan.check()
     lod.check()
-
     ms_step = (t1 - t0) * 1e3 / args.steps
     vox_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / args.steps
     lod_ms = sum(b.elapsed_time(c) for _, b, c in ev) / args.steps
-    counts = {"key_bytes": 4 if wl.grid.log2_res <= 10 else 8, "n_pairs": plan.n_pairs, "n_cand": plan.n_cand,
-              "n_prims": plan.n_prims, "n_vox": leaf.n, "n_fib": plan.n_fib}
-    kernels = {}
-    for name, (ms, n) in sorted(kt.items(), key=lambda x: -x[1][0]):
-        avg = ms / max(n, 1)
-        b = kernel_bytes(name, counts)
-        kernels[name] = {"ms_per_step": round(ms / args.steps, 4), "launches_per_step": n // args.steps,
-                         "avg_ms": round(avg, 4),
-                         "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b is not None and avg > 0 else None}
-    # dominant kernel with a byte model
-    dom = next(k for k in kernels if kernel_bytes(k, counts) is not None)
-    dom_avg = kernels[dom]["avg_ms"]
+    dom_ms, dom_n = kd[dom]
+    dom_avg = dom_ms / dom_n
+
+    # the same step captured once as a graph and replayed
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = vx.capture(lambda st: (plan.run(st), lod.run(st)), side)
+    for _ in range(args.warmup):
+        graph.replay()
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    side.synchronize()
+    for a, b in gev:
+        a.record(side)
+        graph.replay()
+        b.record(side)
+    side.synchronize()
+    graph_ms = sum(a.elapsed_time(b) for a, b in gev) / args.steps
+    del graph
+    plan.check()
+
+    # a plain copy of known size, for scaling the HBM byte counters of a profiler run
+    probe = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+    probe2 = torch.empty_like(probe)
+    probe2.copy_(probe)
+    torch.neg(probe.view(torch.float32), out=probe2.view(torch.float32))
+    torch.cuda.synchronize()
+    del probe, probe2
+
     dom_b = kernel_bytes(dom, counts)
-    ach = dom_b / (dom_avg * 1e-3) / 1e9
+    if dom_b is not None:
+        ach = dom_b / (dom_avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_bytes(dom),
+                "algorithmic_bytes_per_launch": dom_b, "avg_launch_ms": round(dom_avg, 5),
+                "launches_timed": dom_n}
+    else:
+        roof = {"bound": "unmodelled", "kernel": dom, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "avg_launch_ms": round(dom_avg, 5)}
     out = {
         "metric": METRIC, "value": plan.n_pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "plain_weave: 2000 fibers x 256 segments, radius 0.5 voxel, 1024^3, 11 levels, K=1",
                    "n_pairs": plan.n_pairs, "n_candidates": plan.n_cand, "n_leaf_voxels": leaf.n,
+                   "n_tile_records": plan.n_records, "n_units": plan.n_units,
                    "level_voxels": [leaf.n] + caps},
-        "voxelize_ms": vox_ms, "lod_build_ms": lod_ms,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes_per_launch": dom_b, "avg_launch_ms": dom_avg},
+        "voxelize_ms": vox_ms, "lod_build_ms": lod_ms, "graph_ms_per_step": graph_ms,
+        "graph_pairs_per_s": plan.n_pairs / (graph_ms * 1e-3),
+        "roofline": roof,
         "kernels": kernels,
     }
     if not args.no_fit:

@@ -68,9 +68,20 @@ typedef enum {
 #define VX_FLAG_VOXEL_CAPACITY 4
 #define VX_FLAG_INPUT          8
 #define VX_FLAG_OFFSETS        16
+#define VX_FLAG_RECORD_CAPACITY 32
+#define VX_FLAG_UNIT_CAPACITY  64
 
-/* indices into the int64 stats array (device) */
-enum { VX_STAT_CAND = 0, VX_STAT_PAIRS = 1, VX_STAT_VOXELS = 2, VX_STAT_FLAGS = 3, VX_NSTAT = 4 };
+/* indices into the int64 stats array (device): candidates tested, touching pairs, leaf voxels,
+ * flags, primitive-tile records, work units */
+enum {
+  VX_STAT_CAND = 0,
+  VX_STAT_PAIRS = 1,
+  VX_STAT_VOXELS = 2,
+  VX_STAT_FLAGS = 3,
+  VX_STAT_RECORDS = 4,
+  VX_STAT_UNITS = 5,
+  VX_NSTAT = 6
+};
 
 typedef struct {
   double bmin[3];
@@ -100,27 +111,31 @@ typedef struct {
 /* ------------------------------------------------------------------------------------------
  * Voxelization (Sec. 3.1-3.4).
  *
+ * The grid is cut into aligned tiles of 16^3 voxels (Sec. 3.1's blocks); every primitive is
+ * listed once per tile its candidate box (closed bounding box, dilated by the radius for
+ * fibers, clipped to the grid) overlaps, and tiles with many candidates are split into octants
+ * ("units") whose candidates fit on chip.  Capacities:
  * kind: 0 = triangles (n_prims = number of triangles), 1 = fibers (n_prims = number of points).
- * max_cand: capacity of the candidate space (sum over primitives of the voxels of their
- *   closed bounding box, dilated by the radius for fibers, clipped to the grid).
- * max_pairs: capacity for touching (primitive, voxel) pairs; at most 2^31 - 1.
+ * max_records: primitive-tile records (stats[VX_STAT_RECORDS] of a call with 0 reports it).
+ * max_units: work units (stats[VX_STAT_UNITS]).
+ * max_voxels: the leaf capacity the call will be given (out->cap <= max_voxels).
  * Returns the workspace size in bytes (0 on bad arguments).
  * ------------------------------------------------------------------------------------------ */
-size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
-                                  int32_t log2_res);
+size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_records, int64_t max_units,
+                                  int64_t max_voxels, int32_t log2_res);
 
 /* tris: float32 [n_tris][3][3] (vertex-major; a soup of non-shared vertices, Sec. 3.2).
  * out: leaf voxels (out->mask unused), sorted by key, unique keys.
  * stats: int64[VX_NSTAT] on the device, overwritten. */
 vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris,
-                                int64_t max_cand, int64_t max_pairs, void* workspace, size_t ws_bytes,
+                                int64_t max_records, int64_t max_units, void* workspace, size_t ws_bytes,
                                 const vx_voxels* out, int64_t* stats, vx_stream stream);
 
 /* pts: float32 [n_pts][3] polyline nodes (Sec. 3.1 node collections); offsets: int64
  * [n_fibers + 1] (device), offsets[0] = 0, non-decreasing, offsets[n_fibers] = n_pts.  Segment
  * (i, i+1) exists when both points belong to one fiber; radius in world units, >= 0. */
 vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
-                             int64_t n_fibers, float radius, int64_t max_cand, int64_t max_pairs,
+                             int64_t n_fibers, float radius, int64_t max_records, int64_t max_units,
                              void* workspace, size_t ws_bytes, const vx_voxels* out, int64_t* stats,
                              vx_stream stream);
 
@@ -184,8 +199,10 @@ vx_status vx_fit_forward(const vx_grid* grid, const vx_voxels* levels, const int
                          const int64_t* caps, void* workspace, size_t ws_bytes, vx_stream stream);
 
 /* dloss: device float [1] (upstream gradient); dpts: device float [n_pts][3], overwritten;
- * stats: device int64 [VX_NSTAT] for the re-emitted pairs (max_cand / max_pairs as for
- * vx_voxelize_fibers on the same fibers). */
+ * stats: device int64 [VX_NSTAT] for the re-emitted pairs.  max_cand / max_pairs: capacities
+ * of the candidate space and of the (primitive, voxel) pairs, which the backward pass lists
+ * per primitive (at least stats[VX_STAT_CAND] / stats[VX_STAT_PAIRS] of vx_voxelize_fibers on
+ * the same fibers; pairs at most 2^31 - 1). */
 vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fibers, int64_t max_cand, int64_t max_pairs,
                           const vx_voxels* levels, const int64_t* n_levels, int32_t lo, int32_t hi,
                           const float* const* params, const float* dirs, int32_t ndir, const float* dloss,
@@ -211,7 +228,7 @@ typedef struct {
   int32_t reserved;
 } vx_patch;
 
-size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_cand, int64_t max_pairs,
+size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_records, int64_t max_units,
                                int64_t leaf_cap);
 
 /* patches: host array (validated) and the same array in device memory (read by the kernels);
@@ -219,10 +236,11 @@ size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_can
  * out: host array of `levels` level descriptors, leaf first (out[0].mask may be NULL);
  * lobes: host array of levels - 1 descriptors when K > 1, else NULL;
  * n_levels: device int64 [levels + 1] (counts, then flags); patch_table: device int64
- * [levels][n_patches + 1]; stats: device int64 [VX_NSTAT] (pair and leaf totals, flags). */
+ * [levels][n_patches + 1]; stats: device int64 [VX_NSTAT] (totals and flags);
+ * max_records / max_units / out[0].cap: as for vx_voxelize_fibers, over the whole batch. */
 vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, int32_t n_patches, const float* pts,
                          int64_t n_pts, const int64_t* offsets, int64_t n_fibers, int32_t levels, int32_t K,
-                         int32_t kmeans_iters, int64_t max_cand, int64_t max_pairs, const vx_voxels* out,
+                         int32_t kmeans_iters, int64_t max_records, int64_t max_units, const vx_voxels* out,
                          const vx_lobes* lobes, int64_t* n_levels, int64_t* patch_table, int64_t* stats,
                          void* workspace, size_t ws_bytes, vx_stream stream);
 
@@ -255,6 +273,9 @@ const char* vx_status_str(vx_status s);
  * name once vx_timing_collect() (which synchronises the device) is called. */
 void vx_timing_enable(int32_t on);
 void vx_timing_reset(void);
+/* Restricts timing to launches of one kernel name (NULL or "": every launch), so that a timed
+ * region carries events only around the kernel being measured. */
+void vx_timing_filter(const char* name);
 /* Writes up to max_entries (name, total ms, launches) triples; returns the number of kernels. */
 int32_t vx_timing_collect(char names[][48], double* total_ms, int64_t* launches, int32_t max_entries);
 

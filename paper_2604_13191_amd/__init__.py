@@ -21,9 +21,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvx.so")
 
-VX_NSTAT = 4
-STAT_CAND, STAT_PAIRS, STAT_VOXELS, STAT_FLAGS = range(4)
+VX_NSTAT = 6
+STAT_CAND, STAT_PAIRS, STAT_VOXELS, STAT_FLAGS, STAT_RECORDS, STAT_UNITS = range(6)
 FLAG_CAND_CAPACITY, FLAG_PAIR_CAPACITY, FLAG_VOXEL_CAPACITY, FLAG_INPUT, FLAG_OFFSETS = 1, 2, 4, 8, 16
+FLAG_RECORD_CAPACITY, FLAG_UNIT_CAPACITY = 32, 64
 STATUS = {0: "ok", 1: "invalid argument", 2: "capacity exceeded", 3: "HIP runtime error",
           4: "non-finite or out-of-range input, or invalid fiber offsets", 5: "bad workspace"}
 
@@ -73,7 +74,7 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
     L.vx_voxelize_workspace_size.restype = sz
-    L.vx_voxelize_workspace_size.argtypes = [i32, i64, i64, i64, i32]
+    L.vx_voxelize_workspace_size.argtypes = [i32, i64, i64, i64, i64, i32]
     L.vx_voxelize_triangles.restype = ctypes.c_int
     L.vx_voxelize_triangles.argtypes = [ctypes.POINTER(CGrid), vp, i64, i64, i64, vp, sz,
                                         ctypes.POINTER(CVoxels), vp, vp]
@@ -114,6 +115,8 @@ def load():
     L.vx_set_launch_grids.argtypes = [ctypes.POINTER(i32), i32]
     L.vx_get_launch_grids.restype = None
     L.vx_get_launch_grids.argtypes = [ctypes.POINTER(i32), i32]
+    L.vx_timing_filter.argtypes = [ctypes.c_char_p]
+    L.vx_timing_filter.restype = None
     L.vx_timing_enable.argtypes = [i32]
     L.vx_timing_reset.argtypes = []
     L.vx_timing_collect.restype = i32
@@ -190,12 +193,12 @@ def alloc_voxels(cap, log2_res, device, with_mask):
 class VoxelizePlan:
     """Buffers and capacities for voxelizing one set of primitives, reusable across runs.
 
-    The capacities come from the library's own counts: a first call with zero capacities
-    reports the candidate total, a second one the pair total (both via device stats, read
-    back once here).  ``run()`` then enqueues the whole voxelize pass with no host sync.
+    The capacities come from the library's own counts: counting calls report the
+    primitive-tile records, then the work units, then the leaf voxels (device stats, read back
+    once each).  ``run()`` then enqueues the whole voxelize pass with no host sync.
     """
 
-    def __init__(self, kind, grid, data, offsets=None, radius=0.0, max_cand=None, max_pairs=None, out_cap=None):
+    def __init__(self, kind, grid, data, offsets=None, radius=0.0, max_records=None, max_units=None, out_cap=None):
         import torch
         self.L = load()
         self.kind = kind
@@ -215,55 +218,66 @@ class VoxelizePlan:
             self.n_fib = int(self.offsets.numel() - 1)
         self.radius = float(radius)
         self.stats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.device)
-        if max_cand is None or max_pairs is None:
-            mc, mp = self._count()
-            max_cand = mc if max_cand is None else max_cand
-            max_pairs = mp if max_pairs is None else max_pairs
-        self.max_cand = int(max_cand)
-        self.max_pairs = int(max_pairs)
-        nb = self.L.vx_voxelize_workspace_size(kind, self.n_prims, self.max_cand, self.max_pairs,
-                                               int(grid.log2_res))
-        if nb == 0:
-            raise VxError(1, "vx_voxelize_workspace_size")
-        self.ws = _ws(nb, self.device)
-        self.out = alloc_voxels(out_cap if out_cap is not None else self.max_pairs, grid.log2_res, self.device,
-                                False)
+        if max_records is None or max_units is None or out_cap is None:
+            r, u, v = self._count(max_records, max_units)
+            max_records = r if max_records is None else max_records
+            max_units = u if max_units is None else max_units
+            out_cap = v if out_cap is None else out_cap
+        self.max_records = int(max_records)
+        self.max_units = int(max_units)
+        self.out = alloc_voxels(max(int(out_cap), 1), grid.log2_res, self.device, False)
+        self.ws = self._ws_for(self.max_records, self.max_units, self.out.cap)
         self._cout = self.out.cstruct()
 
-    def _call(self, max_cand, max_pairs, ws, ws_bytes, cout, stream):
+    def _ws_for(self, max_records, max_units, max_voxels):
+        nb = self.L.vx_voxelize_workspace_size(self.kind, self.n_prims, max_records, max_units, max(max_voxels, 1),
+                                               int(self.grid.log2_res))
+        if nb == 0:
+            raise VxError(1, "vx_voxelize_workspace_size")
+        return _ws(nb, self.device)
+
+    def _call(self, max_records, max_units, ws, ws_bytes, cout, stream):
         if self.kind == 0:
-            st = self.L.vx_voxelize_triangles(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims, max_cand,
-                                              max_pairs, ws, ws_bytes, ctypes.byref(cout), _ptr(self.stats), stream)
+            st = self.L.vx_voxelize_triangles(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims, max_records,
+                                              max_units, ws, ws_bytes, ctypes.byref(cout), _ptr(self.stats), stream)
         else:
             st = self.L.vx_voxelize_fibers(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims,
-                                           _ptr(self.offsets), self.n_fib, self.radius, max_cand, max_pairs, ws,
+                                           _ptr(self.offsets), self.n_fib, self.radius, max_records, max_units, ws,
                                            ws_bytes, ctypes.byref(cout), _ptr(self.stats), stream)
         if st != 0:
             raise VxError(st, "voxelize")
 
-    def _count(self):
-        """Candidate and pair totals from two counting calls (zero capacities)."""
+    def _count(self, max_records=None, max_units=None):
+        """Record, unit and leaf-voxel totals from counting calls (capacities still unknown are 0)."""
         s = _stream()
         tmp_out = alloc_voxels(1, self.grid.log2_res, self.device, False)
         cout = tmp_out.cstruct()
-        for step in range(2):
-            mc = 0 if step == 0 else n_cand
-            nb = self.L.vx_voxelize_workspace_size(self.kind, self.n_prims, mc, 0, int(self.grid.log2_res))
-            ws = _ws(nb, self.device)
-            self._call(mc, 0, _ptr(ws), nb, cout, s)
-            st = self.L.vx_check_stats(_ptr(self.stats), s)
+        r = max_records
+        u = max_units
+        for step in range(3):
+            if step == 0 and r is not None:
+                continue
+            if step == 1 and u is not None:
+                continue
+            rr = 0 if r is None else r
+            uu = 0 if u is None else u
+            ws = self._ws_for(rr, uu, 1)
+            self._call(rr, uu, _ptr(ws), ws.numel(), cout, s)
+            self.L.vx_check_stats(_ptr(self.stats), s)
             h = self.stats.cpu().numpy()
             if h[STAT_FLAGS] & (FLAG_INPUT | FLAG_OFFSETS):
                 raise VxError(4, "voxelize")
             if step == 0:
-                n_cand = int(h[STAT_CAND])
+                r = int(h[STAT_RECORDS])
+            elif step == 1:
+                u = int(h[STAT_UNITS])
             else:
-                n_pairs = int(h[STAT_PAIRS])
+                v = int(h[STAT_VOXELS])
             del ws
-        return n_cand, n_pairs
+        return r, u, v
 
     def run(self, stream=None):
-        self._call(self.max_cand, self.max_pairs, _ptr(self.ws), self.ws.numel(), self._cout, _stream(stream))
+        self._call(self.max_records, self.max_units, _ptr(self.ws), self.ws.numel(), self._cout, _stream(stream))
         return self
 
     def check(self, stream=None):
@@ -274,6 +288,8 @@ class VoxelizePlan:
         self.out.n = int(h[STAT_VOXELS])
         self.n_pairs = int(h[STAT_PAIRS])
         self.n_cand = int(h[STAT_CAND])
+        self.n_records = int(h[STAT_RECORDS])
+        self.n_units = int(h[STAT_UNITS])
         return self.out
 
 
@@ -376,6 +392,11 @@ def timing_enable(on=True):
     load().vx_timing_enable(1 if on else 0)
 
 
+def timing_filter(name=None):
+    """Time only launches named `name` (None: all)."""
+    load().vx_timing_filter(name.encode() if name else None)
+
+
 def timing_reset():
     load().vx_timing_reset()
 
@@ -419,9 +440,14 @@ class FitPlan:
         self.offsets = offsets.to(device=self.pts.device, dtype=torch.int64).contiguous()
         self.radius = float(radius)
         cal = VoxelizePlan(1, grid, self.pts, offsets=self.offsets, radius=radius)
-        mc = int(cal.max_cand * slack) + 64
-        mp = int(cal.max_pairs * slack) + 64
-        self.vox = VoxelizePlan(1, grid, self.pts, offsets=self.offsets, radius=radius, max_cand=mc, max_pairs=mp)
+        cal.run()
+        cal.check()
+        mc = int(cal.n_cand * slack) + 64
+        mp = int(cal.n_pairs * slack) + 64
+        self.vox = VoxelizePlan(1, grid, self.pts, offsets=self.offsets, radius=radius,
+                                max_records=int(cal.max_records * slack) + 64,
+                                max_units=int(cal.max_units * slack) + 64, out_cap=int(cal.out.n * slack) + 64)
+        del cal
         self.vox.run()
         leaf = self.vox.check()
         lodc = LodPlan(grid, leaf, self.vox.stats[2:3], self.hi + 1).run()
@@ -669,16 +695,16 @@ class BatchPlan:
         self._plan_capacities()
 
     # -- one call of the entry point ------------------------------------------------------------
-    def _call(self, levels, K, max_cand, max_pairs, cout, clobes, ws, stream):
+    def _call(self, levels, K, max_records, max_units, cout, clobes, ws, stream):
         st = self.L.vx_batch_build(self._cp, _ptr(self.patches_dev), self.n_patches, _ptr(self.pts), self.n_pts,
-                                   _ptr(self.offsets), self.n_fib, levels, K, self.iters, max_cand, max_pairs, cout,
+                                   _ptr(self.offsets), self.n_fib, levels, K, self.iters, max_records, max_units, cout,
                                    clobes, _ptr(self.n_levels), _ptr(self.patch_table), _ptr(self.stats), _ptr(ws),
                                    ws.numel(), stream)
         if st != 0:
             raise VxError(st, "vx_batch_build")
 
-    def _ws_for(self, max_cand, max_pairs, leaf_cap):
-        nb = self.L.vx_batch_workspace_size(self.n_patches, self.n_pts, max_cand, max_pairs, leaf_cap)
+    def _ws_for(self, max_records, max_units, leaf_cap):
+        nb = self.L.vx_batch_workspace_size(self.n_patches, self.n_pts, max_records, max_units, leaf_cap)
         if nb == 0:
             raise VxError(1, "vx_batch_workspace_size")
         return _ws(nb, self.device)
@@ -697,13 +723,13 @@ class BatchPlan:
         c1 = (CVoxels * 1)(one.cstruct())
         ws = self._ws_for(0, 0, 1)
         self._call(1, 1, 0, 0, c1, None, ws, s)
-        n_cand = int(self._stats(s)[STAT_CAND])
-        ws = self._ws_for(n_cand, 0, 1)
-        self._call(1, 1, n_cand, 0, c1, None, ws, s)
-        n_pairs = int(self._stats(s)[STAT_PAIRS])
+        n_rec = int(self._stats(s)[STAT_RECORDS])
+        ws = self._ws_for(n_rec, 0, 1)
+        self._call(1, 1, n_rec, 0, c1, None, ws, s)
+        n_units = int(self._stats(s)[STAT_UNITS])
         del ws
-        ws = self._ws_for(n_cand, n_pairs, 1)
-        self._call(1, 1, n_cand, n_pairs, c1, None, ws, s)
+        ws = self._ws_for(n_rec, n_units, 1)
+        self._call(1, 1, n_rec, n_units, c1, None, ws, s)
         n_leaf = max(1, int(self._stats(s)[STAT_VOXELS]))
         del ws
         # per-level counts: K = 1, two level buffers of the leaf's size used in turn
@@ -711,13 +737,13 @@ class BatchPlan:
         ping = [alloc_voxels(n_leaf, 11, self.device, True) for _ in range(min(2, self.levels - 1))]
         cl = [leaf] + [ping[(L - 1) % 2] for L in range(1, self.levels)]
         cout = (CVoxels * self.levels)(*[v.cstruct() for v in cl])
-        ws = self._ws_for(n_cand, n_pairs, n_leaf)
-        self._call(self.levels, 1, n_cand, n_pairs, cout, None, ws, s)
+        ws = self._ws_for(n_rec, n_units, n_leaf)
+        self._call(self.levels, 1, n_rec, n_units, cout, None, ws, s)
         self._stats(s)
         torch.cuda.synchronize()
         counts = [int(x) for x in self.n_levels[:self.levels].cpu()]
-        del leaf, ping, cl, cout
-        self.max_cand, self.max_pairs, self.counts = n_cand, n_pairs, counts
+        del leaf, ping, cl, cout, ws
+        self.max_records, self.max_units, self.counts = n_rec, n_units, counts
         self.out = [alloc_voxels(max(c, 1), 11, self.device, L > 0) for L, c in enumerate(counts)]
         self._cout = (CVoxels * self.levels)(*[v.cstruct() for v in self.out])
         self.lobes, self._clobes = [], None
@@ -727,11 +753,11 @@ class BatchPlan:
                                 torch.empty((6, self.K, v.cap), dtype=torch.float32, device=self.device))
                           for v in self.out[1:]]
             self._clobes = (CLobes * len(self.lobes))(*[lb.cstruct() for lb in self.lobes])
-        self.ws = self._ws_for(n_cand, n_pairs, self.out[0].cap)
+        self.ws = self._ws_for(n_rec, n_units, self.out[0].cap)
 
     # -- hot path -------------------------------------------------------------------------------
     def run(self, stream=None):
-        self._call(self.levels, self.K, self.max_cand, self.max_pairs, self._cout, self._clobes, self.ws,
+        self._call(self.levels, self.K, self.max_records, self.max_units, self._cout, self._clobes, self.ws,
                    _stream(stream))
         return self
 

@@ -27,6 +27,7 @@ struct Acc {
 };
 std::mutex g_mu;
 bool g_on = false;
+std::string g_filter;            // time only launches of this name (empty: all)
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::vector<Acc> g_acc;
@@ -47,6 +48,10 @@ hipEvent_t get_event() {
 void timing_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
+  if (!g_filter.empty() && g_filter != name) {
+    g_open.push_back(SIZE_MAX);
+    return;
+  }
   Pending p{name, get_event(), get_event()};
   (void)hipEventRecord(p.a, s);
   g_pending.push_back(p);
@@ -58,6 +63,7 @@ void timing_end(hipStream_t s) {
   if (!g_on || g_open.empty()) return;
   size_t i = g_open.back();
   g_open.pop_back();
+  if (i == SIZE_MAX) return;
   (void)hipEventRecord(g_pending[i].b, s);
 }
 
@@ -120,24 +126,25 @@ bool ws_ok(void* ws, size_t have, size_t need) {
 }
 
 constexpr int64_t kMaxPairs = 0x7fffffff;
+constexpr int64_t kMaxPrims = 0xffffffffll;   // primitive ids are 32-bit
 
 }  // namespace
 
 extern "C" {
 
-size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
-                                  int32_t log2_res) {
-  if ((kind != 0 && kind != 1) || n_prims < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs ||
-      log2_res < 1 || log2_res > 20)
+size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_records, int64_t max_units,
+                                  int64_t max_voxels, int32_t log2_res) {
+  if ((kind != 0 && kind != 1) || n_prims < 0 || n_prims > kMaxPrims || max_records < 0 || max_units < 0 ||
+      max_voxels < 1 || log2_res < 1 || log2_res > 20)
     return 0;
-  return voxelize_ws_bytes(n_prims, max_cand, max_pairs, log2_res > 10);
+  return tile_ws_bytes(n_prims, max_records, max_units, max_voxels, log2_res > 10);
 }
 
 static vx_status voxelize_common(int kind, const vx_grid* grid, const float* data, int64_t n_prims,
-                                 const int64_t* offsets, int64_t n_fib, float radius, int64_t max_cand,
-                                 int64_t max_pairs, void* ws, size_t ws_bytes, const vx_voxels* out,
+                                 const int64_t* offsets, int64_t n_fib, float radius, int64_t max_records,
+                                 int64_t max_units, void* ws, size_t ws_bytes, const vx_voxels* out,
                                  int64_t* stats, vx_stream stream) {
-  if (!grid_ok(grid) || n_prims < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs || !stats ||
+  if (!grid_ok(grid) || n_prims < 0 || n_prims > kMaxPrims || max_records < 0 || max_units < 0 || !stats ||
       !voxels_ok(out, false) || (n_prims > 0 && !data))
     return VX_ERR_ARG;
   if (kind == 1) {
@@ -146,23 +153,24 @@ static vx_status voxelize_common(int kind, const vx_grid* grid, const float* dat
     const double rho = std::rint(double(radius) * (std::ldexp(1.0, 23) / grid->extent));
     if (rho > 8388608.0) return VX_ERR_ARG;
   }
-  if (!ws_ok(ws, ws_bytes, voxelize_ws_bytes(n_prims, max_cand, max_pairs, grid->log2_res > 10)))
+  if (!ws_ok(ws, ws_bytes, tile_ws_bytes(n_prims, max_records, max_units, out->cap, grid->log2_res > 10)))
     return VX_ERR_WORKSPACE;
-  return voxelize_run(kind, grid, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, ws, out, stats,
-                      reinterpret_cast<hipStream_t>(stream));
+  const int tb = std::min(kTileBits, int(grid->log2_res));
+  return tile_voxelize(kind, grid, data, n_prims, offsets, n_fib, radius, max_records, max_units, ws, out, stats,
+                       reinterpret_cast<hipStream_t>(stream), nullptr, tb);
 }
 
-vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, int64_t max_cand,
-                                int64_t max_pairs, void* ws, size_t ws_bytes, const vx_voxels* out,
+vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, int64_t max_records,
+                                int64_t max_units, void* ws, size_t ws_bytes, const vx_voxels* out,
                                 int64_t* stats, vx_stream stream) {
-  return voxelize_common(0, grid, tris, n_tris, nullptr, 0, 0.0f, max_cand, max_pairs, ws, ws_bytes, out, stats,
+  return voxelize_common(0, grid, tris, n_tris, nullptr, 0, 0.0f, max_records, max_units, ws, ws_bytes, out, stats,
                          stream);
 }
 
 vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
-                             int64_t n_fibers, float radius, int64_t max_cand, int64_t max_pairs, void* ws,
+                             int64_t n_fibers, float radius, int64_t max_records, int64_t max_units, void* ws,
                              size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream) {
-  return voxelize_common(1, grid, pts, n_pts, offsets, n_fibers, radius, max_cand, max_pairs, ws, ws_bytes, out,
+  return voxelize_common(1, grid, pts, n_pts, offsets, n_fibers, radius, max_records, max_units, ws, ws_bytes, out,
                          stats, stream);
 }
 
@@ -262,30 +270,30 @@ vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fib, int64_t max
                           reinterpret_cast<hipStream_t>(stream));
 }
 
-size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_cand, int64_t max_pairs,
+size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_records, int64_t max_units,
                                int64_t leaf_cap) {
-  if (n_patches < 1 || n_patches > 65536 || n_pts < 0 || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs ||
+  if (n_patches < 1 || n_patches > 65536 || n_pts < 0 || n_pts > kMaxPrims || max_records < 0 || max_units < 0 ||
       leaf_cap < 1)
     return 0;
-  // batch tables + the voxelize workspace with 64-bit keys + the pyramid's parent starts
+  // batch tables + the tile workspace with 64-bit keys + the pyramid's parent starts
   Carver cv(nullptr);
   cv.take<Lat>(n_patches);
   cv.take<int64_t>(n_patches + 1);
   cv.take<int64_t>(leaf_cap + 1);
   cv.take<int64_t>(kGrid + 1);
-  return cv.off + voxelize_ws_bytes(n_pts, max_cand, max_pairs, true) + 512;
+  return cv.off + tile_ws_bytes(n_pts, max_records, max_units, leaf_cap, true) + 512;
 }
 
 vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, int32_t n_patches, const float* pts,
                          int64_t n_pts, const int64_t* offsets, int64_t n_fibers, int32_t levels, int32_t K,
-                         int32_t kmeans_iters, int64_t max_cand, int64_t max_pairs, const vx_voxels* out,
+                         int32_t kmeans_iters, int64_t max_records, int64_t max_units, const vx_voxels* out,
                          const vx_lobes* lobes, int64_t* n_levels, int64_t* patch_table, int64_t* stats, void* ws,
                          size_t ws_bytes, vx_stream stream) {
-  if (!patches || !patches_dev || n_patches < 1 || n_patches > 65536 || n_pts < 0 || !offsets || n_fibers < 0 ||
-      (n_pts > 0 && (!pts || n_fibers < 1)) || levels < 1 || K < 1 || K > 8 || kmeans_iters < 0 || max_cand < 0 ||
-      max_pairs < 0 || max_pairs > kMaxPairs || !out || !n_levels || !patch_table || !stats)
+  if (!patches || !patches_dev || n_patches < 1 || n_patches > 65536 || n_pts < 0 || n_pts > kMaxPrims || !offsets ||
+      n_fibers < 0 || (n_pts > 0 && (!pts || n_fibers < 1)) || levels < 1 || K < 1 || K > 8 || kmeans_iters < 0 ||
+      max_records < 0 || max_units < 0 || !out || !n_levels || !patch_table || !stats)
     return VX_ERR_ARG;
-  int max_levels = 0;
+  int max_levels = 0, min_log2 = 64;
   for (int p = 0; p < n_patches; ++p) {
     const vx_patch& P = patches[p];
     if (!grid_ok(&P.grid) || P.grid.log2_res > 11) return VX_ERR_ARG;
@@ -293,6 +301,7 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
     if (std::rint(double(P.radius) * (std::ldexp(1.0, 23) / P.grid.extent)) > 8388608.0) return VX_ERR_ARG;
     if (P.pt_begin != (p == 0 ? 0 : patches[p - 1].pt_end) || P.pt_end < P.pt_begin) return VX_ERR_ARG;
     max_levels = std::max(max_levels, P.grid.log2_res + 1);
+    min_log2 = std::min(min_log2, int(P.grid.log2_res));
   }
   if (patches[n_patches - 1].pt_end != n_pts || levels > max_levels) return VX_ERR_ARG;
   if (!voxels_ok(&out[0], false)) return VX_ERR_ARG;
@@ -302,7 +311,7 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
       return VX_ERR_ARG;
   }
   const int64_t leaf_cap = out[0].cap;
-  if (!ws_ok(ws, ws_bytes, vx_batch_workspace_size(n_patches, n_pts, max_cand, max_pairs, leaf_cap)))
+  if (!ws_ok(ws, ws_bytes, vx_batch_workspace_size(n_patches, n_pts, max_records, max_units, leaf_cap)))
     return VX_ERR_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Carver cv(ws);
@@ -314,10 +323,8 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
   hipLaunchKernelGGL(k_batch_setup, dim3((n_patches + 255) / 256), dim3(256), 0, s, patches_dev, n_patches, lats,
                      pt_begin);
   BatchLattice bl{lats, pt_begin, n_patches};
-  int patch_bits = 1;
-  while ((1 << patch_bits) < n_patches) ++patch_bits;
-  vx_status st = voxelize_batch_run(&patches[0].grid, pts, n_pts, offsets, n_fibers, max_cand, max_pairs, vws,
-                                    &out[0], stats, s, bl, kPatchShift + patch_bits);
+  vx_status st = tile_voxelize(1, &patches[0].grid, pts, n_pts, offsets, n_fibers, 0.0f, max_records, max_units, vws,
+                               &out[0], stats, s, &bl, std::min(kTileBits, min_log2));
   if (st != VX_OK) return st;
   // the pyramid, with the patch-preserving parent
   launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
@@ -393,7 +400,9 @@ vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {
   if (hipMemcpy(h, stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) return VX_ERR_HIP;
   const int64_t f = h[VX_STAT_FLAGS];
   if (f & (VX_FLAG_INPUT | VX_FLAG_OFFSETS)) return VX_ERR_INPUT;
-  if (f & (VX_FLAG_CAND_CAPACITY | VX_FLAG_PAIR_CAPACITY | VX_FLAG_VOXEL_CAPACITY)) return VX_ERR_CAPACITY;
+  if (f & (VX_FLAG_CAND_CAPACITY | VX_FLAG_PAIR_CAPACITY | VX_FLAG_VOXEL_CAPACITY | VX_FLAG_RECORD_CAPACITY |
+           VX_FLAG_UNIT_CAPACITY))
+    return VX_ERR_CAPACITY;
   return VX_OK;
 }
 
@@ -412,6 +421,11 @@ const char* vx_status_str(vx_status s) {
 void vx_timing_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_on = on != 0;
+}
+
+void vx_timing_filter(const char* name) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_filter = name ? name : "";
 }
 
 void vx_timing_reset(void) {

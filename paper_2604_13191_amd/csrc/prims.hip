@@ -91,25 +91,52 @@ __global__ void k_check_offsets(const int64_t* __restrict__ offsets, int64_t n_f
 // ---------------------------------------------------------------------------------------------
 // test: one wave per 64 candidates
 // ---------------------------------------------------------------------------------------------
+// chunk_prim[ch]: the primitive holding candidate 64 ch, one bisection per chunk (independent
+// threads, so the dependent loads of many chunks overlap)
+__global__ void __launch_bounds__(kBlock) k_chunk_start(const int64_t* __restrict__ cand_off, int64_t n_prims,
+                                                        const int64_t* __restrict__ ctl,
+                                                        int64_t* __restrict__ chunk_prim) {
+  const int64_t n_chunks = ctl[CTL_N_CHUNKS];
+  for (int64_t ch = int64_t(blockIdx.x) * kBlock + threadIdx.x; ch < n_chunks; ch += int64_t(gridDim.x) * kBlock)
+    chunk_prim[ch] = find_prim_bisect(cand_off, n_prims, ch * 64);
+}
+
+// Primitive of candidate ci for every lane of a wave whose chunk starts in primitive p0 (all 64
+// lanes call it): the starts of the next 64 primitives are loaded once, coalesced, and each lane
+// counts those at or below its candidate with a 6-step search across lanes; a lane past all of
+// them (more than 63 primitives begin inside the chunk) continues by galloping.
+__device__ __forceinline__ int64_t wave_find_prim(const int64_t* __restrict__ cand_off, int64_t p0, int64_t n_prims,
+                                                  int64_t ci) {
+  const int64_t j = p0 + 1 + lane_id();
+  const int64_t b = j < n_prims ? cand_off[j] : INT64_MAX;
+  int k = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1) {
+    const int64_t bk = __shfl(b, k + step - 1, 64);
+    if (bk <= ci) k += step;
+  }
+  const int64_t b63 = __shfl(b, 63, 64);
+  if (k == 63 && b63 <= ci) return find_prim(cand_off, p0 + 64, n_prims, ci);
+  return p0 + k;
+}
+
+// ---------------------------------------------------------------------------------------------
+// test: one wave per 64 candidates
+// ---------------------------------------------------------------------------------------------
 template <int KIND>
 __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec, const int64_t* __restrict__ cand_off,
                                                  int64_t n_prims, const int64_t* __restrict__ ctl, Lat L,
                                                  const Lat* __restrict__ lats, uint64_t* __restrict__ masks,
-                                                 int64_t* __restrict__ chunk_prim) {
+                                                 const int64_t* __restrict__ chunk_prim) {
   const int64_t n_cand = ctl[CTL_N_CAND];
   const int64_t n_chunks = ctl[CTL_N_CHUNKS];
-  const int lane = lane_id();
   const int64_t w0 = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
   const int64_t ws = int64_t(gridDim.x) * kWaves;
   for (int64_t ch = w0; ch < n_chunks; ch += ws) {
-    const int64_t c0 = ch * 64;
-    int64_t p0 = 0;
-    if (lane == 0) p0 = find_prim_bisect(cand_off, n_prims, c0);
-    p0 = __shfl(p0, 0, 64);
-    const int64_t ci = c0 + lane;
+    const int64_t ci = ch * 64 + lane_id();
+    const int64_t p = wave_find_prim(cand_off, chunk_prim[ch], n_prims, ci);
     bool hit = false;
     if (ci < n_cand) {
-      const int64_t p = find_prim(cand_off, p0, n_prims, ci);
       const int32_t* r = rec + p * kRec;
       int64_t v[3];
       candidate_voxel(r, ci - cand_off[p], v);
@@ -118,10 +145,7 @@ __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec
       else hit = cap_touch(r, v, Lp.s, Lp.Sb, Lp.rho);
     }
     const uint64_t m = __ballot(hit);
-    if (lane == 0) {
-      masks[ch] = m;
-      chunk_prim[ch] = p0;
-    }
+    if (lane_id() == 0) masks[ch] = m;
   }
 }
 
@@ -144,10 +168,11 @@ __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec
   const uint64_t lt = (uint64_t(1) << lane) - 1;
   for (int64_t ch = w0; ch < n_chunks; ch += ws) {
     const uint64_t m = masks[ch];
+    if (m == 0) continue;
+    const int64_t ci = ch * 64 + lane;
+    const int64_t p = wave_find_prim(cand_off, chunk_prim[ch], n_prims, ci);
     if (!((m >> lane) & 1)) continue;
     const int64_t pos = wave_off[ch] + __popcll(m & lt);
-    const int64_t ci = ch * 64 + lane;
-    const int64_t p = find_prim(cand_off, chunk_prim[ch], n_prims, ci);
     const int32_t* r = rec + p * kRec;
     int64_t v[3];
     candidate_voxel(r, ci - cand_off[p], v);
@@ -244,39 +269,10 @@ void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_p
   if (f) *f = x;
 }
 
-struct VoxWs {
-  FrontWs f;
-  PairBufs pb;
-  int32_t* hist;
-  int64_t* seg_start;
-};
-
-static size_t voxelize_ws_layout(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, void* base,
-                                 VoxWs* w) {
-  Carver cv(base);
-  VoxWs x;
-  front_ws_carve(cv, n_prims, max_cand, max_pairs, key64, &x.f);
-  x.pb.keys = cv.take<uint8_t>(max_pairs * (key64 ? 8 : 4));
-  x.pb.w = cv.take<float>(max_pairs);
-  x.pb.prim = cv.take<uint32_t>(max_pairs);
-  x.hist = cv.take<int32_t>(int64_t(256) * kGrid);
-  x.seg_start = cv.take<int64_t>(max_pairs + 1);
-  if (w) *w = x;
-  return cv.off + 256;
-}
-
-size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64) {
-  return voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, nullptr, nullptr);
-}
-
-
-// prep -> candidate scan -> exact test -> pair scan -> emit: pairs in emission order in f.pa
-void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
-                    int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
-                    int64_t* stats, hipStream_t s, const BatchLattice* batch) {
-  const bool key64 = batch || g->log2_res > 10;
+void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                int64_t n_fib, float radius, const FrontWs& w, int64_t* stats, hipStream_t s,
+                const BatchLattice* batch) {
   const Lat L = make_lat(g, kind, radius);
-  const Lat* lats = batch ? batch->lats : nullptr;
   launch_fill_i64(stats, VX_NSTAT, 0, s);
   launch_fill_i64(w.ctl, CTL_SIZE, 0, s);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
@@ -298,10 +294,24 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
       hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, L, w.rec,
                          w.dirs, w.cand_cnt, stats);
   }
+}
+
+// prep -> candidate scan -> exact test -> pair scan -> emit: pairs in emission order in f.pa
+void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                    int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
+                    int64_t* stats, hipStream_t s, const BatchLattice* batch) {
+  const bool key64 = batch || g->log2_res > 10;
+  const Lat L = make_lat(g, kind, radius);
+  const Lat* lats = batch ? batch->lats : nullptr;
+  prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, w, stats, s, batch);
   {
     VX_TIMED("scan_cand", s);
     device_scan(ArrIn{w.cand_cnt}, ArrOut{w.cand_off}, CandTotal{w.cand_off, w.ctl, stats, max_cand}, nullptr,
                 n_prims, w.partial, s);
+  }
+  {
+    VX_TIMED("chunk_start", s);
+    hipLaunchKernelGGL(k_chunk_start, dim3(kGrid), dim3(kBlock), 0, s, w.cand_off, n_prims, w.ctl, w.chunk_prim);
   }
   {
     VX_TIMED(kind == 0 ? "test_tri" : "test_fib", s);
@@ -340,35 +350,6 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
     if (key64) VX_EMIT(1, uint64_t); else VX_EMIT(1, uint32_t);
   }
 #undef VX_EMIT
-}
-
-vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
-                       int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws_ptr,
-                       const vx_voxels* out, int64_t* stats, hipStream_t s) {
-  const bool key64 = g->log2_res > 10;
-  VoxWs w;
-  voxelize_ws_layout(n_prims, max_cand, max_pairs, key64, ws_ptr, &w);
-  voxelize_front(kind, g, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s, nullptr);
-  const int key_bits = 3 * g->log2_res;
-  const int res = radix_sort_pairs(key64, key_bits, w.f.pa, w.pb, w.f.ctl + CTL_N_PAIRS, max_pairs, w.hist,
-                                   w.f.partial, s);
-  reduce_pairs(key64, res ? w.pb : w.f.pa, w.f.ctl + CTL_N_PAIRS, w.f.dirs, kind, w.seg_start, w.f.partial, w.f.ctl,
-               stats, *out, s);
-  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
-}
-
-// batched fiber patches: 64-bit keys (patch << 33 | Morton), each primitive on its patch's lattice
-vx_status voxelize_batch_run(const vx_grid* g0, const float* pts, int64_t n_pts, const int64_t* offsets,
-                             int64_t n_fib, int64_t max_cand, int64_t max_pairs, void* ws_ptr, const vx_voxels* out,
-                             int64_t* stats, hipStream_t s, const BatchLattice& bl, int key_bits) {
-  VoxWs w;
-  voxelize_ws_layout(n_pts, max_cand, max_pairs, true, ws_ptr, &w);
-  voxelize_front(1, g0, pts, n_pts, offsets, n_fib, 0.0f, max_cand, max_pairs, w.f, stats, s, &bl);
-  const int res = radix_sort_pairs(true, key_bits, w.f.pa, w.pb, w.f.ctl + CTL_N_PAIRS, max_pairs, w.hist,
-                                   w.f.partial, s);
-  reduce_pairs(true, res ? w.pb : w.f.pa, w.f.ctl + CTL_N_PAIRS, w.f.dirs, 1, w.seg_start, w.f.partial, w.f.ctl,
-               stats, *out, s);
-  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
 
 }  // namespace vx

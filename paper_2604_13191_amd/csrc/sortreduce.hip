@@ -1,10 +1,8 @@
-// sortreduce.hip -- ordering the (key, weight, primitive) pairs and aggregating them.
+// sortreduce.hip -- ordering keyed records and the parent levels of the pyramid.
 //   radix sort  : Sec. 3.3 orders the samples by voxel id so that each voxel's samples are
 //                 contiguous; here a stable LSD radix sort (8-bit digits) with wave-level
-//                 ranking in LDS, fixed grid, no atomics on global memory.
-//   reduce      : Sec. 3.3 finds the positions where the id changes (head flags, scanned into
-//                 segment starts); Sec. 3.4 / Sec. 4.1 aggregate each voxel's orientation data
-//                 into one SGGX matrix -- here the weighted second moment S = sum w M.
+//                 ranking in LDS, fixed grid, no atomics on global memory -- applied to the
+//                 primitive-tile records, which group the work by tile.
 //   LoD level   : Sec. 4.3 aggregates 2x2x2 children into a coarser voxel; children of a parent
 //                 are contiguous in Morton order, so this is a segmented sum over key >> 3.
 #include "vx_internal.hpp"
@@ -138,117 +136,6 @@ int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int
 }
 
 // ---------------------------------------------------------------------------------------------
-// segmented reduce: leaf voxels
-// ---------------------------------------------------------------------------------------------
-// parent key: the Morton code shifted by one level; batched keys keep their patch id above
-// bit kPatchShift
-template <bool BATCH, class Key>
-__device__ __forceinline__ Key parent_key(Key k) {
-  if (!BATCH) return k >> 3;
-  const Key lowmask = (Key(1) << kPatchShift) - 1;
-  return (k & ~lowmask) | ((k & lowmask) >> 3);
-}
-
-template <class Key, int SHIFT, bool BATCH = false>
-struct HeadIn {
-  const Key* k;
-  __device__ int64_t operator()(int64_t i) const {
-    if (SHIFT == 0) return i == 0 || k[i] != k[i - 1];
-    return i == 0 || parent_key<BATCH>(k[i]) != parent_key<BATCH>(k[i - 1]);
-  }
-};
-struct HeadOut {
-  int64_t* start;
-  __device__ void operator()(int64_t i, int64_t ex, int64_t v) const {
-    if (v) start[ex] = i;
-  }
-};
-struct SegTotal {
-  int64_t* start;
-  int64_t* ctl;
-  int64_t* stats;
-  int64_t cap;
-  __device__ void operator()(int64_t total, int64_t n) const {
-    start[total] = n;
-    stats[VX_STAT_VOXELS] = total;
-    const bool over = total > cap;
-    if (over) flag_or_s(stats + VX_STAT_FLAGS, VX_FLAG_VOXEL_CAPACITY);
-    ctl[CTL_N_VOX] = over ? 0 : total;
-  }
-};
-
-// one thread per voxel; the voxel's pairs are summed in sorted (stable, emission) order
-template <class Key, int KIND>
-__global__ void __launch_bounds__(kBlock) k_seg_reduce(const Key* __restrict__ keys, const float* __restrict__ wts,
-                                                       const uint32_t* __restrict__ prim,
-                                                       const float4* __restrict__ dirs,
-                                                       const int64_t* __restrict__ start,
-                                                       const int64_t* __restrict__ n_ptr, vx_voxels out) {
-  const int64_t n = *n_ptr;
-  const int64_t cap = out.cap;
-  Key* okeys = reinterpret_cast<Key*>(out.keys);
-  for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n; v += int64_t(gridDim.x) * kBlock) {
-    const int64_t a = start[v], b = start[v + 1];
-    float W = 0.f, Sxx = 0.f, Syy = 0.f, Szz = 0.f, Sxy = 0.f, Sxz = 0.f, Syz = 0.f;
-    for (int64_t j = a; j < b; ++j) {
-      const float wj = wts[j];
-      const float4 t = dirs[prim[j]];
-      W += wj;
-      if (KIND == 0) {          // surface: n n^T
-        const float ax = wj * t.x, ay = wj * t.y;
-        Sxx = fmaf(ax, t.x, Sxx);
-        Syy = fmaf(ay, t.y, Syy);
-        Szz = fmaf(wj * t.z, t.z, Szz);
-        Sxy = fmaf(ax, t.y, Sxy);
-        Sxz = fmaf(ax, t.z, Sxz);
-        Syz = fmaf(ay, t.z, Syz);
-      } else {                  // fiber: I - t t^T
-        const float ax = wj * t.x, ay = wj * t.y;
-        Sxx += wj - ax * t.x;
-        Syy += wj - ay * t.y;
-        Szz += wj - wj * t.z * t.z;
-        Sxy = fmaf(-ax, t.y, Sxy);
-        Sxz = fmaf(-ax, t.z, Sxz);
-        Syz = fmaf(-ay, t.z, Syz);
-      }
-    }
-    okeys[v] = keys[a];
-    out.count[v] = uint32_t(b - a);
-    out.w[v] = W;
-    out.S[v] = Sxx;
-    out.S[cap + v] = Syy;
-    out.S[2 * cap + v] = Szz;
-    out.S[3 * cap + v] = Sxy;
-    out.S[4 * cap + v] = Sxz;
-    out.S[5 * cap + v] = Syz;
-  }
-}
-
-void reduce_pairs(bool key64, PairBufs p, const int64_t* n_pairs_dev, const float4* dirs, int kind,
-                  int64_t* seg_start, int64_t* partial, int64_t* ctl, int64_t* stats, const vx_voxels& out,
-                  hipStream_t s) {
-  {
-    VX_TIMED("seg_heads", s);
-    if (key64)
-      device_scan(HeadIn<uint64_t, 0>{(const uint64_t*)p.keys}, HeadOut{seg_start},
-                  SegTotal{seg_start, ctl, stats, out.cap}, n_pairs_dev, 0, partial, s);
-    else
-      device_scan(HeadIn<uint32_t, 0>{(const uint32_t*)p.keys}, HeadOut{seg_start},
-                  SegTotal{seg_start, ctl, stats, out.cap}, n_pairs_dev, 0, partial, s);
-  }
-  VX_TIMED("seg_reduce", s);
-#define VX_SEG(K, KD)                                                                                            \
-  hipLaunchKernelGGL((k_seg_reduce<K, KD>), dim3(tuned_grid(kTuneReduce)), dim3(kBlock), 0, s, (const K*)p.keys, p.w, p.prim, dirs, \
-                     seg_start, ctl + CTL_N_VOX, out)
-  if (key64) {
-    if (kind == 0) VX_SEG(uint64_t, 0); else VX_SEG(uint64_t, 1);
-  } else {
-    if (kind == 0) VX_SEG(uint32_t, 0); else VX_SEG(uint32_t, 1);
-  }
-#undef VX_SEG
-}
-
-// ---------------------------------------------------------------------------------------------
 // LoD: parent = sum of its (<= 8, contiguous) children
 // ---------------------------------------------------------------------------------------------
 struct LodTotal {
@@ -283,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) k_lod_reduce(vx_voxels in, const int64
 #pragma unroll
       for (int k = 0; k < 6; ++k) S[k] += in.S[k * ci + j];
     }
-    okeys[p] = parent_key<BATCH>(ikeys[a]);
+    okeys[p] = parent_key<Key, BATCH>(ikeys[a]);
     out.count[p] = c;
     out.mask[p] = uint8_t(mask);
     out.w[p] = W;

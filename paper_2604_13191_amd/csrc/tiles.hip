@@ -1,0 +1,743 @@
+// tiles.hip -- the leaf pass by spatial tiles (Sec. 3.2-3.4 on a tiled grid).
+//
+// Space is cut into aligned tiles of 2^tb voxels per axis (tb = 4: 16^3 voxels, one Morton
+// range each).  Every primitive is listed once per tile its candidate box overlaps; the list is
+// sorted by tile (a small radix sort over primitive-tile records, not over pairs).  Tiles whose
+// candidate count exceeds what a work unit holds are split into octants, recursively, down to
+// single voxels.  One block then takes a unit: it tests the unit's candidates, keeps the
+// surviving (voxel, weight, primitive) triples in LDS, groups them by voxel and sums every
+// voxel's pairs in primitive order -- the order of the pair list of the global path, so the
+// sums are bit-identical -- and writes the unit's voxels.  No pair list goes through HBM.
+#include "geom.hpp"
+#include "vx_internal.hpp"
+
+namespace vx {
+
+namespace {
+
+__device__ __forceinline__ void flag_set(int64_t* stats, int64_t bit) {
+  atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)bit);
+}
+
+// inverse of the Morton spread: every third bit of x, from bit 0
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x | (x >> 16)) & 0x1f00000000ffffull;
+  x = (x | (x >> 32)) & 0x1fffffull;
+  return uint32_t(x);
+}
+
+// a block-wide sum (all threads get it); tmp: kWaves + 1 entries
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T* tmp) {
+  T tot;
+  (void)block_exclusive_scan(v, tmp, tot);
+  return tot;
+}
+
+// candidates of primitive record r inside the box [o, o + size)^3: per-axis first voxel and extent
+__device__ __forceinline__ int64_t clip_box(const int32_t* r, const int32_t o[3], int32_t size, int32_t lo[3],
+                                            int32_t n[3]) {
+  int64_t c = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int32_t l = r[9 + a] > o[a] ? r[9 + a] : o[a];
+    const int32_t h0 = r[9 + a] + r[12 + a] - 1, h1 = o[a] + size - 1;
+    const int32_t h = h0 < h1 ? h0 : h1;
+    lo[a] = l;
+    n[a] = h >= l ? h - l + 1 : 0;
+    c *= n[a];
+  }
+  return c;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// primitive-tile records
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_rec_count(const int32_t* __restrict__ rec,
+                                                      const int64_t* __restrict__ cand_cnt, int64_t n_prims, int tb,
+                                                      int64_t* __restrict__ rcnt) {
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n_prims; p += int64_t(gridDim.x) * kBlock) {
+    int64_t c = 0;
+    if (cand_cnt[p] > 0) {
+      const int32_t* r = rec + p * kRec;
+      c = 1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c *= int64_t(((r[9 + a] + r[12 + a] - 1) >> tb) - (r[9 + a] >> tb) + 1);
+    }
+    rcnt[p] = c;
+  }
+}
+
+struct RecTotal {
+  int64_t* off;
+  int64_t* ctl;
+  int64_t* stats;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    off[n] = total;
+    stats[VX_STAT_RECORDS] = total;
+    const bool over = total > cap;
+    if (over) flag_set(stats, VX_FLAG_RECORD_CAPACITY);
+    ctl[CTL_N_REC] = over ? 0 : total;
+  }
+};
+
+// record (tile key, primitive) for every tile a primitive's candidate box overlaps; the tile key
+// is the Morton code of the tile coordinates (batched: with the patch id above it)
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_rec_emit(const int32_t* __restrict__ rec,
+                                                     const int64_t* __restrict__ cand_cnt,
+                                                     const int64_t* __restrict__ roff, int64_t n_prims,
+                                                     const int64_t* __restrict__ ctl, int tb, int batch,
+                                                     Key* __restrict__ rkeys, float* __restrict__ rw,
+                                                     uint32_t* __restrict__ rprim) {
+  if (ctl[CTL_N_REC] == 0) return;
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n_prims; p += int64_t(gridDim.x) * kBlock) {
+    if (cand_cnt[p] <= 0) continue;
+    const int32_t* r = rec + p * kRec;
+    int32_t t0[3], t1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      t0[a] = r[9 + a] >> tb;
+      t1[a] = (r[9 + a] + r[12 + a] - 1) >> tb;
+    }
+    const Key hi = batch ? Key(uint64_t(uint32_t(r[15])) << (kPatchShift - 3 * tb)) : Key(0);
+    int64_t o = roff[p];
+    for (int32_t z = t0[2]; z <= t1[2]; ++z)
+      for (int32_t y = t0[1]; y <= t1[1]; ++y)
+        for (int32_t x = t0[0]; x <= t1[0]; ++x) {
+          rkeys[o] = hi | Key(morton3(uint32_t(x), uint32_t(y), uint32_t(z)));
+          rw[o] = 0.f;
+          rprim[o] = uint32_t(p);
+          ++o;
+        }
+  }
+}
+
+struct TileTotal {
+  int64_t* start;
+  int64_t* ctl;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    start[total] = n;
+    ctl[CTL_N_TILES] = total;
+  }
+};
+
+// ---------------------------------------------------------------------------------------------
+// work units: a tile, or an octant of one, whose candidates fit a block's LDS
+// ---------------------------------------------------------------------------------------------
+struct Unit {
+  int64_t tile;       // index into the tile list
+  int64_t cand;       // candidates inside the unit
+  int32_t o[3];       // first voxel
+  int32_t lev;        // 2^lev voxels per axis
+};
+
+// Per tile (one block each): walk the octant tree depth first in Morton order and count (PASS 0)
+// or write (PASS 1) the units.  A box is a unit when its candidates fit kUnitCand, or when it is
+// a single voxel (then summed in streaming order).
+template <int PASS, class Key>
+__global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict__ rec,
+                                                      const Key* __restrict__ rkeys,
+                                                      const uint32_t* __restrict__ rprim,
+                                                      const int64_t* __restrict__ tstart,
+                                                      const int64_t* __restrict__ ctl, int tb, int batch,
+                                                      int64_t* __restrict__ ucnt, const int64_t* __restrict__ uoff,
+                                                      Unit* __restrict__ units) {
+  __shared__ int32_t stk[8 * 8][4];
+  __shared__ int64_t tmp[kWaves + 1];
+  __shared__ int32_t s_top;
+  const int64_t n_tiles = ctl[CTL_N_TILES];
+  if (PASS == 1 && ctl[CTL_N_UNITS] == 0) return;
+  // tile coordinates: the Morton bits below the patch id (batched) or the whole key
+  const uint64_t lowmask = batch ? (uint64_t(1) << (kPatchShift - 3 * tb)) - 1 : ~uint64_t(0);
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t s = tstart[t], e = tstart[t + 1];
+    const uint64_t tk = uint64_t(rkeys[s]) & lowmask;
+    if (threadIdx.x == 0) {
+      stk[0][0] = int32_t(compact3(tk)) << tb;
+      stk[0][1] = int32_t(compact3(tk >> 1)) << tb;
+      stk[0][2] = int32_t(compact3(tk >> 2)) << tb;
+      stk[0][3] = tb;
+      s_top = 1;
+    }
+    __syncthreads();
+    int64_t nu = 0;
+    int64_t out = PASS == 1 ? uoff[t] : 0;
+    while (s_top > 0) {
+      const int top = s_top - 1;
+      const int32_t o[3] = {stk[top][0], stk[top][1], stk[top][2]};
+      const int32_t lev = stk[top][3];
+      __syncthreads();                               // everyone has read the top before it changes
+      int64_t c = 0;
+      for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
+        int32_t lo[3], n[3];
+        c += clip_box(rec + int64_t(rprim[j]) * kRec, o, 1 << lev, lo, n);
+      }
+      c = block_sum(c, tmp);
+      const bool unit = c <= kUnitCand || lev == 0;
+      if (threadIdx.x == 0) {
+        s_top = top;                                 // pop
+        if (!unit) {
+          for (int k = 7; k >= 0; --k) {             // push children, Morton order on top
+            const int q = s_top++;
+            const int32_t h = 1 << (lev - 1);
+            stk[q][0] = o[0] + ((k & 1) ? h : 0);
+            stk[q][1] = o[1] + ((k & 2) ? h : 0);
+            stk[q][2] = o[2] + ((k & 4) ? h : 0);
+            stk[q][3] = lev - 1;
+          }
+        } else if (c > 0 && PASS == 1) {
+          Unit u;
+          u.tile = t;
+          u.cand = c;
+          u.o[0] = o[0];
+          u.o[1] = o[1];
+          u.o[2] = o[2];
+          u.lev = lev;
+          units[out] = u;
+        }
+      }
+      if (unit && c > 0) {
+        ++nu;
+        ++out;
+      }
+      __syncthreads();
+    }
+    if (PASS == 0 && threadIdx.x == 0) ucnt[t] = nu;
+    __syncthreads();
+  }
+}
+
+struct UnitTotal {
+  int64_t* off;
+  int64_t* ctl;
+  int64_t* stats;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    off[n] = total;
+    stats[VX_STAT_UNITS] = total;
+    const bool over = total > cap;
+    if (over) flag_set(stats, VX_FLAG_UNIT_CAPACITY);
+    ctl[CTL_N_UNITS] = over ? 0 : total;
+  }
+};
+
+// ---------------------------------------------------------------------------------------------
+// the unit kernel: test, weigh, group by voxel and sum in LDS
+// ---------------------------------------------------------------------------------------------
+struct UnitLds {
+  uint32_t* start;    // [4097] voxel starts in the grouped order
+  uint32_t* cur;      // [4096] placement cursors, then voxel ranks
+  uint16_t* key;      // [kUnitCand] unit-local Morton code of each pair
+  uint16_t* idx;      // [kUnitCand] grouped order -> pair
+  float* w;           // [kUnitCand]
+  uint32_t* prim;     // [kUnitCand]
+  int32_t* bprim;     // [kBlock] the current record batch
+  int32_t* blo;       // [3][kBlock]
+  int32_t* bn;        // [3][kBlock]
+  int32_t* boff;      // [kBlock] candidate offsets within the batch
+  int32_t* tmp32;     // [kWaves + 1]
+  int32_t* misc;      // [8]
+};
+
+constexpr size_t kUnitLdsBytes = 4097 * 4 + 4096 * 4 + kUnitCand * (2 + 2 + 4 + 4) + kBlock * 4 * 8 +
+                                 (kWaves + 1) * 4 + 8 * 4 + 64;
+
+__device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
+  UnitLds L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += (bytes + 7) & ~size_t(7);
+    return p;
+  };
+  L.start = reinterpret_cast<uint32_t*>(take(4097 * 4));
+  L.cur = reinterpret_cast<uint32_t*>(take(4096 * 4));
+  L.w = reinterpret_cast<float*>(take(kUnitCand * 4));
+  L.prim = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
+  L.key = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
+  L.blo = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
+  L.bn = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
+  L.boff = reinterpret_cast<int32_t*>(take(kBlock * 4));
+  L.tmp32 = reinterpret_cast<int32_t*>(take((kWaves + 1) * 4));
+  L.misc = reinterpret_cast<int32_t*>(take(8 * 4));
+  return L;
+}
+
+// Load records [j0, j0 + kBlock) of the tile clipped to the unit box; returns the batch's
+// candidate total.  Contains __syncthreads().
+__device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* __restrict__ rec,
+                                              const uint32_t* __restrict__ rprim, int64_t j0, int64_t e,
+                                              const int32_t o[3], int32_t size) {
+  const int64_t j = j0 + threadIdx.x;
+  int32_t c = 0;
+  if (j < e) {
+    const uint32_t p = rprim[j];
+    int32_t lo[3], n[3];
+    c = int32_t(clip_box(rec + int64_t(p) * kRec, o, size, lo, n));
+    S.bprim[threadIdx.x] = int32_t(p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      S.blo[a * kBlock + threadIdx.x] = lo[a];
+      S.bn[a * kBlock + threadIdx.x] = n[a];
+    }
+  }
+  int32_t tot;
+  const int32_t ex = block_exclusive_scan(c, S.tmp32, tot);
+  S.boff[threadIdx.x] = j < e ? ex : tot;
+  __syncthreads();
+  return tot;
+}
+
+// candidate c of the batch -> (record slot, voxel)
+__device__ __forceinline__ int find_slot(const UnitLds& S, int nb, int32_t c, int64_t v[3]) {
+  int lo = 0, hi = nb;                              // last slot with boff <= c
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (S.boff[mid] <= c) lo = mid; else hi = mid;
+  }
+  const int32_t li = c - S.boff[lo];
+  const int32_t nx = S.bn[lo], ny = S.bn[kBlock + lo];
+  const int32_t t = li / nx;
+  v[0] = S.blo[lo] + (li - t * nx);
+  v[1] = S.blo[kBlock + lo] + (t % ny);
+  v[2] = S.blo[2 * kBlock + lo] + t / ny;
+  return lo;
+}
+
+template <int KIND>
+__device__ __forceinline__ bool unit_test(const int32_t* r, const int64_t v[3], const Lat& Lp) {
+  if (KIND == 0) return tri_touch(r, v, Lp.s, Lp.Sb);
+  return cap_touch(r, v, Lp.s, Lp.Sb, Lp.rho);
+}
+
+template <int KIND>
+__device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3], const Lat& Lp, float len,
+                                             double* poly) {
+  if (KIND == 0) return tri_area(r, v, Lp.Sb, len, poly);
+  return seg_length(r, v, Lp.Sb, len);
+}
+
+// Staging of a unit's voxels (SoA, capacity cap); units claim contiguous ranges in any order.
+struct Stage {
+  uint64_t* key;
+  uint32_t* count;
+  float* w;
+  float* S;           // [6][cap]
+  int64_t cap;
+};
+
+template <int KIND>
+__device__ __forceinline__ void write_voxel(const Stage& st, int64_t i, uint64_t key, uint32_t cnt, const Moment& m) {
+  st.key[i] = key;
+  st.count[i] = cnt;
+  st.w[i] = m.W;
+  st.S[i] = m.xx;
+  st.S[st.cap + i] = m.yy;
+  st.S[2 * st.cap + i] = m.zz;
+  st.S[3 * st.cap + i] = m.xy;
+  st.S[4 * st.cap + i] = m.xz;
+  st.S[5 * st.cap + i] = m.yz;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec, const float4* __restrict__ dirs,
+                                                 const uint32_t* __restrict__ rprim,
+                                                 const int64_t* __restrict__ tstart, const Unit* __restrict__ units,
+                                                 const int64_t* __restrict__ ctl, Lat L, const Lat* __restrict__ lats,
+                                                 int64_t* __restrict__ unv, int64_t* __restrict__ unp,
+                                                 int64_t* __restrict__ usoff, Stage st, int64_t* stage_ctr,
+                                                 int64_t* stats) {
+  extern __shared__ double lds_dyn[];
+  double* poly = lds_dyn;                                               // triangles: clipping slots
+  char* base = reinterpret_cast<char*>(lds_dyn) + (KIND == 0 ? kTriEmitLds : 0);
+  const UnitLds S = carve_unit_lds(base);
+  const int64_t n_units = ctl[CTL_N_UNITS];
+  const int tid = threadIdx.x;
+  for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const Unit U = units[u];
+    const int64_t s = tstart[U.tile], e = tstart[U.tile + 1];
+    const int32_t size = 1 << U.lev;
+    const bool stream = U.cand > kUnitCand;          // a single voxel holding too many candidates
+    const uint32_t nk = 1u << (3 * U.lev);
+    int32_t np = 0;                                   // pairs so far (uniform)
+    Moment acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // streaming sums (thread 0)
+    uint32_t acc_n = 0;
+    for (int64_t j0 = s; j0 < e; j0 += kBlock) {
+      const int nb = int(e - j0 < kBlock ? e - j0 : kBlock);
+      const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, size);
+      for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
+        const int32_t c = c0 + tid;
+        bool hit = false;
+        float wgt = 0.f;
+        uint32_t lk = 0, p = 0;
+        if (c < cb) {
+          int64_t v[3];
+          const int slot = find_slot(S, nb, c, v);
+          p = uint32_t(S.bprim[slot]);
+          const int32_t* r = rec + int64_t(p) * kRec;
+          const Lat& Lp = lats ? lats[r[15]] : L;
+          hit = unit_test<KIND>(r, v, Lp);
+          if (hit) {
+            wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
+            lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
+          }
+        }
+        int32_t tot;
+        const int32_t pos = block_exclusive_scan(int32_t(hit), S.tmp32, tot);
+        if (!stream) {
+          if (hit) {
+            const int32_t q = np + pos;
+            if (q < kUnitCand) {
+              S.key[q] = uint16_t(lk);
+              S.w[q] = wgt;
+              S.prim[q] = p;
+            } else {
+              flag_set(stats, VX_FLAG_UNIT_CAPACITY);  // planning and test disagree: never expected
+            }
+          }
+        } else {
+          // one voxel: sum this chunk's hits in order (thread 0), chunk by chunk
+          if (hit) {
+            S.w[pos] = wgt;
+            S.prim[pos] = p;
+          }
+          __syncthreads();
+          if (tid == 0) {
+            for (int32_t i = 0; i < tot; ++i) accum_pair<KIND>(acc, S.w[i], dirs[S.prim[i]]);
+            acc_n += uint32_t(tot);
+          }
+        }
+        np += tot;
+        __syncthreads();
+      }
+    }
+    if (stream) {
+      if (tid == 0) {
+        const int64_t nv = acc_n > 0 ? 1 : 0;
+        int64_t b = 0;
+        if (nv) {
+          b = int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(stage_ctr), 1ull));
+          const uint64_t key = morton3(uint32_t(U.o[0]), uint32_t(U.o[1]), uint32_t(U.o[2])) |
+                               (lats ? uint64_t(uint32_t(rec[int64_t(rprim[s]) * kRec + 15])) << kPatchShift : 0ull);
+          if (b < st.cap) write_voxel<KIND>(st, b, key, acc_n, acc);
+          else flag_set(stats, VX_FLAG_VOXEL_CAPACITY);
+        }
+        unv[u] = nv;
+        unp[u] = np;
+        usoff[u] = b;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int32_t npairs = np < kUnitCand ? np : kUnitCand;
+    // group the pairs by voxel: counts, starts, placement
+    for (uint32_t k = tid; k < nk; k += kBlock) S.start[k] = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < npairs; i += kBlock) atomicAdd(&S.start[S.key[i]], 1u);
+    __syncthreads();
+    // exclusive scan of counts and of voxel presence, 16 keys per thread (nk <= 4096)
+    {
+      const uint32_t per = (nk + kBlock - 1) / kBlock;
+      const uint32_t k0 = tid * per;
+      uint32_t cs = 0, vs = 0;
+      for (uint32_t k = k0; k < k0 + per && k < nk; ++k) {
+        cs += S.start[k];
+        vs += S.start[k] ? 1u : 0u;
+      }
+      int32_t tc, tv;
+      const int32_t ec = block_exclusive_scan(int32_t(cs), S.tmp32, tc);
+      const int32_t ev = block_exclusive_scan(int32_t(vs), S.tmp32, tv);
+      uint32_t rc = uint32_t(ec), rv = uint32_t(ev);
+      for (uint32_t k = k0; k < k0 + per && k < nk; ++k) {
+        const uint32_t c = S.start[k];
+        S.start[k] = rc;
+        S.cur[k] = rc;
+        rc += c;
+      }
+      if (tid == 0) {
+        S.start[nk] = uint32_t(tc);
+        S.misc[0] = tv;
+      }
+      __syncthreads();
+      // placement in the grouped order
+      for (int32_t i = tid; i < npairs; i += kBlock) {
+        const uint32_t q = atomicAdd(&S.cur[S.key[i]], 1u);
+        S.idx[q] = uint16_t(i);
+      }
+      __syncthreads();
+      // voxel ranks in key order (cur is free again)
+      for (uint32_t k = k0; k < k0 + per && k < nk; ++k) {
+        S.cur[k] = rv;
+        rv += S.start[k + 1] > S.start[k] ? 1u : 0u;
+      }
+    }
+    const int64_t nv = S.misc[0];
+    if (tid == 0) {
+      const int64_t b = nv ? int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(stage_ctr),
+                                               (unsigned long long)nv))
+                           : 0;
+      S.misc[1] = int32_t(b & 0xffffffff);
+      S.misc[2] = int32_t(b >> 32);
+      if (b + nv > st.cap) flag_set(stats, VX_FLAG_VOXEL_CAPACITY);
+      unv[u] = nv;
+      unp[u] = np;
+      usoff[u] = b;
+    }
+    __syncthreads();
+    const int64_t b = int64_t(uint32_t(S.misc[1])) | (int64_t(S.misc[2]) << 32);
+    const uint64_t hi = lats ? uint64_t(uint32_t(rec[int64_t(rprim[s]) * kRec + 15])) << kPatchShift : 0ull;
+    if (b + nv <= st.cap) {
+      for (uint32_t k = tid; k < nk; k += kBlock) {
+        const uint32_t a = S.start[k], z = S.start[k + 1];
+        if (z == a) continue;
+        // the voxel's pairs in primitive order (insertion sort; primitives are distinct)
+        for (uint32_t i = a + 1; i < z; ++i) {
+          const uint16_t x = S.idx[i];
+          const uint32_t px = S.prim[x];
+          uint32_t j = i;
+          while (j > a && S.prim[S.idx[j - 1]] > px) {
+            S.idx[j] = S.idx[j - 1];
+            --j;
+          }
+          S.idx[j] = x;
+        }
+        Moment m{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (uint32_t i = a; i < z; ++i) {
+          const uint16_t x = S.idx[i];
+          accum_pair<KIND>(m, S.w[x], dirs[S.prim[x]]);
+        }
+        const uint32_t vx = U.o[0] + compact3(k), vy = U.o[1] + compact3(uint64_t(k) >> 1),
+                       vz = U.o[2] + compact3(uint64_t(k) >> 2);
+        write_voxel<KIND>(st, b + S.cur[k], hi | morton3(vx, vy, vz), z - a, m);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// totals and the final, dense leaf
+// ---------------------------------------------------------------------------------------------
+struct VoxTotal {
+  int64_t* pos;
+  int64_t* ctl;
+  int64_t* stats;
+  int64_t cap;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    pos[n] = total;
+    stats[VX_STAT_VOXELS] = total;
+    const bool over = total > cap;
+    if (over) flag_set(stats, VX_FLAG_VOXEL_CAPACITY);
+    ctl[CTL_N_VOX] = over ? 0 : total;
+  }
+};
+struct SumTotal {
+  int64_t* dst;
+  __device__ void operator()(int64_t total, int64_t) const { *dst = total; }
+};
+struct NoOut {
+  __device__ void operator()(int64_t, int64_t, int64_t) const {}
+};
+struct UnitCand {
+  const Unit* u;
+  __device__ int64_t operator()(int64_t i) const { return u[i].cand; }
+};
+
+// one block per unit: copy its staged voxels to their place in the leaf
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_unit_compact(const int64_t* __restrict__ unv,
+                                                         const int64_t* __restrict__ usoff,
+                                                         const int64_t* __restrict__ upos,
+                                                         const int64_t* __restrict__ ctl, Stage st, vx_voxels out) {
+  const int64_t n_units = ctl[CTL_N_UNITS];
+  if (ctl[CTL_N_VOX] == 0) return;
+  Key* okeys = reinterpret_cast<Key*>(out.keys);
+  for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const int64_t n = unv[u], src = usoff[u], dst = upos[u];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      okeys[dst + i] = Key(st.key[src + i]);
+      out.count[dst + i] = st.count[src + i];
+      out.w[dst + i] = st.w[src + i];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out.S[c * out.cap + dst + i] = st.S[c * st.cap + src + i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// orchestration
+// ---------------------------------------------------------------------------------------------
+struct TileWs {
+  int64_t* ctl;
+  int32_t* rec;
+  float4* dirs;
+  int64_t* cand_cnt;
+  int64_t* roff;          // [n_prims + 1]
+  PairBufs ra, rb;        // records (tile key, unused weight, primitive), ping-pong
+  int32_t* hist;
+  int64_t* partial;
+  int64_t* tstart;        // [max_records + 1]
+  int64_t* ucnt;          // [max_records + 1] units per tile, then their offsets
+  int64_t* uoff;
+  Unit* units;            // [max_units]
+  int64_t* unv;           // [max_units + 1]
+  int64_t* unp;
+  int64_t* usoff;
+  int64_t* upos;          // [max_units + 1]
+  int64_t* stage_ctr;
+  Stage st;
+};
+
+static size_t tile_ws_layout(int64_t n_prims, int64_t max_rec, int64_t max_units, int64_t max_vox, bool key64,
+                             void* base, TileWs* w) {
+  Carver cv(base);
+  TileWs x;
+  const int kb = key64 ? 8 : 4;
+  x.ctl = cv.take<int64_t>(CTL_SIZE);
+  x.rec = cv.take<int32_t>(n_prims * kRec);
+  x.dirs = cv.take<float4>(n_prims);
+  x.cand_cnt = cv.take<int64_t>(n_prims);
+  x.roff = cv.take<int64_t>(n_prims + 1);
+  x.ra.keys = cv.take<uint8_t>(max_rec * kb);
+  x.ra.w = cv.take<float>(max_rec);
+  x.ra.prim = cv.take<uint32_t>(max_rec);
+  x.rb.keys = cv.take<uint8_t>(max_rec * kb);
+  x.rb.w = cv.take<float>(max_rec);
+  x.rb.prim = cv.take<uint32_t>(max_rec);
+  x.hist = cv.take<int32_t>(int64_t(256) * kGrid);
+  x.partial = cv.take<int64_t>(kGrid + 1);
+  x.tstart = cv.take<int64_t>(max_rec + 1);
+  x.ucnt = cv.take<int64_t>(max_rec + 1);
+  x.uoff = cv.take<int64_t>(max_rec + 1);
+  x.units = cv.take<Unit>(max_units);
+  x.unv = cv.take<int64_t>(max_units + 1);
+  x.unp = cv.take<int64_t>(max_units + 1);
+  x.usoff = cv.take<int64_t>(max_units + 1);
+  x.upos = cv.take<int64_t>(max_units + 1);
+  x.stage_ctr = cv.take<int64_t>(1);
+  x.st.key = cv.take<uint64_t>(max_vox);
+  x.st.count = cv.take<uint32_t>(max_vox);
+  x.st.w = cv.take<float>(max_vox);
+  x.st.S = cv.take<float>(6 * max_vox);
+  x.st.cap = max_vox;
+  if (w) *w = x;
+  return cv.off + 256;
+}
+
+size_t tile_ws_bytes(int64_t n_prims, int64_t max_rec, int64_t max_units, int64_t max_vox, bool key64) {
+  return tile_ws_layout(n_prims, max_rec, max_units, max_vox, key64, nullptr, nullptr);
+}
+
+struct ArrIn64 {
+  const int64_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i]; }
+};
+struct ArrOut64 {
+  int64_t* o;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t) const { o[i] = ex; }
+};
+
+vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                        int64_t n_fib, float radius, int64_t max_rec, int64_t max_units, void* ws_ptr,
+                        const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb) {
+  const bool key64 = batch || g->log2_res > 10;
+  TileWs w;
+  tile_ws_layout(n_prims, max_rec, max_units, out->cap, key64, ws_ptr, &w);
+  // prep (snap, candidate boxes) is shared with the pair path
+  FrontWs f{};
+  f.ctl = w.ctl;
+  f.rec = w.rec;
+  f.dirs = w.dirs;
+  f.cand_cnt = w.cand_cnt;
+  f.partial = w.partial;
+  prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch);
+  launch_fill_i64(w.stage_ctr, 1, 0, s);
+  const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
+  {
+    VX_TIMED("tile_records", s);
+    hipLaunchKernelGGL(k_rec_count, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, n_prims, tb, w.roff);
+    device_scan(ArrIn64{w.roff}, ArrOut64{w.roff}, RecTotal{w.roff, w.ctl, stats, max_rec}, nullptr, n_prims,
+                w.partial, s);
+    if (key64)
+      hipLaunchKernelGGL(k_rec_emit<uint64_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, w.roff, n_prims,
+                         w.ctl, tb, batch ? 1 : 0, (uint64_t*)w.ra.keys, w.ra.w, w.ra.prim);
+    else
+      hipLaunchKernelGGL(k_rec_emit<uint32_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, w.roff, n_prims,
+                         w.ctl, tb, 0, (uint32_t*)w.ra.keys, w.ra.w, w.ra.prim);
+  }
+  int key_bits = 3 * (g->log2_res - tb);
+  if (batch) {
+    int pb = 1;
+    while ((1 << pb) < batch->n_patches) ++pb;
+    key_bits = kPatchShift - 3 * tb + pb;
+  }
+  const int res = radix_sort_pairs(key64, key_bits, w.ra, w.rb, w.ctl + CTL_N_REC, max_rec, w.hist, w.partial, s);
+  const PairBufs R = res ? w.rb : w.ra;
+  {
+    VX_TIMED("tile_heads", s);
+    if (key64)
+      device_scan(HeadIn<uint64_t, 0>{(const uint64_t*)R.keys}, HeadOut{w.tstart}, TileTotal{w.tstart, w.ctl},
+                  w.ctl + CTL_N_REC, 0, w.partial, s);
+    else
+      device_scan(HeadIn<uint32_t, 0>{(const uint32_t*)R.keys}, HeadOut{w.tstart}, TileTotal{w.tstart, w.ctl},
+                  w.ctl + CTL_N_REC, 0, w.partial, s);
+  }
+  {
+    VX_TIMED("unit_plan", s);
+    const int grid = kGrid;
+#define VX_PLAN(P, K)                                                                                        \
+  hipLaunchKernelGGL((k_unit_plan<P, K>), dim3(grid), dim3(kBlock), 0, s, w.rec, (const K*)R.keys, R.prim, w.tstart, \
+                     w.ctl, tb, batch ? 1 : 0, w.ucnt, w.uoff, w.units)
+    if (key64) VX_PLAN(0, uint64_t); else VX_PLAN(0, uint32_t);
+    device_scan(ArrIn64{w.ucnt}, ArrOut64{w.uoff}, UnitTotal{w.uoff, w.ctl, stats, max_units}, w.ctl + CTL_N_TILES,
+                0, w.partial, s);
+    if (key64) VX_PLAN(1, uint64_t); else VX_PLAN(1, uint32_t);
+#undef VX_PLAN
+  }
+  {
+    VX_TIMED(kind == 0 ? "unit_tri" : "unit_fib", s);
+    const size_t lds = kUnitLdsBytes + (kind == 0 ? kTriEmitLds : 0);
+    static bool attr[2] = {false, false};
+    if (!attr[kind]) {
+      if (kind == 0)
+        (void)hipFuncSetAttribute((const void*)k_unit<0>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      else
+        (void)hipFuncSetAttribute((const void*)k_unit<1>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      attr[kind] = true;
+    }
+    const Lat L = make_lat(g, kind, radius);
+    const Lat* lats = batch ? batch->lats : nullptr;
+    if (kind == 0)
+      hipLaunchKernelGGL(k_unit<0>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
+                         w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);
+    else
+      hipLaunchKernelGGL(k_unit<1>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
+                         w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);
+  }
+  {
+    VX_TIMED("unit_compact", s);
+    device_scan(ArrIn64{w.unp}, NoOut{}, SumTotal{stats + VX_STAT_PAIRS}, w.ctl + CTL_N_UNITS, 0, w.partial, s);
+    device_scan(UnitCand{w.units}, NoOut{}, SumTotal{stats + VX_STAT_CAND}, w.ctl + CTL_N_UNITS, 0, w.partial, s);
+    device_scan(ArrIn64{w.unv}, ArrOut64{w.upos}, VoxTotal{w.upos, w.ctl, stats, out->cap}, w.ctl + CTL_N_UNITS, 0,
+                w.partial, s);
+    if (key64)
+      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos, w.ctl,
+                         w.st, *out);
+    else
+      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos, w.ctl,
+                         w.st, *out);
+  }
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+}  // namespace vx

@@ -12,6 +12,8 @@ constexpr int kBlock = 256;          // threads per block: 4 waves of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kGrid = 1024;          // persistent grid of the streaming kernels: 4 blocks per CU
 constexpr int kPatchShift = 33;      // batched keys: patch id above a 33-bit Morton code (R <= 2048)
+constexpr int kTileBits = 4;         // leaf tiles of 16^3 voxels
+constexpr int kUnitCand = 3072;      // candidates (so pairs) one work unit keeps in LDS
 
 // ---------------------------------------------------------------------------------------------
 // Kernel timing (measurement only): events around every launch when enabled.
@@ -122,34 +124,32 @@ __global__ void __launch_bounds__(kBlock) k_scan_partial(In in, const int64_t* n
   }
 }
 
-// One block of 1024 threads scans kGrid partials in place (exclusive).
-template <class Total>
-__global__ void __launch_bounds__(1024) k_scan_top(int64_t* partial, const int64_t* n_ptr, int64_t n_const,
-                                                   Total total) {
-  __shared__ int64_t tmp[16];
-  const int t = threadIdx.x;
-  int64_t v = t < kGrid ? partial[t] : 0;
-  int64_t inc = wave_inclusive_scan(v);
-  if (lane_id() == 63) tmp[t >> 6] = inc;
-  __syncthreads();
-  int64_t base = 0, tot = 0;
-  for (int i = 0; i < 16; ++i) {
-    if (i < (t >> 6)) base += tmp[i];
-    tot += tmp[i];
-  }
-  if (t < kGrid) partial[t] = base + inc - v;
-  if (t == 0) total(tot, scan_n(n_ptr, n_const));
-}
-
-template <class In, class Out>
-__global__ void __launch_bounds__(kBlock) k_scan_apply(In in, Out out, const int64_t* n_ptr, int64_t n_const,
-                                                       const int64_t* partial) {
+// Every block adds up the partials of the blocks before it (kGrid int64 values, read from L2),
+// so no separate pass scans the partials; block 0 also forms the total.
+template <class In, class Out, class Total>
+__global__ void __launch_bounds__(kBlock) k_scan_apply(In in, Out out, Total total, const int64_t* n_ptr,
+                                                       int64_t n_const, const int64_t* partial) {
   __shared__ int64_t tmp[kWaves + 1];
   const int64_t n = scan_n(n_ptr, n_const);
   const int64_t chunk = scan_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
-  int64_t base = partial[blockIdx.x];
+  int64_t pre = 0, all = 0;
+  for (int i = threadIdx.x; i < kGrid; i += kBlock) {
+    const int64_t v = partial[i];
+    if (i < int(blockIdx.x)) pre += v;
+    all += v;
+  }
+  int64_t base;
+  {
+    int64_t t;
+    (void)block_exclusive_scan(pre, tmp, base);
+    if (blockIdx.x == 0) {
+      (void)block_exclusive_scan(all, tmp, t);
+      if (threadIdx.x == 0) total(t, n);
+    }
+  }
+  if (b0 >= b1) return;
   for (int64_t t0 = b0; t0 < b1; t0 += kBlock) {
     const int64_t i = t0 + threadIdx.x;
     const int64_t v = i < b1 ? in(i) : 0;
@@ -164,9 +164,8 @@ template <class In, class Out, class Total>
 inline void device_scan(In in, Out out, Total total, const int64_t* n_ptr, int64_t n_const, int64_t* partial,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_scan_partial<In>, dim3(kGrid), dim3(kBlock), 0, s, in, n_ptr, n_const, partial);
-  hipLaunchKernelGGL(k_scan_top<Total>, dim3(1), dim3(1024), 0, s, partial, n_ptr, n_const, total);
-  hipLaunchKernelGGL((k_scan_apply<In, Out>), dim3(kGrid), dim3(kBlock), 0, s, in, out, n_ptr, n_const,
-                     partial);
+  hipLaunchKernelGGL((k_scan_apply<In, Out, Total>), dim3(kGrid), dim3(kBlock), 0, s, in, out, total, n_ptr,
+                     n_const, partial);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -193,7 +192,35 @@ struct Carver {
 };
 
 // internal control block (device): effective counts that later kernels iterate over
-enum { CTL_N_CAND = 0, CTL_N_CHUNKS, CTL_N_PAIRS, CTL_N_VOX, CTL_SIZE = 8 };
+enum { CTL_N_CAND = 0, CTL_N_CHUNKS, CTL_N_PAIRS, CTL_N_VOX, CTL_N_REC, CTL_N_TILES, CTL_N_UNITS, CTL_SIZE = 8 };
+
+// ---------------------------------------------------------------------------------------------
+// per-voxel sums: count, w and S = sum w M, accumulated pair by pair in primitive order
+// ---------------------------------------------------------------------------------------------
+struct Moment {
+  float W, xx, yy, zz, xy, xz, yz;
+};
+// t: unit normal (KIND 0, M = n n^T) or unit tangent (KIND 1, M = I - t t^T)
+template <int KIND>
+__device__ __forceinline__ void accum_pair(Moment& m, float wj, float4 t) {
+  const float ax = wj * t.x, ay = wj * t.y;
+  m.W += wj;
+  if (KIND == 0) {
+    m.xx = fmaf(ax, t.x, m.xx);
+    m.yy = fmaf(ay, t.y, m.yy);
+    m.zz = fmaf(wj * t.z, t.z, m.zz);
+    m.xy = fmaf(ax, t.y, m.xy);
+    m.xz = fmaf(ax, t.z, m.xz);
+    m.yz = fmaf(ay, t.z, m.yz);
+  } else {
+    m.xx += wj - ax * t.x;
+    m.yy += wj - ay * t.y;
+    m.zz += wj - wj * t.z * t.z;
+    m.xy = fmaf(-ax, t.y, m.xy);
+    m.xz = fmaf(-ax, t.z, m.xz);
+    m.yz = fmaf(-ay, t.z, m.yz);
+  }
+}
 
 // ---------------------------------------------------------------------------------------------
 // launchers implemented in the .hip files
@@ -210,10 +237,27 @@ void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int64_t* n_dev, int64_t cap,
                      int32_t* hist, int64_t* partial, hipStream_t s);
 
-// segmented reduce of sorted pairs into leaf voxels
-void reduce_pairs(bool key64, PairBufs p, const int64_t* n_pairs_dev, const float4* dirs, int kind,
-                  int64_t* seg_start, int64_t* partial, int64_t* ctl, int64_t* stats, const vx_voxels& out,
-                  hipStream_t s);
+// head flags of sorted keys (SHIFT 0: the key, 3: the parent key) and segment starts
+template <class Key, bool BATCH>
+__device__ __forceinline__ Key parent_key(Key k) {
+  if (!BATCH) return k >> 3;
+  const Key lowmask = (Key(1) << kPatchShift) - 1;
+  return (k & ~lowmask) | ((k & lowmask) >> 3);
+}
+template <class Key, int SHIFT, bool BATCH = false>
+struct HeadIn {
+  const Key* k;
+  __device__ int64_t operator()(int64_t i) const {
+    if (SHIFT == 0) return i == 0 || k[i] != k[i - 1];
+    return i == 0 || parent_key<Key, BATCH>(k[i]) != parent_key<Key, BATCH>(k[i - 1]);
+  }
+};
+struct HeadOut {
+  int64_t* start;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t v) const {
+    if (v) start[ex] = i;
+  }
+};
 
 // one LoD level: parent reduce of `in` (n_in on the device) into `out`; n_out receives the
 // new count clamped to out.cap, and flags the capacity bit when it had to be clamped
@@ -251,6 +295,10 @@ struct BatchLattice {
 void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                     int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
                     int64_t* stats, hipStream_t s, const BatchLattice* batch);
+// its first step: clear stats and control, snap the primitives, write records and candidate counts
+void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                int64_t n_fib, float radius, const FrontWs& w, int64_t* stats, hipStream_t s,
+                const BatchLattice* batch);
 
 // the differentiable two-lobe fit (fit.hip)
 size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, bool key64);
@@ -263,13 +311,10 @@ vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, co
                            int ndir, const float* dloss, float* const* dparams, float* dpts, int64_t* stats,
                            void* ws, const int64_t* caps, hipStream_t s);
 
-// the voxelize pass (prims.hip)
-size_t voxelize_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64);
-vx_status voxelize_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
-                       int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, void* ws,
-                       const vx_voxels* out, int64_t* stats, hipStream_t s);
-vx_status voxelize_batch_run(const vx_grid* g0, const float* pts, int64_t n_pts, const int64_t* offsets,
-                             int64_t n_fib, int64_t max_cand, int64_t max_pairs, void* ws, const vx_voxels* out,
-                             int64_t* stats, hipStream_t s, const BatchLattice& bl, int key_bits);
+// the voxelize pass by tiles (tiles.hip); tb = tile bits per axis
+size_t tile_ws_bytes(int64_t n_prims, int64_t max_rec, int64_t max_units, int64_t max_vox, bool key64);
+vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                        int64_t n_fib, float radius, int64_t max_rec, int64_t max_units, void* ws,
+                        const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb);
 
 }  // namespace vx

@@ -35,11 +35,13 @@ def test_every_declared_symbol_is_exported(lib):
 def test_host_only_calls(lib):
     f = lib.vx_voxelize_workspace_size
     f.restype = ctypes.c_size_t
-    f.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
-    assert f(0, 100, 1000, 500, 6) > 0
-    assert f(1, 100, 1000, 500, 12) > f(1, 100, 1000, 500, 6)      # 64-bit keys need more room
-    assert f(0, 100, 1000, 1 << 31, 6) == 0                          # pairs beyond 2^31 - 1
-    assert f(3, 100, 1000, 500, 6) == 0 and f(0, -1, 0, 0, 6) == 0 and f(0, 1, 1, 1, 21) == 0
+    f.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    assert f(0, 100, 1000, 500, 800, 6) > 0
+    assert f(1, 100, 1000, 500, 800, 12) > f(1, 100, 1000, 500, 800, 6)      # 64-bit keys need more room
+    assert f(1, 100, 1000, 500, 80000, 6) > f(1, 100, 1000, 500, 800, 6)     # leaf staging
+    assert f(0, 1 << 32, 1, 1, 1, 6) == 0                                     # primitive ids are 32-bit
+    assert f(3, 100, 1000, 500, 800, 6) == 0 and f(0, -1, 0, 0, 1, 6) == 0 and f(0, 1, 1, 1, 1, 21) == 0
+    assert f(0, 1, 1, 1, 0, 6) == 0
     g = lib.vx_lod_workspace_size
     g.restype = ctypes.c_size_t
     g.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
@@ -67,7 +69,7 @@ def test_batch_graph_and_grid_calls_host_side(lib):
     ws.restype = ctypes.c_size_t
     ws.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
     assert ws(1000, 1000, 5000, 4000, 4000) > ws(1, 1000, 5000, 4000, 4000) > 0
-    assert ws(0, 1, 1, 1, 1) == 0 and ws(70000, 1, 1, 1, 1) == 0 and ws(2, 1, 1, 1 << 31, 1) == 0
+    assert ws(0, 1, 1, 1, 1) == 0 and ws(70000, 1, 1, 1, 1) == 0 and ws(2, 1 << 32, 1, 1, 1) == 0
     assert ws(2, 1, 1, 1, 0) == 0
     b = lib.vx_batch_build
     b.restype = ctypes.c_int

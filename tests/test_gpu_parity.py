@@ -191,20 +191,28 @@ def test_errors(vx):
     wl = synth.icosphere(subdiv=2)
     t = _dev(wl.tris)
     plan = vx.VoxelizePlan(0, wl.grid, t)
-    small = vx.VoxelizePlan(0, wl.grid, t, max_cand=plan.max_cand, max_pairs=plan.max_pairs - 1)
-    small.run()
-    with pytest.raises(vx.VxError) as e:
-        small.check()
-    assert e.value.status == 2
-    assert int(small.stats[1].item()) == plan.max_pairs
+    plan.run()
+    n_vox = plan.check().n
+    # each capacity one short: records, units, leaf voxels
+    for kw, idx, need in (({"max_records": plan.max_records - 1}, vx.STAT_RECORDS, plan.max_records),
+                          ({"max_units": plan.max_units - 1}, vx.STAT_UNITS, plan.max_units),
+                          ({"out_cap": n_vox - 1}, vx.STAT_VOXELS, n_vox)):
+        args = {"max_records": plan.max_records, "max_units": plan.max_units, "out_cap": n_vox}
+        args.update(kw)
+        small = vx.VoxelizePlan(0, wl.grid, t, **args)
+        small.run()
+        with pytest.raises(vx.VxError) as e:
+            small.check()
+        assert e.value.status == 2, kw
+        assert int(small.stats[idx].item()) == need, kw
     plan.run()
     v = plan.check()
     ref = oracle.voxelize_triangles(wl.grid, wl.tris)
     compare_level(v.numpy(), ref.keys, ref.count, ref.w, ref.S, what="after capacity error")
     # host-checked arguments
     L = vx.load()
-    assert L.vx_voxelize_workspace_size(0, 10, 10, 1 << 31, 4) == 0
-    assert L.vx_voxelize_workspace_size(2, 10, 10, 10, 4) == 0
+    assert L.vx_voxelize_workspace_size(0, 1 << 32, 10, 10, 10, 4) == 0
+    assert L.vx_voxelize_workspace_size(2, 10, 10, 10, 10, 4) == 0
     bad = vx.CGrid((vx.ctypes.c_double * 3)(0, 0, 0), -1.0, 4)
     st = L.vx_voxelize_triangles(vx.ctypes.byref(bad), vx._ptr(t), 1, 0, 0, None, 0, None, vx._ptr(plan.stats), None)
     assert st == 1
@@ -212,7 +220,8 @@ def test_errors(vx):
 
 
 def test_repeat_runs_identical(vx):
-    """Deterministic: no atomics on the data path, so repeated runs give identical bits."""
+    """Deterministic: every voxel sums its pairs in primitive order whatever order the work is
+    done in, so repeated runs give identical bits."""
     wl = synth.plain_weave(n_fibers=64, seed=9)
     say("case: repeatability")
     plan = vx.VoxelizePlan(1, wl.grid, _dev(wl.pts), offsets=_dev(wl.offsets), radius=wl.radius)
