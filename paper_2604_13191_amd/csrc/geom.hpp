@@ -307,50 +307,64 @@ VX_HD inline __attribute__((noinline)) bool cap_exact(const int64_t c[3], const 
 // against rho^2.  FP64 with an error bound (all inputs are exact integers below 2^26; every
 // rounding of the bracketing, the interpolation and the evaluation stays far inside
 // M^2 2^-44); exact 128-bit integers when too close to call.
-VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
+struct CapIn {
   int64_t ci[3], di[3];
   double c[3], d[3];
+  double err;
+};
+
+VX_HD inline void cap_setup(const int32_t* r, const int64_t v[3], int64_t s, int Sb, CapIn& q) {
   double M = double(s);
   for (int a = 0; a < 3; ++a) {
-    ci[a] = int64_t(r[a]) - (v[a] << Sb);
-    di[a] = int64_t(r[3 + a]) - int64_t(r[a]);
-    c[a] = double(ci[a]);
-    d[a] = double(di[a]);
-    M = fmax(M, fabs(c[a]) + fabs(d[a]) + double(s));
+    q.ci[a] = int64_t(r[a]) - (v[a] << Sb);
+    q.di[a] = int64_t(r[3 + a]) - int64_t(r[a]);
+    q.c[a] = double(q.ci[a]);
+    q.d[a] = double(q.di[a]);
+    M = fmax(M, fabs(q.c[a]) + fabs(q.d[a]) + double(s));
   }
+  q.err = M * M * 0x1p-44;
+}
+
+// The box holds the ball of radius h = s/2 around its centre and lies in the ball of radius
+// h sqrt(3): the distance from the centre to the segment decides most candidates.
+// Returns 1 (touch), 0 (no touch) or -1 (undecided: cap_bracket decides).
+VX_HD inline int cap_ball(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
+  CapIn q;
+  cap_setup(r, v, s, Sb, q);
+  const double h = 0.5 * double(s);
+  double wx = h - q.c[0], wy = h - q.c[1], wz = h - q.c[2];
+  const double dd = q.d[0] * q.d[0] + q.d[1] * q.d[1] + q.d[2] * q.d[2];
+  double tc = dd > 0 ? (wx * q.d[0] + wy * q.d[1] + wz * q.d[2]) / dd : 0.0;
+  tc = fmin(fmax(tc, 0.0), 1.0);
+  wx = fma(-tc, q.d[0], wx);
+  wy = fma(-tc, q.d[1], wy);
+  wz = fma(-tc, q.d[2], wz);
+  const double dc2 = wx * wx + wy * wy + wz * wz;
+  const double rin = h + double(rho);
+  if (dc2 + q.err <= rin * rin) return 1;
+  const double rout = h * 1.7320508075688772 + double(rho);
+  if (dc2 - q.err > rout * rout * (1.0 + 0x1p-40)) return 0;
+  return -1;
+}
+
+// f is convex and piecewise quadratic, so f' is monotone and piecewise linear with its
+// breakpoints where a coordinate crosses 0 or s.  Let t_lo be the largest of {0, 1,
+// breakpoints} with f' <= 0 and t_hi the smallest with f' >= 0: no breakpoint lies strictly
+// between them, f' is linear there and its zero is the minimiser.
+VX_HD inline bool cap_bracket(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
+  CapIn q;
+  cap_setup(r, v, s, Sb, q);
   const double ds = double(s);
   const double r2 = double(rho) * double(rho);
-  const double err = M * M * 0x1p-44;
-  {
-    // the box holds the ball of radius h around its centre and lies in the ball of radius
-    // h sqrt(3): distance from the centre to the segment decides most candidates
-    const double h = 0.5 * ds;
-    double wx = h - c[0], wy = h - c[1], wz = h - c[2];
-    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    double tc = dd > 0 ? (wx * d[0] + wy * d[1] + wz * d[2]) / dd : 0.0;
-    tc = fmin(fmax(tc, 0.0), 1.0);
-    wx = fma(-tc, d[0], wx);
-    wy = fma(-tc, d[1], wy);
-    wz = fma(-tc, d[2], wz);
-    const double dc2 = wx * wx + wy * wy + wz * wz;
-    const double rin = h + double(rho);
-    if (dc2 + err <= rin * rin) return true;
-    const double rout = h * 1.7320508075688772 + double(rho);
-    if (dc2 - err > rout * rout * (1.0 + 0x1p-40)) return false;
-  }
-  // f is convex and piecewise quadratic, so f' is monotone and piecewise linear with its
-  // breakpoints where a coordinate crosses 0 or s.  Let t_lo be the largest of {0, 1,
-  // breakpoints} with f' <= 0 and t_hi the smallest with f' >= 0: no breakpoint lies strictly
-  // between them, f' is linear there and its zero is the minimiser.
   double tb[8];
   tb[0] = 0.0;
   tb[1] = 1.0;
   for (int a = 0; a < 3; ++a) {
     double t0 = 0.0, t1 = 0.0;
-    if (di[a] != 0) {
-      const double inv = 1.0 / d[a];
-      t0 = fmin(fmax(-c[a] * inv, 0.0), 1.0);
-      t1 = fmin(fmax((ds - c[a]) * inv, 0.0), 1.0);
+    if (q.di[a] != 0) {
+      const double inv = 1.0 / q.d[a];
+      t0 = fmin(fmax(-q.c[a] * inv, 0.0), 1.0);
+      t1 = fmin(fmax((ds - q.c[a]) * inv, 0.0), 1.0);
     }
     tb[2 + 2 * a] = t0;
     tb[3 + 2 * a] = t1;
@@ -360,9 +374,9 @@ VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int
     const double t = tb[k];
     double g = 0.0;                         // f'(t) / 2
     for (int a = 0; a < 3; ++a) {
-      const double x = fma(t, d[a], c[a]);
+      const double x = fma(t, q.d[a], q.c[a]);
       const double e = x < 0 ? x : (x > ds ? x - ds : 0.0);
-      g = fma(e, d[a], g);
+      g = fma(e, q.d[a], g);
     }
     if (g <= 0.0 && t > t_lo) { t_lo = t; g_lo = g; }
     if (g >= 0.0 && t < t_hi) { t_hi = t; g_hi = g; }
@@ -372,10 +386,15 @@ VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int
   else if (t_hi > 1.0) ts = 1.0;            // f' < 0 on [0, 1]
   else if (t_hi <= t_lo || g_hi - g_lo <= 0.0) ts = t_lo;
   else ts = fmin(fmax(t_lo - g_lo * (t_hi - t_lo) / (g_hi - g_lo), t_lo), t_hi);
-  const double fmin_ = fdist2(ts, c, d, ds);
-  if (fmin_ + err <= r2) return true;
-  if (fmin_ - err > r2) return false;
-  return cap_exact(ci, di, s, rho);
+  const double fmin_ = fdist2(ts, q.c, q.d, ds);
+  if (fmin_ + q.err <= r2) return true;
+  if (fmin_ - q.err > r2) return false;
+  return cap_exact(q.ci, q.di, s, rho);
+}
+
+VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
+  const int b = cap_ball(r, v, s, Sb, rho);
+  return b >= 0 ? b == 1 : cap_bracket(r, v, s, Sb, rho);
 }
 
 // ---------------------------------------------------------------------------------------------

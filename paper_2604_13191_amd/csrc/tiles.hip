@@ -233,12 +233,15 @@ struct UnitTotal {
 // the unit kernel: test, weigh, group by voxel and sum in LDS
 // ---------------------------------------------------------------------------------------------
 struct UnitLds {
-  uint32_t* start;    // [4097] voxel starts in the grouped order
-  uint32_t* cur;      // [4096] placement cursors, then voxel ranks
+  uint32_t* start;    // [kUnitCand + 1] counts, then starts, of the unit's voxels in key order
+  uint32_t* cur;      // [kUnitCand] placement cursors
   uint16_t* key;      // [kUnitCand] unit-local Morton code of each pair
+  uint16_t* vid;      // [kUnitCand] rank of the pair's voxel among the unit's voxels
   uint16_t* idx;      // [kUnitCand] grouped order -> pair
   float* w;           // [kUnitCand]
   uint32_t* prim;     // [kUnitCand]
+  uint64_t* occ;      // [64] occupancy bitmap of the (at most 4096) unit-local keys
+  uint32_t* wpre;     // [64] voxels below each bitmap word
   int32_t* bprim;     // [kBlock] the current record batch
   int32_t* blo;       // [3][kBlock]
   int32_t* bn;        // [3][kBlock]
@@ -247,8 +250,8 @@ struct UnitLds {
   int32_t* misc;      // [8]
 };
 
-constexpr size_t kUnitLdsBytes = 4097 * 4 + 4096 * 4 + kUnitCand * (2 + 2 + 4 + 4) + kBlock * 4 * 8 +
-                                 (kWaves + 1) * 4 + 8 * 4 + 64;
+constexpr size_t kUnitLdsBytes = (kUnitCand + 1) * 4 + kUnitCand * (4 + 2 + 2 + 2 + 4 + 4) + 64 * 8 + 64 * 4 +
+                                 kBlock * 4 * 8 + (kWaves + 1) * 4 + 8 * 4 + 192;
 
 __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   UnitLds L;
@@ -258,12 +261,15 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
     off += (bytes + 7) & ~size_t(7);
     return p;
   };
-  L.start = reinterpret_cast<uint32_t*>(take(4097 * 4));
-  L.cur = reinterpret_cast<uint32_t*>(take(4096 * 4));
+  L.occ = reinterpret_cast<uint64_t*>(take(64 * 8));
+  L.start = reinterpret_cast<uint32_t*>(take((kUnitCand + 1) * 4));
+  L.cur = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
   L.w = reinterpret_cast<float*>(take(kUnitCand * 4));
   L.prim = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
   L.key = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.vid = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.wpre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.blo = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
   L.bn = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
@@ -273,44 +279,58 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   return L;
 }
 
-// Load records [j0, j0 + kBlock) of the tile clipped to the unit box; returns the batch's
-// candidate total.  Contains __syncthreads().
+// Load records [j0, j0 + kBlock) of the tile clipped to the unit box, keeping those with
+// candidates in it (compacted, in record order); returns the batch's candidate total and the
+// number of slots kept.  Contains __syncthreads().
 __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* __restrict__ rec,
                                               const uint32_t* __restrict__ rprim, int64_t j0, int64_t e,
-                                              const int32_t o[3], int32_t size) {
+                                              const int32_t o[3], int32_t size, int& nslot) {
   const int64_t j = j0 + threadIdx.x;
-  int32_t c = 0;
+  int32_t c = 0, lo[3], n[3];
+  uint32_t p = 0;
+  const int32_t* r = nullptr;
   if (j < e) {
-    const uint32_t p = rprim[j];
-    int32_t lo[3], n[3];
-    c = int32_t(clip_box(rec + int64_t(p) * kRec, o, size, lo, n));
-    S.bprim[threadIdx.x] = int32_t(p);
+    p = rprim[j];
+    r = rec + int64_t(p) * kRec;
+    c = int32_t(clip_box(r, o, size, lo, n));
+  }
+  // candidates (below 2^21 per batch) and kept slots (bits 21 and up) in one scan
+  int32_t tot;
+  const int32_t ex = block_exclusive_scan(c | (c > 0 ? (1 << 21) : 0), S.tmp32, tot);
+  if (c > 0) {
+    const int q = ex >> 21;
+    S.bprim[q] = int32_t(p);
+    S.boff[q] = ex & ((1 << 21) - 1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      S.blo[a * kBlock + threadIdx.x] = lo[a];
-      S.bn[a * kBlock + threadIdx.x] = n[a];
+      S.blo[a * kBlock + q] = lo[a];
+      S.bn[a * kBlock + q] = n[a];
     }
   }
-  int32_t tot;
-  const int32_t ex = block_exclusive_scan(c, S.tmp32, tot);
-  S.boff[threadIdx.x] = j < e ? ex : tot;
+  nslot = tot >> 21;
   __syncthreads();
-  return tot;
+  return tot & ((1 << 21) - 1);
 }
 
-// candidate c of the batch -> (record slot, voxel)
-__device__ __forceinline__ int find_slot(const UnitLds& S, int nb, int32_t c, int64_t v[3]) {
-  int lo = 0, hi = nb;                              // last slot with boff <= c
+// voxel of candidate li (x fastest) of the record in batch slot `slot`.  li < 16^3 and extents
+// <= 16: the quotients by float reciprocal are exact (the rounding error, below 1e-3, stays
+// under the 1/32 margin of (li + 1/2) / n to the next integer)
+__device__ __forceinline__ void slot_voxel(const UnitLds& S, int slot, int32_t li, int64_t v[3]) {
+  const int32_t nx = S.bn[slot], ny = S.bn[kBlock + slot];
+  const int32_t t = int32_t((float(li) + 0.5f) * __builtin_amdgcn_rcpf(float(nx)));
+  const int32_t iz = int32_t((float(t) + 0.5f) * __builtin_amdgcn_rcpf(float(ny)));
+  v[0] = S.blo[slot] + (li - t * nx);
+  v[1] = S.blo[kBlock + slot] + (t - iz * ny);
+  v[2] = S.blo[2 * kBlock + slot] + iz;
+}
+
+// candidate c of the batch -> record slot (the last slot whose first candidate is <= c)
+__device__ __forceinline__ int find_slot(const UnitLds& S, int nb, int32_t c) {
+  int lo = 0, hi = nb;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (S.boff[mid] <= c) lo = mid; else hi = mid;
   }
-  const int32_t li = c - S.boff[lo];
-  const int32_t nx = S.bn[lo], ny = S.bn[kBlock + lo];
-  const int32_t t = li / nx;
-  v[0] = S.blo[lo] + (li - t * nx);
-  v[1] = S.blo[kBlock + lo] + (t % ny);
-  v[2] = S.blo[2 * kBlock + lo] + t / ny;
   return lo;
 }
 
@@ -368,44 +388,34 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     const int64_t s = tstart[U.tile], e = tstart[U.tile + 1];
     const int32_t size = 1 << U.lev;
     const bool stream = U.cand > kUnitCand;          // a single voxel holding too many candidates
-    const uint32_t nk = 1u << (3 * U.lev);
     int32_t np = 0;                                   // pairs so far (uniform)
     Moment acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // streaming sums (thread 0)
     uint32_t acc_n = 0;
+    if (tid == 0) {
+      S.misc[4] = 0;                                  // pairs appended (LDS counter)
+      S.misc[5] = 0;                                  // undecided candidates queued
+    }
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
-      const int nb = int(e - j0 < kBlock ? e - j0 : kBlock);
-      const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, size);
-      for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
-        const int32_t c = c0 + tid;
-        bool hit = false;
-        float wgt = 0.f;
-        uint32_t lk = 0, p = 0;
-        if (c < cb) {
-          int64_t v[3];
-          const int slot = find_slot(S, nb, c, v);
-          p = uint32_t(S.bprim[slot]);
-          const int32_t* r = rec + int64_t(p) * kRec;
-          const Lat& Lp = lats ? lats[r[15]] : L;
-          hit = unit_test<KIND>(r, v, Lp);
-          if (hit) {
-            wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
-            lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
+      int nb;
+      const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, size, nb);
+      if (stream) {
+        for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
+          const int32_t c = c0 + tid;
+          bool hit = false;
+          float wgt = 0.f;
+          uint32_t p = 0;
+          if (c < cb) {
+            const int slot = find_slot(S, nb, c);
+            int64_t v[3];
+            slot_voxel(S, slot, c - S.boff[slot], v);
+            p = uint32_t(S.bprim[slot]);
+            const int32_t* r = rec + int64_t(p) * kRec;
+            const Lat& Lp = lats ? lats[r[15]] : L;
+            hit = unit_test<KIND>(r, v, Lp);
+            if (hit) wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
           }
-        }
-        int32_t tot;
-        const int32_t pos = block_exclusive_scan(int32_t(hit), S.tmp32, tot);
-        if (!stream) {
-          if (hit) {
-            const int32_t q = np + pos;
-            if (q < kUnitCand) {
-              S.key[q] = uint16_t(lk);
-              S.w[q] = wgt;
-              S.prim[q] = p;
-            } else {
-              flag_set(stats, VX_FLAG_UNIT_CAPACITY);  // planning and test disagree: never expected
-            }
-          }
-        } else {
+          int32_t tot;
+          const int32_t pos = block_exclusive_scan(int32_t(hit), S.tmp32, tot);
           // one voxel: sum this chunk's hits in order (thread 0), chunk by chunk
           if (hit) {
             S.w[pos] = wgt;
@@ -416,11 +426,96 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
             for (int32_t i = 0; i < tot; ++i) accum_pair<KIND>(acc, S.w[i], dirs[S.prim[i]]);
             acc_n += uint32_t(tot);
           }
+          np += tot;
+          __syncthreads();
         }
-        np += tot;
-        __syncthreads();
+        continue;
       }
+      // Test in two rounds so that lanes stay busy: a cheap filter decides most candidates and
+      // queues the rest (fibers: the centre-ball filter), then the queue gets the full test.
+      // Waves work independently and append with one LDS atomic per wave: the order of the pair
+      // list does not matter, since every voxel's pairs are put in primitive order before they
+      // are summed.  Weights are computed afterwards over the compacted pairs.
+      const int wv = tid >> 6, lane = tid & 63;
+      const uint64_t lt = (uint64_t(1) << lane) - 1;
+      for (int32_t c0 = wv * 64; c0 < cb; c0 += kBlock) {
+        const int32_t c = c0 + lane;
+        int res = 0;                                   // 0 miss, 1 touch, 2 undecided
+        uint32_t lk = 0, p = 0;
+        int slot = 0;
+        if (c < cb) {
+          slot = find_slot(S, nb, c);
+          int64_t v[3];
+          slot_voxel(S, slot, c - S.boff[slot], v);
+          p = uint32_t(S.bprim[slot]);
+          const int32_t* r = rec + int64_t(p) * kRec;
+          const Lat& Lp = lats ? lats[r[15]] : L;
+          if (KIND == 0) {
+            res = tri_touch(r, v, Lp.s, Lp.Sb) ? 1 : 0;
+          } else {
+            const int b = cap_ball(r, v, Lp.s, Lp.Sb, Lp.rho);
+            res = b < 0 ? 2 : b;
+          }
+          if (res == 1)
+            lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
+        }
+        const uint64_t mh = __ballot(res == 1), mb = __ballot(res == 2);
+        int32_t bh = 0, bb = 0;
+        if (lane == 0) {
+          if (mh) bh = atomicAdd(&S.misc[4], int32_t(__popcll(mh)));
+          if (mb) bb = atomicAdd(&S.misc[5], int32_t(__popcll(mb)));
+        }
+        bh = __shfl(bh, 0, 64);
+        bb = __shfl(bb, 0, 64);
+        if (res == 1) {
+          const int32_t q = bh + int32_t(__popcll(mh & lt));
+          if (q < kUnitCand) {
+            S.key[q] = uint16_t(lk);
+            S.prim[q] = p;
+          } else {
+            flag_set(stats, VX_FLAG_UNIT_CAPACITY);   // planning and test disagree: never expected
+          }
+        } else if (res == 2) {
+          const int32_t q = bb + int32_t(__popcll(mb & lt));   // undecided <= candidates <= kUnitCand
+          S.idx[q] = uint16_t(slot);
+          S.vid[q] = uint16_t(c - S.boff[slot]);
+        }
+      }
+      __syncthreads();
+      const int32_t nq = S.misc[5];
+      for (int32_t q0 = wv * 64; KIND == 1 && q0 < nq; q0 += kBlock) {
+        const int32_t q = q0 + lane;
+        bool hit = false;
+        uint32_t lk = 0, p = 0;
+        if (q < nq) {
+          const int slot = S.idx[q];
+          int64_t v[3];
+          slot_voxel(S, slot, S.vid[q], v);
+          p = uint32_t(S.bprim[slot]);
+          const int32_t* r = rec + int64_t(p) * kRec;
+          const Lat& Lp = lats ? lats[r[15]] : L;
+          hit = cap_bracket(r, v, Lp.s, Lp.Sb, Lp.rho);
+          if (hit)
+            lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
+        }
+        const uint64_t mh = __ballot(hit);
+        int32_t bh = 0;
+        if (lane == 0 && mh) bh = atomicAdd(&S.misc[4], int32_t(__popcll(mh)));
+        bh = __shfl(bh, 0, 64);
+        if (hit) {
+          const int32_t qq = bh + int32_t(__popcll(mh & lt));
+          if (qq < kUnitCand) {
+            S.key[qq] = uint16_t(lk);
+            S.prim[qq] = p;
+          } else {
+            flag_set(stats, VX_FLAG_UNIT_CAPACITY);
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) S.misc[5] = 0;                     // the next batch's queue (after its barrier)
     }
+    if (!stream) np = S.misc[4];
     if (stream) {
       if (tid == 0) {
         const int64_t nv = acc_n > 0 ? 1 : 0;
@@ -440,49 +535,34 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       continue;
     }
     const int32_t npairs = np < kUnitCand ? np : kUnitCand;
-    // group the pairs by voxel: counts, starts, placement
-    for (uint32_t k = tid; k < nk; k += kBlock) S.start[k] = 0;
-    __syncthreads();
-    for (int32_t i = tid; i < npairs; i += kBlock) atomicAdd(&S.start[S.key[i]], 1u);
-    __syncthreads();
-    // exclusive scan of counts and of voxel presence, 16 keys per thread (nk <= 4096)
-    {
-      const uint32_t per = (nk + kBlock - 1) / kBlock;
-      const uint32_t k0 = tid * per;
-      uint32_t cs = 0, vs = 0;
-      for (uint32_t k = k0; k < k0 + per && k < nk; ++k) {
-        cs += S.start[k];
-        vs += S.start[k] ? 1u : 0u;
-      }
-      int32_t tc, tv;
-      const int32_t ec = block_exclusive_scan(int32_t(cs), S.tmp32, tc);
-      const int32_t ev = block_exclusive_scan(int32_t(vs), S.tmp32, tv);
-      uint32_t rc = uint32_t(ec), rv = uint32_t(ev);
-      for (uint32_t k = k0; k < k0 + per && k < nk; ++k) {
-        const uint32_t c = S.start[k];
-        S.start[k] = rc;
-        S.cur[k] = rc;
-        rc += c;
-      }
-      if (tid == 0) {
-        S.start[nk] = uint32_t(tc);
-        S.misc[0] = tv;
-      }
-      __syncthreads();
-      // placement in the grouped order
-      for (int32_t i = tid; i < npairs; i += kBlock) {
-        const uint32_t q = atomicAdd(&S.cur[S.key[i]], 1u);
-        S.idx[q] = uint16_t(i);
-      }
-      __syncthreads();
-      // voxel ranks in key order (cur is free again)
-      for (uint32_t k = k0; k < k0 + per && k < nk; ++k) {
-        S.cur[k] = rv;
-        rv += S.start[k + 1] > S.start[k] ? 1u : 0u;
-      }
+    // weights of the compacted pairs
+    for (int32_t i = tid; i < npairs; i += kBlock) {
+      const uint32_t p = S.prim[i], k = S.key[i];
+      const int32_t* r = rec + int64_t(p) * kRec;
+      const Lat& Lp = lats ? lats[r[15]] : L;
+      const int64_t v[3] = {U.o[0] + int64_t(compact3(k)), U.o[1] + int64_t(compact3(uint64_t(k) >> 1)),
+                            U.o[2] + int64_t(compact3(uint64_t(k) >> 2))};
+      S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
     }
-    const int64_t nv = S.misc[0];
+    // group the pairs by voxel.  Voxels are ranked through an occupancy bitmap of the unit's
+    // keys, so the work below scales with pairs and voxels, not with the unit's volume.
+    if (tid < 64) S.occ[tid] = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < npairs; i += kBlock) {
+      const uint32_t k = S.key[i];
+      atomicOr(reinterpret_cast<unsigned long long*>(&S.occ[k >> 6]), 1ull << (k & 63));
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const uint32_t c = uint32_t(__popcll(S.occ[tid]));
+      const uint32_t inc = wave_inclusive_scan(c);
+      S.wpre[tid] = inc - c;
+      if (tid == 63) S.misc[0] = int32_t(inc);
+    }
+    __syncthreads();
+    const int32_t nv = S.misc[0];
     if (tid == 0) {
+      // claim the staging range now; the claim's round trip overlaps the grouping below
       const int64_t b = nv ? int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(stage_ctr),
                                                (unsigned long long)nv))
                            : 0;
@@ -493,13 +573,41 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       unp[u] = np;
       usoff[u] = b;
     }
+    for (int32_t v = tid; v < nv; v += kBlock) S.start[v] = 0;
+    for (int32_t i = tid; i < npairs; i += kBlock) {
+      const uint32_t k = S.key[i];
+      S.vid[i] = uint16_t(S.wpre[k >> 6] + uint32_t(__popcll(S.occ[k >> 6] & ((1ull << (k & 63)) - 1))));
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < npairs; i += kBlock) atomicAdd(&S.start[S.vid[i]], 1u);
+    __syncthreads();
+    {
+      const int32_t per = (nv + kBlock - 1) / kBlock;
+      const int32_t k0 = tid * per;
+      const int32_t k1 = k0 + per < nv ? k0 + per : nv;
+      uint32_t cs = 0;
+      for (int32_t k = k0; k < k1; ++k) cs += S.start[k];
+      int32_t tc;
+      uint32_t rc = uint32_t(block_exclusive_scan(int32_t(cs), S.tmp32, tc));
+      for (int32_t k = k0; k < k1; ++k) {
+        const uint32_t c = S.start[k];
+        S.start[k] = rc;
+        S.cur[k] = rc;
+        rc += c;
+      }
+      if (tid == 0) S.start[nv] = uint32_t(tc);
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < npairs; i += kBlock) {
+      const uint32_t q = atomicAdd(&S.cur[S.vid[i]], 1u);
+      S.idx[q] = uint16_t(i);
+    }
     __syncthreads();
     const int64_t b = int64_t(uint32_t(S.misc[1])) | (int64_t(S.misc[2]) << 32);
     const uint64_t hi = lats ? uint64_t(uint32_t(rec[int64_t(rprim[s]) * kRec + 15])) << kPatchShift : 0ull;
     if (b + nv <= st.cap) {
-      for (uint32_t k = tid; k < nk; k += kBlock) {
-        const uint32_t a = S.start[k], z = S.start[k + 1];
-        if (z == a) continue;
+      for (int32_t v = tid; v < nv; v += kBlock) {
+        const uint32_t a = S.start[v], z = S.start[v + 1];
         // the voxel's pairs in primitive order (insertion sort; primitives are distinct)
         for (uint32_t i = a + 1; i < z; ++i) {
           const uint16_t x = S.idx[i];
@@ -512,13 +620,26 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           S.idx[j] = x;
         }
         Moment m{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        for (uint32_t i = a; i < z; ++i) {
-          const uint16_t x = S.idx[i];
-          accum_pair<KIND>(m, S.w[x], dirs[S.prim[x]]);
+        for (uint32_t i0 = a; i0 < z; i0 += 8) {
+          // the loads of a group do not wait for each other, the sums stay in order
+          float4 t[8];
+          float wv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (i0 + k < z) {
+              const uint16_t x = S.idx[i0 + k];
+              t[k] = dirs[S.prim[x]];
+              wv[k] = S.w[x];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (i0 + k < z) accum_pair<KIND>(m, wv[k], t[k]);
         }
+        const uint32_t k = S.key[S.idx[a]];
         const uint32_t vx = U.o[0] + compact3(k), vy = U.o[1] + compact3(uint64_t(k) >> 1),
                        vz = U.o[2] + compact3(uint64_t(k) >> 2);
-        write_voxel<KIND>(st, b + S.cur[k], hi | morton3(vx, vy, vz), z - a, m);
+        write_voxel<KIND>(st, b + v, hi | morton3(vx, vy, vz), z - a, m);
       }
     }
     __syncthreads();
@@ -731,11 +852,11 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     device_scan(ArrIn64{w.unv}, ArrOut64{w.upos}, VoxTotal{w.upos, w.ctl, stats, out->cap}, w.ctl + CTL_N_UNITS, 0,
                 w.partial, s);
     if (key64)
-      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos, w.ctl,
-                         w.st, *out);
+      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(4 * kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos,
+                         w.ctl, w.st, *out);
     else
-      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos, w.ctl,
-                         w.st, *out);
+      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(4 * kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos,
+                         w.ctl, w.st, *out);
   }
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
