@@ -233,25 +233,27 @@ struct UnitTotal {
 // the unit kernel: test, weigh, group by voxel and sum in LDS
 // ---------------------------------------------------------------------------------------------
 struct UnitLds {
-  uint32_t* start;    // [kUnitCand + 1] counts, then starts, of the unit's voxels in key order
-  uint32_t* cur;      // [kUnitCand] placement cursors
+  uint32_t* start;    // [kUnitCand] counts, then starts, then ends of the unit's voxels (key order)
   uint16_t* key;      // [kUnitCand] unit-local Morton code of each pair
-  uint16_t* vid;      // [kUnitCand] rank of the pair's voxel among the unit's voxels
   uint16_t* idx;      // [kUnitCand] grouped order -> pair
-  float* w;           // [kUnitCand]
+  float* w;           // [kUnitCand] (before the weights: the queue of undecided candidates)
   uint32_t* prim;     // [kUnitCand]
   uint64_t* occ;      // [64] occupancy bitmap of the (at most 4096) unit-local keys
   uint32_t* wpre;     // [64] voxels below each bitmap word
+  uint64_t* sbm;      // [64] batch: bit c set where a slot's first candidate is c
+  uint32_t* spre;     // [64] slot starts below each word
   int32_t* bprim;     // [kBlock] the current record batch
   int32_t* blo;       // [3][kBlock]
   int32_t* bn;        // [3][kBlock]
   int32_t* boff;      // [kBlock] candidate offsets within the batch
+  int32_t* brec;      // [kBlock][9] the slot's primitive vertices (record words 0..8)
+  int32_t* bpatch;    // [kBlock] the slot's patch (batched)
   int32_t* tmp32;     // [kWaves + 1]
   int32_t* misc;      // [8]
 };
 
-constexpr size_t kUnitLdsBytes = (kUnitCand + 1) * 4 + kUnitCand * (4 + 2 + 2 + 2 + 4 + 4) + 64 * 8 + 64 * 4 +
-                                 kBlock * 4 * 8 + (kWaves + 1) * 4 + 8 * 4 + 192;
+constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4) + 2 * (64 * 8 + 64 * 4) +
+                                 kBlock * 4 * (8 + 9 + 1) + (kWaves + 1) * 4 + 8 * 4 + 256;
 
 __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   UnitLds L;
@@ -262,26 +264,28 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
     return p;
   };
   L.occ = reinterpret_cast<uint64_t*>(take(64 * 8));
-  L.start = reinterpret_cast<uint32_t*>(take((kUnitCand + 1) * 4));
-  L.cur = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
+  L.sbm = reinterpret_cast<uint64_t*>(take(64 * 8));
+  L.start = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
   L.w = reinterpret_cast<float*>(take(kUnitCand * 4));
   L.prim = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
   L.key = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
-  L.vid = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.wpre = reinterpret_cast<uint32_t*>(take(64 * 4));
+  L.spre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.blo = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
   L.bn = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
   L.boff = reinterpret_cast<int32_t*>(take(kBlock * 4));
+  L.brec = reinterpret_cast<int32_t*>(take(kBlock * 9 * 4));
+  L.bpatch = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.tmp32 = reinterpret_cast<int32_t*>(take((kWaves + 1) * 4));
   L.misc = reinterpret_cast<int32_t*>(take(8 * 4));
   return L;
 }
 
 // Load records [j0, j0 + kBlock) of the tile clipped to the unit box, keeping those with
-// candidates in it (compacted, in record order); returns the batch's candidate total and the
-// number of slots kept.  Contains __syncthreads().
+// candidates in it (compacted, in record order, with a copy of their vertices); returns the
+// batch's candidate total and the number of slots kept.  Contains __syncthreads().
 __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* __restrict__ rec,
                                               const uint32_t* __restrict__ rprim, int64_t j0, int64_t e,
                                               const int32_t o[3], int32_t size, int& nslot) {
@@ -289,6 +293,7 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
   int32_t c = 0, lo[3], n[3];
   uint32_t p = 0;
   const int32_t* r = nullptr;
+  if (threadIdx.x < 64) S.sbm[threadIdx.x] = 0;
   if (j < e) {
     p = rprim[j];
     r = rec + int64_t(p) * kRec;
@@ -299,15 +304,26 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
   const int32_t ex = block_exclusive_scan(c | (c > 0 ? (1 << 21) : 0), S.tmp32, tot);
   if (c > 0) {
     const int q = ex >> 21;
+    const int32_t off = ex & ((1 << 21) - 1);
     S.bprim[q] = int32_t(p);
-    S.boff[q] = ex & ((1 << 21) - 1);
+    S.boff[q] = off;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       S.blo[a * kBlock + q] = lo[a];
       S.bn[a * kBlock + q] = n[a];
     }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S.brec[q * 9 + k] = r[k];
+    S.bpatch[q] = r[15];
+    atomicOr(reinterpret_cast<unsigned long long*>(&S.sbm[off >> 6]), 1ull << (off & 63));
   }
   nslot = tot >> 21;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const uint32_t cnt = uint32_t(__popcll(S.sbm[threadIdx.x]));
+    const uint32_t inc = wave_inclusive_scan(cnt);
+    S.spre[threadIdx.x] = inc - cnt;
+  }
   __syncthreads();
   return tot & ((1 << 21) - 1);
 }
@@ -324,14 +340,10 @@ __device__ __forceinline__ void slot_voxel(const UnitLds& S, int slot, int32_t l
   v[2] = S.blo[2 * kBlock + slot] + iz;
 }
 
-// candidate c of the batch -> record slot (the last slot whose first candidate is <= c)
-__device__ __forceinline__ int find_slot(const UnitLds& S, int nb, int32_t c) {
-  int lo = 0, hi = nb;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (S.boff[mid] <= c) lo = mid; else hi = mid;
-  }
-  return lo;
+// candidate c (< 4096) of the batch -> its record slot: the slot starts at or below c, less one
+__device__ __forceinline__ int find_slot(const UnitLds& S, int32_t c) {
+  const int wd = c >> 6;
+  return int(S.spre[wd] + uint32_t(__popcll(S.sbm[wd] & ((2ull << (c & 63)) - 1)))) - 1;
 }
 
 template <int KIND>
@@ -398,6 +410,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
       int nb;
       const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, size, nb);
+      (void)nb;
       if (stream) {
         for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
           const int32_t c = c0 + tid;
@@ -405,12 +418,12 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           float wgt = 0.f;
           uint32_t p = 0;
           if (c < cb) {
-            const int slot = find_slot(S, nb, c);
+            const int slot = find_slot(S, c);
             int64_t v[3];
             slot_voxel(S, slot, c - S.boff[slot], v);
             p = uint32_t(S.bprim[slot]);
-            const int32_t* r = rec + int64_t(p) * kRec;
-            const Lat& Lp = lats ? lats[r[15]] : L;
+            const int32_t* r = S.brec + slot * 9;
+            const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
             hit = unit_test<KIND>(r, v, Lp);
             if (hit) wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
           }
@@ -444,12 +457,12 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
         uint32_t lk = 0, p = 0;
         int slot = 0;
         if (c < cb) {
-          slot = find_slot(S, nb, c);
+          slot = find_slot(S, c);
           int64_t v[3];
           slot_voxel(S, slot, c - S.boff[slot], v);
           p = uint32_t(S.bprim[slot]);
-          const int32_t* r = rec + int64_t(p) * kRec;
-          const Lat& Lp = lats ? lats[r[15]] : L;
+          const int32_t* r = S.brec + slot * 9;
+          const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
           if (KIND == 0) {
             res = tri_touch(r, v, Lp.s, Lp.Sb) ? 1 : 0;
           } else {
@@ -477,8 +490,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           }
         } else if (res == 2) {
           const int32_t q = bb + int32_t(__popcll(mb & lt));   // undecided <= candidates <= kUnitCand
-          S.idx[q] = uint16_t(slot);
-          S.vid[q] = uint16_t(c - S.boff[slot]);
+          reinterpret_cast<uint32_t*>(S.w)[q] = (uint32_t(slot) << 16) | uint32_t(c - S.boff[slot]);
         }
       }
       __syncthreads();
@@ -488,12 +500,13 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
         bool hit = false;
         uint32_t lk = 0, p = 0;
         if (q < nq) {
-          const int slot = S.idx[q];
+          const uint32_t qe = reinterpret_cast<const uint32_t*>(S.w)[q];
+          const int slot = int(qe >> 16);
           int64_t v[3];
-          slot_voxel(S, slot, S.vid[q], v);
+          slot_voxel(S, slot, int32_t(qe & 0xffff), v);
           p = uint32_t(S.bprim[slot]);
-          const int32_t* r = rec + int64_t(p) * kRec;
-          const Lat& Lp = lats ? lats[r[15]] : L;
+          const int32_t* r = S.brec + slot * 9;
+          const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
           hit = cap_bracket(r, v, Lp.s, Lp.Sb, Lp.rho);
           if (hit)
             lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
@@ -573,13 +586,12 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       unp[u] = np;
       usoff[u] = b;
     }
+    auto voxel_rank = [&](uint32_t k) {
+      return S.wpre[k >> 6] + uint32_t(__popcll(S.occ[k >> 6] & ((1ull << (k & 63)) - 1)));
+    };
     for (int32_t v = tid; v < nv; v += kBlock) S.start[v] = 0;
-    for (int32_t i = tid; i < npairs; i += kBlock) {
-      const uint32_t k = S.key[i];
-      S.vid[i] = uint16_t(S.wpre[k >> 6] + uint32_t(__popcll(S.occ[k >> 6] & ((1ull << (k & 63)) - 1))));
-    }
     __syncthreads();
-    for (int32_t i = tid; i < npairs; i += kBlock) atomicAdd(&S.start[S.vid[i]], 1u);
+    for (int32_t i = tid; i < npairs; i += kBlock) atomicAdd(&S.start[voxel_rank(S.key[i])], 1u);
     __syncthreads();
     {
       const int32_t per = (nv + kBlock - 1) / kBlock;
@@ -592,14 +604,13 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       for (int32_t k = k0; k < k1; ++k) {
         const uint32_t c = S.start[k];
         S.start[k] = rc;
-        S.cur[k] = rc;
         rc += c;
       }
-      if (tid == 0) S.start[nv] = uint32_t(tc);
     }
     __syncthreads();
+    // placement: afterwards start[v] is the end of voxel v's range
     for (int32_t i = tid; i < npairs; i += kBlock) {
-      const uint32_t q = atomicAdd(&S.cur[S.vid[i]], 1u);
+      const uint32_t q = atomicAdd(&S.start[voxel_rank(S.key[i])], 1u);
       S.idx[q] = uint16_t(i);
     }
     __syncthreads();
@@ -607,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     const uint64_t hi = lats ? uint64_t(uint32_t(rec[int64_t(rprim[s]) * kRec + 15])) << kPatchShift : 0ull;
     if (b + nv <= st.cap) {
       for (int32_t v = tid; v < nv; v += kBlock) {
-        const uint32_t a = S.start[v], z = S.start[v + 1];
+        const uint32_t a = v ? S.start[v - 1] : 0u, z = S.start[v];
         // the voxel's pairs in primitive order (insertion sort; primitives are distinct)
         for (uint32_t i = a + 1; i < z; ++i) {
           const uint16_t x = S.idx[i];
