@@ -226,7 +226,7 @@ size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs,
     return 0;
   for (int L = 0; L <= hi; ++L)
     if (caps[L] < 1) return 0;
-  return fit_ws_bytes(n_pts, max_cand, max_pairs, caps, hi, log2_res > 10);
+  return fit_ws_bytes(n_pts, max_cand, max_pairs, caps, hi, log2_res);
 }
 
 static bool fit_args_ok(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
@@ -245,7 +245,7 @@ vx_status vx_fit_forward(const vx_grid* grid, const vx_voxels* levels, const int
                          int32_t hi, const float* const* params, const float* dirs, int32_t ndir, float* loss,
                          const int64_t* caps, void* ws, size_t ws_bytes, vx_stream stream) {
   if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, dirs, ndir, caps) || !loss) return VX_ERR_ARG;
-  if (!ws_ok(ws, ws_bytes, fit_ws_bytes(0, 0, 0, caps, hi, grid->log2_res > 10))) return VX_ERR_WORKSPACE;
+  if (!ws_ok(ws, ws_bytes, fit_ws_bytes(0, 0, 0, caps, hi, grid->log2_res))) return VX_ERR_WORKSPACE;
   return fit_forward_run(grid, levels, n_levels, lo, hi, params, dirs, ndir, loss, ws, caps,
                          reinterpret_cast<hipStream_t>(stream));
 }
@@ -263,7 +263,7 @@ vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fib, int64_t max
   if (!(fib->radius >= 0.0f) || !std::isfinite(fib->radius)) return VX_ERR_ARG;
   for (int L = lo; L <= hi; ++L)
     if (!dparams[L - lo]) return VX_ERR_ARG;
-  if (!ws_ok(ws, ws_bytes, fit_ws_bytes(fib->n_pts, max_cand, max_pairs, caps, hi, grid->log2_res > 10)))
+  if (!ws_ok(ws, ws_bytes, fit_ws_bytes(fib->n_pts, max_cand, max_pairs, caps, hi, grid->log2_res)))
     return VX_ERR_WORKSPACE;
   return fit_backward_run(grid, fib->pts, fib->n_pts, fib->offsets, fib->n_fibers, fib->radius, max_cand, max_pairs,
                           levels, n_levels, lo, hi, params, dirs, ndir, dloss, dparams, dpts, stats, ws, caps,

@@ -34,81 +34,131 @@ __device__ __forceinline__ float quadf(const float* S, float x, float y, float z
 
 constexpr int kMaxChild = 8;
 
-// children of parent key pk in the level below: [first, first + nc)
-template <class Key>
-__device__ __forceinline__ int child_range(const Key* ck, int64_t nch, uint64_t pk, int64_t& first) {
-  first = key_lower_bound(ck, nch, pk << 3);
+// children of voxel u in the level below: [cstart[u], cstart[u + 1]), at most 8
+__device__ __forceinline__ int child_range(const int64_t* __restrict__ cstart, int64_t u, int64_t& first) {
+  first = cstart[u];
+  const int64_t n = cstart[u + 1] - first;
+  return int(n < kMaxChild ? n : kMaxChild);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Layout of both passes: 16 lanes per voxel (four voxels per wave), each lane taking every 16th
+// direction; a voxel's children (w, S) are staged in LDS by its group, the directions of the set
+// once per block.  Sums over a group's lanes are butterfly reductions over 16 lanes.
+// ---------------------------------------------------------------------------------------------
+constexpr int kGroup = 16;                      // lanes per voxel
+constexpr int kGroups = kBlock / kGroup;        // voxels in flight per block
+constexpr int kMaxDir = 256;
+
+template <class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = kGroup / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kGroup);
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// the children of voxel u staged by the group: cw[c], cS[c][6]; returns their number
+__device__ __forceinline__ int stage_children(const vx_voxels& ch, const int64_t* cstart, int64_t u, bool active,
+                                              int gl, float* cw, float (*cS)[6], int64_t& first) {
   int nc = 0;
-  while (nc < kMaxChild && first + nc < nch && (uint64_t(ck[first + nc]) >> 3) == pk) ++nc;
+  first = 0;
+  if (active) nc = child_range(cstart, u, first);
+  if (active && gl < nc) {
+    const int64_t cc = first + gl;
+    cw[gl] = ch.w[cc];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) cS[gl][t] = ch.S[int64_t(t) * ch.cap + cc];
+  }
+  wave_sync_lds();
   return nc;
 }
 
 // ---------------------------------------------------------------------------------------------
-// forward: one wave per voxel, lanes over directions
+// forward
 // ---------------------------------------------------------------------------------------------
-template <class Key>
 __global__ void __launch_bounds__(kBlock) k_fit_fwd(vx_voxels par, const int64_t* n_par_p, vx_voxels ch,
-                                                    const int64_t* n_ch_p, const float* __restrict__ Lp,
+                                                    const int64_t* __restrict__ cstart, const float* __restrict__ Lp,
                                                     const float* __restrict__ dirs, int ndir,
                                                     float* __restrict__ loss_vox) {
-  const int lane = lane_id();
-  const int64_t n_par = *n_par_p, n_ch = *n_ch_p;
-  const Key* pk = reinterpret_cast<const Key*>(par.keys);
-  const Key* ck = reinterpret_cast<const Key*>(ch.keys);
-  for (int64_t u = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6); u < n_par; u += int64_t(gridDim.x) * kWaves) {
-    const float W = par.w[u];
-    if (!(W > 0.f)) {
-      if (lane == 0) loss_vox[u] = 0.f;
-      continue;
-    }
+  __shared__ float sdir[kMaxDir][3];
+  __shared__ float scw[kGroups][kMaxChild];
+  __shared__ float scS[kGroups][kMaxChild][6];
+  for (int k = threadIdx.x; k < ndir; k += kBlock)
+    for (int a = 0; a < 3; ++a) sdir[k][a] = dirs[3 * k + a];
+  __syncthreads();
+  const int grp = threadIdx.x / kGroup, gl = threadIdx.x % kGroup;
+  const int64_t n_par = *n_par_p;
+  // the four groups of a wave advance together (uniform trip count per wave)
+  const int wgrp0 = (threadIdx.x >> 6) * (64 / kGroup);
+  for (int64_t u0 = int64_t(blockIdx.x) * kGroups + wgrp0; u0 < n_par; u0 += int64_t(gridDim.x) * kGroups) {
+    const int64_t u = u0 + (grp - wgrp0);
+    const bool in = u < n_par;
+    const float W = in ? par.w[u] : 0.f;
+    const bool active = in && W > 0.f;
     int64_t first;
-    const int nc = child_range(ck, n_ch, uint64_t(pk[u]), first);
-    float cw[kMaxChild], cS[kMaxChild][6];
-#pragma unroll
-    for (int c = 0; c < kMaxChild; ++c) {
-      cw[c] = c < nc ? ch.w[first + c] : 0.f;
-#pragma unroll
-      for (int t = 0; t < 6; ++t) cS[c][t] = c < nc ? ch.S[int64_t(t) * ch.cap + first + c] : 0.f;
-    }
-    float l[12];
-    for (int t = 0; t < 12; ++t) l[t] = Lp[u * 12 + t];
-    const float invW = 1.0f / W;
+    const int nc = stage_children(ch, cstart, u, active, gl, scw[grp], scS[grp], first);
     float acc = 0.f;
-    for (int k = lane; k < ndir; k += 64) {
-      const float x = dirs[3 * k], y = dirs[3 * k + 1], z = dirs[3 * k + 2];
-      float tau = 0.f;
-#pragma unroll
-      for (int c = 0; c < kMaxChild; ++c)
-        if (c < nc && cw[c] > 0.f) tau += sqrtf(fmaxf(cw[c] * quadf(cS[c], x, y, z), 0.f));
-      tau *= invW;
-      float f = 0.f;
-      for (int j = 0; j < 2; ++j) {
-        const float* lj = l + 6 * j;
-        const float y0 = lj[0] * x + lj[1] * y + lj[3] * z, y1 = lj[2] * y + lj[4] * z, y2 = lj[5] * z;
-        f += sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+    if (active) {
+      float l[12];
+      for (int t = 0; t < 12; ++t) l[t] = Lp[u * 12 + t];
+      const float invW = 1.0f / W;
+      for (int k = gl; k < ndir; k += kGroup) {
+        const float x = sdir[k][0], y = sdir[k][1], z = sdir[k][2];
+        float tau = 0.f;
+        for (int c = 0; c < nc; ++c)
+          if (scw[grp][c] > 0.f) tau += sqrtf(fmaxf(scw[grp][c] * quadf(scS[grp][c], x, y, z), 0.f));
+        tau *= invW;
+        float f = 0.f;
+        for (int j = 0; j < 2; ++j) {
+          const float* lj = l + 6 * j;
+          const float y0 = lj[0] * x + lj[1] * y + lj[3] * z, y1 = lj[2] * y + lj[4] * z, y2 = lj[5] * z;
+          f += sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+        }
+        const float r = f - tau;
+        acc = fmaf(r, r, acc);
       }
-      const float r = f - tau;
-      acc = fmaf(r, r, acc);
     }
-    acc = wave_sum(acc);
-    if (lane == 0) loss_vox[u] = acc / float(ndir);
+    acc = group_sum(acc);
+    if (in && gl == 0) loss_vox[u] = active ? acc / float(ndir) : 0.f;
+    wave_sync_lds();                                  // the group's LDS slots are reused next
   }
 }
 
-// deterministic sum of the per-voxel losses of all levels into loss[0] (one block)
+// deterministic sum of the per-voxel losses of all levels into loss[0]: fixed per-block chunks
+// of every level, then one block adds the block sums in order
 struct LossLevels {
   const float* p[24];
   const int64_t* n[24];
   int count;
 };
 
-__global__ void __launch_bounds__(1024) k_fit_total(LossLevels lv, float* loss) {
-  __shared__ float red[16];
+__global__ void __launch_bounds__(kBlock) k_fit_partial(LossLevels lv, float* __restrict__ part) {
+  __shared__ float red[kWaves];
   float acc = 0.f;
   for (int i = 0; i < lv.count; ++i) {
     const int64_t n = *lv.n[i];
-    for (int64_t j = threadIdx.x; j < n; j += 1024) acc += lv.p[i][j];
+    const int64_t chunk = (n + kGrid - 1) / kGrid;
+    const int64_t b0 = int64_t(blockIdx.x) * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+    for (int64_t j = b0 + threadIdx.x; j < b1; j += kBlock) acc += lv.p[i][j];
   }
+  acc = wave_sum(acc);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w = 0; w < kWaves; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_fit_total(const float* __restrict__ part, float* loss) {
+  __shared__ float red[16];
+  float acc = threadIdx.x < kGrid ? part[threadIdx.x] : 0.f;
   acc = wave_sum(acc);
   if (lane_id() == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -123,62 +173,58 @@ __global__ void __launch_bounds__(1024) k_fit_total(LossLevels lv, float* loss) 
 // backward per voxel: lobe gradients and the gradient of the target w.r.t. the children's sums.
 // FP64: the derivative of the target along a child's own (w, S) direction nearly cancels (the
 // target is invariant when all children scale alike), so the parts must be accurate.
-// gch: [7][gcap] (S components, then w) for the level below
+// gch: [7][gcap] (S components, then w) for the level below.  DPL: directions per lane.
 // ---------------------------------------------------------------------------------------------
-constexpr int kMaxDirPerLane = 4;     // up to 256 directions
-
-__device__ __forceinline__ double quadd(const double* S, double x, double y, double z) {
-  return S[0] * x * x + S[1] * y * y + S[2] * z * z + 2.0 * (S[3] * x * y + S[4] * x * z + S[5] * y * z);
+__device__ __forceinline__ double quadd(const float* S, double x, double y, double z) {
+  return double(S[0]) * x * x + double(S[1]) * y * y + double(S[2]) * z * z +
+         2.0 * (double(S[3]) * x * y + double(S[4]) * x * z + double(S[5]) * y * z);
 }
 
-template <class Key>
+template <int DPL>
 __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t* n_par_p, vx_voxels ch,
-                                                    const int64_t* n_ch_p, const float* __restrict__ Lp,
+                                                    const int64_t* __restrict__ cstart, const float* __restrict__ Lp,
                                                     const float* __restrict__ dirs, int ndir,
                                                     const float* __restrict__ dloss, float* __restrict__ dLp,
                                                     double* __restrict__ gch, int64_t gcap) {
-  const int lane = lane_id();
-  const int64_t n_par = *n_par_p, n_ch = *n_ch_p;
-  const Key* pk = reinterpret_cast<const Key*>(par.keys);
-  const Key* ck = reinterpret_cast<const Key*>(ch.keys);
+  __shared__ float sdir[kMaxDir][3];
+  __shared__ float scw[kGroups][kMaxChild];
+  __shared__ float scS[kGroups][kMaxChild][6];
+  for (int k = threadIdx.x; k < ndir; k += kBlock)
+    for (int a = 0; a < 3; ++a) sdir[k][a] = dirs[3 * k + a];
+  __syncthreads();
+  const int grp = threadIdx.x / kGroup, gl = threadIdx.x % kGroup;
+  const int64_t n_par = *n_par_p;
   const double g0 = double(dloss[0]);
-  for (int64_t u = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6); u < n_par; u += int64_t(gridDim.x) * kWaves) {
-    const float Wf = par.w[u];
-    if (!(Wf > 0.f)) {
-      if (lane < 12) dLp[u * 12 + lane] = 0.f;
-      continue;
-    }
+  const double g2 = 2.0 / double(ndir) * g0;
+  const int wgrp0 = (threadIdx.x >> 6) * (64 / kGroup);
+  for (int64_t u0 = int64_t(blockIdx.x) * kGroups + wgrp0; u0 < n_par; u0 += int64_t(gridDim.x) * kGroups) {
+    const int64_t u = u0 + (grp - wgrp0);
+    const bool in = u < n_par;
+    const float Wf = in ? par.w[u] : 0.f;
+    const bool active = in && Wf > 0.f;
     int64_t first;
-    const int nc = child_range(ck, n_ch, uint64_t(pk[u]), first);
-    double l[12];
+    const int nc = stage_children(ch, cstart, u, active, gl, scw[grp], scS[grp], first);
+    const float* cw = scw[grp];
+    double l[12], gl12[12], dg[DPL], dt[DPL];
 #pragma unroll
-    for (int t = 0; t < 12; ++t) l[t] = double(Lp[u * 12 + t]);
-    const double invW = 1.0 / double(Wf);
-    // pass 1 (lanes over directions): target, fit, residual; lobe gradients
-    double dx[kMaxDirPerLane], dy[kMaxDirPerLane], dz[kMaxDirPerLane], dg[kMaxDirPerLane], dt[kMaxDirPerLane];
-    double gl[12];
+    for (int t = 0; t < 12; ++t) {
+      l[t] = active ? double(Lp[u * 12 + t]) : 0.0;
+      gl12[t] = 0.0;
+    }
+    const double invW = active ? 1.0 / double(Wf) : 0.0;
+    // pass 1 (this lane's directions): target, fit, residual; lobe gradients
 #pragma unroll
-    for (int t = 0; t < 12; ++t) gl[t] = 0.0;
-#pragma unroll
-    for (int i = 0; i < kMaxDirPerLane; ++i) {
-      const int k = lane + 64 * i;
+    for (int i = 0; i < DPL; ++i) {
+      const int k = gl + kGroup * i;
       dg[i] = 0.0;
       dt[i] = 0.0;
-      dx[i] = dy[i] = dz[i] = 0.0;
-      if (k >= ndir) continue;
-      const double x = dirs[3 * k], y = dirs[3 * k + 1], z = dirs[3 * k + 2];
-      dx[i] = x;
-      dy[i] = y;
-      dz[i] = z;
+      if (!active || k >= ndir) continue;
+      const double x = sdir[k][0], y = sdir[k][1], z = sdir[k][2];
       double tau = 0.0;
       for (int c = 0; c < nc; ++c) {
-        const int64_t cc = first + c;
-        const double wc = double(ch.w[cc]);
+        const double wc = double(cw[c]);
         if (!(wc > 0.0)) continue;
-        double S[6];
-#pragma unroll
-        for (int t = 0; t < 6; ++t) S[t] = double(ch.S[int64_t(t) * ch.cap + cc]);
-        tau += sqrt(fmax(wc * quadd(S, x, y, z), 0.0));
+        tau += sqrt(fmax(wc * quadd(scS[grp][c], x, y, z), 0.0));
       }
       tau *= invW;
       double f = 0.0, yv[2][3], ny[2];
@@ -191,77 +237,88 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
         ny[j] = sqrt(yv[j][0] * yv[j][0] + yv[j][1] * yv[j][1] + yv[j][2] * yv[j][2]);
         f += ny[j];
       }
-      const double g = 2.0 * (f - tau) / double(ndir) * g0;     // d loss / d f;  d loss / d tau = -g
+      const double g = (f - tau) * g2;                          // d loss / d f;  d loss / d tau = -g
       dg[i] = g;
       dt[i] = tau;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         if (!(ny[j] > 0.0)) continue;
-        const double s = g / ny[j];
-        double* gj = gl + 6 * j;
-        gj[0] += s * yv[j][0] * x;
-        gj[1] += s * yv[j][0] * y;
-        gj[2] += s * yv[j][1] * y;
-        gj[3] += s * yv[j][0] * z;
-        gj[4] += s * yv[j][1] * z;
-        gj[5] += s * yv[j][2] * z;
+        const double sj = g / ny[j];
+        double* gj = gl12 + 6 * j;
+        gj[0] += sj * yv[j][0] * x;
+        gj[1] += sj * yv[j][0] * y;
+        gj[2] += sj * yv[j][1] * y;
+        gj[3] += sj * yv[j][0] * z;
+        gj[4] += sj * yv[j][1] * z;
+        gj[5] += sj * yv[j][2] * z;
       }
     }
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
-      const double v = wave_sum(gl[t]);
-      if (lane == t) dLp[u * 12 + t] = float(v);
+      const double v = group_sum(gl12[t]);
+      if (active && gl == t) dLp[u * 12 + t] = float(v);
     }
+    if (in && !active && gl < 12) dLp[u * 12 + gl] = 0.f;
     // pass 2 (one child at a time): d loss / d (S_c, w_c)
-    for (int c = 0; c < nc; ++c) {
-      const int64_t cc = first + c;
-      const double wc = double(ch.w[cc]);
-      double S[6];
-#pragma unroll
-      for (int t = 0; t < 6; ++t) S[t] = double(ch.S[int64_t(t) * ch.cap + cc]);
+    for (int c = 0; c < kMaxChild; ++c) {
+      if (!__any(active && c < nc)) break;                 // uniform over the wave
       double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-      if (wc > 0.0) {
+      const bool on = active && c < nc;
+      const double wc = on ? double(cw[c]) : 0.0;
+      if (on && wc > 0.0) {
 #pragma unroll
-        for (int i = 0; i < kMaxDirPerLane; ++i) {
-          if (lane + 64 * i >= ndir) continue;
-          const double x = dx[i], y = dy[i], z = dz[i], g = dg[i];
-          const double qs = quadd(S, x, y, z);
+        for (int i = 0; i < DPL; ++i) {
+          const int k = gl + kGroup * i;
+          if (k >= ndir) continue;
+          const double x = sdir[k][0], y = sdir[k][1], z = sdir[k][2], g = dg[i];
+          const double qs = quadd(scS[grp][c], x, y, z);
           const double q = sqrt(fmax(wc * qs, 0.0));
           double dw = -dt[i] * invW;
           if (q > 0.0) {
-            const double k2 = -g * wc / (2.0 * q) * invW;      // d loss / d (w^T S_c w)
+            const double h = 0.5 / q * invW;
+            const double k2 = -g * wc * h;                      // d loss / d (w^T S_c w)
             acc[0] += k2 * x * x;
             acc[1] += k2 * y * y;
             acc[2] += k2 * z * z;
             acc[3] += k2 * 2.0 * x * y;
             acc[4] += k2 * 2.0 * x * z;
             acc[5] += k2 * 2.0 * y * z;
-            dw += qs / (2.0 * q) * invW;
+            dw += qs * h;
           }
           acc[6] += -g * dw;
         }
       }
 #pragma unroll
       for (int t = 0; t < 7; ++t) {
-        const double v = wave_sum(acc[t]);
-        if (lane == t) gch[int64_t(t) * gcap + cc] = v;
+        const double v = group_sum(acc[t]);
+        if (on && gl == t) gch[int64_t(t) * gcap + first + c] = v;
       }
     }
+    wave_sync_lds();                                  // the group's LDS slots are reused next
   }
 }
 
 // top-down: every voxel of level L adds its parent's accumulated gradient (level L+1)
-template <class Key>
-__global__ void __launch_bounds__(kBlock) k_fit_down(vx_voxels lv, const int64_t* n_p, double* __restrict__ g,
-                                                     int64_t gcap, vx_voxels up, const int64_t* n_up_p,
+__global__ void __launch_bounds__(kBlock) k_fit_down(const int32_t* __restrict__ pidx, const int64_t* n_p,
+                                                     double* __restrict__ g, int64_t gcap,
                                                      const double* __restrict__ gup, int64_t gupcap) {
-  const int64_t n = *n_p, n_up = *n_up_p;
-  const Key* k = reinterpret_cast<const Key*>(lv.keys);
-  const Key* ku = reinterpret_cast<const Key*>(up.keys);
+  const int64_t n = *n_p;
   for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n; c += int64_t(gridDim.x) * kBlock) {
-    const int64_t p = key_lower_bound(ku, n_up, uint64_t(k[c]) >> 3);
-    if (p >= n_up) continue;
+    const int64_t p = pidx[c];
+#pragma unroll
     for (int t = 0; t < 7; ++t) g[int64_t(t) * gcap + c] += gup[int64_t(t) * gupcap + p];
+  }
+}
+
+// leaf lookup table: first and end leaf index of every 16^3 tile (empty tiles: 0, 0)
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_tile_index(const Key* __restrict__ keys, const int64_t* n_p,
+                                                       int64_t* __restrict__ tfirst, int64_t* __restrict__ tend) {
+  const int64_t n = *n_p;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    const uint64_t t = uint64_t(keys[i]) >> (3 * kTileBits);
+    if (i == 0 || (uint64_t(keys[i - 1]) >> (3 * kTileBits)) != t) tfirst[t] = i;
+    if (i == n - 1 || (uint64_t(keys[i + 1]) >> (3 * kTileBits)) != t) tend[t] = i + 1;
   }
 }
 
@@ -275,7 +332,8 @@ __global__ void __launch_bounds__(kBlock) k_fit_pairs(const int32_t* __restrict_
                                                       const int64_t* __restrict__ ctl, const Key* __restrict__ pkeys,
                                                       vx_voxels leaf, const int64_t* n_leaf_p,
                                                       const double* __restrict__ gleaf, int64_t gcap, int Sb,
-                                                      int log2R, double vs, float* __restrict__ seg_grad) {
+                                                      int log2R, double vs, const int64_t* __restrict__ tfirst,
+                                                      const int64_t* __restrict__ tend, float* __restrict__ seg_grad) {
   const int64_t n_leaf = *n_leaf_p;
   const int64_t n_cand = ctl[CTL_N_CAND];
   const int64_t n_pairs = ctl[CTL_N_PAIRS];
@@ -313,7 +371,15 @@ __global__ void __launch_bounds__(kBlock) k_fit_pairs(const int32_t* __restrict_
         double dA[3], dB[3];
         const double w = seg_length_grad(A, B, lo, dA, dB);
         if (!(w > 0.0)) continue;
-        const int64_t v = key_lower_bound(lk, n_leaf, key);
+        int64_t v;
+        if (tfirst) {
+          const uint64_t t = key >> (3 * kTileBits);
+          const int64_t a = tfirst[t], b = tend[t];
+          v = a + key_lower_bound(lk + a, b - a, key);
+          if (v >= b) continue;
+        } else {
+          v = key_lower_bound(lk, n_leaf, key);
+        }
         if (v >= n_leaf || uint64_t(lk[v]) != key) continue;
         double gS[6];
         for (int q = 0; q < 6; ++q) gS[q] = gleaf[int64_t(q) * gcap + v];
@@ -365,24 +431,71 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
 struct FitWs {
   float* loss_vox[21];
   double* g[21];           // [7][cap_L] per level 0..hi-1
+  int64_t* cstart[21];     // [cap_L + 1] per level 1..hi: first child (in level L-1) of every voxel
+  int32_t* pidx[21];       // [cap_L] per level 0..hi-1: index of every voxel's parent in level L+1
+  int64_t* tfirst;         // [tiles] leaf lookup: first and end leaf index of every 16^3 tile
+  int64_t* tend;
+  float* part;             // [kGrid] block sums of the loss
+  int64_t* partial;        // [kGrid + 1] scan partials
   float* seg_grad;         // [n_pts][6]
   FrontWs f;
 };
 
+// dense table of 16^3 tiles for the leaf lookup of the backward pass (grids up to 2048^3)
+static int64_t leaf_tiles(int log2R) {
+  return log2R > kTileBits && log2R <= 11 ? int64_t(1) << (3 * (log2R - kTileBits)) : 0;
+}
+
 static size_t fit_ws_layout(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi,
-                            bool key64, void* base, FitWs* w) {
+                            int log2R, void* base, FitWs* w) {
+  const bool key64 = log2R > 10;
   Carver cv(base);
   FitWs x;
   for (int L = 0; L <= hi; ++L) x.loss_vox[L] = cv.take<float>(caps[L]);
   for (int L = 0; L < hi; ++L) x.g[L] = cv.take<double>(7 * caps[L]);
+  for (int L = 1; L <= hi; ++L) x.cstart[L] = cv.take<int64_t>(caps[L] + 1);
+  for (int L = 0; L < hi; ++L) x.pidx[L] = cv.take<int32_t>(caps[L]);
+  const int64_t tiles = leaf_tiles(log2R);
+  x.tfirst = cv.take<int64_t>(tiles);
+  x.tend = cv.take<int64_t>(tiles);
+  x.part = cv.take<float>(kGrid);
+  x.partial = cv.take<int64_t>(kGrid + 1);
   x.seg_grad = cv.take<float>(6 * n_pts);
   front_ws_carve(cv, n_pts, max_cand, max_pairs, key64, &x.f);
   if (w) *w = x;
   return cv.off + 256;
 }
 
-size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, bool key64) {
-  return fit_ws_layout(n_pts, max_cand, max_pairs, caps, hi, key64, nullptr, nullptr);
+size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, int log2R) {
+  return fit_ws_layout(n_pts, max_cand, max_pairs, caps, hi, log2R, nullptr, nullptr);
+}
+
+struct StartTotal {
+  int64_t* start;
+  __device__ void operator()(int64_t total, int64_t n) const { start[total] = n; }
+};
+// heads of the parent key: the parent's first child, and every child's parent index
+struct ChildOut {
+  int64_t* start;
+  int32_t* parent;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t v) const {
+    if (v) start[ex] = i;
+    parent[i] = int32_t(ex + v - 1);
+  }
+};
+
+// first child of every voxel of levels 1..hi: heads of the parent key over each level below
+static void child_starts(bool key64, const vx_voxels* levels, const int64_t* n_levels, int hi, const FitWs& w,
+                         hipStream_t s) {
+  VX_TIMED("fit_children", s);
+  for (int L = 1; L <= hi; ++L) {
+    if (key64)
+      device_scan(HeadIn<uint64_t, 3>{(const uint64_t*)levels[L - 1].keys}, ChildOut{w.cstart[L], w.pidx[L - 1]},
+                  StartTotal{w.cstart[L]}, n_levels + L - 1, 0, w.partial, s);
+    else
+      device_scan(HeadIn<uint32_t, 3>{(const uint32_t*)levels[L - 1].keys}, ChildOut{w.cstart[L], w.pidx[L - 1]},
+                  StartTotal{w.cstart[L]}, n_levels + L - 1, 0, w.partial, s);
+  }
 }
 
 static int blocks_for(int64_t n) {
@@ -395,22 +508,21 @@ vx_status fit_forward_run(const vx_grid* g, const vx_voxels* levels, const int64
                           const int64_t* caps, hipStream_t s) {
   const bool key64 = g->log2_res > 10;
   FitWs w;
-  fit_ws_layout(0, 0, 0, caps, hi, key64, ws, &w);
+  fit_ws_layout(0, 0, 0, caps, hi, g->log2_res, ws, &w);
+  child_starts(key64, levels, n_levels, hi, w, s);
   LossLevels ll;
   ll.count = 0;
   for (int L = lo; L <= hi; ++L) {
     VX_TIMED("fit_fwd", s);
-#define VX_FWD(K)                                                                                              \
-  hipLaunchKernelGGL(k_fit_fwd<K>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],      \
-                     n_levels + L - 1, params[L - lo], dirs, ndir, w.loss_vox[L])
-    if (key64) VX_FWD(uint64_t); else VX_FWD(uint32_t);
-#undef VX_FWD
+    hipLaunchKernelGGL(k_fit_fwd, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],
+                       w.cstart[L], params[L - lo], dirs, ndir, w.loss_vox[L]);
     ll.p[ll.count] = w.loss_vox[L];
     ll.n[ll.count] = n_levels + L;
     ++ll.count;
   }
   VX_TIMED("fit_total", s);
-  hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(1024), 0, s, ll, loss);
+  hipLaunchKernelGGL(k_fit_partial, dim3(kGrid), dim3(kBlock), 0, s, ll, w.part);
+  hipLaunchKernelGGL(k_fit_total, dim3(1), dim3(1024), 0, s, w.part, loss);
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
 
@@ -421,42 +533,52 @@ vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, co
                            void* ws, const int64_t* caps, hipStream_t s) {
   const bool key64 = g->log2_res > 10;
   FitWs w;
-  fit_ws_layout(n_pts, max_cand, max_pairs, caps, hi, key64, ws, &w);
+  fit_ws_layout(n_pts, max_cand, max_pairs, caps, hi, g->log2_res, ws, &w);
   for (int L = 0; L < hi; ++L)
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(7 * caps[L])), dim3(kBlock), 0, s, w.g[L], 7 * caps[L], 0.0);
+  child_starts(key64, levels, n_levels, hi, w, s);
   // lobe gradients and the children's (S, w) gradients, level by level
   for (int L = lo; L <= hi; ++L) {
     VX_TIMED("fit_bwd", s);
-#define VX_BWD(K)                                                                                              \
-  hipLaunchKernelGGL(k_fit_bwd<K>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],      \
-                     n_levels + L - 1, params[L - lo], dirs, ndir, dloss, dparams[L - lo], w.g[L - 1], caps[L - 1])
-    if (key64) VX_BWD(uint64_t); else VX_BWD(uint32_t);
-#undef VX_BWD
+    if (ndir <= 128)
+      hipLaunchKernelGGL(k_fit_bwd<8>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],
+                         w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo], w.g[L - 1], caps[L - 1]);
+    else
+      hipLaunchKernelGGL(k_fit_bwd<16>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],
+                         w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo], w.g[L - 1], caps[L - 1]);
   }
   // top-down accumulation to the leaf
   for (int L = hi - 2; L >= 0; --L) {
     VX_TIMED("fit_down", s);
-    if (key64)
-      hipLaunchKernelGGL(k_fit_down<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, w.g[L],
-                         caps[L], levels[L + 1], n_levels + L + 1, w.g[L + 1], caps[L + 1]);
-    else
-      hipLaunchKernelGGL(k_fit_down<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, w.g[L],
-                         caps[L], levels[L + 1], n_levels + L + 1, w.g[L + 1], caps[L + 1]);
+    hipLaunchKernelGGL(k_fit_down, dim3(kGrid), dim3(kBlock), 0, s, w.pidx[L], n_levels + L, w.g[L], caps[L],
+                       w.g[L + 1], caps[L + 1]);
   }
   // re-emit the pairs in primitive order, then the chain rule per segment and per point
   voxelize_front(1, g, pts, n_pts, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s, nullptr);
   const Lat lat = make_lat(g, 1, radius);
   const double vs = double(int64_t(1) << g->log2_res) / g->extent;
+  const int64_t tiles = leaf_tiles(g->log2_res);
+  if (tiles) {
+    VX_TIMED("fit_tiles", s);
+    launch_fill_i64(w.tfirst, tiles, 0, s);
+    launch_fill_i64(w.tend, tiles, 0, s);
+    if (key64)
+      hipLaunchKernelGGL(k_tile_index<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint64_t*)levels[0].keys,
+                         n_levels, w.tfirst, w.tend);
+    else
+      hipLaunchKernelGGL(k_tile_index<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint32_t*)levels[0].keys,
+                         n_levels, w.tfirst, w.tend);
+  }
   {
     VX_TIMED("fit_pairs", s);
     if (key64)
       hipLaunchKernelGGL(k_fit_pairs<uint64_t>, dim3(blocks_for(n_pts)), dim3(kBlock), 0, s, w.f.rec, w.f.cand_off,
                          n_pts, w.f.masks, w.f.wave_off, w.f.ctl, (const uint64_t*)w.f.pa.keys, levels[0], n_levels,
-                         w.g[0], caps[0], lat.Sb, g->log2_res, vs, w.seg_grad);
+                         w.g[0], caps[0], lat.Sb, g->log2_res, vs, tiles ? w.tfirst : nullptr, w.tend, w.seg_grad);
     else
       hipLaunchKernelGGL(k_fit_pairs<uint32_t>, dim3(blocks_for(n_pts)), dim3(kBlock), 0, s, w.f.rec, w.f.cand_off,
                          n_pts, w.f.masks, w.f.wave_off, w.f.ctl, (const uint32_t*)w.f.pa.keys, levels[0], n_levels,
-                         w.g[0], caps[0], lat.Sb, g->log2_res, vs, w.seg_grad);
+                         w.g[0], caps[0], lat.Sb, g->log2_res, vs, tiles ? w.tfirst : nullptr, w.tend, w.seg_grad);
   }
   {
     VX_TIMED("fit_points", s);

@@ -301,7 +301,7 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
                 const BatchLattice* batch);
 
 // the differentiable two-lobe fit (fit.hip)
-size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, bool key64);
+size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, int log2R);
 vx_status fit_forward_run(const vx_grid* g, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
                           const float* const* params, const float* dirs, int ndir, float* loss, void* ws,
                           const int64_t* caps, hipStream_t s);
