@@ -227,23 +227,24 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
         tau += sqrt(fmax(wc * quadd(scS[grp][c], x, y, z), 0.0));
       }
       tau *= invW;
-      double f = 0.0, yv[2][3], ny[2];
+      double f = 0.0, yv[2][3], ry[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const double* lj = l + 6 * j;
         yv[j][0] = lj[0] * x + lj[1] * y + lj[3] * z;
         yv[j][1] = lj[2] * y + lj[4] * z;
         yv[j][2] = lj[5] * z;
-        ny[j] = sqrt(yv[j][0] * yv[j][0] + yv[j][1] * yv[j][1] + yv[j][2] * yv[j][2]);
-        f += ny[j];
+        const double n2 = yv[j][0] * yv[j][0] + yv[j][1] * yv[j][1] + yv[j][2] * yv[j][2];
+        ry[j] = n2 > 0.0 ? rsqrt(n2) : 0.0;                    // 1 / |L_j^T w|
+        f += n2 * ry[j];
       }
       const double g = (f - tau) * g2;                          // d loss / d f;  d loss / d tau = -g
       dg[i] = g;
       dt[i] = tau;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        if (!(ny[j] > 0.0)) continue;
-        const double sj = g / ny[j];
+        if (!(ry[j] > 0.0)) continue;
+        const double sj = g * ry[j];
         double* gj = gl12 + 6 * j;
         gj[0] += sj * yv[j][0] * x;
         gj[1] += sj * yv[j][0] * y;
@@ -272,10 +273,10 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
           if (k >= ndir) continue;
           const double x = sdir[k][0], y = sdir[k][1], z = sdir[k][2], g = dg[i];
           const double qs = quadd(scS[grp][c], x, y, z);
-          const double q = sqrt(fmax(wc * qs, 0.0));
+          const double q2 = wc * qs;
           double dw = -dt[i] * invW;
-          if (q > 0.0) {
-            const double h = 0.5 / q * invW;
+          if (q2 > 0.0) {
+            const double h = 0.5 * rsqrt(q2) * invW;            // 1 / (2 sqrt(w_c w^T S_c w)) / W
             const double k2 = -g * wc * h;                      // d loss / d (w^T S_c w)
             acc[0] += k2 * x * x;
             acc[1] += k2 * y * y;
