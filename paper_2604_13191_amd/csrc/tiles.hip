@@ -38,14 +38,14 @@ __device__ __forceinline__ T block_sum(T v, T* tmp) {
   return tot;
 }
 
-// candidates of primitive record r inside the box [o, o + size)^3: per-axis first voxel and extent
-__device__ __forceinline__ int64_t clip_box(const int32_t* r, const int32_t o[3], int32_t size, int32_t lo[3],
+// candidates of primitive record r inside the box [o, o + sz): per-axis first voxel and extent
+__device__ __forceinline__ int64_t clip_box(const int32_t* r, const int32_t o[3], const int32_t sz[3], int32_t lo[3],
                                             int32_t n[3]) {
   int64_t c = 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int32_t l = r[9 + a] > o[a] ? r[9 + a] : o[a];
-    const int32_t h0 = r[9 + a] + r[12 + a] - 1, h1 = o[a] + size - 1;
+    const int32_t h0 = r[9 + a] + r[12 + a] - 1, h1 = o[a] + sz[a] - 1;
     const int32_t h = h0 < h1 ? h0 : h1;
     lo[a] = l;
     n[a] = h >= l ? h - l + 1 : 0;
@@ -136,12 +136,31 @@ struct Unit {
   int64_t tile;       // index into the tile list
   int64_t cand;       // candidates inside the unit
   int32_t o[3];       // first voxel
-  int32_t lev;        // 2^lev voxels per axis
+  int16_t lev;        // cells of 2^lev voxels per axis
+  int16_t ncell;      // 1, 2 or 4 sibling cells, consecutive in Morton order (one box)
 };
 
+// box of a unit: ncell aligned siblings of 2^lev cells; 2 spans x, 4 spans x and y
+__device__ __forceinline__ void unit_box(int lev, int ncell, int32_t sz[3]) {
+  sz[0] = (ncell >= 2 ? 2 : 1) << lev;
+  sz[1] = (ncell >= 4 ? 2 : 1) << lev;
+  sz[2] = 1 << lev;
+}
+
 // Per tile (one block each): walk the octant tree depth first in Morton order and count (PASS 0)
-// or write (PASS 1) the units.  A box is a unit when its candidates fit kUnitCand, or when it is
-// a single voxel (then summed in streaming order).
+// or write (PASS 1) the units.  A cell whose candidates exceed kUnitCand is split; among its
+// eight children, aligned groups of four or two siblings whose candidates fit together become
+// one unit, the others single-cell units or further splits.  A single voxel is always a unit
+// (summed in streaming order when it holds more than kUnitCand candidates).
+namespace {
+enum { kEntUnit = 0, kEntSplit = 1 };
+struct PlanEntry {
+  int32_t o[3];
+  int16_t lev, ncell, kind, pad;
+  int64_t cand;
+};
+}  // namespace
+
 template <int PASS, class Key>
 __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict__ rec,
                                                       const Key* __restrict__ rkeys,
@@ -150,7 +169,8 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
                                                       const int64_t* __restrict__ ctl, int tb, int batch,
                                                       int64_t* __restrict__ ucnt, const int64_t* __restrict__ uoff,
                                                       Unit* __restrict__ units) {
-  __shared__ int32_t stk[8 * 8][4];
+  __shared__ PlanEntry stk[48];
+  __shared__ int64_t csum[8];
   __shared__ int64_t tmp[kWaves + 1];
   __shared__ int32_t s_top;
   const int64_t n_tiles = ctl[CTL_N_TILES];
@@ -160,53 +180,117 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
   for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int64_t s = tstart[t], e = tstart[t + 1];
     const uint64_t tk = uint64_t(rkeys[s]) & lowmask;
+    const int32_t to[3] = {int32_t(compact3(tk)) << tb, int32_t(compact3(tk >> 1)) << tb,
+                           int32_t(compact3(tk >> 2)) << tb};
+    // the whole tile
+    int64_t c = 0;
+    for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
+      int32_t lo[3], n[3];
+      const int32_t sz[3] = {1 << tb, 1 << tb, 1 << tb};
+      c += clip_box(rec + int64_t(rprim[j]) * kRec, to, sz, lo, n);
+    }
+    c = block_sum(c, tmp);
     if (threadIdx.x == 0) {
-      stk[0][0] = int32_t(compact3(tk)) << tb;
-      stk[0][1] = int32_t(compact3(tk >> 1)) << tb;
-      stk[0][2] = int32_t(compact3(tk >> 2)) << tb;
-      stk[0][3] = tb;
+      PlanEntry r;
+      r.o[0] = to[0];
+      r.o[1] = to[1];
+      r.o[2] = to[2];
+      r.lev = int16_t(tb);
+      r.ncell = 1;
+      r.kind = (c <= kUnitCand || tb == 0) ? kEntUnit : kEntSplit;
+      r.cand = c;
+      stk[0] = r;
       s_top = 1;
     }
     __syncthreads();
     int64_t nu = 0;
     int64_t out = PASS == 1 ? uoff[t] : 0;
     while (s_top > 0) {
-      const int top = s_top - 1;
-      const int32_t o[3] = {stk[top][0], stk[top][1], stk[top][2]};
-      const int32_t lev = stk[top][3];
+      const PlanEntry E = stk[s_top - 1];
       __syncthreads();                               // everyone has read the top before it changes
-      int64_t c = 0;
-      for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
-        int32_t lo[3], n[3];
-        c += clip_box(rec + int64_t(rprim[j]) * kRec, o, 1 << lev, lo, n);
-      }
-      c = block_sum(c, tmp);
-      const bool unit = c <= kUnitCand || lev == 0;
-      if (threadIdx.x == 0) {
-        s_top = top;                                 // pop
-        if (!unit) {
-          for (int k = 7; k >= 0; --k) {             // push children, Morton order on top
-            const int q = s_top++;
-            const int32_t h = 1 << (lev - 1);
-            stk[q][0] = o[0] + ((k & 1) ? h : 0);
-            stk[q][1] = o[1] + ((k & 2) ? h : 0);
-            stk[q][2] = o[2] + ((k & 4) ? h : 0);
-            stk[q][3] = lev - 1;
+      if (E.kind == kEntUnit) {
+        if (threadIdx.x == 0) {
+          s_top = s_top - 1;
+          if (PASS == 1 && E.cand > 0) {
+            Unit u;
+            u.tile = t;
+            u.cand = E.cand;
+            u.o[0] = E.o[0];
+            u.o[1] = E.o[1];
+            u.o[2] = E.o[2];
+            u.lev = E.lev;
+            u.ncell = E.ncell;
+            units[out] = u;
           }
-        } else if (c > 0 && PASS == 1) {
-          Unit u;
-          u.tile = t;
-          u.cand = c;
-          u.o[0] = o[0];
-          u.o[1] = o[1];
-          u.o[2] = o[2];
-          u.lev = lev;
-          units[out] = u;
         }
+        if (E.cand > 0) {
+          ++nu;
+          ++out;
+        }
+        __syncthreads();
+        continue;
       }
-      if (unit && c > 0) {
-        ++nu;
-        ++out;
+      // split: candidates of the eight children in one pass (halves per axis)
+      const int32_t h = 1 << (E.lev - 1);
+      if (threadIdx.x < 8) csum[threadIdx.x] = 0;
+      __syncthreads();
+      int64_t cc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
+        const int32_t* r = rec + int64_t(rprim[j]) * kRec;
+        int64_t nh[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int32_t l = r[9 + a], hh = r[9 + a] + r[12 + a] - 1;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int32_t c0 = E.o[a] + q * h, c1 = c0 + h - 1;
+            const int32_t lo = l > c0 ? l : c0, hi = hh < c1 ? hh : c1;
+            nh[a][q] = hi >= lo ? hi - lo + 1 : 0;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cc[k] += nh[0][k & 1] * nh[1][(k >> 1) & 1] * nh[2][k >> 2];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int64_t v = wave_sum(cc[k]);
+        if (lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&csum[k]), (unsigned long long)v);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int top = s_top - 1;                          // pop the split entry
+        // groups in Morton order, pushed in reverse so that they pop in order
+        PlanEntry g[8];
+        int ng = 0;
+        auto child = [&](int k, int ncell, int64_t cnt, int kind) {
+          PlanEntry r;
+          r.o[0] = E.o[0] + ((k & 1) ? h : 0);
+          r.o[1] = E.o[1] + ((k & 2) ? h : 0);
+          r.o[2] = E.o[2] + ((k & 4) ? h : 0);
+          r.lev = int16_t(E.lev - 1);
+          r.ncell = int16_t(ncell);
+          r.kind = int16_t(kind);
+          r.cand = cnt;
+          g[ng++] = r;
+        };
+        for (int q = 0; q < 8; q += 4) {
+          const int64_t s4 = csum[q] + csum[q + 1] + csum[q + 2] + csum[q + 3];
+          if (s4 <= kUnitCand) {
+            child(q, 4, s4, kEntUnit);
+            continue;
+          }
+          for (int pp = q; pp < q + 4; pp += 2) {
+            const int64_t s2 = csum[pp] + csum[pp + 1];
+            if (s2 <= kUnitCand) {
+              child(pp, 2, s2, kEntUnit);
+              continue;
+            }
+            for (int k = pp; k < pp + 2; ++k)
+              child(k, 1, csum[k], (csum[k] <= kUnitCand || E.lev - 1 == 0) ? kEntUnit : kEntSplit);
+          }
+        }
+        for (int i = ng - 1; i >= 0; --i) stk[top++] = g[i];
+        s_top = top;
       }
       __syncthreads();
     }
@@ -288,7 +372,7 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
 // batch's candidate total and the number of slots kept.  Contains __syncthreads().
 __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* __restrict__ rec,
                                               const uint32_t* __restrict__ rprim, int64_t j0, int64_t e,
-                                              const int32_t o[3], int32_t size, int& nslot) {
+                                              const int32_t o[3], const int32_t sz[3], int& nslot) {
   const int64_t j = j0 + threadIdx.x;
   int32_t c = 0, lo[3], n[3];
   uint32_t p = 0;
@@ -297,7 +381,7 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
   if (j < e) {
     p = rprim[j];
     r = rec + int64_t(p) * kRec;
-    c = int32_t(clip_box(r, o, size, lo, n));
+    c = int32_t(clip_box(r, o, sz, lo, n));
   }
   // candidates (below 2^21 per batch) and kept slots (bits 21 and up) in one scan
   int32_t tot;
@@ -398,7 +482,9 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
   for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
     const Unit U = units[u];
     const int64_t s = tstart[U.tile], e = tstart[U.tile + 1];
-    const int32_t size = 1 << U.lev;
+    int32_t usz[3];
+    unit_box(U.lev, U.ncell, usz);
+    const uint64_t m0 = morton3(uint32_t(U.o[0]), uint32_t(U.o[1]), uint32_t(U.o[2]));   // the unit's first key
     const bool stream = U.cand > kUnitCand;          // a single voxel holding too many candidates
     int32_t np = 0;                                   // pairs so far (uniform)
     Moment acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // streaming sums (thread 0)
@@ -409,7 +495,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     }
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
       int nb;
-      const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, size, nb);
+      const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, usz, nb);
       (void)nb;
       if (stream) {
         for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
@@ -470,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
             res = b < 0 ? 2 : b;
           }
           if (res == 1)
-            lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
+            lk = uint32_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
         }
         const uint64_t mh = __ballot(res == 1), mb = __ballot(res == 2);
         int32_t bh = 0, bb = 0;
@@ -509,7 +595,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
           hit = cap_bracket(r, v, Lp.s, Lp.Sb, Lp.rho);
           if (hit)
-            lk = uint32_t(morton3(uint32_t(v[0] - U.o[0]), uint32_t(v[1] - U.o[1]), uint32_t(v[2] - U.o[2])));
+            lk = uint32_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
         }
         const uint64_t mh = __ballot(hit);
         int32_t bh = 0;
@@ -553,8 +639,8 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       const uint32_t p = S.prim[i], k = S.key[i];
       const int32_t* r = rec + int64_t(p) * kRec;
       const Lat& Lp = lats ? lats[r[15]] : L;
-      const int64_t v[3] = {U.o[0] + int64_t(compact3(k)), U.o[1] + int64_t(compact3(uint64_t(k) >> 1)),
-                            U.o[2] + int64_t(compact3(uint64_t(k) >> 2))};
+      const uint64_t m = m0 + k;
+      const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
       S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
     }
     // group the pairs by voxel.  Voxels are ranked through an occupancy bitmap of the unit's
@@ -647,10 +733,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           for (int k = 0; k < 8; ++k)
             if (i0 + k < z) accum_pair<KIND>(m, wv[k], t[k]);
         }
-        const uint32_t k = S.key[S.idx[a]];
-        const uint32_t vx = U.o[0] + compact3(k), vy = U.o[1] + compact3(uint64_t(k) >> 1),
-                       vz = U.o[2] + compact3(uint64_t(k) >> 2);
-        write_voxel<KIND>(st, b + v, hi | morton3(vx, vy, vz), z - a, m);
+        write_voxel<KIND>(st, b + v, hi | (m0 + S.key[S.idx[a]]), z - a, m);
       }
     }
     __syncthreads();
