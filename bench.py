@@ -216,6 +216,8 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    from paper_2604_13191_amd import autotune
+    tuned = autotune.apply("plain_weave")          # launch grids chosen by the autotuner, if tuned
     wl = synth.plain_weave()
     pts = torch.as_tensor(wl.pts).cuda()
     offs = torch.as_tensor(wl.offsets).cuda()
@@ -332,6 +334,7 @@ def main():
         "config": {"workload": "plain_weave: 2000 fibers x 256 segments, radius 0.5 voxel, 1024^3, 11 levels, K=1",
                    "n_pairs": plan.n_pairs, "n_candidates": plan.n_cand, "n_leaf_voxels": leaf.n,
                    "n_tile_records": plan.n_records, "n_units": plan.n_units,
+                   "launch_grids": tuned if tuned is not None else vx.get_launch_grids(),
                    "level_voxels": [leaf.n] + caps},
         "voxelize_ms": vox_ms, "lod_build_ms": lod_ms, "graph_ms_per_step": graph_ms,
         "graph_pairs_per_s": plan.n_pairs / (graph_ms * 1e-3),

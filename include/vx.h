@@ -255,9 +255,10 @@ vx_status vx_graph_end(vx_stream stream, vx_graph* graph);
 vx_status vx_graph_launch(vx_graph graph, vx_stream stream);
 void vx_graph_destroy(vx_graph graph);
 
-/* Launch geometry (set by the autotuner): grid sizes of the persistent kernels for the exact
- * test, the emission, the leaf reduce, the parent reduce and the lobe clustering, in that
- * order; each 64 .. 16384 blocks of 256 threads. */
+/* Launch geometry (set by the autotuner): grid sizes of the persistent kernels -- the unit kernel
+ * (exact test, weights, per-voxel sums), the unit planner, the leaf compaction, the parent reduce
+ * and the lobe clustering, in that order; each 64 .. 16384 blocks of 256 threads.  The grid
+ * changes no result. */
 #define VX_TUNE_COUNT 5
 vx_status vx_set_launch_grids(const int32_t* grids, int32_t n);
 void vx_get_launch_grids(int32_t* grids, int32_t n);

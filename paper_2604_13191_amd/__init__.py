@@ -582,7 +582,7 @@ def fit_init(plan, seed=4, noise=0.01):
 # Launch geometry and graphs
 # ------------------------------------------------------------------------------------------------
 
-TUNE_KERNELS = ("test_fib", "emit_fib", "seg_reduce", "lod_reduce", "lod_cluster")
+TUNE_KERNELS = ("unit_fib", "unit_plan", "unit_compact", "lod_reduce", "lod_cluster")
 
 
 def get_launch_grids():

@@ -67,7 +67,7 @@ void timing_end(hipStream_t s) {
   (void)hipEventRecord(g_pending[i].b, s);
 }
 
-int g_grids[kTuneCount] = {kGrid, kGrid, kGrid, kGrid, kGrid};
+int g_grids[kTuneCount] = {kGrid, kGrid, 4 * kGrid, kGrid, kGrid};
 int tuned_grid(int which) { return g_grids[which]; }
 
 // batched patches: device lattice table and point ranges from the caller's device patch array

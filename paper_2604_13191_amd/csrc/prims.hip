@@ -316,10 +316,10 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
   {
     VX_TIMED(kind == 0 ? "test_tri" : "test_fib", s);
     if (kind == 0)
-      hipLaunchKernelGGL(k_test<0>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims,
+      hipLaunchKernelGGL(k_test<0>, dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims,
                          w.ctl, L, lats, w.masks, w.chunk_prim);
     else
-      hipLaunchKernelGGL(k_test<1>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims,
+      hipLaunchKernelGGL(k_test<1>, dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.cand_off, n_prims,
                          w.ctl, L, lats, w.masks, w.chunk_prim);
   }
   {
@@ -342,7 +342,7 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
   }
   VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
 #define VX_EMIT(KD, K)                                                                                        \
-  hipLaunchKernelGGL((k_emit<KD, K>), dim3(tuned_grid(kTuneEmit)), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off, \
+  hipLaunchKernelGGL((k_emit<KD, K>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off, \
                      n_prims, w.ctl, L, lats, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim)
   if (kind == 0) {
     if (key64) VX_EMIT(0, uint64_t); else VX_EMIT(0, uint32_t);

@@ -909,7 +909,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   }
   {
     VX_TIMED("unit_plan", s);
-    const int grid = kGrid;
+    const int grid = tuned_grid(kTunePlan);
 #define VX_PLAN(P, K)                                                                                        \
   hipLaunchKernelGGL((k_unit_plan<P, K>), dim3(grid), dim3(kBlock), 0, s, w.rec, (const K*)R.keys, R.prim, w.tstart, \
                      w.ctl, tb, batch ? 1 : 0, w.ucnt, w.uoff, w.units)
@@ -933,10 +933,10 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     const Lat L = make_lat(g, kind, radius);
     const Lat* lats = batch ? batch->lats : nullptr;
     if (kind == 0)
-      hipLaunchKernelGGL(k_unit<0>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
+      hipLaunchKernelGGL(k_unit<0>, dim3(tuned_grid(kTuneUnit)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
                          w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);
     else
-      hipLaunchKernelGGL(k_unit<1>, dim3(tuned_grid(kTuneTest)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
+      hipLaunchKernelGGL(k_unit<1>, dim3(tuned_grid(kTuneUnit)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
                          w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);
   }
   {
@@ -946,11 +946,11 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     device_scan(ArrIn64{w.unv}, ArrOut64{w.upos}, VoxTotal{w.upos, w.ctl, stats, out->cap}, w.ctl + CTL_N_UNITS, 0,
                 w.partial, s);
     if (key64)
-      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(4 * kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos,
-                         w.ctl, w.st, *out);
+      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(tuned_grid(kTuneCompact)), dim3(kBlock), 0, s, w.unv,
+                         w.usoff, w.upos, w.ctl, w.st, *out);
     else
-      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(4 * kGrid), dim3(kBlock), 0, s, w.unv, w.usoff, w.upos,
-                         w.ctl, w.st, *out);
+      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(tuned_grid(kTuneCompact)), dim3(kBlock), 0, s, w.unv,
+                         w.usoff, w.upos, w.ctl, w.st, *out);
   }
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }

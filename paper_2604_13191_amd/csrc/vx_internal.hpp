@@ -171,7 +171,7 @@ inline void device_scan(In in, Out out, Total total, const int64_t* n_ptr, int64
 // ---------------------------------------------------------------------------------------------
 // Launch geometry chosen by the autotuner: grid sizes of the persistent streaming kernels.
 // ---------------------------------------------------------------------------------------------
-enum { kTuneTest = 0, kTuneEmit, kTuneReduce, kTuneLod, kTuneCluster, kTuneCount };
+enum { kTuneUnit = 0, kTunePlan, kTuneCompact, kTuneLod, kTuneCluster, kTuneCount };
 int tuned_grid(int which);
 
 // ---------------------------------------------------------------------------------------------

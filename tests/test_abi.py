@@ -89,7 +89,7 @@ def test_batch_graph_and_grid_calls_host_side(lib):
     arr = (ctypes.c_int32 * 5)()
     gg(arr, 5)
     default = list(arr)
-    assert default == [1024] * 5
+    assert default == [1024, 1024, 4096, 1024, 1024]
     assert sg((ctypes.c_int32 * 5)(64, 128, 256, 512, 16384), 5) == 0
     gg(arr, 5)
     assert list(arr) == [64, 128, 256, 512, 16384]
