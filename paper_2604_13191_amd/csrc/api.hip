@@ -205,9 +205,12 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
   int64_t* partial = cv.take<int64_t>(kGrid + 1);
   launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
   lod_clamp(n_leaf, leaf->cap, n_levels, s);
-  for (int L = 1; L < levels; ++L) {
+  int L = 1;
+  for (; L < levels; ++L) {
     const vx_voxels& in = L == 1 ? *leaf : out[L - 2];
-    lod_level(key64, in, n_levels + L - 1, out[L - 1], n_levels + L, n_levels + levels, pstart, partial, s);
+    if (K == 1 && in.cap <= kTailMax) break;       // the small top levels go in one launch
+    lod_level(key64, in, n_levels + L - 1, out[L - 1], n_levels + L, n_levels + levels, pstart,
+              partial, s);
     if (K > 1) {
       if (L == 1)
         cluster_level(pstart, n_levels + 1, leaf->w, leaf->S, nullptr, 1, leaf->cap, K, kmeans_iters, lobes[0], s);
@@ -215,6 +218,17 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
         cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
                       kmeans_iters, lobes[L - 1], s);
     }
+  }
+  if (L < levels) {
+    vx_voxels lv[21];
+    int64_t* nl[21];
+    lv[0] = L == 1 ? *leaf : out[L - 2];
+    nl[0] = n_levels + L - 1;
+    for (int i = 1; i <= levels - L; ++i) {
+      lv[i] = out[L - 2 + i];
+      nl[i] = n_levels + L - 1 + i;
+    }
+    lod_tail(key64, false, lv, nl, levels - L, n_levels + levels, s);
   }
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
@@ -329,9 +343,11 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
   // the pyramid, with the patch-preserving parent
   launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
   lod_clamp(stats + VX_STAT_VOXELS, leaf_cap, n_levels, s);
-  for (int L = 1; L < levels; ++L) {
-    lod_level(true, out[L - 1], n_levels + L - 1, out[L], n_levels + L, n_levels + levels, pstart, partial, s,
-              true);
+  int L = 1;
+  for (; L < levels; ++L) {
+    if (K == 1 && out[L - 1].cap <= kTailMax) break;
+    lod_level(true, out[L - 1], n_levels + L - 1, out[L], n_levels + L, n_levels + levels, pstart,
+              partial, s, true);
     if (K > 1) {
       if (L == 1)
         cluster_level(pstart, n_levels + 1, out[0].w, out[0].S, nullptr, 1, out[0].cap, K, kmeans_iters, lobes[0], s);
@@ -339,6 +355,15 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
         cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
                       kmeans_iters, lobes[L - 1], s);
     }
+  }
+  if (L < levels) {
+    vx_voxels lv[21];
+    int64_t* nl[21];
+    for (int i = 0; i <= levels - L; ++i) {
+      lv[i] = out[L - 1 + i];
+      nl[i] = n_levels + L - 1 + i;
+    }
+    lod_tail(true, true, lv, nl, levels - L, n_levels + levels, s);
   }
   for (int L = 0; L < levels; ++L)
     hipLaunchKernelGGL(k_patch_table, dim3((n_patches + 256) / 256), dim3(256), 0, s, (const uint64_t*)out[L].keys,

@@ -138,6 +138,28 @@ int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int
 // ---------------------------------------------------------------------------------------------
 // LoD: parent = sum of its (<= 8, contiguous) children
 // ---------------------------------------------------------------------------------------------
+// sum of the children [a, b) of one parent (in Morton order, so the sums are sequential and fixed)
+template <class Key, bool BATCH>
+__device__ __forceinline__ void lod_parent(const vx_voxels& in, const Key* ikeys, int64_t a, int64_t b,
+                                           const vx_voxels& out, int64_t p) {
+  const int64_t ci = in.cap, co = out.cap;
+  uint32_t c = 0, mask = 0;
+  float W = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int64_t j = a; j < b; ++j) {
+    c += in.count[j];
+    mask |= 1u << uint32_t(ikeys[j] & 7);
+    W += in.w[j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S[k] += in.S[k * ci + j];
+  }
+  reinterpret_cast<Key*>(out.keys)[p] = parent_key<Key, BATCH>(ikeys[a]);
+  out.count[p] = c;
+  out.mask[p] = uint8_t(mask);
+  out.w[p] = W;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.S[k * co + p] = S[k];
+}
+
 struct LodTotal {
   int64_t* start;
   int64_t* n_out;     // clamped count of the new level
@@ -152,30 +174,60 @@ struct LodTotal {
   }
 };
 
+
 template <class Key, bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_lod_reduce(vx_voxels in, const int64_t* __restrict__ start,
                                                        const int64_t* __restrict__ n_ptr, vx_voxels out) {
   const int64_t n = *n_ptr;
   const Key* ikeys = reinterpret_cast<const Key*>(in.keys);
-  Key* okeys = reinterpret_cast<Key*>(out.keys);
-  const int64_t ci = in.cap, co = out.cap;
-  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n; p += int64_t(gridDim.x) * kBlock) {
-    const int64_t a = start[p], b = start[p + 1];
-    uint32_t c = 0, mask = 0;
-    float W = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int64_t j = a; j < b; ++j) {
-      c += in.count[j];
-      mask |= 1u << uint32_t(ikeys[j] & 7);
-      W += in.w[j];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) S[k] += in.S[k * ci + j];
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n; p += int64_t(gridDim.x) * kBlock)
+    lod_parent<Key, BATCH>(in, ikeys, start[p], start[p + 1], out, p);
+}
+
+constexpr int kLodBlock = 1024;
+constexpr int kLodWaves = kLodBlock / 64;
+
+// The small top levels in one launch (one block): level after level, heads of the parent key
+// in chunks, ranks by block scan, children summed as above.  in_cap of every level <= kTailMax.
+constexpr int kTailLevels = 21;
+struct TailLevels {
+  vx_voxels lv[kTailLevels];    // lv[0] = the input of the first level built here
+  int64_t* n[kTailLevels];      // device counts, n[0] the input's
+  int count;                    // levels to build: lv[1 .. count]
+};
+
+template <class Key, bool BATCH>
+__global__ void __launch_bounds__(kLodBlock) k_lod_tail(TailLevels T, int64_t* __restrict__ flags) {
+  __shared__ int64_t tmp[kLodWaves + 1];
+  for (int L = 1; L <= T.count; ++L) {
+    const vx_voxels& in = T.lv[L - 1];
+    const vx_voxels& out = T.lv[L];
+    const int64_t n = *T.n[L - 1];
+    const Key* k = reinterpret_cast<const Key*>(in.keys);
+    int64_t base = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += kLodBlock) {
+      const int64_t i = t0 + threadIdx.x;
+      const bool head = i < n && (i == 0 || parent_key<Key, BATCH>(k[i]) != parent_key<Key, BATCH>(k[i - 1]));
+      int64_t tot;
+      const int64_t ex = block_exclusive_scan_n<kLodWaves>(int64_t(head), tmp, tot);
+      if (head) {
+        const int64_t p = base + ex;
+        if (p < out.cap) {
+          const Key pk = parent_key<Key, BATCH>(k[i]);
+          int64_t j = i + 1;
+          while (j < n && j < i + 8 && parent_key<Key, BATCH>(k[j]) == pk) ++j;
+          lod_parent<Key, BATCH>(in, k, i, j, out, p);
+        }
+      }
+      base += tot;
     }
-    okeys[p] = parent_key<Key, BATCH>(ikeys[a]);
-    out.count[p] = c;
-    out.mask[p] = uint8_t(mask);
-    out.w[p] = W;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) out.S[k * co + p] = S[k];
+    if (threadIdx.x == 0) {
+      const bool over = base > out.cap;
+      if (over) flag_or_s(flags, VX_FLAG_VOXEL_CAPACITY);
+      *T.n[L] = over ? out.cap : base;
+    }
+    __threadfence();                                // this level's writes before the next reads them
+    __syncthreads();
   }
 }
 
@@ -212,6 +264,24 @@ void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_vo
     hipLaunchKernelGGL((k_lod_reduce<uint64_t, false>), grid, dim3(kBlock), 0, s, in, pstart, n_out, out);
   else
     hipLaunchKernelGGL((k_lod_reduce<uint32_t, false>), grid, dim3(kBlock), 0, s, in, pstart, n_out, out);
+}
+
+void lod_tail(bool key64, bool batch, const vx_voxels* lv, int64_t* const* n, int count, int64_t* flags,
+              hipStream_t s) {
+  if (count < 1) return;
+  VX_TIMED("lod_tail", s);
+  TailLevels T;
+  for (int i = 0; i <= count && i < kTailLevels; ++i) {
+    T.lv[i] = lv[i];
+    T.n[i] = n[i];
+  }
+  T.count = count < kTailLevels ? count : kTailLevels - 1;
+  if (batch)
+    hipLaunchKernelGGL((k_lod_tail<uint64_t, true>), dim3(1), dim3(kLodBlock), 0, s, T, flags);
+  else if (key64)
+    hipLaunchKernelGGL((k_lod_tail<uint64_t, false>), dim3(1), dim3(kLodBlock), 0, s, T, flags);
+  else
+    hipLaunchKernelGGL((k_lod_tail<uint32_t, false>), dim3(1), dim3(kLodBlock), 0, s, T, flags);
 }
 
 }  // namespace vx

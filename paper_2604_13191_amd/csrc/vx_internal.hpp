@@ -89,6 +89,25 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T& total) {
   return base + inc - v;
 }
 
+// The same for a block of NW waves; `tmp` holds NW + 1 entries.
+template <int NW, class T>
+__device__ __forceinline__ T block_exclusive_scan_n(T v, T* tmp, T& total) {
+  const int w = threadIdx.x >> 6;
+  T inc = wave_inclusive_scan(v);
+  if (lane_id() == 63) tmp[w] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    T x = tmp[i];
+    if (i < w) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - v;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Device-wide exclusive scan with a fixed grid (reduce, scan the partials, apply).
 // The element count may live in device memory (n_ptr), so the launch needs no host sync.
@@ -260,10 +279,16 @@ struct HeadOut {
 };
 
 // one LoD level: parent reduce of `in` (n_in on the device) into `out`; n_out receives the
-// new count clamped to out.cap, and flags the capacity bit when it had to be clamped
+// new count clamped to out.cap, and flags the capacity bit when it had to be clamped; pstart
+// receives every parent's first child
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
                int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s, bool batch = false);
 void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s);
+// levels lv[1 .. count] from lv[0] in one single-block launch (small levels, no lobes):
+// n[i] the device count of lv[i]
+constexpr int64_t kTailMax = 2048;
+void lod_tail(bool key64, bool batch, const vx_voxels* lv, int64_t* const* n, int count, int64_t* flags,
+              hipStream_t s);
 
 // lobe clustering of one level (cluster.hip): parents [0, *n_par) with children
 // [pstart[p], pstart[p+1]) whose lobes are cw[k * cap_c + c], cS[(j * Kc + k) * cap_c + c]
