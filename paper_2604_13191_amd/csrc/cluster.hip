@@ -9,20 +9,25 @@
 //
 // Mapping: a group of G lanes (G = 8 at level 1, 8K rounded up to a power of two above)
 // handles one parent voxel; lane m holds input lobe m; the cluster sums and the pairwise cost
-// matrix live in the group's LDS.  All reductions are fixed butterflies: the result is
-// deterministic.
+// matrix live in the group's LDS.  Every reduction has a fixed order (butterflies for the
+// argmin, member-order sums for the Lloyd centroids): the result is deterministic.
 #include "vx_internal.hpp"
 
 namespace vx {
 
-__device__ __forceinline__ float lobe_dist(const float* a, float wa, const float* b, float wb) {
-  const float ia = 1.0f / wa, ib = 1.0f / wb;
+// D between two normalised lobes a = S_a / w_a, b = S_b / w_b
+__device__ __forceinline__ float lobe_dist_n(const float* a, const float* b) {
   float d[6];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) d[j] = a[j] * ia - b[j] * ib;
+  for (int j = 0; j < 6; ++j) d[j] = a[j] - b[j];
   const float tr = d[0] + d[1] + d[2];
   const float t2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0f * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
   return 2.0f * t2 + tr * tr;
+}
+
+// Ward's merge cost w_a w_b / (w_a + w_b) D (reciprocals to 1 ulp)
+__device__ __forceinline__ float ward_cost(float wa, float wb, const float* na, const float* nb) {
+  return wa * wb * __builtin_amdgcn_rcpf(wa + wb) * lobe_dist_n(na, nb);
 }
 
 template <int G>
@@ -32,19 +37,14 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int gi) {
 }
 
 template <int G>
-__device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, G);
-  return v;
-}
-
-template <int G>
 struct ClusterLds {
   float lw[64 / G][G];
   float lS[64 / G][6][G];
   float cw[64 / G][G];
   float cS[64 / G][6][G];
+  float nS[64 / G][6][G];     // cluster lobes normalised by their weight
   float mat[64 / G][G][G];
+  int asg[64 / G][G];
 };
 
 // One level: parents [0, *n_par) with children [pstart[p], pstart[p+1]) of the level below,
@@ -97,14 +97,21 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const bool mine = g < n;
-    float lw = 0.f, lS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float lw = 0.f, lS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ln[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (mine) {
       lw = L.lw[gi][g];
+      const float il = __builtin_amdgcn_rcpf(lw);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) lS[j] = L.lS[gi][j][g];
+      for (int j = 0; j < 6; ++j) {
+        lS[j] = L.lS[gi][j][g];
+        ln[j] = lS[j] * il;
+      }
       L.cw[gi][g] = lw;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) L.cS[gi][j][g] = lS[j];
+      for (int j = 0; j < 6; ++j) {
+        L.cS[gi][j][g] = lS[j];
+        L.nS[gi][j][g] = ln[j];
+      }
     }
     uint64_t act = n == 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
     __builtin_amdgcn_wave_barrier();
@@ -112,58 +119,76 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
     if (n > K) {
       // ---- Ward agglomeration: cost matrix, upper triangle, row g written by lane g
       if (mine) {
-        float a[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) a[j] = lS[j];
         for (int j = g + 1; j < n; ++j) {
           float b[6];
 #pragma unroll
-          for (int t = 0; t < 6; ++t) b[t] = L.cS[gi][t][j];
-          const float wb = L.cw[gi][j];
-          L.mat[gi][g][j] = lw * wb / (lw + wb) * lobe_dist(a, lw, b, wb);
+          for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
+          L.mat[gi][g][j] = ward_cost(lw, L.cw[gi][j], ln, b);
         }
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      for (int step = n; step > K; --step) {
-        float best = INFINITY;
-        int bj = G;
+      // Each lane caches the minimum of its row (least cost, then least column); a merge of
+      // (bi, bj) only invalidates rows whose cached column was bi or bj, and row bi itself.
+      float best = INFINITY;
+      int bjr = G;
+      auto scan_row = [&]() {
+        best = INFINITY;
+        bjr = G;
         if (mine && ((act >> g) & 1)) {
           for (int j = g + 1; j < n; ++j) {
             if (!((act >> j) & 1)) continue;
             const float c = L.mat[gi][g][j];
-            if (c < best) { best = c; bj = j; }
+            if (c < best) { best = c; bjr = j; }
           }
         }
-        int bi = bj < G ? g : G;
+      };
+      scan_row();
+      for (int step = n; step > K; --step) {
+        float cb = best;
+        int bi = bjr < G ? g : G, bj = bjr;
         // group argmin of (cost, i); the row minimum already carries the smallest j
 #pragma unroll
         for (int off = 1; off < G; off <<= 1) {
-          const float oc = __shfl_xor(best, off, G);
+          const float oc = __shfl_xor(cb, off, G);
           const int oi = __shfl_xor(bi, off, G);
           const int oj = __shfl_xor(bj, off, G);
-          if (oc < best || (oc == best && oi < bi)) { best = oc; bi = oi; bj = oj; }
+          if (oc < cb || (oc == cb && oi < bi)) { cb = oc; bi = oi; bj = oj; }
         }
         // merge cluster bj into bi
         if (g == bi) {
           const float nw = L.cw[gi][bi] + L.cw[gi][bj];
+          const float inw = __builtin_amdgcn_rcpf(nw);
           L.cw[gi][bi] = nw;
 #pragma unroll
-          for (int t = 0; t < 6; ++t) L.cS[gi][t][bi] = L.cS[gi][t][bi] + L.cS[gi][t][bj];
+          for (int t = 0; t < 6; ++t) {
+            const float v = L.cS[gi][t][bi] + L.cS[gi][t][bj];
+            L.cS[gi][t][bi] = v;
+            L.nS[gi][t][bi] = v * inw;
+          }
         }
         act &= ~(uint64_t(1) << bj);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        float cnew = INFINITY;
         if (mine && ((act >> g) & 1) && g != bi) {
           float a[6], b[6];
 #pragma unroll
-          for (int t = 0; t < 6; ++t) { a[t] = L.cS[gi][t][bi]; b[t] = L.cS[gi][t][g]; }
-          const float wa = L.cw[gi][bi], wb = L.cw[gi][g];
-          const float c = wa * wb / (wa + wb) * lobe_dist(a, wa, b, wb);
-          if (g < bi) L.mat[gi][g][bi] = c; else L.mat[gi][bi][g] = c;
+          for (int t = 0; t < 6; ++t) { a[t] = L.nS[gi][t][bi]; b[t] = L.nS[gi][t][g]; }
+          cnew = ward_cost(L.cw[gi][bi], L.cw[gi][g], a, b);
+          if (g < bi) L.mat[gi][g][bi] = cnew; else L.mat[gi][bi][g] = cnew;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // refresh the cached row minima
+        if (g == bj) {
+          best = INFINITY;
+          bjr = G;
+        } else if (g == bi || bjr == bi || bjr == bj) {
+          scan_row();
+        } else if (g < bi && mine && ((act >> g) & 1)) {
+          if (cnew < best || (cnew == best && bi < bjr)) { best = cnew; bjr = bi; }
+        }
       }
       // ---- weighted Lloyd passes over the original lobes
       for (int it = 0; it < iters; ++it) {
@@ -174,29 +199,45 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
             if (!((act >> k) & 1)) continue;
             float b[6];
 #pragma unroll
-            for (int t = 0; t < 6; ++t) b[t] = L.cS[gi][t][k];
-            const float d = lobe_dist(lS, lw, b, L.cw[gi][k]);
+            for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][k];
+            const float d = lobe_dist_n(ln, b);
             if (d < bestd) { bestd = d; assign = k; }
           }
+        }
+        if (mine) L.asg[gi][g] = assign;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // new cluster sums: one lane per (active cluster, component), adding the members in
+        // lobe order (sequential, so the sums are fixed)
+        const int na = __popcll(act);
+        for (int q = g; q < 7 * na; q += G) {
+          const int r = q / 7, t = q - 7 * r;
+          uint64_t m = act;
+          for (int i = 0; i < r; ++i) m &= m - 1;
+          const int k = __ffsll((unsigned long long)m) - 1;
+          float sum = 0.f;
+          for (int mm = 0; mm < n; ++mm)
+            if (L.asg[gi][mm] == k) sum += t == 6 ? L.lw[gi][mm] : L.lS[gi][t][mm];
+          if (t == 6) L.cw[gi][k] = sum;
+          else L.cS[gi][t][k] = sum;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         uint64_t nact = 0;
-        for (int k = 0; k < n; ++k) {
-          if (!((act >> k) & 1)) continue;
-          const bool in = assign == k;
-          const float sw = group_sum<G>(in ? lw : 0.f);
-          float sS[6];
-#pragma unroll
-          for (int t = 0; t < 6; ++t) sS[t] = group_sum<G>(in ? lS[t] : 0.f);
-          if (sw > 0.f) nact |= uint64_t(1) << k;
-          if (g == 0) {
-            L.cw[gi][k] = sw;
-#pragma unroll
-            for (int t = 0; t < 6; ++t) L.cS[gi][t][k] = sS[t];
-          }
+        for (uint64_t m = act; m; m &= m - 1) {
+          const int k = __ffsll((unsigned long long)m) - 1;
+          if (L.cw[gi][k] > 0.f) nact |= uint64_t(1) << k;
         }
         act = nact;
+        // the new centroids, normalised
+        for (int q = g; q < 6 * na; q += G) {
+          const int r = q / 6, t = q - 6 * r;
+          uint64_t m = nact;
+          for (int i = 0; i < r && m; ++i) m &= m - 1;
+          if (!m) continue;
+          const int k = __ffsll((unsigned long long)m) - 1;
+          L.nS[gi][t][k] = L.cS[gi][t][k] * __builtin_amdgcn_rcpf(L.cw[gi][k]);
+        }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
@@ -231,7 +272,8 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
                    int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, hipStream_t s) {
   const int need = 8 * Kc;
-  VX_TIMED("lod_cluster", s);
+  // timing names by group width: the first level (one lobe per child) and the levels above
+  VX_TIMED(need <= 8 ? "lod_cluster" : "lod_cluster_up", s);
   if (need <= 8)
     hipLaunchKernelGGL(k_cluster<8>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
