@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
           if (oc < cb || (oc == cb && oi < bi)) { cb = oc; bi = oi; bj = oj; }
         }
         // merge cluster bj into bi
-        if (g == bi) {
+        if (g == bi && bj < G) {
           const float nw = L.cw[gi][bi] + L.cw[gi][bj];
           const float inw = __builtin_amdgcn_rcpf(nw);
           L.cw[gi][bi] = nw;
@@ -167,11 +167,11 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
             L.nS[gi][t][bi] = v * inw;
           }
         }
-        act &= ~(uint64_t(1) << bj);
+        if (bj < G) act &= ~(uint64_t(1) << bj);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         float cnew = INFINITY;
-        if (mine && ((act >> g) & 1) && g != bi) {
+        if (bj < G && mine && ((act >> g) & 1) && g != bi) {
           float a[6], b[6];
 #pragma unroll
           for (int t = 0; t < 6; ++t) { a[t] = L.nS[gi][t][bi]; b[t] = L.nS[gi][t][g]; }
@@ -253,9 +253,11 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
           const float wk = L.cw[gi][k];
           rank += (wk > wg || (wk == wg && k < g)) ? 1 : 0;
         }
-        out.w[int64_t(rank) * cap + p] = wg;
+        if (rank < K) {                             // at most K clusters remain; never write past them
+          out.w[int64_t(rank) * cap + p] = wg;
 #pragma unroll
-        for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + rank) * cap + p] = L.cS[gi][t][g];
+          for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + rank) * cap + p] = L.cS[gi][t][g];
+        }
       }
       if (g >= nl && g < K) {
         out.w[int64_t(g) * cap + p] = 0.f;
