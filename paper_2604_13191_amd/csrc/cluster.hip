@@ -36,6 +36,51 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int gi) {
   return (ballot >> (gi * G)) & ((uint64_t(1) << G) - 1);
 }
 
+// minimum of a 64-bit key over the G lanes of a group: DPP within rows of 16 (xor 1 and 2 by
+// quad permutes, then the half-row and row mirrors, each pairing every lane with a partner of
+// the other half), then cross-row exchanges for G = 32 and 64
+__device__ __forceinline__ uint64_t dpp_min_u64(uint64_t v, int ctrl_tag) {
+  const int lo = int(uint32_t(v)), hi = int(uint32_t(v >> 32));
+  int olo, ohi;
+  switch (ctrl_tag) {
+    case 0:
+      olo = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
+      ohi = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:
+      olo = __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false);
+      ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 2:
+      olo = __builtin_amdgcn_update_dpp(lo, lo, 0x141, 0xF, 0xF, false);
+      ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x141, 0xF, 0xF, false);
+      break;
+    default:
+      olo = __builtin_amdgcn_update_dpp(lo, lo, 0x140, 0xF, 0xF, false);
+      ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x140, 0xF, 0xF, false);
+      break;
+  }
+  const uint64_t o = (uint64_t(uint32_t(ohi)) << 32) | uint32_t(olo);
+  return o < v ? o : v;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_min_u64(uint64_t v) {
+  v = dpp_min_u64(v, 0);
+  v = dpp_min_u64(v, 1);
+  if (G > 4) v = dpp_min_u64(v, 2);
+  if (G > 8) v = dpp_min_u64(v, 3);
+  if (G > 16) {
+    const uint64_t o = uint64_t(__shfl_xor((unsigned long long)v, 16, 64));
+    v = o < v ? o : v;
+  }
+  if (G > 32) {
+    const uint64_t o = uint64_t(__shfl_xor((unsigned long long)v, 32, 64));
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
 template <int G>
 struct ClusterLds {
   float lw[64 / G][G];
@@ -145,16 +190,12 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
       };
       scan_row();
       for (int step = n; step > K; --step) {
-        float cb = best;
-        int bi = bjr < G ? g : G, bj = bjr;
-        // group argmin of (cost, i); the row minimum already carries the smallest j
-#pragma unroll
-        for (int off = 1; off < G; off <<= 1) {
-          const float oc = __shfl_xor(cb, off, G);
-          const int oi = __shfl_xor(bi, off, G);
-          const int oj = __shfl_xor(bj, off, G);
-          if (oc < cb || (oc == cb && oi < bi)) { cb = oc; bi = oi; bj = oj; }
-        }
+        // group argmin of (cost, i); the row minimum already carries the smallest j.  Costs are
+        // non-negative, so their bits order like the values: one 64-bit key (cost, i, j).
+        const uint64_t key = (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(bjr < G ? g : G) << 16) |
+                             uint64_t(bjr);
+        const uint64_t kmin = group_min_u64<G>(key);
+        const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
         // merge cluster bj into bi
         if (g == bi && bj < G) {
           const float nw = L.cw[gi][bi] + L.cw[gi][bj];
