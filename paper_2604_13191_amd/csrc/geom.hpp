@@ -23,6 +23,21 @@ struct Lat {
   int64_t rho;       // capsule radius in lattice units (fibers)
 };
 
+// The lattice figures the touch tests and weights need, selected by value: choosing between
+// a kernel argument and a table entry by address would put the argument in scratch memory.
+struct LatQ {
+  int64_t s;
+  int64_t rho;
+  int32_t Sb;
+};
+VX_HD inline LatQ lat_q(const Lat* lats, int32_t patch, const Lat& L) {
+  if (lats) {
+    const Lat& P = lats[patch];
+    return LatQ{P.s, P.rho, P.Sb};
+  }
+  return LatQ{L.s, L.rho, L.Sb};
+}
+
 // per-primitive record, 16 x int32: [0..8] snapped vertices (fibers: A, B, unused),
 // [9..11] first candidate voxel, [12..14] candidate extent per axis
 constexpr int kRec = 16;
@@ -173,7 +188,11 @@ VX_HD inline void candidate_voxel(const int32_t* r, int64_t li, int64_t v[3]) {
 // exact triangle / closed box test (the box-axis tests hold by construction of the candidate
 // range): the triangle's plane and the nine edge x axis directions.
 // ---------------------------------------------------------------------------------------------
-VX_HD inline __attribute__((noinline)) bool plane_exact(const int64_t n[3], const int64_t rel[3], int64_t s) {
+// The rare exact paths are out of line and take their operands by value: an array argument
+// would make every caller keep its copy in scratch memory, whether the path runs or not.
+VX_HD inline __attribute__((noinline)) bool plane_exact(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1,
+                                                        int64_t r2, int64_t s) {
+  const int64_t n[3] = {n0, n1, n2}, rel[3] = {r0, r1, r2};
   __int128 base = 0, lo = 0, hi = 0;
   for (int a = 0; a < 3; ++a) {
     base += (__int128)n[a] * rel[a];
@@ -230,7 +249,7 @@ VX_HD inline bool tri_touch(const int32_t* q, const int64_t v[3], int64_t s, int
   if (lo > err || hi < -err) return false;           // strictly on one side
   if (lo < -err && hi > err) return true;            // strictly across
   int64_t rel[3] = {-c[0][0], -c[0][1], -c[0][2]};
-  return plane_exact(n, rel, s);
+  return plane_exact(n[0], n[1], n[2], rel[0], rel[1], rel[2], s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -249,7 +268,9 @@ VX_HD inline double fdist2(double t, const double c[3], const double d[3], doubl
 
 // exact: f is evaluated at 0, 1, every breakpoint, and at the stationary point of the quadratic
 // of every (axis state) combination whose region contains it.
-VX_HD inline __attribute__((noinline)) bool cap_exact(const int64_t c[3], const int64_t d[3], int64_t s, int64_t rho) {
+VX_HD inline __attribute__((noinline)) bool cap_exact(int64_t c0, int64_t c1, int64_t c2, int64_t d0, int64_t d1,
+                                                      int64_t d2, int64_t s, int64_t rho) {
+  const int64_t c[3] = {c0, c1, c2}, d[3] = {d0, d1, d2};
   typedef __int128 I;
   const I r2 = (I)rho * rho;
   // f(num / den) * den^2 <= rho^2 den^2 at den > 0
@@ -389,7 +410,7 @@ VX_HD inline bool cap_bracket(const int32_t* r, const int64_t v[3], int64_t s, i
   const double fmin_ = fdist2(ts, q.c, q.d, ds);
   if (fmin_ + q.err <= r2) return true;
   if (fmin_ - q.err > r2) return false;
-  return cap_exact(q.ci, q.di, s, rho);
+  return cap_exact(q.ci[0], q.ci[1], q.ci[2], q.di[0], q.di[1], q.di[2], s, rho);
 }
 
 VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {

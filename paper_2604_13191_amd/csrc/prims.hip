@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kBlock) k_test(const int32_t* __restrict__ rec
       const int32_t* r = rec + p * kRec;
       int64_t v[3];
       candidate_voxel(r, ci - cand_off[p], v);
-      const Lat& Lp = lats ? lats[r[15]] : L;        // batched patches: the primitive's own lattice
+      const LatQ Lp = lat_q(lats, r[15], L);          // batched patches: the primitive's own lattice
       if (KIND == 0) hit = tri_touch(r, v, Lp.s, Lp.Sb);
       else hit = cap_touch(r, v, Lp.s, Lp.Sb, Lp.rho);
     }

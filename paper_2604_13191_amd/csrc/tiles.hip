@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
                                                       int64_t* __restrict__ ucnt, const int64_t* __restrict__ uoff,
                                                       Unit* __restrict__ units) {
   __shared__ PlanEntry stk[48];
+  __shared__ PlanEntry g[8];                         // one split's groups, before they are pushed
   __shared__ int64_t csum[8];
   __shared__ int64_t tmp[kWaves + 1];
   __shared__ int32_t s_top;
@@ -260,7 +261,6 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
       if (threadIdx.x == 0) {
         int top = s_top - 1;                          // pop the split entry
         // groups in Morton order, pushed in reverse so that they pop in order
-        PlanEntry g[8];
         int ng = 0;
         auto child = [&](int k, int ncell, int64_t cnt, int kind) {
           PlanEntry r;
@@ -324,6 +324,8 @@ struct UnitLds {
   uint32_t* prim;     // [kUnitCand]
   uint64_t* occ;      // [64] occupancy bitmap of the (at most 4096) unit-local keys
   uint32_t* wpre;     // [64] voxels below each bitmap word
+  uint8_t* code;      // [kUnitCand] per candidate of the batch: 0 miss, 1 touch, 2 undecided
+  uint16_t* ckey;     // [kUnitCand] per touching candidate: its unit-local key
   uint64_t* sbm;      // [64] batch: bit c set where a slot's first candidate is c
   uint32_t* spre;     // [64] slot starts below each word
   int32_t* bprim;     // [kBlock] the current record batch
@@ -336,7 +338,10 @@ struct UnitLds {
   int32_t* misc;      // [8]
 };
 
-constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4) + 2 * (64 * 8 + 64 * 4) +
+// above this many pairs per voxel (unit mean) the grouping places stably instead of sorting
+constexpr int32_t kStableMean = 4;
+
+constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4 + 1 + 2) + 2 * (64 * 8 + 64 * 4) +
                                  kBlock * 4 * (8 + 9 + 1) + (kWaves + 1) * 4 + 8 * 4 + 256;
 
 __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
@@ -354,6 +359,8 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   L.prim = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
   L.key = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.ckey = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.code = reinterpret_cast<uint8_t*>(take(kUnitCand));
   L.wpre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.spre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
@@ -431,13 +438,13 @@ __device__ __forceinline__ int find_slot(const UnitLds& S, int32_t c) {
 }
 
 template <int KIND>
-__device__ __forceinline__ bool unit_test(const int32_t* r, const int64_t v[3], const Lat& Lp) {
+__device__ __forceinline__ bool unit_test(const int32_t* r, const int64_t v[3], const LatQ& Lp) {
   if (KIND == 0) return tri_touch(r, v, Lp.s, Lp.Sb);
   return cap_touch(r, v, Lp.s, Lp.Sb, Lp.rho);
 }
 
 template <int KIND>
-__device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3], const Lat& Lp, float len,
+__device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3], const LatQ& Lp, float len,
                                              double* poly) {
   if (KIND == 0) return tri_area(r, v, Lp.Sb, len, poly);
   return seg_length(r, v, Lp.Sb, len);
@@ -489,10 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     int32_t np = 0;                                   // pairs so far (uniform)
     Moment acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // streaming sums (thread 0)
     uint32_t acc_n = 0;
-    if (tid == 0) {
-      S.misc[4] = 0;                                  // pairs appended (LDS counter)
-      S.misc[5] = 0;                                  // undecided candidates queued
-    }
+    if (tid == 0) S.misc[5] = 0;                      // undecided candidates queued
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
       int nb;
       const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, usz, nb);
@@ -509,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
             slot_voxel(S, slot, c - S.boff[slot], v);
             p = uint32_t(S.bprim[slot]);
             const int32_t* r = S.brec + slot * 9;
-            const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
+            const LatQ Lp = lat_q(lats, S.bpatch[slot], L);
             hit = unit_test<KIND>(r, v, Lp);
             if (hit) wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
           }
@@ -532,89 +536,84 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       }
       // Test in two rounds so that lanes stay busy: a cheap filter decides most candidates and
       // queues the rest (fibers: the centre-ball filter), then the queue gets the full test.
-      // Waves work independently and append with one LDS atomic per wave: the order of the pair
-      // list does not matter, since every voxel's pairs are put in primitive order before they
-      // are summed.  Weights are computed afterwards over the compacted pairs.
+      // Waves work independently; every candidate records its outcome in place, and the
+      // touching ones are then compacted in candidate order, which is primitive order.
       const int wv = tid >> 6, lane = tid & 63;
       const uint64_t lt = (uint64_t(1) << lane) - 1;
       for (int32_t c0 = wv * 64; c0 < cb; c0 += kBlock) {
         const int32_t c = c0 + lane;
         int res = 0;                                   // 0 miss, 1 touch, 2 undecided
-        uint32_t lk = 0, p = 0;
-        int slot = 0;
         if (c < cb) {
-          slot = find_slot(S, c);
+          const int slot = find_slot(S, c);
           int64_t v[3];
           slot_voxel(S, slot, c - S.boff[slot], v);
-          p = uint32_t(S.bprim[slot]);
           const int32_t* r = S.brec + slot * 9;
-          const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
+          const LatQ Lp = lat_q(lats, S.bpatch[slot], L);
           if (KIND == 0) {
             res = tri_touch(r, v, Lp.s, Lp.Sb) ? 1 : 0;
           } else {
             const int b = cap_ball(r, v, Lp.s, Lp.Sb, Lp.rho);
             res = b < 0 ? 2 : b;
           }
-          if (res == 1)
-            lk = uint32_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
+          if (res == 1) S.ckey[c] = uint16_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
+          S.code[c] = uint8_t(res);
         }
-        const uint64_t mh = __ballot(res == 1), mb = __ballot(res == 2);
-        int32_t bh = 0, bb = 0;
-        if (lane == 0) {
-          if (mh) bh = atomicAdd(&S.misc[4], int32_t(__popcll(mh)));
-          if (mb) bb = atomicAdd(&S.misc[5], int32_t(__popcll(mb)));
-        }
-        bh = __shfl(bh, 0, 64);
+        const uint64_t mb = __ballot(res == 2);
+        int32_t bb = 0;
+        if (lane == 0 && mb) bb = atomicAdd(&S.misc[5], int32_t(__popcll(mb)));
         bb = __shfl(bb, 0, 64);
-        if (res == 1) {
-          const int32_t q = bh + int32_t(__popcll(mh & lt));
-          if (q < kUnitCand) {
-            S.key[q] = uint16_t(lk);
-            S.prim[q] = p;
-          } else {
-            flag_set(stats, VX_FLAG_UNIT_CAPACITY);   // planning and test disagree: never expected
-          }
-        } else if (res == 2) {
-          const int32_t q = bb + int32_t(__popcll(mb & lt));   // undecided <= candidates <= kUnitCand
-          reinterpret_cast<uint32_t*>(S.w)[q] = (uint32_t(slot) << 16) | uint32_t(c - S.boff[slot]);
-        }
+        if (res == 2) reinterpret_cast<uint32_t*>(S.w)[bb + int32_t(__popcll(mb & lt))] = uint32_t(c);
       }
       __syncthreads();
       const int32_t nq = S.misc[5];
-      for (int32_t q0 = wv * 64; KIND == 1 && q0 < nq; q0 += kBlock) {
-        const int32_t q = q0 + lane;
-        bool hit = false;
-        uint32_t lk = 0, p = 0;
-        if (q < nq) {
-          const uint32_t qe = reinterpret_cast<const uint32_t*>(S.w)[q];
-          const int slot = int(qe >> 16);
-          int64_t v[3];
-          slot_voxel(S, slot, int32_t(qe & 0xffff), v);
-          p = uint32_t(S.bprim[slot]);
-          const int32_t* r = S.brec + slot * 9;
-          const Lat& Lp = lats ? lats[S.bpatch[slot]] : L;
-          hit = cap_bracket(r, v, Lp.s, Lp.Sb, Lp.rho);
-          if (hit)
-            lk = uint32_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
-        }
-        const uint64_t mh = __ballot(hit);
-        int32_t bh = 0;
-        if (lane == 0 && mh) bh = atomicAdd(&S.misc[4], int32_t(__popcll(mh)));
-        bh = __shfl(bh, 0, 64);
-        if (hit) {
-          const int32_t qq = bh + int32_t(__popcll(mh & lt));
-          if (qq < kUnitCand) {
-            S.key[qq] = uint16_t(lk);
-            S.prim[qq] = p;
-          } else {
-            flag_set(stats, VX_FLAG_UNIT_CAPACITY);
-          }
-        }
+      for (int32_t q = tid; KIND == 1 && q < nq; q += kBlock) {
+        const int32_t c = int32_t(reinterpret_cast<const uint32_t*>(S.w)[q]);
+        const int slot = find_slot(S, c);
+        int64_t v[3];
+        slot_voxel(S, slot, c - S.boff[slot], v);
+        const int32_t* r = S.brec + slot * 9;
+        const LatQ Lp = lat_q(lats, S.bpatch[slot], L);
+        const bool hit = cap_bracket(r, v, Lp.s, Lp.Sb, Lp.rho);
+        if (hit) S.ckey[c] = uint16_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
+        S.code[c] = hit ? 1 : 0;
       }
       __syncthreads();
+      // ordered compaction: wave w takes candidates [w span, (w + 1) span)
+      {
+        const int32_t span = ((cb + kWaves * 64 - 1) / (kWaves * 64)) * 64;
+        const int32_t w0 = wv * span, w1 = w0 + span < cb ? w0 + span : cb;
+        int32_t cnt = 0;
+        for (int32_t c0 = w0; c0 < w1; c0 += 64) {
+          const int32_t c = c0 + lane;
+          cnt += int32_t(__popcll(__ballot(c < w1 && S.code[c] == 1)));
+        }
+        if (lane == 0) S.tmp32[wv] = cnt;
+        __syncthreads();
+        int32_t base = np, tot = 0;
+        for (int i = 0; i < kWaves; ++i) {
+          if (i < wv) base += S.tmp32[i];
+          tot += S.tmp32[i];
+        }
+        for (int32_t c0 = w0; c0 < w1; c0 += 64) {
+          const int32_t c = c0 + lane;
+          const bool hit = c < w1 && S.code[c] == 1;
+          const uint64_t mh = __ballot(hit);
+          if (hit) {
+            const int32_t q = base + int32_t(__popcll(mh & lt));
+            if (q < kUnitCand) {
+              S.key[q] = S.ckey[c];
+              S.prim[q] = uint32_t(S.bprim[find_slot(S, c)]);
+            } else {
+              flag_set(stats, VX_FLAG_UNIT_CAPACITY);   // planning and test disagree: never expected
+            }
+          }
+          base += int32_t(__popcll(mh));
+        }
+        np += tot;
+        __syncthreads();
+      }
       if (tid == 0) S.misc[5] = 0;                     // the next batch's queue (after its barrier)
     }
-    if (!stream) np = S.misc[4];
     if (stream) {
       if (tid == 0) {
         const int64_t nv = acc_n > 0 ? 1 : 0;
@@ -638,7 +637,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     for (int32_t i = tid; i < npairs; i += kBlock) {
       const uint32_t p = S.prim[i], k = S.key[i];
       const int32_t* r = rec + int64_t(p) * kRec;
-      const Lat& Lp = lats ? lats[r[15]] : L;
+      const LatQ Lp = lat_q(lats, r[15], L);
       const uint64_t m = m0 + k;
       const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
       S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
@@ -694,10 +693,39 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       }
     }
     __syncthreads();
-    // placement: afterwards start[v] is the end of voxel v's range
-    for (int32_t i = tid; i < npairs; i += kBlock) {
-      const uint32_t q = atomicAdd(&S.start[voxel_rank(S.key[i])], 1u);
-      S.idx[q] = uint16_t(i);
+    // Place the pairs by voxel; afterwards start[v] is the end of voxel v's range.  Sparse units
+    // (few pairs per voxel) place with atomics and restore primitive order per voxel by insertion
+    // sort below; dense ones place stably: one wave walks the list (primitive order) and lanes
+    // holding the same voxel rank find each other by ballots over the rank bits.
+    const bool stable = npairs > kStableMean * nv;
+    if (!stable) {
+      for (int32_t i = tid; i < npairs; i += kBlock) {
+        const uint32_t q = atomicAdd(&S.start[voxel_rank(S.key[i])], 1u);
+        S.idx[q] = uint16_t(i);
+      }
+    } else if (tid < 64) {
+      const uint64_t lt = (uint64_t(1) << tid) - 1;
+      for (int32_t i0 = 0; i0 < npairs; i0 += 64) {
+        const int32_t i = i0 + tid;
+        const bool ok = i < npairs;
+        const uint32_t vr = ok ? voxel_rank(S.key[i]) : 0u;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 12; ++bit) {
+          const uint64_t m = __ballot((vr >> bit) & 1);
+          peers &= ((vr >> bit) & 1) ? m : ~m;
+        }
+        uint32_t q = 0;
+        if (ok) q = S.start[vr] + uint32_t(__popcll(peers & lt));
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (ok) {
+          S.idx[q] = uint16_t(i);
+          if ((peers & lt) == 0) S.start[vr] += uint32_t(__popcll(peers));   // the group's first lane
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
     }
     __syncthreads();
     const int64_t b = int64_t(uint32_t(S.misc[1])) | (int64_t(S.misc[2]) << 32);
@@ -706,7 +734,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       for (int32_t v = tid; v < nv; v += kBlock) {
         const uint32_t a = v ? S.start[v - 1] : 0u, z = S.start[v];
         // the voxel's pairs in primitive order (insertion sort; primitives are distinct)
-        for (uint32_t i = a + 1; i < z; ++i) {
+        for (uint32_t i = a + 1; !stable && i < z; ++i) {
           const uint16_t x = S.idx[i];
           const uint32_t px = S.prim[x];
           uint32_t j = i;
