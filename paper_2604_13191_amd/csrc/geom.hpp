@@ -365,6 +365,21 @@ VX_HD inline int cap_ball(const int32_t* r, const int64_t v[3], int64_t s, int S
   if (dc2 + q.err <= rin * rin) return 1;
   const double rout = h * 1.7320508075688772 + double(rho);
   if (dc2 - q.err > rout * rout * (1.0 + 0x1p-40)) return 0;
+  // Second look at the same point: f(t), the squared distance from the segment's point at t to
+  // the box, is convex and continuously differentiable, so f(tc) <= rho^2 is a touch and the
+  // tangent at tc bounds f from below on [0, 1].  Every rounding here stays far inside err.
+  const double ds = double(s);
+  double f = 0.0, g = 0.0;                  // f(tc) and f'(tc) / 2
+  for (int a = 0; a < 3; ++a) {
+    const double x = fma(tc, q.d[a], q.c[a]);
+    const double e = x < 0 ? x : (x > ds ? x - ds : 0.0);
+    f = fma(e, e, f);
+    g = fma(e, q.d[a], g);
+  }
+  const double r2 = double(rho) * double(rho);
+  if (f + q.err <= r2) return 1;
+  const double lb = g > 0.0 ? fma(-2.0 * g, tc, f) : fma(2.0 * g, 1.0 - tc, f);
+  if (lb - q.err > r2) return 0;
   return -1;
 }
 
