@@ -99,3 +99,58 @@ def test_cluster_weave(vx):
     for L in range(1, wl.levels):
         rep = compare_lobes(lobes[L - 1].numpy(), olobes[L], lod[L].w, lod[L].S, 4, what=f"weave L{L}")
         say(L, rep)
+
+
+def test_brushed_metal_full_sampled_regions(vx):
+    """The brushed-metal height field at full size (33,538,050 triangles, 4096^3, 64-bit keys,
+    13 levels, K = 4): on sampled 32^3 regions the leaf, levels 1-5 and their lobes against the
+    oracle restricted to the same regions; over the whole grid, conservation of area."""
+    import torch
+    from parity import compare_level
+    n = 4096
+    wl = synth.brushed_metal(n=n)
+    say("case: brushed metal full 4096x4096 vertices (33.5M triangles), 4096^3, 13 levels, K=4, sampled regions")
+    leaf = vx.voxelize_triangles(torch.as_tensor(wl.tris).cuda(), wl.grid)
+    pyr, lobes = vx.build_lod(wl.grid, leaf, wl.levels, K=4, iters=2, return_lobes=True)
+    torch.cuda.synchronize()
+    say("gpu done:", leaf.plan.n_pairs, "pairs,", [p.n for p in pyr[:3]], "voxels in levels 0-2")
+    g0 = pyr[0].numpy()
+    # every triangle lies inside the grid: the leaf holds the whole area (FP32 sums, FP64 total)
+    t = wl.tris.astype(np.float64)
+    area = 0.5 * np.linalg.norm(np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0]), axis=1).sum()
+    assert abs(g0["w"].astype(np.float64).sum() - area) <= 1e-5 * area
+    assert abs(pyr[-1].numpy()["w"].astype(np.float64).sum() - area) <= 1e-5 * area
+    # surface lobes S = w n n^T: trace w
+    assert np.allclose(g0["S"][:, :3].sum(1), g0["w"], rtol=1e-5, atol=1e-6)
+    rng = np.random.default_rng(11)
+    corners = [(0, 0), (n - 32, n - 32), (n // 2, n // 2)]
+    corners += [tuple(int(32 * v) for v in rng.integers(0, n // 32, 2)) for _ in range(3)]
+    levels_gpu = [p.numpy() for p in pyr[:6]]
+    lobes_gpu = [lb.numpy() for lb in lobes[:5]]
+    for r, (x0, y0) in enumerate(corners):
+        # the surface lies within 2 voxels of z = n / 2, a block boundary: take both sides
+        z0 = n // 2 - 32 if r % 2 else n // 2
+        lo = np.array([x0, y0, z0])
+        hi = lo + 32
+        # the triangles of the cells around the region (the oracle clips to the region itself)
+        i0, i1 = max(x0 - 2, 0), min(x0 + 34, n - 1)
+        j0, j1 = max(y0 - 2, 0), min(y0 + 34, n - 1)
+        ii, jj = np.meshgrid(np.arange(i0, i1), np.arange(j0, j1), indexing="ij")
+        cell = (ii * (n - 1) + jj).ravel()
+        sel_t = np.stack([2 * cell, 2 * cell + 1], 1).ravel()
+        ref = oracle.voxelize_triangles(wl.grid, wl.tris[sel_t], region=np.concatenate([lo, hi]))
+        lod = oracle.build_lod(ref, 6)
+        olobes = oracle.cluster_pyramid(lod, 4, 2)
+        for L in range(6):
+            g = levels_gpu[L]
+            c = oracle.demorton(g["keys"].astype(np.uint64), wl.grid.log2_res - L)
+            sel = np.all((c >= (lo >> L)) & (c < (hi >> L)), axis=1)
+            sub = {k: v[sel] for k, v in g.items()}
+            o = lod[L]
+            rep = compare_level(sub, o.keys, o.count, o.w, o.S, o.mask if L > 0 else None,
+                                what=f"brushed full region {lo.tolist()} L{L}")
+            assert rep["n"] > 0
+            if L > 0:
+                gl = {k: v[sel] for k, v in lobes_gpu[L - 1].items()}
+                compare_lobes(gl, olobes[L], o.w, o.S, 4, what=f"brushed full region {lo.tolist()} L{L}")
+        say("region", lo.tolist(), "ok:", rep)
