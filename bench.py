@@ -197,6 +197,54 @@ def batch_timing(vx, args):
             "launch_grids": grids if grids is not None else "default (1024)"}
 
 
+def brushed_timing(vx, args):
+    """Brushed-metal height field at full size (33,538,050 triangles, 4096^3, 13 levels, K = 4):
+    voxelize (exact triangle-box test, clipped areas) and the pyramid with lobe clustering."""
+    import torch
+    import synth
+    wl = synth.brushed_metal()
+    tris = torch.as_tensor(wl.tris).cuda()
+    grid, levels = wl.grid, wl.levels
+    del wl
+    plan = vx.VoxelizePlan(0, grid, tris)
+    plan.run()
+    leaf = plan.check()
+    cal = vx.LodPlan(grid, leaf, plan.stats[2:3], levels).run()
+    caps = [max(v.n, 1) for v in cal.check()[1:]]
+    del cal
+    lod = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, K=4, iters=2, caps=caps)
+    for _ in range(max(1, min(args.warmup, 2))):
+        plan.run()
+        lod.run()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    vx.timing_reset()
+    vx.timing_filter(None)
+    vx.timing_enable(True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for a, b, c in ev:
+        a.record()
+        plan.run()
+        b.record()
+        lod.run()
+        c.record()
+    torch.cuda.synchronize()
+    vx.timing_enable(False)
+    kt = vx.timing_collect()
+    plan.check()
+    lod.check()
+    vox = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    lodm = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    top = sorted(kt.items(), key=lambda x: -x[1][0])[:6]
+    out = {"workload": "brushed metal: 4096x4096 vertices (33,538,050 triangles), 4096^3, 13 levels, K=4",
+           "pairs": plan.n_pairs, "leaf_voxels": leaf.n, "voxelize_ms": vox, "lod_build_ms": lodm,
+           "pairs_per_s": plan.n_pairs / ((vox + lodm) * 1e-3), "voxelize_pairs_per_s": plan.n_pairs / (vox * 1e-3),
+           "kernels_ms_per_step": {k: round(ms / steps, 3) for k, (ms, n) in top}}
+    del plan, lod, leaf, tris
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +253,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--no-brushed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design note, "
@@ -343,8 +392,12 @@ def main():
     }
     if not args.no_fit:
         out["fit"] = fit_timing(vx, wl, pts, offs, args, ms_step)
-    if not args.no_batch:
+    if not args.no_batch or not args.no_brushed:
         del plan, lod
+        torch.cuda.empty_cache()
+    if not args.no_brushed:
+        out["brushed_metal"] = brushed_timing(vx, args)
+    if not args.no_batch:
         torch.cuda.empty_cache()
         out["batched"] = batch_timing(vx, args)
     if not args.no_cpu_baseline:
