@@ -88,7 +88,7 @@ struct ClusterLds {
   float cw[64 / G][G];
   float cS[64 / G][6][G];
   float nS[64 / G][6][G];     // cluster lobes normalised by their weight
-  float mat[64 / G][G][G];
+  float mat[64 / G][G][G + 1];   // [j][g]: row g's cost to column j (rows padded: no bank clashes)
   int asg[64 / G][G];
 };
 
@@ -162,74 +162,196 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     if (n > K) {
-      // ---- Ward agglomeration: cost matrix, upper triangle, row g written by lane g
-      if (mine) {
-        for (int j = g + 1; j < n; ++j) {
-          float b[6];
-#pragma unroll
-          for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
-          L.mat[gi][g][j] = ward_cost(lw, L.cw[gi][j], ln, b);
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      // Each lane caches the minimum of its row (least cost, then least column); a merge of
-      // (bi, bj) only invalidates rows whose cached column was bi or bj, and row bi itself.
-      float best = INFINITY;
-      int bjr = G;
-      auto scan_row = [&]() {
-        best = INFINITY;
-        bjr = G;
-        if (mine && ((act >> g) & 1)) {
+      if constexpr (G <= 8) {
+        // ---- Ward agglomeration, few lobes per voxel (G <= 8): clusters and the upper triangle
+        // of the cost matrix in LDS, row g written by lane g
+        if (mine) {
           for (int j = g + 1; j < n; ++j) {
-            if (!((act >> j) & 1)) continue;
-            const float c = L.mat[gi][g][j];
-            if (c < best) { best = c; bjr = j; }
-          }
-        }
-      };
-      scan_row();
-      for (int step = n; step > K; --step) {
-        // group argmin of (cost, i); the row minimum already carries the smallest j.  Costs are
-        // non-negative, so their bits order like the values: one 64-bit key (cost, i, j).
-        const uint64_t key = (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(bjr < G ? g : G) << 16) |
-                             uint64_t(bjr);
-        const uint64_t kmin = group_min_u64<G>(key);
-        const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
-        // merge cluster bj into bi
-        if (g == bi && bj < G) {
-          const float nw = L.cw[gi][bi] + L.cw[gi][bj];
-          const float inw = __builtin_amdgcn_rcpf(nw);
-          L.cw[gi][bi] = nw;
+            float b[6];
 #pragma unroll
-          for (int t = 0; t < 6; ++t) {
-            const float v = L.cS[gi][t][bi] + L.cS[gi][t][bj];
-            L.cS[gi][t][bi] = v;
-            L.nS[gi][t][bi] = v * inw;
+            for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
+            L.mat[gi][g][j] = ward_cost(lw, L.cw[gi][j], ln, b);
           }
-        }
-        if (bj < G) act &= ~(uint64_t(1) << bj);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        float cnew = INFINITY;
-        if (bj < G && mine && ((act >> g) & 1) && g != bi) {
-          float a[6], b[6];
-#pragma unroll
-          for (int t = 0; t < 6; ++t) { a[t] = L.nS[gi][t][bi]; b[t] = L.nS[gi][t][g]; }
-          cnew = ward_cost(L.cw[gi][bi], L.cw[gi][g], a, b);
-          if (g < bi) L.mat[gi][g][bi] = cnew; else L.mat[gi][bi][g] = cnew;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // refresh the cached row minima
-        if (g == bj) {
+        // Each lane caches the minimum of its row (least cost, then least column); a merge of
+        // (bi, bj) only invalidates rows whose cached column was bi or bj, and row bi itself.
+        float best = INFINITY;
+        int bjr = G;
+        auto scan_row = [&]() {
           best = INFINITY;
           bjr = G;
-        } else if (g == bi || bjr == bi || bjr == bj) {
-          scan_row();
-        } else if (g < bi && mine && ((act >> g) & 1)) {
-          if (cnew < best || (cnew == best && bi < bjr)) { best = cnew; bjr = bi; }
+          if (mine && ((act >> g) & 1)) {
+            for (int j = g + 1; j < n; ++j) {
+              if (!((act >> j) & 1)) continue;
+              const float c = L.mat[gi][g][j];
+              if (c < best) { best = c; bjr = j; }
+            }
+          }
+        };
+        scan_row();
+        for (int step = n; step > K; --step) {
+          // group argmin of (cost, i); the row minimum already carries the smallest j.  Costs are
+          // non-negative, so their bits order like the values: one 64-bit key (cost, i, j).
+          const uint64_t key = (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(bjr < G ? g : G) << 16) |
+                               uint64_t(bjr);
+          const uint64_t kmin = group_min_u64<G>(key);
+          const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
+          // merge cluster bj into bi
+          if (g == bi && bj < G) {
+            const float nw = L.cw[gi][bi] + L.cw[gi][bj];
+            const float inw = __builtin_amdgcn_rcpf(nw);
+            L.cw[gi][bi] = nw;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+              const float v = L.cS[gi][t][bi] + L.cS[gi][t][bj];
+              L.cS[gi][t][bi] = v;
+              L.nS[gi][t][bi] = v * inw;
+            }
+          }
+          if (bj < G) act &= ~(uint64_t(1) << bj);
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          float cnew = INFINITY;
+          if (bj < G && mine && ((act >> g) & 1) && g != bi) {
+            float a[6], b[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) { a[t] = L.nS[gi][t][bi]; b[t] = L.nS[gi][t][g]; }
+            cnew = ward_cost(L.cw[gi][bi], L.cw[gi][g], a, b);
+            if (g < bi) L.mat[gi][g][bi] = cnew; else L.mat[gi][bi][g] = cnew;
+          }
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          // refresh the cached row minima
+          if (g == bj) {
+            best = INFINITY;
+            bjr = G;
+          } else if (g == bi || bjr == bi || bjr == bj) {
+            scan_row();
+          } else if (g < bi && mine && ((act >> g) & 1)) {
+            if (cnew < best || (cnew == best && bi < bjr)) { best = cnew; bjr = bi; }
+          }
         }
+      } else {
+        // ---- Ward agglomeration.  Lane g holds cluster g (weight, sums, normalised sums) in
+        // registers and row g of the symmetric cost matrix in LDS; a dead cluster costs +inf.
+        float cw = lw, cS[6], nS[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          cS[t] = lS[t];
+          nS[t] = ln[t];
+        }
+        // Each lane caches the minimum of its row (least cost, then least column).
+        float best = INFINITY;
+        int bjr = G;
+        if (mine) {
+          for (int j = 0; j < n; ++j) {
+            float c = INFINITY;
+            if (j != g) {
+              float b[6];
+#pragma unroll
+              for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
+              c = ward_cost(lw, L.cw[gi][j], ln, b);
+            }
+            L.mat[gi][j][g] = c;
+            if (c < best) {
+              best = c;
+              bjr = j;
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const int base = lane - g;                  // the group's first lane
+        for (int step = n; step > K; --step) {
+          // group argmin of the cached row minima as one 64-bit key (cost, i, j), i < j: costs
+          // are non-negative, so their bits order like the values, and the least key is the
+          // first pair in (i, j) order among the least costs
+          const int lo = g < bjr ? g : bjr, hi = g < bjr ? bjr : g;
+          const uint64_t key = bjr < G ? (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(lo) << 16) | uint64_t(hi)
+                                       : ~uint64_t(0);
+          const uint64_t kmin = group_min_u64<G>(key);
+          const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
+          const bool merge = bj < G;
+          // the merged cluster (bi absorbs bj), computed by every lane from the two lanes' registers
+          const int si = base + (merge ? bi : 0), sj = base + (merge ? bj : 0);
+          const float mw = __shfl(cw, si, 64) + __shfl(cw, sj, 64);
+          const float inw = __builtin_amdgcn_rcpf(mw);
+          float mS[6], mn[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            mS[t] = __shfl(cS[t], si, 64) + __shfl(cS[t], sj, 64);
+            mn[t] = mS[t] * inw;
+          }
+          if (merge) {
+            act &= ~(uint64_t(1) << bj);
+            if (g == bi) {
+              cw = mw;
+#pragma unroll
+              for (int t = 0; t < 6; ++t) {
+                cS[t] = mS[t];
+                nS[t] = mn[t];
+              }
+            }
+          }
+          const bool alive = mine && ((act >> g) & 1);
+          float cnew = INFINITY;
+          if (merge && alive && g != bi) {
+            cnew = ward_cost(mw, cw, mn, nS);
+            L.mat[gi][bi][g] = cnew;                // row g, column bi
+            L.mat[gi][g][bi] = cnew;                // row bi, column g
+          }
+          if (merge && mine) L.mat[gi][bj][g] = INFINITY;
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          // the merged row's minimum over the new costs (least cost, then least column)
+          const uint64_t k2 = (uint64_t(__float_as_uint(cnew)) << 32) | uint64_t(g);
+          const uint64_t m2 = group_min_u64<G>(k2);
+          // refresh the cached row minima: only column bi changed (to cnew) and column bj died
+          bool rescan = false;
+          if (merge) {
+            if (g == bj) {
+              best = INFINITY;
+              bjr = G;
+            } else if (g == bi) {
+              best = __uint_as_float(uint32_t(m2 >> 32));
+              bjr = best < INFINITY ? int(m2 & 0xffff) : G;
+            } else if (alive) {
+              if (bjr == bi) {
+                if (cnew <= best) best = cnew;
+                else rescan = true;
+              } else if (bjr == bj) {
+                rescan = true;
+              } else if (cnew < best || (cnew == best && bi < bjr)) {
+                best = cnew;
+                bjr = bi;
+              }
+            }
+          }
+          if (rescan) {
+            best = INFINITY;
+            bjr = G;
+            for (int j = 0; j < n; ++j) {
+              const float c = L.mat[gi][j][g];
+              if (c < best) {
+                best = c;
+                bjr = j;
+              }
+            }
+          }
+        }
+        // the clusters back to LDS for the Lloyd passes and the output
+        if (mine) {
+          L.cw[gi][g] = cw;
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            L.cS[gi][t][g] = cS[t];
+            L.nS[gi][t][g] = nS[t];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
       // ---- weighted Lloyd passes over the original lobes
       for (int it = 0; it < iters; ++it) {
