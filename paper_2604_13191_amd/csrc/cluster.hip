@@ -92,32 +92,32 @@ struct ClusterLds {
   int asg[64 / G][G];
 };
 
-// One level: parents [0, *n_par) with children [pstart[p], pstart[p+1]) of the level below,
-// whose lobes are cw[k * cap_c + c] and cS[(j * Kc + k) * cap_c + c] (cnl == nullptr: one lobe
-// per child, present when its weight is positive).
+// One round of one wave: parents base + gi (gi < 64 / G) of a level whose children
+// [pstart[p], pstart[p+1]) in the level below carry lobes cw[k * cap_c + c] and
+// cS[(j * Kc + k) * cap_c + c] (cnl == nullptr: one lobe per child, present when its weight is
+// positive).
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
-                                                    const float* __restrict__ cw, const float* __restrict__ cS,
-                                                    const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
-                                                    int iters, vx_lobes out) {
-  __shared__ ClusterLds<G> sm[kWaves];
+__device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const int64_t* __restrict__ pstart,
+                                              const float* __restrict__ cw, const float* __restrict__ cS,
+                                              const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
+                                              int iters, const vx_lobes& out, ClusterLds<G>& L) {
   const int lane = lane_id();
   const int g = lane % G, gi = lane / G;
-  ClusterLds<G>& L = sm[threadIdx.x >> 6];
-  const int64_t n_par = *n_par_ptr;
   const int64_t cap = out.cap;
-  constexpr int per_wave = 64 / G;
-  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per_wave;
-  const int64_t stride = int64_t(gridDim.x) * kWaves * per_wave;
-  for (int64_t base = w0; base < n_par; base += stride) {
-    const int64_t p = base + gi;
-    const bool live = p < n_par;
-    // ---- gather the children's lobes in canonical order, compacted to lanes 0..n-1
+  const int64_t p = base + gi;
+  const bool live = p < n_par;
+  // ---- gather the children's lobes in canonical order (child, then lobe), compacted to lanes
+  // 0..n-1.  Lane g takes slots g, g + G, ... of the 8 Kc (child, lobe) slots; n <= G is the
+  // caller's guarantee (G >= 8 Kc, or a parent known to gather at most G lobes).
+  const int slots = 8 * Kc;
+  int n = 0;
+  for (int s0 = 0; s0 < slots; s0 += G) {
     float w = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     bool valid = false;
-    if (live) {
+    const int slot = s0 + g;
+    if (live && slot < slots) {
       const int64_t cs = pstart[p], ce = pstart[p + 1];
-      const int ch = g / Kc, k = g % Kc;
+      const int ch = slot / Kc, k = slot % Kc;
       if (cs + ch < ce) {
         const int64_t c = cs + ch;
         const int nl = cnl ? int(cnl[c]) : 1;
@@ -132,302 +132,358 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
       }
     }
     const uint64_t vm = group_bits<G>(__ballot(valid), gi);
-    const int n = __popcll(vm);
-    if (valid) {
-      const int m = __popcll(vm & ((uint64_t(1) << g) - 1));
+    const int m = n + __popcll(vm & ((uint64_t(1) << g) - 1));
+    if (valid && m < G) {
       L.lw[gi][m] = w;
 #pragma unroll
       for (int j = 0; j < 6; ++j) L.lS[gi][j][m] = S[j];
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    const bool mine = g < n;
-    float lw = 0.f, lS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ln[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (mine) {
-      lw = L.lw[gi][g];
-      const float il = __builtin_amdgcn_rcpf(lw);
+    n += __popcll(vm);
+  }
+  n = n < G ? n : G;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const bool mine = g < n;
+  float lw = 0.f, lS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ln[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (mine) {
+    lw = L.lw[gi][g];
+    const float il = __builtin_amdgcn_rcpf(lw);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        lS[j] = L.lS[gi][j][g];
-        ln[j] = lS[j] * il;
-      }
-      L.cw[gi][g] = lw;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        L.cS[gi][j][g] = lS[j];
-        L.nS[gi][j][g] = ln[j];
-      }
+    for (int j = 0; j < 6; ++j) {
+      lS[j] = L.lS[gi][j][g];
+      ln[j] = lS[j] * il;
     }
-    uint64_t act = n == 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    if (n > K) {
-      if constexpr (G <= 8) {
-        // ---- Ward agglomeration, few lobes per voxel (G <= 8): clusters and the upper triangle
-        // of the cost matrix in LDS, row g written by lane g
-        if (mine) {
-          for (int j = g + 1; j < n; ++j) {
-            float b[6];
+    L.cw[gi][g] = lw;
 #pragma unroll
-            for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
-            L.mat[gi][g][j] = ward_cost(lw, L.cw[gi][j], ln, b);
+    for (int j = 0; j < 6; ++j) {
+      L.cS[gi][j][g] = lS[j];
+      L.nS[gi][j][g] = ln[j];
+    }
+  }
+  uint64_t act = n == 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  if (n > K) {
+    if constexpr (G <= 8) {
+      // ---- Ward agglomeration, few lobes per voxel (G <= 8): clusters and the upper triangle
+      // of the cost matrix in LDS, row g written by lane g
+      if (mine) {
+        for (int j = g + 1; j < n; ++j) {
+          float b[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
+          L.mat[gi][g][j] = ward_cost(lw, L.cw[gi][j], ln, b);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // Each lane caches the minimum of its row (least cost, then least column); a merge of
+      // (bi, bj) only invalidates rows whose cached column was bi or bj, and row bi itself.
+      float best = INFINITY;
+      int bjr = G;
+      auto scan_row = [&]() {
+        best = INFINITY;
+        bjr = G;
+        if (mine && ((act >> g) & 1)) {
+          for (int j = g + 1; j < n; ++j) {
+            if (!((act >> j) & 1)) continue;
+            const float c = L.mat[gi][g][j];
+            if (c < best) { best = c; bjr = j; }
           }
+        }
+      };
+      scan_row();
+      for (int step = n; step > K; --step) {
+        // group argmin of (cost, i); the row minimum already carries the smallest j.  Costs are
+        // non-negative, so their bits order like the values: one 64-bit key (cost, i, j).
+        const uint64_t key = (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(bjr < G ? g : G) << 16) |
+                             uint64_t(bjr);
+        const uint64_t kmin = group_min_u64<G>(key);
+        const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
+        // merge cluster bj into bi
+        if (g == bi && bj < G) {
+          const float nw = L.cw[gi][bi] + L.cw[gi][bj];
+          const float inw = __builtin_amdgcn_rcpf(nw);
+          L.cw[gi][bi] = nw;
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            const float v = L.cS[gi][t][bi] + L.cS[gi][t][bj];
+            L.cS[gi][t][bi] = v;
+            L.nS[gi][t][bi] = v * inw;
+          }
+        }
+        if (bj < G) act &= ~(uint64_t(1) << bj);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        float cnew = INFINITY;
+        if (bj < G && mine && ((act >> g) & 1) && g != bi) {
+          float a[6], b[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) { a[t] = L.nS[gi][t][bi]; b[t] = L.nS[gi][t][g]; }
+          cnew = ward_cost(L.cw[gi][bi], L.cw[gi][g], a, b);
+          if (g < bi) L.mat[gi][g][bi] = cnew; else L.mat[gi][bi][g] = cnew;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // Each lane caches the minimum of its row (least cost, then least column); a merge of
-        // (bi, bj) only invalidates rows whose cached column was bi or bj, and row bi itself.
-        float best = INFINITY;
-        int bjr = G;
-        auto scan_row = [&]() {
+        // refresh the cached row minima
+        if (g == bj) {
           best = INFINITY;
           bjr = G;
-          if (mine && ((act >> g) & 1)) {
-            for (int j = g + 1; j < n; ++j) {
-              if (!((act >> j) & 1)) continue;
-              const float c = L.mat[gi][g][j];
-              if (c < best) { best = c; bjr = j; }
-            }
+        } else if (g == bi || bjr == bi || bjr == bj) {
+          scan_row();
+        } else if (g < bi && mine && ((act >> g) & 1)) {
+          if (cnew < best || (cnew == best && bi < bjr)) { best = cnew; bjr = bi; }
+        }
+      }
+    } else {
+      // ---- Ward agglomeration.  Lane g holds cluster g (weight, sums, normalised sums) in
+      // registers and row g of the symmetric cost matrix in LDS; a dead cluster costs +inf.
+      float cw = lw, cS[6], nS[6];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        cS[t] = lS[t];
+        nS[t] = ln[t];
+      }
+      // Each lane caches the minimum of its row (least cost, then least column).
+      float best = INFINITY;
+      int bjr = G;
+      if (mine) {
+        for (int j = 0; j < n; ++j) {
+          float c = INFINITY;
+          if (j != g) {
+            float b[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
+            c = ward_cost(lw, L.cw[gi][j], ln, b);
           }
-        };
-        scan_row();
-        for (int step = n; step > K; --step) {
-          // group argmin of (cost, i); the row minimum already carries the smallest j.  Costs are
-          // non-negative, so their bits order like the values: one 64-bit key (cost, i, j).
-          const uint64_t key = (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(bjr < G ? g : G) << 16) |
-                               uint64_t(bjr);
-          const uint64_t kmin = group_min_u64<G>(key);
-          const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
-          // merge cluster bj into bi
-          if (g == bi && bj < G) {
-            const float nw = L.cw[gi][bi] + L.cw[gi][bj];
-            const float inw = __builtin_amdgcn_rcpf(nw);
-            L.cw[gi][bi] = nw;
+          L.mat[gi][j][g] = c;
+          if (c < best) {
+            best = c;
+            bjr = j;
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int base = lane - g;                  // the group's first lane
+      for (int step = n; step > K; --step) {
+        // group argmin of the cached row minima as one 64-bit key (cost, i, j), i < j: costs
+        // are non-negative, so their bits order like the values, and the least key is the
+        // first pair in (i, j) order among the least costs
+        const int lo = g < bjr ? g : bjr, hi = g < bjr ? bjr : g;
+        const uint64_t key = bjr < G ? (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(lo) << 16) | uint64_t(hi)
+                                     : ~uint64_t(0);
+        const uint64_t kmin = group_min_u64<G>(key);
+        const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
+        const bool merge = bj < G;
+        // the merged cluster (bi absorbs bj), computed by every lane from the two lanes' registers
+        const int si = base + (merge ? bi : 0), sj = base + (merge ? bj : 0);
+        const float mw = __shfl(cw, si, 64) + __shfl(cw, sj, 64);
+        const float inw = __builtin_amdgcn_rcpf(mw);
+        float mS[6], mn[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          mS[t] = __shfl(cS[t], si, 64) + __shfl(cS[t], sj, 64);
+          mn[t] = mS[t] * inw;
+        }
+        if (merge) {
+          act &= ~(uint64_t(1) << bj);
+          if (g == bi) {
+            cw = mw;
 #pragma unroll
             for (int t = 0; t < 6; ++t) {
-              const float v = L.cS[gi][t][bi] + L.cS[gi][t][bj];
-              L.cS[gi][t][bi] = v;
-              L.nS[gi][t][bi] = v * inw;
+              cS[t] = mS[t];
+              nS[t] = mn[t];
             }
           }
-          if (bj < G) act &= ~(uint64_t(1) << bj);
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          float cnew = INFINITY;
-          if (bj < G && mine && ((act >> g) & 1) && g != bi) {
-            float a[6], b[6];
-#pragma unroll
-            for (int t = 0; t < 6; ++t) { a[t] = L.nS[gi][t][bi]; b[t] = L.nS[gi][t][g]; }
-            cnew = ward_cost(L.cw[gi][bi], L.cw[gi][g], a, b);
-            if (g < bi) L.mat[gi][g][bi] = cnew; else L.mat[gi][bi][g] = cnew;
-          }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          // refresh the cached row minima
+        }
+        const bool alive = mine && ((act >> g) & 1);
+        float cnew = INFINITY;
+        if (merge && alive && g != bi) {
+          cnew = ward_cost(mw, cw, mn, nS);
+          L.mat[gi][bi][g] = cnew;                // row g, column bi
+          L.mat[gi][g][bi] = cnew;                // row bi, column g
+        }
+        if (merge && mine) L.mat[gi][bj][g] = INFINITY;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // the merged row's minimum over the new costs (least cost, then least column)
+        const uint64_t k2 = (uint64_t(__float_as_uint(cnew)) << 32) | uint64_t(g);
+        const uint64_t m2 = group_min_u64<G>(k2);
+        // refresh the cached row minima: only column bi changed (to cnew) and column bj died
+        bool rescan = false;
+        if (merge) {
           if (g == bj) {
             best = INFINITY;
             bjr = G;
-          } else if (g == bi || bjr == bi || bjr == bj) {
-            scan_row();
-          } else if (g < bi && mine && ((act >> g) & 1)) {
-            if (cnew < best || (cnew == best && bi < bjr)) { best = cnew; bjr = bi; }
+          } else if (g == bi) {
+            best = __uint_as_float(uint32_t(m2 >> 32));
+            bjr = best < INFINITY ? int(m2 & 0xffff) : G;
+          } else if (alive) {
+            if (bjr == bi) {
+              if (cnew <= best) best = cnew;
+              else rescan = true;
+            } else if (bjr == bj) {
+              rescan = true;
+            } else if (cnew < best || (cnew == best && bi < bjr)) {
+              best = cnew;
+              bjr = bi;
+            }
           }
         }
-      } else {
-        // ---- Ward agglomeration.  Lane g holds cluster g (weight, sums, normalised sums) in
-        // registers and row g of the symmetric cost matrix in LDS; a dead cluster costs +inf.
-        float cw = lw, cS[6], nS[6];
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-          cS[t] = lS[t];
-          nS[t] = ln[t];
-        }
-        // Each lane caches the minimum of its row (least cost, then least column).
-        float best = INFINITY;
-        int bjr = G;
-        if (mine) {
+        if (rescan) {
+          best = INFINITY;
+          bjr = G;
           for (int j = 0; j < n; ++j) {
-            float c = INFINITY;
-            if (j != g) {
-              float b[6];
-#pragma unroll
-              for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][j];
-              c = ward_cost(lw, L.cw[gi][j], ln, b);
-            }
-            L.mat[gi][j][g] = c;
+            const float c = L.mat[gi][j][g];
             if (c < best) {
               best = c;
               bjr = j;
             }
           }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        const int base = lane - g;                  // the group's first lane
-        for (int step = n; step > K; --step) {
-          // group argmin of the cached row minima as one 64-bit key (cost, i, j), i < j: costs
-          // are non-negative, so their bits order like the values, and the least key is the
-          // first pair in (i, j) order among the least costs
-          const int lo = g < bjr ? g : bjr, hi = g < bjr ? bjr : g;
-          const uint64_t key = bjr < G ? (uint64_t(__float_as_uint(best)) << 32) | (uint64_t(lo) << 16) | uint64_t(hi)
-                                       : ~uint64_t(0);
-          const uint64_t kmin = group_min_u64<G>(key);
-          const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
-          const bool merge = bj < G;
-          // the merged cluster (bi absorbs bj), computed by every lane from the two lanes' registers
-          const int si = base + (merge ? bi : 0), sj = base + (merge ? bj : 0);
-          const float mw = __shfl(cw, si, 64) + __shfl(cw, sj, 64);
-          const float inw = __builtin_amdgcn_rcpf(mw);
-          float mS[6], mn[6];
-#pragma unroll
-          for (int t = 0; t < 6; ++t) {
-            mS[t] = __shfl(cS[t], si, 64) + __shfl(cS[t], sj, 64);
-            mn[t] = mS[t] * inw;
-          }
-          if (merge) {
-            act &= ~(uint64_t(1) << bj);
-            if (g == bi) {
-              cw = mw;
-#pragma unroll
-              for (int t = 0; t < 6; ++t) {
-                cS[t] = mS[t];
-                nS[t] = mn[t];
-              }
-            }
-          }
-          const bool alive = mine && ((act >> g) & 1);
-          float cnew = INFINITY;
-          if (merge && alive && g != bi) {
-            cnew = ward_cost(mw, cw, mn, nS);
-            L.mat[gi][bi][g] = cnew;                // row g, column bi
-            L.mat[gi][g][bi] = cnew;                // row bi, column g
-          }
-          if (merge && mine) L.mat[gi][bj][g] = INFINITY;
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          // the merged row's minimum over the new costs (least cost, then least column)
-          const uint64_t k2 = (uint64_t(__float_as_uint(cnew)) << 32) | uint64_t(g);
-          const uint64_t m2 = group_min_u64<G>(k2);
-          // refresh the cached row minima: only column bi changed (to cnew) and column bj died
-          bool rescan = false;
-          if (merge) {
-            if (g == bj) {
-              best = INFINITY;
-              bjr = G;
-            } else if (g == bi) {
-              best = __uint_as_float(uint32_t(m2 >> 32));
-              bjr = best < INFINITY ? int(m2 & 0xffff) : G;
-            } else if (alive) {
-              if (bjr == bi) {
-                if (cnew <= best) best = cnew;
-                else rescan = true;
-              } else if (bjr == bj) {
-                rescan = true;
-              } else if (cnew < best || (cnew == best && bi < bjr)) {
-                best = cnew;
-                bjr = bi;
-              }
-            }
-          }
-          if (rescan) {
-            best = INFINITY;
-            bjr = G;
-            for (int j = 0; j < n; ++j) {
-              const float c = L.mat[gi][j][g];
-              if (c < best) {
-                best = c;
-                bjr = j;
-              }
-            }
-          }
-        }
-        // the clusters back to LDS for the Lloyd passes and the output
-        if (mine) {
-          L.cw[gi][g] = cw;
-#pragma unroll
-          for (int t = 0; t < 6; ++t) {
-            L.cS[gi][t][g] = cS[t];
-            L.nS[gi][t][g] = nS[t];
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
-      // ---- weighted Lloyd passes over the original lobes
-      for (int it = 0; it < iters; ++it) {
-        int assign = -1;
-        if (mine) {
-          float bestd = INFINITY;
-          for (int k = 0; k < n; ++k) {
-            if (!((act >> k) & 1)) continue;
-            float b[6];
+      // the clusters back to LDS for the Lloyd passes and the output
+      if (mine) {
+        L.cw[gi][g] = cw;
 #pragma unroll
-            for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][k];
-            const float d = lobe_dist_n(ln, b);
-            if (d < bestd) { bestd = d; assign = k; }
-          }
+        for (int t = 0; t < 6; ++t) {
+          L.cS[gi][t][g] = cS[t];
+          L.nS[gi][t][g] = nS[t];
         }
-        if (mine) L.asg[gi][g] = assign;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // new cluster sums: one lane per (active cluster, component), adding the members in
-        // lobe order (sequential, so the sums are fixed)
-        const int na = __popcll(act);
-        for (int q = g; q < 7 * na; q += G) {
-          const int r = q / 7, t = q - 7 * r;
-          uint64_t m = act;
-          for (int i = 0; i < r; ++i) m &= m - 1;
-          const int k = __ffsll((unsigned long long)m) - 1;
-          float sum = 0.f;
-          for (int mm = 0; mm < n; ++mm)
-            if (L.asg[gi][mm] == k) sum += t == 6 ? L.lw[gi][mm] : L.lS[gi][t][mm];
-          if (t == 6) L.cw[gi][k] = sum;
-          else L.cS[gi][t][k] = sum;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    // ---- weighted Lloyd passes over the original lobes
+    for (int it = 0; it < iters; ++it) {
+      int assign = -1;
+      if (mine) {
+        float bestd = INFINITY;
+        for (int k = 0; k < n; ++k) {
+          if (!((act >> k) & 1)) continue;
+          float b[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][k];
+          const float d = lobe_dist_n(ln, b);
+          if (d < bestd) { bestd = d; assign = k; }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        uint64_t nact = 0;
-        for (uint64_t m = act; m; m &= m - 1) {
-          const int k = __ffsll((unsigned long long)m) - 1;
-          if (L.cw[gi][k] > 0.f) nact |= uint64_t(1) << k;
-        }
-        act = nact;
-        // the new centroids, normalised
-        for (int q = g; q < 6 * na; q += G) {
-          const int r = q / 6, t = q - 6 * r;
-          uint64_t m = nact;
-          for (int i = 0; i < r && m; ++i) m &= m - 1;
-          if (!m) continue;
-          const int k = __ffsll((unsigned long long)m) - 1;
-          L.nS[gi][t][k] = L.cS[gi][t][k] * __builtin_amdgcn_rcpf(L.cw[gi][k]);
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      if (mine) L.asg[gi][g] = assign;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // new cluster sums: one lane per (active cluster, component), adding the members in
+      // lobe order (sequential, so the sums are fixed)
+      const int na = __popcll(act);
+      for (int q = g; q < 7 * na; q += G) {
+        const int r = q / 7, t = q - 7 * r;
+        uint64_t m = act;
+        for (int i = 0; i < r; ++i) m &= m - 1;
+        const int k = __ffsll((unsigned long long)m) - 1;
+        float sum = 0.f;
+        for (int mm = 0; mm < n; ++mm)
+          if (L.asg[gi][mm] == k) sum += t == 6 ? L.lw[gi][mm] : L.lS[gi][t][mm];
+        if (t == 6) L.cw[gi][k] = sum;
+        else L.cS[gi][t][k] = sum;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      uint64_t nact = 0;
+      for (uint64_t m = act; m; m &= m - 1) {
+        const int k = __ffsll((unsigned long long)m) - 1;
+        if (L.cw[gi][k] > 0.f) nact |= uint64_t(1) << k;
+      }
+      act = nact;
+      // the new centroids, normalised
+      for (int q = g; q < 6 * na; q += G) {
+        const int r = q / 6, t = q - 6 * r;
+        uint64_t m = nact;
+        for (int i = 0; i < r && m; ++i) m &= m - 1;
+        if (!m) continue;
+        const int k = __ffsll((unsigned long long)m) - 1;
+        L.nS[gi][t][k] = L.cS[gi][t][k] * __builtin_amdgcn_rcpf(L.cw[gi][k]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+  }
+  // ---- output: active clusters sorted by descending weight (ties keep cluster order)
+  if (live) {
+    const int nl = __popcll(act);
+    if (g < G && ((act >> g) & 1)) {
+      const float wg = L.cw[gi][g];
+      int rank = 0;
+      for (int k = 0; k < n; ++k) {
+        if (!((act >> k) & 1) || k == g) continue;
+        const float wk = L.cw[gi][k];
+        rank += (wk > wg || (wk == wg && k < g)) ? 1 : 0;
+      }
+      if (rank < K) {                             // at most K clusters remain; never write past them
+        out.w[int64_t(rank) * cap + p] = wg;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + rank) * cap + p] = L.cS[gi][t][g];
       }
     }
-    // ---- output: active clusters sorted by descending weight (ties keep cluster order)
-    if (live) {
-      const int nl = __popcll(act);
-      if (g < G && ((act >> g) & 1)) {
-        const float wg = L.cw[gi][g];
-        int rank = 0;
-        for (int k = 0; k < n; ++k) {
-          if (!((act >> k) & 1) || k == g) continue;
-          const float wk = L.cw[gi][k];
-          rank += (wk > wg || (wk == wg && k < g)) ? 1 : 0;
-        }
-        if (rank < K) {                             // at most K clusters remain; never write past them
-          out.w[int64_t(rank) * cap + p] = wg;
+    if (g >= nl && g < K) {
+      out.w[int64_t(g) * cap + p] = 0.f;
 #pragma unroll
-          for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + rank) * cap + p] = L.cS[gi][t][g];
-        }
-      }
-      if (g >= nl && g < K) {
-        out.w[int64_t(g) * cap + p] = 0.f;
-#pragma unroll
-        for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + g) * cap + p] = 0.f;
-      }
-      if (g == 0) out.nl[p] = uint8_t(nl);
+      for (int t = 0; t < 6; ++t) out.S[(int64_t(t) * K + g) * cap + p] = 0.f;
+    }
+    if (g == 0) out.nl[p] = uint8_t(nl);
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// One level with a fixed group width G (G lanes per parent, 64 / G parents per wave).
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
+                                                    const float* __restrict__ cw, const float* __restrict__ cS,
+                                                    const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
+                                                    int iters, vx_lobes out) {
+  __shared__ ClusterLds<G> sm[kWaves];
+  ClusterLds<G>& L = sm[threadIdx.x >> 6];
+  const int64_t n_par = *n_par_ptr;
+  constexpr int per_wave = 64 / G;
+  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per_wave;
+  const int64_t stride = int64_t(gridDim.x) * kWaves * per_wave;
+  for (int64_t base = w0; base < n_par; base += stride)
+    cluster_round<G>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
+}
+
+// Levels whose parents may gather up to GM lobes: a wave takes four parents at a time and
+// serves them with 16 lanes each when none of them gathers more than 16 lobes, else two (or one)
+// at a time with GM lanes.  The group width changes no result.
+template <int GM>
+__global__ void __launch_bounds__(kBlock) k_cluster_adapt(const int64_t* __restrict__ pstart,
+                                                          const int64_t* n_par_ptr, const float* __restrict__ cw,
+                                                          const float* __restrict__ cS,
+                                                          const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c,
+                                                          int K, int iters, vx_lobes out) {
+  struct PerWave {
+    union {
+      ClusterLds<16> narrow;
+      ClusterLds<GM> wide;
+    };
+  };
+  __shared__ PerWave sm[kWaves];
+  PerWave& W = sm[threadIdx.x >> 6];
+  const int lane = lane_id();
+  const int64_t n_par = *n_par_ptr;
+  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * 4;
+  const int64_t stride = int64_t(gridDim.x) * kWaves * 4;
+  for (int64_t base = w0; base < n_par; base += stride) {
+    // lanes 0..3: how many lobes parent base + lane gathers (the children's lobe counts)
+    int nq = 0;
+    if (lane < 4 && base + lane < n_par) {
+      const int64_t cs = pstart[base + lane], ce = pstart[base + lane + 1];
+      for (int64_t c = cs; c < ce; ++c) nq += cnl ? (int(cnl[c]) < Kc ? int(cnl[c]) : Kc) : 1;
+    }
+    if (__ballot(nq > 16) == 0) {
+      cluster_round<16>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, W.narrow);
+    } else {
+      for (int h = 0; h < 4; h += 64 / GM)
+        cluster_round<GM>(base + h, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, W.wide);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -446,11 +502,11 @@ void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw,
     hipLaunchKernelGGL(k_cluster<16>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
   else if (need <= 32)
-    hipLaunchKernelGGL(k_cluster<32>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
-                       iters, out);
+    hipLaunchKernelGGL(k_cluster_adapt<32>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
+                       Kc, cap_c, K, iters, out);
   else
-    hipLaunchKernelGGL(k_cluster<64>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
-                       iters, out);
+    hipLaunchKernelGGL(k_cluster_adapt<64>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
+                       Kc, cap_c, K, iters, out);
 }
 
 }  // namespace vx
