@@ -334,13 +334,18 @@ struct CapIn {
   double err;
 };
 
+// Lattice coordinates lie within [-2^24, 2^24] and voxel corners within [0, 2^23), so the
+// differences fit int32.
 VX_HD inline void cap_setup(const int32_t* r, const int64_t v[3], int64_t s, int Sb, CapIn& q) {
   double M = double(s);
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    q.ci[a] = int64_t(r[a]) - (v[a] << Sb);
-    q.di[a] = int64_t(r[3 + a]) - int64_t(r[a]);
-    q.c[a] = double(q.ci[a]);
-    q.d[a] = double(q.di[a]);
+    const int32_t ci = r[a] - (int32_t(v[a]) << Sb);
+    const int32_t di = r[3 + a] - r[a];
+    q.ci[a] = ci;
+    q.di[a] = di;
+    q.c[a] = double(ci);
+    q.d[a] = double(di);
     M = fmax(M, fabs(q.c[a]) + fabs(q.d[a]) + double(s));
   }
   q.err = M * M * 0x1p-44;
