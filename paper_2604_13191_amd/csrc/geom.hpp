@@ -354,13 +354,27 @@ VX_HD inline void cap_setup(const int32_t* r, const int64_t v[3], int64_t s, int
 // The box holds the ball of radius h = s/2 around its centre and lies in the ball of radius
 // h sqrt(3): the distance from the centre to the segment decides most candidates.
 // Returns 1 (touch), 0 (no touch) or -1 (undecided: cap_bracket decides).
-VX_HD inline int cap_ball(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
+// 1 / |B - A|^2 of a segment record in lattice units (0 for a point): the ball test's only
+// quotient, the same for all of the segment's candidates
+VX_HD inline double cap_inv_len2(const int32_t* r) {
+  double dd = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double d = double(r[3 + a] - r[a]);
+    dd = fma(d, d, dd);
+  }
+  return dd > 0.0 ? 1.0 / dd : 0.0;
+}
+
+// inv_dd: cap_inv_len2(r).  The parameter tc of the point nearest the centre is a product by it
+// rather than a quotient: any tc in [0, 1] names a point of the segment, and its rounding moves
+// the distance by far less than err.
+VX_HD inline int cap_ball(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho, double inv_dd) {
   CapIn q;
   cap_setup(r, v, s, Sb, q);
   const double h = 0.5 * double(s);
   double wx = h - q.c[0], wy = h - q.c[1], wz = h - q.c[2];
-  const double dd = q.d[0] * q.d[0] + q.d[1] * q.d[1] + q.d[2] * q.d[2];
-  double tc = dd > 0 ? (wx * q.d[0] + wy * q.d[1] + wz * q.d[2]) / dd : 0.0;
+  double tc = (wx * q.d[0] + wy * q.d[1] + wz * q.d[2]) * inv_dd;
   tc = fmin(fmax(tc, 0.0), 1.0);
   wx = fma(-tc, q.d[0], wx);
   wy = fma(-tc, q.d[1], wy);
@@ -434,7 +448,7 @@ VX_HD inline bool cap_bracket(const int32_t* r, const int64_t v[3], int64_t s, i
 }
 
 VX_HD inline bool cap_touch(const int32_t* r, const int64_t v[3], int64_t s, int Sb, int64_t rho) {
-  const int b = cap_ball(r, v, s, Sb, rho);
+  const int b = cap_ball(r, v, s, Sb, rho, cap_inv_len2(r));
   return b >= 0 ? b == 1 : cap_bracket(r, v, s, Sb, rho);
 }
 

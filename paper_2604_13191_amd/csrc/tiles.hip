@@ -317,32 +317,39 @@ struct UnitTotal {
 // the unit kernel: test, weigh, group by voxel and sum in LDS
 // ---------------------------------------------------------------------------------------------
 struct UnitLds {
-  uint32_t* start;    // [kUnitCand] counts, then starts, then ends of the unit's voxels (key order)
+  uint32_t* start;    // [kUnitCand] after the batches: the voxels' keys and range ends (2 x u16)
   uint16_t* key;      // [kUnitCand] unit-local Morton code of each pair
   uint16_t* idx;      // [kUnitCand] grouped order -> pair
   float* w;           // [kUnitCand] (before the weights: the queue of undecided candidates)
   uint32_t* prim;     // [kUnitCand]
-  uint64_t* occ;      // [64] occupancy bitmap of the (at most 4096) unit-local keys
-  uint32_t* wpre;     // [64] voxels below each bitmap word
   uint8_t* code;      // [kUnitCand] per candidate of the batch: 0 miss, 1 touch, 2 undecided
-  uint16_t* ckey;     // [kUnitCand] per touching candidate: its unit-local key
+  uint16_t* ckey;     // [kUnitCand] per touching candidate: its unit-local key (after the
+                      // batches: each pair's arrival slot among its voxel's pairs)
   uint64_t* sbm;      // [64] batch: bit c set where a slot's first candidate is c
   uint32_t* spre;     // [64] slot starts below each word
   int32_t* bprim;     // [kBlock] the current record batch
   int32_t* blo;       // [3][kBlock]
   int32_t* bn;        // [3][kBlock]
   int32_t* boff;      // [kBlock] candidate offsets within the batch
-  int32_t* brec;      // [kBlock][9] the slot's primitive vertices (record words 0..8)
+  int32_t* brec;      // [kBlock][9] the slot's primitive vertices (record words 0..8; after
+                      // the batches: the per-key counters, then starts)
   int32_t* bpatch;    // [kBlock] the slot's patch (batched)
+  double* binv;       // [kBlock] fibers: the slot's 1 / |B - A|^2 (lattice units)
   int32_t* tmp32;     // [kWaves + 1]
   int32_t* misc;      // [8]
 };
 
 // above this many pairs per voxel (unit mean) the grouping places stably instead of sorting
 constexpr int32_t kStableMean = 4;
+// keys of a unit's range: at most one 16^3 tile
+constexpr int32_t kUnitKeys = 4096;
+static_assert(kBlock * 9 * 4 >= kUnitKeys * 2, "per-key counters live in the record batch's space");
+static_assert(kBlock * 16 == kUnitKeys, "each thread owns 16 keys in the scan of the counters");
+static_assert(kUnitCand <= 0xffff, "pair positions are 16-bit");
 
-constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4 + 1 + 2) + 2 * (64 * 8 + 64 * 4) +
-                                 kBlock * 4 * (8 + 9 + 1) + (kWaves + 1) * 4 + 8 * 4 + 256;
+constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4 + 1 + 2) + 64 * 8 + 64 * 4 +
+                                 kBlock * 4 * (8 + 9 + 1) + kBlock * 8 + (kWaves + 1) * 4 + 8 * 4 + 256;
+static_assert(2 * kUnitLdsBytes <= 160 * 1024, "two fiber units per CU");
 
 __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   UnitLds L;
@@ -352,7 +359,6 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
     off += (bytes + 7) & ~size_t(7);
     return p;
   };
-  L.occ = reinterpret_cast<uint64_t*>(take(64 * 8));
   L.sbm = reinterpret_cast<uint64_t*>(take(64 * 8));
   L.start = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
   L.w = reinterpret_cast<float*>(take(kUnitCand * 4));
@@ -361,7 +367,6 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.ckey = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.code = reinterpret_cast<uint8_t*>(take(kUnitCand));
-  L.wpre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.spre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.blo = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
@@ -369,6 +374,7 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   L.boff = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.brec = reinterpret_cast<int32_t*>(take(kBlock * 9 * 4));
   L.bpatch = reinterpret_cast<int32_t*>(take(kBlock * 4));
+  L.binv = reinterpret_cast<double*>(take(kBlock * 8));
   L.tmp32 = reinterpret_cast<int32_t*>(take((kWaves + 1) * 4));
   L.misc = reinterpret_cast<int32_t*>(take(8 * 4));
   return L;
@@ -377,6 +383,7 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
 // Load records [j0, j0 + kBlock) of the tile clipped to the unit box, keeping those with
 // candidates in it (compacted, in record order, with a copy of their vertices); returns the
 // batch's candidate total and the number of slots kept.  Contains __syncthreads().
+template <int KIND>
 __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* __restrict__ rec,
                                               const uint32_t* __restrict__ rprim, int64_t j0, int64_t e,
                                               const int32_t o[3], const int32_t sz[3], int& nslot) {
@@ -406,6 +413,7 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
 #pragma unroll
     for (int k = 0; k < 9; ++k) S.brec[q * 9 + k] = r[k];
     S.bpatch[q] = r[15];
+    if (KIND == 1) S.binv[q] = cap_inv_len2(r);
     atomicOr(reinterpret_cast<unsigned long long*>(&S.sbm[off >> 6]), 1ull << (off & 63));
   }
   nslot = tot >> 21;
@@ -499,7 +507,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     if (tid == 0) S.misc[5] = 0;                      // undecided candidates queued
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
       int nb;
-      const int32_t cb = load_batch(S, rec, rprim, j0, e, U.o, usz, nb);
+      const int32_t cb = load_batch<KIND>(S, rec, rprim, j0, e, U.o, usz, nb);
       (void)nb;
       if (stream) {
         for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
@@ -552,7 +560,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           if (KIND == 0) {
             res = tri_touch(r, v, Lp.s, Lp.Sb) ? 1 : 0;
           } else {
-            const int b = cap_ball(r, v, Lp.s, Lp.Sb, Lp.rho);
+            const int b = cap_ball(r, v, Lp.s, Lp.Sb, Lp.rho, S.binv[slot]);
             res = b < 0 ? 2 : b;
           }
           if (res == 1) S.ckey[c] = uint16_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
@@ -633,34 +641,62 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       continue;
     }
     const int32_t npairs = np < kUnitCand ? np : kUnitCand;
-    // weights of the compacted pairs
+    // Group the pairs by voxel with one counter per key of the unit's range (at most 4096 keys;
+    // 16-bit counts packed two to a word, in the record batch's space, dead now); the weights
+    // are computed in the same pass.  Each pair keeps its arrival slot among its voxel's pairs.
+    uint32_t* kcw = reinterpret_cast<uint32_t*>(S.brec);                 // [2048] packed counts
+    uint16_t* kst = reinterpret_cast<uint16_t*>(S.brec);                 // [4096] then starts
+    uint16_t* slot = S.ckey;                                              // [npairs]
+    uint16_t* vkey = reinterpret_cast<uint16_t*>(S.start);               // [nv] key of voxel v
+    uint16_t* vend = reinterpret_cast<uint16_t*>(S.start) + kUnitCand;   // [nv] end of its pairs
+    for (int32_t j = tid; j < kUnitKeys / 2; j += kBlock) kcw[j] = 0u;
+    __syncthreads();
     for (int32_t i = tid; i < npairs; i += kBlock) {
       const uint32_t p = S.prim[i], k = S.key[i];
+      const uint32_t sh = 16u * (k & 1u);
+      slot[i] = uint16_t(atomicAdd(&kcw[k >> 1], 1u << sh) >> sh);
       const int32_t* r = rec + int64_t(p) * kRec;
       const LatQ Lp = lat_q(lats, r[15], L);
       const uint64_t m = m0 + k;
       const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
       S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
     }
-    // group the pairs by voxel.  Voxels are ranked through an occupancy bitmap of the unit's
-    // keys, so the work below scales with pairs and voxels, not with the unit's volume.
-    if (tid < 64) S.occ[tid] = 0;
     __syncthreads();
-    for (int32_t i = tid; i < npairs; i += kBlock) {
-      const uint32_t k = S.key[i];
-      atomicOr(reinterpret_cast<unsigned long long*>(&S.occ[k >> 6]), 1ull << (k & 63));
+    // starts and the voxel list: thread t owns keys [16 t, 16 t + 16); one block scan of the
+    // (pairs, voxels) counts packed in one word (at most 3072 pairs and 4096 voxels)
+    int32_t nv;
+    {
+      uint32_t c[16];
+      uint32_t sp = 0, sv = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t w2 = kcw[tid * 8 + j];
+        c[2 * j] = w2 & 0xffffu;
+        c[2 * j + 1] = w2 >> 16;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        sp += c[k];
+        sv += c[k] != 0u ? 1u : 0u;
+      }
+      int32_t tot;
+      const uint32_t pre = uint32_t(block_exclusive_scan(int32_t(sp | (sv << 16)), S.tmp32, tot));
+      nv = tot >> 16;
+      uint32_t rp = pre & 0xffffu, rv = pre >> 16;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t key = uint32_t(tid) * 16u + uint32_t(k);
+        kst[key] = uint16_t(rp);
+        if (c[k] != 0u) {
+          vkey[rv] = uint16_t(key);
+          vend[rv] = uint16_t(rp + c[k]);
+          ++rv;
+        }
+        rp += c[k];
+      }
     }
-    __syncthreads();
-    if (tid < 64) {
-      const uint32_t c = uint32_t(__popcll(S.occ[tid]));
-      const uint32_t inc = wave_inclusive_scan(c);
-      S.wpre[tid] = inc - c;
-      if (tid == 63) S.misc[0] = int32_t(inc);
-    }
-    __syncthreads();
-    const int32_t nv = S.misc[0];
     if (tid == 0) {
-      // claim the staging range now; the claim's round trip overlaps the grouping below
+      // claim the staging range now; the claim's round trip overlaps the placement below
       const int64_t b = nv ? int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(stage_ctr),
                                                (unsigned long long)nv))
                            : 0;
@@ -671,57 +707,33 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       unp[u] = np;
       usoff[u] = b;
     }
-    auto voxel_rank = [&](uint32_t k) {
-      return S.wpre[k >> 6] + uint32_t(__popcll(S.occ[k >> 6] & ((1ull << (k & 63)) - 1)));
-    };
-    for (int32_t v = tid; v < nv; v += kBlock) S.start[v] = 0;
     __syncthreads();
-    for (int32_t i = tid; i < npairs; i += kBlock) atomicAdd(&S.start[voxel_rank(S.key[i])], 1u);
-    __syncthreads();
-    {
-      const int32_t per = (nv + kBlock - 1) / kBlock;
-      const int32_t k0 = tid * per;
-      const int32_t k1 = k0 + per < nv ? k0 + per : nv;
-      uint32_t cs = 0;
-      for (int32_t k = k0; k < k1; ++k) cs += S.start[k];
-      int32_t tc;
-      uint32_t rc = uint32_t(block_exclusive_scan(int32_t(cs), S.tmp32, tc));
-      for (int32_t k = k0; k < k1; ++k) {
-        const uint32_t c = S.start[k];
-        S.start[k] = rc;
-        rc += c;
-      }
-    }
-    __syncthreads();
-    // Place the pairs by voxel; afterwards start[v] is the end of voxel v's range.  Sparse units
-    // (few pairs per voxel) place with atomics and restore primitive order per voxel by insertion
-    // sort below; dense ones place stably: one wave walks the list (primitive order) and lanes
-    // holding the same voxel rank find each other by ballots over the rank bits.
+    // Place the pairs by voxel.  Sparse units (few pairs per voxel) place by arrival slot and
+    // restore primitive order per voxel by insertion sort below; dense ones place stably: one
+    // wave walks the list (primitive order) and lanes holding the same key find each other by
+    // ballots over the 12 key bits.
     const bool stable = npairs > kStableMean * nv;
     if (!stable) {
-      for (int32_t i = tid; i < npairs; i += kBlock) {
-        const uint32_t q = atomicAdd(&S.start[voxel_rank(S.key[i])], 1u);
-        S.idx[q] = uint16_t(i);
-      }
+      for (int32_t i = tid; i < npairs; i += kBlock) S.idx[kst[S.key[i]] + slot[i]] = uint16_t(i);
     } else if (tid < 64) {
       const uint64_t lt = (uint64_t(1) << tid) - 1;
       for (int32_t i0 = 0; i0 < npairs; i0 += 64) {
         const int32_t i = i0 + tid;
         const bool ok = i < npairs;
-        const uint32_t vr = ok ? voxel_rank(S.key[i]) : 0u;
+        const uint32_t k = ok ? uint32_t(S.key[i]) : 0u;
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int bit = 0; bit < 12; ++bit) {
-          const uint64_t m = __ballot((vr >> bit) & 1);
-          peers &= ((vr >> bit) & 1) ? m : ~m;
+          const uint64_t m = __ballot((k >> bit) & 1);
+          peers &= ((k >> bit) & 1) ? m : ~m;
         }
         uint32_t q = 0;
-        if (ok) q = S.start[vr] + uint32_t(__popcll(peers & lt));
+        if (ok) q = uint32_t(kst[k]) + uint32_t(__popcll(peers & lt));
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         if (ok) {
           S.idx[q] = uint16_t(i);
-          if ((peers & lt) == 0) S.start[vr] += uint32_t(__popcll(peers));   // the group's first lane
+          if ((peers & lt) == 0) kst[k] = uint16_t(kst[k] + uint32_t(__popcll(peers)));   // the group's first lane
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -732,13 +744,12 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     const uint64_t hi = lats ? uint64_t(uint32_t(rec[int64_t(rprim[s]) * kRec + 15])) << kPatchShift : 0ull;
     if (b + nv <= st.cap) {
       for (int32_t v = tid; v < nv; v += kBlock) {
-        const uint32_t a = v ? S.start[v - 1] : 0u, z = S.start[v];
-        // the voxel's pairs in primitive order (insertion sort; primitives are distinct)
+        const uint32_t a = v ? uint32_t(vend[v - 1]) : 0u, z = vend[v];
+        // the voxel's pairs in list order, which is primitive order (insertion sort)
         for (uint32_t i = a + 1; !stable && i < z; ++i) {
           const uint16_t x = S.idx[i];
-          const uint32_t px = S.prim[x];
           uint32_t j = i;
-          while (j > a && S.prim[S.idx[j - 1]] > px) {
+          while (j > a && S.idx[j - 1] > x) {
             S.idx[j] = S.idx[j - 1];
             --j;
           }
@@ -761,7 +772,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           for (int k = 0; k < 8; ++k)
             if (i0 + k < z) accum_pair<KIND>(m, wv[k], t[k]);
         }
-        write_voxel<KIND>(st, b + v, hi | (m0 + S.key[S.idx[a]]), z - a, m);
+        write_voxel<KIND>(st, b + v, hi | (m0 + vkey[v]), z - a, m);
       }
     }
     __syncthreads();
