@@ -551,6 +551,18 @@ VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float 
   }
 #define PX(b, i) poly[((b) * 2 * kPolyMax + (i) * 2) * kPolyStride]
 #define PY(b, i) poly[((b) * 2 * kPolyMax + (i) * 2 + 1) * kPolyStride]
+  // A plane that leaves all three vertices strictly inside leaves every clipped piece inside
+  // too: the vertices' coordinates are multiples of the lattice step, and clipped vertices are
+  // convex combinations of them, so rounding cannot carry one across.  Such planes are skipped.
+  int cut = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (skip[a]) continue;
+    const double x0 = cf[a], x1 = cf[a] + e0[a], x2 = cf[a] + e1[a];
+    if (!(x0 > 0.0 && x1 > 0.0 && x2 > 0.0)) cut |= 1 << (2 * a);
+    if (!(x0 < 1.0 && x1 < 1.0 && x2 < 1.0)) cut |= 2 << (2 * a);
+  }
+  if (cut == 0) return float(0.5 * double(area2));
   int n = 3, cur = 0;
   PX(0, 0) = 0.0; PY(0, 0) = 0.0;
   PX(0, 1) = 1.0; PY(0, 1) = 0.0;
@@ -558,6 +570,7 @@ VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float 
   for (int a = 0; a < 3; ++a) {
     if (skip[a]) continue;
     for (int side = 0; side < 2; ++side) {
+      if (!((cut >> (2 * a + side)) & 1)) continue;
       // f >= 0 with f = x_a (side 0) or 1 - x_a (side 1), x_a = cf + l1 e0 + l2 e1
       bool all_in = true, all_out = true;
       for (int i = 0; i < n; ++i) {
