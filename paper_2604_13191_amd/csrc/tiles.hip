@@ -322,9 +322,9 @@ struct UnitLds {
   uint16_t* idx;      // [kUnitCand] grouped order -> pair
   float* w;           // [kUnitCand] (before the weights: the queue of undecided candidates)
   uint32_t* prim;     // [kUnitCand]
-  uint8_t* code;      // [kUnitCand] per candidate of the batch: 0 miss, 1 touch, 2 undecided
-  uint16_t* ckey;     // [kUnitCand] per touching candidate: its unit-local key (after the
-                      // batches: each pair's arrival slot among its voxel's pairs)
+  uint16_t* ckey;     // [kUnitCand] per candidate of the batch: kTouch | its unit-local key,
+                      // kUndecided, or 0 for a miss (after the batches: each pair's arrival
+                      // slot among its voxel's pairs)
   uint64_t* sbm;      // [64] batch: bit c set where a slot's first candidate is c
   uint32_t* spre;     // [64] slot starts below each word
   int32_t* bprim;     // [kBlock] the current record batch
@@ -346,8 +346,11 @@ constexpr int32_t kUnitKeys = 4096;
 static_assert(kBlock * 9 * 4 >= kUnitKeys * 2, "per-key counters live in the record batch's space");
 static_assert(kBlock * 16 == kUnitKeys, "each thread owns 16 keys in the scan of the counters");
 static_assert(kUnitCand <= 0xffff, "pair positions are 16-bit");
+// a candidate's outcome and key in one 16-bit word (keys below 4096)
+constexpr uint16_t kTouch = 0x8000, kUndecided = 0x4000;
+static_assert(kUnitKeys <= kUndecided, "keys fit below the flags");
 
-constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4 + 1 + 2) + 64 * 8 + 64 * 4 +
+constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4 + 2) + 64 * 8 + 64 * 4 +
                                  kBlock * 4 * (8 + 9 + 1) + kBlock * 8 + (kWaves + 1) * 4 + 8 * 4 + 256;
 static_assert(2 * kUnitLdsBytes <= 160 * 1024, "two fiber units per CU");
 
@@ -366,7 +369,6 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   L.key = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
   L.ckey = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
-  L.code = reinterpret_cast<uint8_t*>(take(kUnitCand));
   L.spre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.blo = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
@@ -563,8 +565,8 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
             const int b = cap_ball(r, v, Lp.s, Lp.Sb, Lp.rho, S.binv[slot]);
             res = b < 0 ? 2 : b;
           }
-          if (res == 1) S.ckey[c] = uint16_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
-          S.code[c] = uint8_t(res);
+          S.ckey[c] = res == 1 ? uint16_t(kTouch | (morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0))
+                               : (res == 2 ? kUndecided : uint16_t(0));
         }
         const uint64_t mb = __ballot(res == 2);
         int32_t bb = 0;
@@ -582,8 +584,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
         const int32_t* r = S.brec + slot * 9;
         const LatQ Lp = lat_q(lats, S.bpatch[slot], L);
         const bool hit = cap_bracket(r, v, Lp.s, Lp.Sb, Lp.rho);
-        if (hit) S.ckey[c] = uint16_t(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0);
-        S.code[c] = hit ? 1 : 0;
+        S.ckey[c] = hit ? uint16_t(kTouch | (morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])) - m0)) : uint16_t(0);
       }
       __syncthreads();
       // ordered compaction: wave w takes candidates [w span, (w + 1) span)
@@ -593,7 +594,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
         int32_t cnt = 0;
         for (int32_t c0 = w0; c0 < w1; c0 += 64) {
           const int32_t c = c0 + lane;
-          cnt += int32_t(__popcll(__ballot(c < w1 && S.code[c] == 1)));
+          cnt += int32_t(__popcll(__ballot(c < w1 && (S.ckey[c] & kTouch) != 0)));
         }
         if (lane == 0) S.tmp32[wv] = cnt;
         __syncthreads();
@@ -604,12 +605,12 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
         }
         for (int32_t c0 = w0; c0 < w1; c0 += 64) {
           const int32_t c = c0 + lane;
-          const bool hit = c < w1 && S.code[c] == 1;
+          const bool hit = c < w1 && (S.ckey[c] & kTouch) != 0;
           const uint64_t mh = __ballot(hit);
           if (hit) {
             const int32_t q = base + int32_t(__popcll(mh & lt));
             if (q < kUnitCand) {
-              S.key[q] = S.ckey[c];
+              S.key[q] = uint16_t(S.ckey[c] & (kTouch - 1));
               S.prim[q] = uint32_t(S.bprim[find_slot(S, c)]);
             } else {
               flag_set(stats, VX_FLAG_UNIT_CAPACITY);   // planning and test disagree: never expected
