@@ -1,6 +1,6 @@
 // sortreduce.hip -- ordering keyed records and the parent levels of the pyramid.
 //   radix sort  : Sec. 3.3 orders the samples by voxel id so that each voxel's samples are
-//                 contiguous; here a stable LSD radix sort (8-bit digits) with wave-level
+//                 contiguous; here a stable LSD radix sort (9-bit digits) with wave-level
 //                 ranking in LDS, fixed grid, no atomics on global memory -- applied to the
 //                 primitive-tile records, which group the work by tile.
 //   LoD level   : Sec. 4.3 aggregates 2x2x2 children into a coarser voxel; children of a parent
@@ -16,19 +16,23 @@ __device__ __forceinline__ void flag_or_s(int64_t* p, int64_t bit) {
 // ---------------------------------------------------------------------------------------------
 // radix sort
 // ---------------------------------------------------------------------------------------------
+constexpr int kDigitBits = 9;                 // 18-bit tile keys (1024^3 grids) sort in two passes
+constexpr int kBuckets = 1 << kDigitBits;
+static_assert(kBuckets == kRadixBuckets, "histogram workspace");
+
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const Key* __restrict__ keys, const int64_t* n_ptr, int shift,
                                                        int32_t* __restrict__ hist) {
-  __shared__ int32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ int32_t h[kBuckets];
+  for (int d = threadIdx.x; d < kBuckets; d += kBlock) h[d] = 0;
   __syncthreads();
   const int64_t n = *n_ptr;
   const int64_t chunk = scan_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&h[int((keys[i] >> shift) & 255)], 1);
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&h[int((keys[i] >> shift) & (kBuckets - 1))], 1);
   __syncthreads();
-  hist[int64_t(threadIdx.x) * kGrid + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < kBuckets; d += kBlock) hist[int64_t(d) * kGrid + blockIdx.x] = h[d];
 }
 
 struct I32In {
@@ -49,11 +53,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
                                                           float* __restrict__ wout, uint32_t* __restrict__ pout,
                                                           const int64_t* n_ptr, int shift,
                                                           const int32_t* __restrict__ hist_off) {
-  __shared__ int32_t run[256];
-  __shared__ int32_t cnt[kWaves][256];
-  __shared__ int32_t pre[kWaves][256];
+  __shared__ int32_t run[kBuckets];
+  __shared__ int32_t cnt[kWaves][kBuckets];
+  __shared__ int32_t pre[kWaves][kBuckets];
   const int t = threadIdx.x, w = t >> 6, lane = lane_id();
-  run[t] = hist_off[int64_t(t) * kGrid + blockIdx.x];
+  for (int d = t; d < kBuckets; d += kBlock) run[d] = hist_off[int64_t(d) * kGrid + blockIdx.x];
   const int64_t n = *n_ptr;
   const int64_t chunk = scan_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
@@ -66,28 +70,30 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
     float wv = 0.f;
     uint32_t pv = 0;
     if (valid) { k = kin[i]; wv = win[i]; pv = pin[i]; }
-    const int d = int((k >> shift) & 255);
+    const int d = int((k >> shift) & (kBuckets - 1));
     // lanes of this wave holding the same digit
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kDigitBits; ++b) {
       const uint64_t m = __ballot((d >> b) & 1);
       peers &= ((d >> b) & 1) ? m : ~m;
     }
     const int rank = __popcll(peers & lt);
+    for (int dd = t; dd < kBuckets; dd += kBlock) {
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) cnt[ww][t] = 0;
+      for (int ww = 0; ww < kWaves; ++ww) cnt[ww][dd] = 0;
+    }
     __syncthreads();
     if (valid && rank == 0) cnt[w][d] = __popcll(peers);
     __syncthreads();
-    {
-      int32_t acc = run[t];
+    for (int dd = t; dd < kBuckets; dd += kBlock) {
+      int32_t acc = run[dd];
 #pragma unroll
       for (int ww = 0; ww < kWaves; ++ww) {
-        pre[ww][t] = acc;
-        acc += cnt[ww][t];
+        pre[ww][dd] = acc;
+        acc += cnt[ww][dd];
       }
-      run[t] = acc;
+      run[dd] = acc;
     }
     __syncthreads();
     if (valid) {
@@ -102,10 +108,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
 int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int64_t* n_dev, int64_t cap,
                      int32_t* hist, int64_t* partial, hipStream_t s) {
   (void)cap;
-  const int passes = (key_bits + 7) / 8;
+  const int passes = (key_bits + kDigitBits - 1) / kDigitBits;
   PairBufs src = a, dst = b;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
+    const int shift = kDigitBits * p;
     {
       VX_TIMED("radix_hist", s);
       if (key64)
@@ -117,7 +123,7 @@ int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int
     }
     {
       VX_TIMED("radix_scan", s);
-      device_scan(I32In{hist}, I32Out{hist}, NoTotal{}, nullptr, int64_t(256) * kGrid, partial, s);
+      device_scan(I32In{hist}, I32Out{hist}, NoTotal{}, nullptr, int64_t(kBuckets) * kGrid, partial, s);
     }
     {
       VX_TIMED("radix_scatter", s);

@@ -869,7 +869,7 @@ static size_t tile_ws_layout(int64_t n_prims, int64_t max_rec, int64_t max_units
   x.rb.keys = cv.take<uint8_t>(max_rec * kb);
   x.rb.w = cv.take<float>(max_rec);
   x.rb.prim = cv.take<uint32_t>(max_rec);
-  x.hist = cv.take<int32_t>(int64_t(256) * kGrid);
+  x.hist = cv.take<int32_t>(int64_t(kRadixBuckets) * kGrid);
   x.partial = cv.take<int64_t>(kGrid + 1);
   x.tstart = cv.take<int64_t>(max_rec + 1);
   x.ucnt = cv.take<int64_t>(max_rec + 1);

@@ -253,6 +253,7 @@ struct PairBufs {
 void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 
 // sort pairs by key (stable LSD radix); returns the buffer index (0 = a, 1 = b) holding the result
+constexpr int kRadixBuckets = 512;          // digit values of the record sort (hist is kRadixBuckets x kGrid)
 int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int64_t* n_dev, int64_t cap,
                      int32_t* hist, int64_t* partial, hipStream_t s);
 
