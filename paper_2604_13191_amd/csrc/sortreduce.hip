@@ -19,6 +19,14 @@ __device__ __forceinline__ void flag_or_s(int64_t* p, int64_t bit) {
 constexpr int kDigitBits = 9;                 // 18-bit tile keys (1024^3 grids) sort in two passes
 constexpr int kBuckets = 1 << kDigitBits;
 static_assert(kBuckets == kRadixBuckets, "histogram workspace");
+// blocks of the sort kernels: fewer, longer blocks keep the digit histograms (and their scan) small
+constexpr int kSortGrid = 512;
+static_assert(kSortGrid <= kGrid, "histogram workspace");
+
+__device__ __forceinline__ int64_t sort_chunk(int64_t n) {
+  const int64_t c = (n + kSortGrid - 1) / kSortGrid;
+  return (c + kBlock - 1) / kBlock * kBlock;
+}
 
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const Key* __restrict__ keys, const int64_t* n_ptr, int shift,
@@ -27,12 +35,12 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const Key* __restrict__ k
   for (int d = threadIdx.x; d < kBuckets; d += kBlock) h[d] = 0;
   __syncthreads();
   const int64_t n = *n_ptr;
-  const int64_t chunk = scan_chunk(n);
+  const int64_t chunk = sort_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&h[int((keys[i] >> shift) & (kBuckets - 1))], 1);
   __syncthreads();
-  for (int d = threadIdx.x; d < kBuckets; d += kBlock) hist[int64_t(d) * kGrid + blockIdx.x] = h[d];
+  for (int d = threadIdx.x; d < kBuckets; d += kBlock) hist[int64_t(d) * kSortGrid + blockIdx.x] = h[d];
 }
 
 struct I32In {
@@ -57,9 +65,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
   __shared__ int32_t cnt[kWaves][kBuckets];
   __shared__ int32_t pre[kWaves][kBuckets];
   const int t = threadIdx.x, w = t >> 6, lane = lane_id();
-  for (int d = t; d < kBuckets; d += kBlock) run[d] = hist_off[int64_t(d) * kGrid + blockIdx.x];
+  for (int d = t; d < kBuckets; d += kBlock) run[d] = hist_off[int64_t(d) * kSortGrid + blockIdx.x];
   const int64_t n = *n_ptr;
-  const int64_t chunk = scan_chunk(n);
+  const int64_t chunk = sort_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   const uint64_t lt = (uint64_t(1) << lane) - 1;
@@ -115,23 +123,23 @@ int radix_sort_pairs(bool key64, int key_bits, PairBufs a, PairBufs b, const int
     {
       VX_TIMED("radix_hist", s);
       if (key64)
-        hipLaunchKernelGGL(k_radix_hist<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint64_t*)src.keys, n_dev,
+        hipLaunchKernelGGL(k_radix_hist<uint64_t>, dim3(kSortGrid), dim3(kBlock), 0, s, (const uint64_t*)src.keys, n_dev,
                            shift, hist);
       else
-        hipLaunchKernelGGL(k_radix_hist<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint32_t*)src.keys, n_dev,
+        hipLaunchKernelGGL(k_radix_hist<uint32_t>, dim3(kSortGrid), dim3(kBlock), 0, s, (const uint32_t*)src.keys, n_dev,
                            shift, hist);
     }
     {
       VX_TIMED("radix_scan", s);
-      device_scan(I32In{hist}, I32Out{hist}, NoTotal{}, nullptr, int64_t(kBuckets) * kGrid, partial, s);
+      device_scan(I32In{hist}, I32Out{hist}, NoTotal{}, nullptr, int64_t(kBuckets) * kSortGrid, partial, s);
     }
     {
       VX_TIMED("radix_scatter", s);
       if (key64)
-        hipLaunchKernelGGL(k_radix_scatter<uint64_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint64_t*)src.keys,
+        hipLaunchKernelGGL(k_radix_scatter<uint64_t>, dim3(kSortGrid), dim3(kBlock), 0, s, (const uint64_t*)src.keys,
                            src.w, src.prim, (uint64_t*)dst.keys, dst.w, dst.prim, n_dev, shift, hist);
       else
-        hipLaunchKernelGGL(k_radix_scatter<uint32_t>, dim3(kGrid), dim3(kBlock), 0, s, (const uint32_t*)src.keys,
+        hipLaunchKernelGGL(k_radix_scatter<uint32_t>, dim3(kSortGrid), dim3(kBlock), 0, s, (const uint32_t*)src.keys,
                            src.w, src.prim, (uint32_t*)dst.keys, dst.w, dst.prim, n_dev, shift, hist);
     }
     PairBufs tmp = src;
