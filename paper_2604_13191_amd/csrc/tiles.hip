@@ -183,6 +183,24 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
     const uint64_t tk = uint64_t(rkeys[s]) & lowmask;
     const int32_t to[3] = {int32_t(compact3(tk)) << tb, int32_t(compact3(tk >> 1)) << tb,
                            int32_t(compact3(tk >> 2)) << tb};
+    if (PASS == 1) {
+      // a tile that is one unit as a whole: its candidate count came with the count pass
+      const int64_t wc = ucnt[t] >> 32;
+      if (wc > 0) {
+        if (threadIdx.x == 0 && wc > 1) {
+          Unit u;
+          u.tile = t;
+          u.cand = wc - 1;
+          u.o[0] = to[0];
+          u.o[1] = to[1];
+          u.o[2] = to[2];
+          u.lev = int16_t(tb);
+          u.ncell = 1;
+          units[uoff[t]] = u;
+        }
+        continue;
+      }
+    }
     // the whole tile
     int64_t c = 0;
     for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
@@ -294,7 +312,10 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
       }
       __syncthreads();
     }
-    if (PASS == 0 && threadIdx.x == 0) ucnt[t] = nu;
+    // units per tile (low half); a tile that is one unit as a whole also keeps its candidate
+    // count plus one (high half), so that the writing pass skips it
+    if (PASS == 0 && threadIdx.x == 0)
+      ucnt[t] = nu | ((c <= kUnitCand || tb == 0) && c < (int64_t(1) << 30) ? (c + 1) << 32 : 0);
     __syncthreads();
   }
 }
@@ -897,6 +918,10 @@ struct ArrIn64 {
   const int64_t* a;
   __device__ int64_t operator()(int64_t i) const { return a[i]; }
 };
+struct UnitCountIn {                 // units per tile: the low half of the planner's count word
+  const int64_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i] & 0xffffffff; }
+};
 struct ArrOut64 {
   int64_t* o;
   __device__ void operator()(int64_t i, int64_t ex, int64_t) const { o[i] = ex; }
@@ -954,7 +979,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   hipLaunchKernelGGL((k_unit_plan<P, K>), dim3(grid), dim3(kBlock), 0, s, w.rec, (const K*)R.keys, R.prim, w.tstart, \
                      w.ctl, tb, batch ? 1 : 0, w.ucnt, w.uoff, w.units)
     if (key64) VX_PLAN(0, uint64_t); else VX_PLAN(0, uint32_t);
-    device_scan(ArrIn64{w.ucnt}, ArrOut64{w.uoff}, UnitTotal{w.uoff, w.ctl, stats, max_units}, w.ctl + CTL_N_TILES,
+    device_scan(UnitCountIn{w.ucnt}, ArrOut64{w.uoff}, UnitTotal{w.uoff, w.ctl, stats, max_units}, w.ctl + CTL_N_TILES,
                 0, w.partial, s);
     if (key64) VX_PLAN(1, uint64_t); else VX_PLAN(1, uint32_t);
 #undef VX_PLAN
