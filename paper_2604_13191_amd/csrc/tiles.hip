@@ -483,7 +483,8 @@ __device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3
 
 // Staging of a unit's voxels (SoA, capacity cap); units claim contiguous ranges in any order.
 struct Stage {
-  uint64_t* key;
+  void* key;          // u64, or u32 where the leaf's keys are 32-bit
+  int key64;
   uint32_t* count;
   float* w;
   float* S;           // [6][cap]
@@ -492,7 +493,8 @@ struct Stage {
 
 template <int KIND>
 __device__ __forceinline__ void write_voxel(const Stage& st, int64_t i, uint64_t key, uint32_t cnt, const Moment& m) {
-  st.key[i] = key;
+  if (st.key64) static_cast<uint64_t*>(st.key)[i] = key;
+  else static_cast<uint32_t*>(st.key)[i] = uint32_t(key);
   st.count[i] = cnt;
   st.w[i] = m.W;
   st.S[i] = m.xx;
@@ -841,7 +843,7 @@ __global__ void __launch_bounds__(kBlock) k_unit_compact(const int64_t* __restri
   for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
     const int64_t n = unv[u], src = usoff[u], dst = upos[u];
     for (int64_t i = threadIdx.x; i < n; i += kBlock) {
-      okeys[dst + i] = Key(st.key[src + i]);
+      okeys[dst + i] = static_cast<const Key*>(st.key)[src + i];
       out.count[dst + i] = st.count[src + i];
       out.w[dst + i] = st.w[src + i];
 #pragma unroll
@@ -901,7 +903,8 @@ static size_t tile_ws_layout(int64_t n_prims, int64_t max_rec, int64_t max_units
   x.usoff = cv.take<int64_t>(max_units + 1);
   x.upos = cv.take<int64_t>(max_units + 1);
   x.stage_ctr = cv.take<int64_t>(1);
-  x.st.key = cv.take<uint64_t>(max_vox);
+  x.st.key = cv.take<uint8_t>(max_vox * kb);
+  x.st.key64 = key64 ? 1 : 0;
   x.st.count = cv.take<uint32_t>(max_vox);
   x.st.w = cv.take<float>(max_vox);
   x.st.S = cv.take<float>(6 * max_vox);
