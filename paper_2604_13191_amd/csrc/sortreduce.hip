@@ -202,45 +202,109 @@ constexpr int kLodBlock = 1024;
 constexpr int kLodWaves = kLodBlock / 64;
 
 // The small top levels in one launch (one block): level after level, heads of the parent key
-// in chunks, ranks by block scan, children summed as above.  in_cap of every level <= kTailMax.
+// in chunks, ranks by block scan, children summed as above.  The levels built here stay in LDS
+// between levels (in place: every parent's sums are taken into registers before any parent is
+// written back), so a level never reads global memory written by the one before.  in_cap of the
+// first level <= kTailMax.
 constexpr int kTailLevels = 21;
+constexpr int kTailChunks = int(kTailMax / kLodBlock);
+static_assert(kTailMax % kLodBlock == 0, "whole chunks");
 struct TailLevels {
   vx_voxels lv[kTailLevels];    // lv[0] = the input of the first level built here
   int64_t* n[kTailLevels];      // device counts, n[0] the input's
   int count;                    // levels to build: lv[1 .. count]
 };
 
+template <class Key>
+constexpr size_t tail_lds_bytes() {
+  return size_t(kTailMax) * (sizeof(Key) + 4 + 4 + 24);
+}
+
 template <class Key, bool BATCH>
 __global__ void __launch_bounds__(kLodBlock) k_lod_tail(TailLevels T, int64_t* __restrict__ flags) {
+  extern __shared__ double tail_dyn[];
   __shared__ int64_t tmp[kLodWaves + 1];
-  for (int L = 1; L <= T.count; ++L) {
-    const vx_voxels& in = T.lv[L - 1];
-    const vx_voxels& out = T.lv[L];
-    const int64_t n = *T.n[L - 1];
+  Key* lk = reinterpret_cast<Key*>(tail_dyn);
+  uint32_t* lc = reinterpret_cast<uint32_t*>(lk + kTailMax);
+  float* lw = reinterpret_cast<float*>(lc + kTailMax);
+  float* lS = lw + kTailMax;                                 // [6][kTailMax]
+  const int tid = threadIdx.x;
+  int64_t n = *T.n[0];
+  n = n < kTailMax ? n : kTailMax;
+  {
+    const vx_voxels& in = T.lv[0];
     const Key* k = reinterpret_cast<const Key*>(in.keys);
+    for (int64_t i = tid; i < n; i += kLodBlock) {
+      lk[i] = k[i];
+      lc[i] = in.count[i];
+      lw[i] = in.w[i];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) lS[c * kTailMax + i] = in.S[c * in.cap + i];
+    }
+  }
+  __syncthreads();
+  for (int L = 1; L <= T.count; ++L) {
+    const vx_voxels& out = T.lv[L];
+    // read phase: every parent's sums into registers (chunk q of the children, one per thread)
+    int64_t pp[kTailChunks];
+    Key pk[kTailChunks];
+    uint32_t pc[kTailChunks], pm[kTailChunks];
+    float pw[kTailChunks], pS[kTailChunks][6];
     int64_t base = 0;
-    for (int64_t t0 = 0; t0 < n; t0 += kLodBlock) {
-      const int64_t i = t0 + threadIdx.x;
-      const bool head = i < n && (i == 0 || parent_key<Key, BATCH>(k[i]) != parent_key<Key, BATCH>(k[i - 1]));
+#pragma unroll
+    for (int q = 0; q < kTailChunks; ++q) {
+      pp[q] = -1;
+      if (int64_t(q) * kLodBlock >= n) continue;     // uniform: no children in this chunk
+      const int64_t i = int64_t(q) * kLodBlock + tid;
+      const bool head = i < n && (i == 0 || parent_key<Key, BATCH>(lk[i]) != parent_key<Key, BATCH>(lk[i - 1]));
       int64_t tot;
       const int64_t ex = block_exclusive_scan_n<kLodWaves>(int64_t(head), tmp, tot);
+      pp[q] = head ? base + ex : -1;
+      pk[q] = 0;
+      pc[q] = 0;
+      pm[q] = 0;
+      pw[q] = 0.f;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) pS[q][c] = 0.f;
       if (head) {
-        const int64_t p = base + ex;
-        if (p < out.cap) {
-          const Key pk = parent_key<Key, BATCH>(k[i]);
-          int64_t j = i + 1;
-          while (j < n && j < i + 8 && parent_key<Key, BATCH>(k[j]) == pk) ++j;
-          lod_parent<Key, BATCH>(in, k, i, j, out, p);
+        const Key key = parent_key<Key, BATCH>(lk[i]);
+        pk[q] = key;
+        for (int64_t j = i; j < n && j < i + 8 && parent_key<Key, BATCH>(lk[j]) == key; ++j) {
+          pc[q] += lc[j];
+          pm[q] |= 1u << uint32_t(lk[j] & 7);
+          pw[q] += lw[j];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) pS[q][c] += lS[c * kTailMax + j];
         }
       }
       base += tot;
     }
-    if (threadIdx.x == 0) {
-      const bool over = base > out.cap;
-      if (over) flag_or_s(flags, VX_FLAG_VOXEL_CAPACITY);
-      *T.n[L] = over ? out.cap : base;
+    __syncthreads();                                 // all children read before any is overwritten
+    const int64_t cap = out.cap;
+    Key* ok = reinterpret_cast<Key*>(out.keys);
+#pragma unroll
+    for (int q = 0; q < kTailChunks; ++q) {
+      const int64_t p = pp[q];
+      if (p >= 0 && p < cap) {
+        lk[p] = pk[q];
+        lc[p] = pc[q];
+        lw[p] = pw[q];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) lS[c * kTailMax + p] = pS[q][c];
+        ok[p] = pk[q];
+        out.count[p] = pc[q];
+        out.mask[p] = uint8_t(pm[q]);
+        out.w[p] = pw[q];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) out.S[c * cap + p] = pS[q][c];
+      }
     }
-    __threadfence();                                // this level's writes before the next reads them
+    const bool over = base > cap;
+    if (tid == 0) {
+      if (over) flag_or_s(flags, VX_FLAG_VOXEL_CAPACITY);
+      *T.n[L] = over ? cap : base;
+    }
+    n = over ? cap : base;
     __syncthreads();
   }
 }
@@ -290,12 +354,24 @@ void lod_tail(bool key64, bool batch, const vx_voxels* lv, int64_t* const* n, in
     T.n[i] = n[i];
   }
   T.count = count < kTailLevels ? count : kTailLevels - 1;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_lod_tail<uint64_t, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(tail_lds_bytes<uint64_t>()));
+    (void)hipFuncSetAttribute((const void*)k_lod_tail<uint64_t, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(tail_lds_bytes<uint64_t>()));
+    (void)hipFuncSetAttribute((const void*)k_lod_tail<uint32_t, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(tail_lds_bytes<uint32_t>()));
+    attr = true;
+  }
   if (batch)
-    hipLaunchKernelGGL((k_lod_tail<uint64_t, true>), dim3(1), dim3(kLodBlock), 0, s, T, flags);
+    hipLaunchKernelGGL((k_lod_tail<uint64_t, true>), dim3(1), dim3(kLodBlock), tail_lds_bytes<uint64_t>(), s, T, flags);
   else if (key64)
-    hipLaunchKernelGGL((k_lod_tail<uint64_t, false>), dim3(1), dim3(kLodBlock), 0, s, T, flags);
+    hipLaunchKernelGGL((k_lod_tail<uint64_t, false>), dim3(1), dim3(kLodBlock), tail_lds_bytes<uint64_t>(), s, T,
+                       flags);
   else
-    hipLaunchKernelGGL((k_lod_tail<uint32_t, false>), dim3(1), dim3(kLodBlock), 0, s, T, flags);
+    hipLaunchKernelGGL((k_lod_tail<uint32_t, false>), dim3(1), dim3(kLodBlock), tail_lds_bytes<uint32_t>(), s, T,
+                       flags);
 }
 
 }  // namespace vx
