@@ -256,7 +256,7 @@ def main():
     ap.add_argument("--no-brushed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design note, "
+        print(json.dumps({"error": "this library runs on one GPU; sharding across GPUs is a design note only, "
                                    "run with --gpus 1"}))
         sys.exit(2)
 
