@@ -47,10 +47,10 @@ def kernel_bytes(name, c):
     table = {
         "prep_fib": 12 * N + 8 * (F + 1) + rec * N + 16 * N + 8 * N,
         "check_offsets": 8 * (F + 1),
-        # per unit: its records (primitive id + record), per pair the primitive's direction,
-        # per voxel the staged key, count, w and S
-        "unit_fib": 4 * T + rec * T + 16 * P + 40 * V + 32 * U,
-        "unit_compact": 2 * 40 * V + 24 * U,
+        # per record of a unit: primitive id, record and the primitive's direction; per voxel the
+        # staged key (leaf key width), count, w and S; per unit its descriptor
+        "unit_fib": (4 + rec + 16) * T + (kb + 32) * V + 32 * U,
+        "unit_compact": 2 * (kb + 32) * V + 24 * U,
         "radix_scatter": 2 * (kb + 8) * T,
         "radix_hist": kb * T,
     }
