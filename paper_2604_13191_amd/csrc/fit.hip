@@ -63,16 +63,17 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // the children of voxel u staged by the group: cw[c], cS[c][6]; returns their number
+template <class T>
 __device__ __forceinline__ int stage_children(const vx_voxels& ch, const int64_t* cstart, int64_t u, bool active,
-                                              int gl, float* cw, float (*cS)[6], int64_t& first) {
+                                              int gl, T* cw, T (*cS)[6], int64_t& first) {
   int nc = 0;
   first = 0;
   if (active) nc = child_range(cstart, u, first);
   if (active && gl < nc) {
     const int64_t cc = first + gl;
-    cw[gl] = ch.w[cc];
+    cw[gl] = T(ch.w[cc]);
 #pragma unroll
-    for (int t = 0; t < 6; ++t) cS[gl][t] = ch.S[int64_t(t) * ch.cap + cc];
+    for (int t = 0; t < 6; ++t) cS[gl][t] = T(ch.S[int64_t(t) * ch.cap + cc]);
   }
   wave_sync_lds();
   return nc;
@@ -175,9 +176,18 @@ __global__ void __launch_bounds__(1024) k_fit_total(const float* __restrict__ pa
 // target is invariant when all children scale alike), so the parts must be accurate.
 // gch: [7][gcap] (S components, then w) for the level below.  DPL: directions per lane.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ double quadd(const float* S, double x, double y, double z) {
-  return double(S[0]) * x * x + double(S[1]) * y * y + double(S[2]) * z * z +
-         2.0 * (double(S[3]) * x * y + double(S[4]) * x * z + double(S[5]) * y * z);
+// 1 / sqrt(x), x > 0: the hardware estimate refined by one Newton step,
+// r' = r (3/2 - x r^2 / 2), which squares the estimate's relative error
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * r;
+  return fma(r, fma(-h, r, 0.5), r);
+}
+// sqrt(x) for x >= 0 as x / sqrt(x)
+__device__ __forceinline__ double sqrt_nr(double x) { return x > 0.0 ? x * rsqrt_nr(x) : 0.0; }
+
+__device__ __forceinline__ double quadd(const double* S, double x, double y, double z) {
+  return S[0] * x * x + S[1] * y * y + S[2] * z * z + 2.0 * (S[3] * x * y + S[4] * x * z + S[5] * y * z);
 }
 
 template <int DPL>
@@ -186,9 +196,10 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
                                                     const float* __restrict__ dirs, int ndir,
                                                     const float* __restrict__ dloss, float* __restrict__ dLp,
                                                     double* __restrict__ gch, int64_t gcap) {
-  __shared__ float sdir[kMaxDir][3];
-  __shared__ float scw[kGroups][kMaxChild];
-  __shared__ float scS[kGroups][kMaxChild][6];
+  // directions and the children's sums in FP64 once, not converted in the inner loops
+  __shared__ double sdir[kMaxDir][3];
+  __shared__ double scw[kGroups][kMaxChild];
+  __shared__ double scS[kGroups][kMaxChild][6];
   for (int k = threadIdx.x; k < ndir; k += kBlock)
     for (int a = 0; a < 3; ++a) sdir[k][a] = dirs[3 * k + a];
   __syncthreads();
@@ -204,7 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
     const bool active = in && Wf > 0.f;
     int64_t first;
     const int nc = stage_children(ch, cstart, u, active, gl, scw[grp], scS[grp], first);
-    const float* cw = scw[grp];
+    const double* cw = scw[grp];
     double l[12], gl12[12], dg[DPL], dt[DPL];
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
@@ -224,7 +235,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
       for (int c = 0; c < nc; ++c) {
         const double wc = double(cw[c]);
         if (!(wc > 0.0)) continue;
-        tau += sqrt(fmax(wc * quadd(scS[grp][c], x, y, z), 0.0));
+        tau += sqrt_nr(fmax(wc * quadd(scS[grp][c], x, y, z), 0.0));
       }
       tau *= invW;
       double f = 0.0, yv[2][3], ry[2];
@@ -235,7 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
         yv[j][1] = lj[2] * y + lj[4] * z;
         yv[j][2] = lj[5] * z;
         const double n2 = yv[j][0] * yv[j][0] + yv[j][1] * yv[j][1] + yv[j][2] * yv[j][2];
-        ry[j] = n2 > 0.0 ? rsqrt(n2) : 0.0;                    // 1 / |L_j^T w|
+        ry[j] = n2 > 0.0 ? rsqrt_nr(n2) : 0.0;                 // 1 / |L_j^T w|
         f += n2 * ry[j];
       }
       const double g = (f - tau) * g2;                          // d loss / d f;  d loss / d tau = -g
@@ -276,7 +287,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
           const double q2 = wc * qs;
           double dw = -dt[i] * invW;
           if (q2 > 0.0) {
-            const double h = 0.5 * rsqrt(q2) * invW;            // 1 / (2 sqrt(w_c w^T S_c w)) / W
+            const double h = 0.5 * rsqrt_nr(q2) * invW;         // 1 / (2 sqrt(w_c w^T S_c w)) / W
             const double k2 = -g * wc * h;                      // d loss / d (w^T S_c w)
             acc[0] += k2 * x * x;
             acc[1] += k2 * y * y;
