@@ -157,6 +157,42 @@ def test_adversarial_fibers(vx, log2_res, radius):
     compare_level(leaf.numpy(), ref.keys, ref.count, ref.w, ref.S, what=f"adv fibers R{R} r{radius}")
 
 
+def test_crowded_voxels(vx):
+    """Voxels touched by more primitives than a unit holds (summed in streaming order), siblings
+    of such voxels, and a crowded corner whose tile splits down to single cells and sibling
+    groups; next to large primitives spanning many tiles."""
+    R = 64
+    grid = synth.Grid((0.0, 0.0, 0.0), float(R), 6)
+    rng = np.random.default_rng(41)
+
+    def tiny(n, lo, hi):
+        c = rng.uniform(lo, hi, size=(n, 1, 3))
+        return c + rng.uniform(-0.05, 0.05, size=(n, 3, 3))
+
+    tris = np.concatenate([
+        tiny(5000, 20.1, 20.9),                                            # one voxel, 5000 triangles
+        tiny(3500, 20.1, 20.9) + np.array([1.0, 0.0, 0.0]),               # its sibling, 3500
+        tiny(2500, 16.1, 19.9),                                            # a crowded 4^3 corner
+        rng.uniform(0.0, R, size=(40, 3, 3)),                              # large triangles
+    ]).astype(np.float32)
+    say("case: crowded voxels, triangles R=64")
+    leaf = vx.voxelize_triangles(_dev(tris), grid)
+    ref = oracle.voxelize_triangles(grid, tris)
+    assert leaf.plan.n_pairs == ref.n_pairs
+    compare_pyramid(vx.build_lod(grid, leaf, 7), oracle.build_lod(ref, 7), "crowded tris")
+    # fibers: 4000 short segments inside one voxel, random walks around them
+    a = rng.uniform(30.2, 30.8, size=(4000, 1, 3))
+    seg = np.concatenate([a, a + rng.uniform(-0.15, 0.15, size=(4000, 1, 3))], 1)
+    walks = np.clip(30.5 + np.cumsum(rng.normal(0, 1.5, size=(300, 8, 3)), 1), 0.0, R)
+    pts = np.concatenate([seg.reshape(-1, 3), walks.reshape(-1, 3)]).astype(np.float32)
+    offs = np.concatenate([np.arange(0, 8001, 2), 8000 + np.arange(1, 301) * 8]).astype(np.int64)
+    say("case: crowded voxels, fibers R=64 r=0.5")
+    leaf = vx.voxelize_fibers(_dev(pts), _dev(offs), 0.5, grid)
+    ref = oracle.voxelize_fibers(grid, pts, offs, 0.5)
+    assert leaf.plan.n_pairs == ref.n_pairs
+    compare_pyramid(vx.build_lod(grid, leaf, 7), oracle.build_lod(ref, 7), "crowded fibers")
+
+
 def test_empty_and_outside(vx):
     grid = synth.Grid((0.0, 0.0, 0.0), 16.0, 4)
     say("case: empty input, all outside the grid")
