@@ -193,6 +193,30 @@ def test_crowded_voxels(vx):
     compare_pyramid(vx.build_lod(grid, leaf, 7), oracle.build_lod(ref, 7), "crowded fibers")
 
 
+@pytest.mark.parametrize("log2_res", [10, 11, 20])
+def test_resolution_limits(vx, log2_res):
+    """The last 32-bit-key grid, the first 64-bit one and the finest grid (4 lattice units per
+    voxel): small primitives scattered over the whole grid, the full pyramid."""
+    R = 1 << log2_res
+    grid = synth.Grid((-0.5 * R, 0.25 * R, 3.0), float(R), log2_res)
+    rng = np.random.default_rng(300 + log2_res)
+    c = np.array(grid.bmin) + rng.uniform(0, R, size=(400, 1, 3))
+    tris = (c + rng.normal(0, 1.5, size=(400, 3, 3))).astype(np.float32)
+    say(f"case: triangles at R=2^{log2_res}")
+    leaf = vx.voxelize_triangles(_dev(tris), grid)
+    ref = oracle.voxelize_triangles(grid, tris)
+    assert leaf.plan.n_pairs == ref.n_pairs
+    compare_pyramid(vx.build_lod(grid, leaf, log2_res + 1), oracle.build_lod(ref, log2_res + 1), f"tris 2^{log2_res}")
+    start = np.array(grid.bmin) + rng.uniform(0, R, size=(150, 1, 3))
+    pts = (start + np.cumsum(rng.normal(0, 1.2, size=(150, 6, 3)), 1)).reshape(-1, 3).astype(np.float32)
+    offs = np.arange(0, 151) * 6
+    say(f"case: fibers at R=2^{log2_res}")
+    leaf = vx.voxelize_fibers(_dev(pts), _dev(offs), 0.5, grid)
+    ref = oracle.voxelize_fibers(grid, pts, offs, 0.5)
+    assert leaf.plan.n_pairs == ref.n_pairs
+    compare_pyramid(vx.build_lod(grid, leaf, log2_res + 1), oracle.build_lod(ref, log2_res + 1), f"fibers 2^{log2_res}")
+
+
 def test_empty_and_outside(vx):
     grid = synth.Grid((0.0, 0.0, 0.0), 16.0, 4)
     say("case: empty input, all outside the grid")
