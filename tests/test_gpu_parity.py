@@ -195,7 +195,7 @@ def test_crowded_voxels(vx):
 
 @pytest.mark.parametrize("log2_res", [10, 11, 20])
 def test_resolution_limits(vx, log2_res):
-    """The last 32-bit-key grid, the first 64-bit one and the finest grid (4 lattice units per
+    """The last 32-bit-key grid, the first 64-bit one and the finest grid (8 lattice units per
     voxel): small primitives scattered over the whole grid, the full pyramid."""
     R = 1 << log2_res
     grid = synth.Grid((-0.5 * R, 0.25 * R, 3.0), float(R), log2_res)
