@@ -367,6 +367,7 @@ constexpr int32_t kUnitKeys = 4096;
 static_assert(kBlock * 9 * 4 >= kUnitKeys * 2, "per-key counters live in the record batch's space");
 static_assert(kBlock * 16 == kUnitKeys, "each thread owns 16 keys in the scan of the counters");
 static_assert(kUnitCand <= 0xffff, "pair positions are 16-bit");
+static_assert(kUnitCand % (kWaves * 64) == 0, "each wave's queue holds all of its candidates");
 // a candidate's outcome and key in one 16-bit word (keys below 4096)
 constexpr uint16_t kTouch = 0x8000, kUndecided = 0x4000;
 static_assert(kUnitKeys <= kUndecided, "keys fit below the flags");
@@ -529,7 +530,6 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     int32_t np = 0;                                   // pairs so far (uniform)
     Moment acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // streaming sums (thread 0)
     uint32_t acc_n = 0;
-    if (tid == 0) S.misc[5] = 0;                      // undecided candidates queued
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
       int nb;
       const int32_t cb = load_batch<KIND>(S, rec, rprim, j0, e, U.o, usz, nb);
@@ -569,10 +569,14 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       }
       // Test in two rounds so that lanes stay busy: a cheap filter decides most candidates and
       // queues the rest (fibers: the centre-ball filter), then the queue gets the full test.
-      // Waves work independently; every candidate records its outcome in place, and the
-      // touching ones are then compacted in candidate order, which is primitive order.
+      // Each wave works on its own candidates and drains its own queue (a quarter of the queue
+      // space: a wave holds at most a quarter of a unit's candidates); every candidate records
+      // its outcome in place, and the touching ones are then compacted in candidate order,
+      // which is primitive order.
       const int wv = tid >> 6, lane = tid & 63;
       const uint64_t lt = (uint64_t(1) << lane) - 1;
+      uint32_t* wq = reinterpret_cast<uint32_t*>(S.w) + wv * (kUnitCand / kWaves);
+      int32_t nq = 0;                                  // this wave's queue (uniform)
       for (int32_t c0 = wv * 64; c0 < cb; c0 += kBlock) {
         const int32_t c = c0 + lane;
         int res = 0;                                   // 0 miss, 1 touch, 2 undecided
@@ -592,15 +596,13 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
                                : (res == 2 ? kUndecided : uint16_t(0));
         }
         const uint64_t mb = __ballot(res == 2);
-        int32_t bb = 0;
-        if (lane == 0 && mb) bb = atomicAdd(&S.misc[5], int32_t(__popcll(mb)));
-        bb = __shfl(bb, 0, 64);
-        if (res == 2) reinterpret_cast<uint32_t*>(S.w)[bb + int32_t(__popcll(mb & lt))] = uint32_t(c);
+        if (res == 2) wq[nq + int32_t(__popcll(mb & lt))] = uint32_t(c);
+        nq += int32_t(__popcll(mb));
       }
-      __syncthreads();
-      const int32_t nq = S.misc[5];
-      for (int32_t q = tid; KIND == 1 && q < nq; q += kBlock) {
-        const int32_t c = int32_t(reinterpret_cast<const uint32_t*>(S.w)[q]);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int32_t q = lane; KIND == 1 && q < nq; q += 64) {
+        const int32_t c = int32_t(wq[q]);
         const int slot = find_slot(S, c);
         int64_t v[3];
         slot_voxel(S, slot, c - S.boff[slot], v);
@@ -644,7 +646,6 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
         np += tot;
         __syncthreads();
       }
-      if (tid == 0) S.misc[5] = 0;                     // the next batch's queue (after its barrier)
     }
     if (stream) {
       if (tid == 0) {
