@@ -29,8 +29,7 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64
 def kernel_flops(name, c):
     """Lower-bound FP64 operation count of the exact-test kernels: the centre-ball filter that
     every candidate takes (45 operations: box-relative coordinates and scale bound, the
-    projection of the box centre on the segment with one division, the clamped distance and the
-    two comparisons) and the clipped length of every touching pair (32: two divisions and the
+    projection of the box centre on the segment, the clamped distance and the two comparisons) and the clipped length of every touching pair (32: two divisions and the
     clamps per axis, the product by the length).  The exact bracketing of the candidates the
     filter leaves undecided is not counted."""
     if name in ("unit_fib",):
