@@ -31,17 +31,13 @@ __global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ t
 
 // One thread per point: point i starts segment (i, i+1) when both belong to the same fiber.
 __global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ pts, int64_t n_pts,
-                                                     const int64_t* __restrict__ offsets, int64_t n_fib, Lat L,
+                                                     const uint8_t* __restrict__ fstart, Lat L,
                                                      int32_t* __restrict__ rec, float4* __restrict__ dirs,
                                                      int64_t* __restrict__ cand_cnt, int64_t* stats) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_pts; i += int64_t(gridDim.x) * kBlock) {
-    // fiber of point i: the last f with offsets[f] <= i
-    int64_t lo = 0, hi = n_fib;
-    while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (offsets[mid] <= i) lo = mid; else hi = mid;
-    }
-    const bool seg = (i + 1 < n_pts) && (i + 1 < offsets[lo + 1]);
+    // point i and the next make a segment unless the next starts a fiber (offsets are
+    // non-decreasing, so a later point of the same fiber starts none)
+    const bool seg = (i + 1 < n_pts) && !fstart[i + 1];
     bool ok;
     cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, L, rec + i * kRec, dirs + i, ok);
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
@@ -51,7 +47,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ p
 // Batched fibers: patch p owns points [pt_begin[p], pt_begin[p+1]) and is snapped to its own
 // lattice; the record keeps the patch id in its last slot.
 __global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restrict__ pts, int64_t n_pts,
-                                                           const int64_t* __restrict__ offsets, int64_t n_fib,
+                                                           const uint8_t* __restrict__ fstart,
                                                            const Lat* __restrict__ lats,
                                                            const int64_t* __restrict__ pt_begin, int n_patches,
                                                            int32_t* __restrict__ rec, float4* __restrict__ dirs,
@@ -63,12 +59,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restri
       if (pt_begin[mid] <= i) lo = mid; else hi = mid;
     }
     const int patch = lo;
-    int64_t flo = 0, fhi = n_fib;
-    while (fhi - flo > 1) {
-      const int64_t mid = (flo + fhi) >> 1;
-      if (offsets[mid] <= i) flo = mid; else fhi = mid;
-    }
-    const bool seg = (i + 1 < n_pts) && (i + 1 < offsets[flo + 1]) && (i + 1 < pt_begin[patch + 1]);
+    const bool seg = (i + 1 < n_pts) && !fstart[i + 1] && (i + 1 < pt_begin[patch + 1]);
     bool ok;
     cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, lats[patch], rec + i * kRec, dirs + i,
                                ok);
@@ -77,8 +68,14 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restri
   }
 }
 
-__global__ void k_check_offsets(const int64_t* __restrict__ offsets, int64_t n_fib, int64_t n_pts, int64_t* stats) {
+// also marks the first point of every fiber (fstart cleared beforehand)
+__global__ void k_check_offsets(const int64_t* __restrict__ offsets, int64_t n_fib, int64_t n_pts,
+                                uint8_t* __restrict__ fstart, int64_t* stats) {
   for (int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; f <= n_fib; f += int64_t(gridDim.x) * blockDim.x) {
+    if (f < n_fib) {
+      const int64_t o = offsets[f];
+      if (o >= 0 && o < n_pts) fstart[o] = 1;
+    }
     bool bad = false;
     if (f == 0) bad = offsets[0] != 0;
     else bad = offsets[f] < offsets[f - 1];
@@ -259,6 +256,7 @@ void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_p
   x.dirs = cv.take<float4>(n_prims);
   x.cand_cnt = cv.take<int64_t>(n_prims);
   x.cand_off = cv.take<int64_t>(n_prims + 1);
+  x.fstart = reinterpret_cast<uint8_t*>(x.cand_off);    // free until the candidate scan
   x.masks = cv.take<uint64_t>(n_chunks);
   x.chunk_prim = cv.take<int64_t>(n_chunks);
   x.wave_off = cv.take<int64_t>(n_chunks + 1);
@@ -283,16 +281,17 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
   } else {
     {
       VX_TIMED("check_offsets", s);
+      launch_fill_i64(reinterpret_cast<int64_t*>(w.fstart), (n_prims + 8) / 8, 0, s);
       hipLaunchKernelGGL(k_check_offsets, dim3(int(n_fib / 256 + 1 < 256 ? n_fib / 256 + 1 : 256)), dim3(256), 0,
-                         s, offsets, n_fib, n_prims, stats);
+                         s, offsets, n_fib, n_prims, w.fstart, stats);
     }
     VX_TIMED("prep_fib", s);
     if (batch)
-      hipLaunchKernelGGL(k_prep_fib_batch, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, batch->lats,
+      hipLaunchKernelGGL(k_prep_fib_batch, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, w.fstart, batch->lats,
                          batch->pt_begin, batch->n_patches, w.rec, w.dirs, w.cand_cnt, stats);
     else
-      hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, offsets, n_fib, L, w.rec,
-                         w.dirs, w.cand_cnt, stats);
+      hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, w.fstart, L, w.rec, w.dirs,
+                         w.cand_cnt, stats);
   }
 }
 

@@ -944,6 +944,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   f.dirs = w.dirs;
   f.cand_cnt = w.cand_cnt;
   f.partial = w.partial;
+  f.fstart = reinterpret_cast<uint8_t*>(w.roff);       // free until the record counts
   prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch);
   launch_fill_i64(w.stage_ctr, 1, 0, s);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);

@@ -299,6 +299,7 @@ void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw,
 // the front half of voxelize (prims.hip): pairs in emission order (by primitive, then candidate)
 struct FrontWs {
   int64_t* ctl;
+  uint8_t* fstart;     // [n_prims + 8] fibers: point i starts a fiber (space shared with a later stage)
   int32_t* rec;
   float4* dirs;
   int64_t* cand_cnt;
