@@ -19,12 +19,21 @@ __device__ __forceinline__ void flag_or(int64_t* stats, int64_t bit) {
 // ---------------------------------------------------------------------------------------------
 // prep
 // ---------------------------------------------------------------------------------------------
+// a record (16 x int32, 64-byte aligned) as four 16-byte stores
+__device__ __forceinline__ void store_record(int32_t* __restrict__ dst, const int32_t (&r)[kRec]) {
+  int4* d = reinterpret_cast<int4*>(dst);
+#pragma unroll
+  for (int k = 0; k < kRec / 4; ++k) d[k] = make_int4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+}
+
 __global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ tris, int64_t n, Lat L,
                                                      int32_t* __restrict__ rec, float4* __restrict__ dirs,
                                                      int64_t* __restrict__ cand_cnt, int64_t* stats) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     bool ok;
-    cand_cnt[i] = prep_triangle(tris + i * 9, L, rec + i * kRec, dirs + i, ok);
+    int32_t r[kRec];                                 // built in registers, stored as 4 x 16 bytes
+    cand_cnt[i] = prep_triangle(tris + i * 9, L, r, dirs + i, ok);
+    store_record(rec + i * kRec, r);
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
   }
 }
@@ -39,7 +48,9 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ p
     // non-decreasing, so a later point of the same fiber starts none)
     const bool seg = (i + 1 < n_pts) && !fstart[i + 1];
     bool ok;
-    cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, L, rec + i * kRec, dirs + i, ok);
+    int32_t r[kRec];
+    cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, L, r, dirs + i, ok);
+    store_record(rec + i * kRec, r);
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
   }
 }
@@ -61,9 +72,10 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restri
     const int patch = lo;
     const bool seg = (i + 1 < n_pts) && !fstart[i + 1] && (i + 1 < pt_begin[patch + 1]);
     bool ok;
-    cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, lats[patch], rec + i * kRec, dirs + i,
-                               ok);
-    rec[i * kRec + 15] = patch;
+    int32_t r[kRec];
+    cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, lats[patch], r, dirs + i, ok);
+    r[15] = patch;
+    store_record(rec + i * kRec, r);
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
   }
 }
