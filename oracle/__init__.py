@@ -13,6 +13,8 @@ Functions and the passages they follow:
   (the parent's normalised SGGX is the weight-averaged child SGGX), plus a child mask.
 * ``cluster_pyramid`` -- Sec. 4.4: agglomerative merging of the most similar lobes down to a
   cap of K per voxel, with the deterministic distance and Lloyd refinement in ``vxo.cpp``.
+* ``oracle.compact`` (a module of its own, numpy) -- Sec. 4.1 leaf eigen-fit with an
+  eigenvalue floor, and Sec. 4.3's 6-byte compact SGGX code and its decoding.
 
 Pins (tests/test_oracle_*.py): exact-rational brute force (``oracle/brute.py``) on tiny
 grids; conservation of area / length / moment; closed forms for axis-aligned fibers and
