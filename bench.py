@@ -120,6 +120,36 @@ def fit_timing(vx, wl, pts, offs, args, plain_ms):
             "fitted_voxels": int(sum(plan.counts[1:7]))}
 
 
+def compact_timing(vx, leaf, args):
+    """Leaf eigen-fit + 6-byte SGGX code over every leaf voxel of the fabric, and the decoding of
+    those codes; kernel times from events around each launch on the launch stream."""
+    import torch
+    n = leaf.n
+    code = None
+    for _ in range(max(1, args.warmup)):
+        lam, vec, code = vx.sggx_compact(leaf.w, leaf.S, n=n, eps=1e-3)
+        vx.sggx_decode(code, n=n)
+    torch.cuda.synchronize()
+    vx.timing_reset()
+    vx.timing_filter(None)
+    vx.timing_enable(True)
+    for _ in range(args.steps):
+        vx.sggx_compact(leaf.w, leaf.S, n=n, eps=1e-3)
+        vx.sggx_decode(code, n=n)
+    vx.timing_enable(False)
+    kt = vx.timing_collect()
+    out = {"workload": "leaf voxels of the plain weave", "voxels": n}
+    # algorithmic bytes per voxel: w + S in (28), code (6) + eigenvalues (12) + eigenvectors (36) out;
+    # decoding reads the code (6) and writes S (24)
+    for name, per in (("sggx_compact", 82), ("sggx_decode", 30)):
+        ms, cnt = kt.get(name, (0.0, 0))
+        avg = ms / max(cnt, 1)
+        gbs = per * n / (avg * 1e-3) / 1e9 if avg > 0 else None
+        out[name] = {"avg_ms": avg, "launches": cnt, "bytes_per_voxel": per, "GBps": gbs,
+                     "hbm_frac": gbs / 8000.0 if gbs else None}
+    return out
+
+
 def _single_build(vx, wl, K):
     """Single-instance plain path for one fiber set: voxelize + full pyramid with K lobes."""
     import torch
@@ -253,6 +283,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--no-brushed", action="store_true")
+    ap.add_argument("--no-compact", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; sharding across GPUs is a design note only, "
@@ -391,6 +422,8 @@ def main():
     }
     if not args.no_fit:
         out["fit"] = fit_timing(vx, wl, pts, offs, args, ms_step)
+    if not args.no_compact:
+        out["sggx_compact"] = compact_timing(vx, leaf, args)
     if not args.no_batch or not args.no_brushed:
         del plan, lod
         torch.cuda.empty_cache()

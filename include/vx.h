@@ -245,6 +245,36 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
                          void* workspace, size_t ws_bytes, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Leaf eigen-fit and compact SGGX storage (Sec. 4.1 "Fitting to SGGX distribution"; Sec. 4.3
+ * "Storing data", the compact-SGGX equation).
+ *
+ * For voxel i < min(*n_vox, vox->cap) with w_i > 0: M = S_i / w_i is diagonalised in FP64
+ * (eigenvalues lambda_1 >= lambda_2 >= lambda_3, the projected areas along the eigenvectors;
+ * each eigenvector of unit length with its largest-magnitude component positive), the
+ * eigenvalues are floored at eps * lambda_1 (a voxel of nearly one orientation still gets a
+ * well-defined SGGX), and the SGGX is rebuilt as sum_i lambda_i e_i e_i^T.  Voxels with
+ * w_i <= 0 (or M = 0) get the identity.  The rebuilt matrix, scaled so that its largest
+ * diagonal entry is 1, is stored in 6 bytes: sigma_a = sqrt(S_aa) as rint(255 sigma_a) for
+ * a = x, y, z, then r_ab = S_ab / sqrt(S_aa S_bb) as 128 + rint(127 r_ab) for xy, xz, yz.
+ *
+ * vox: the level (only w, S and cap are read); n_vox: device int64 [1];
+ * eps: in (0, 1]; lam: device float [3 * cap], lam[k * cap + i] (NULL: not written);
+ * vec: device float [9 * cap], component c of eigenvector k at vec[(3k + c) * cap + i]
+ * (NULL: not written); code: device uint8 [6 * cap], 2-byte aligned, voxel i at
+ * code[6i .. 6i + 5].  Entries i >= n are untouched.  Returns VX_ERR_ARG on a NULL
+ * required pointer, cap < 1, eps outside (0, 1] or a misaligned code; VX_ERR_HIP if the
+ * launch fails.  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------------------------ */
+vx_status vx_sggx_compact(const vx_voxels* vox, const int64_t* n_vox, float eps, float* lam, float* vec,
+                          uint8_t* code, vx_stream stream);
+
+/* Inverse of the byte code: sigma = b / 255, r = (b - 128) / 127, S_aa = sigma_a^2,
+ * S_ab = r_ab sigma_a sigma_b (FP64, rounded once to float).  code: device uint8 [6 * cap]
+ * (2-byte aligned); n: device int64 [1]; S: device float [6 * cap], S[c * cap + i] with
+ * c = xx, yy, zz, xy, xz, yz.  Errors as for vx_sggx_compact. */
+vx_status vx_sggx_decode(const uint8_t* code, const int64_t* n, int64_t cap, float* S, vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
  * Graph capture of a whole call (no host work inside, so it replays as one launch).  `stream`
  * must not be the null stream.  Between begin and end, enqueue library calls on `stream`;
  * vx_graph_launch replays them (with the buffers and sizes of the capture).

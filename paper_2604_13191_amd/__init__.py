@@ -121,6 +121,10 @@ def load():
     L.vx_timing_reset.argtypes = []
     L.vx_timing_collect.restype = i32
     L.vx_timing_collect.argtypes = [vp, vp, vp, i32]
+    L.vx_sggx_compact.restype = i32
+    L.vx_sggx_compact.argtypes = [ctypes.POINTER(CVoxels), vp, ctypes.c_float, vp, vp, vp, vp]
+    L.vx_sggx_decode.restype = i32
+    L.vx_sggx_decode.argtypes = [vp, vp, i64, vp, vp]
     _lib = L
     return L
 
@@ -386,6 +390,53 @@ def build_lod(grid, leaf: Voxels, levels, K=1, iters=2, n_leaf_dev=None, caps=No
     if return_lobes:
         return out, p.lobes
     return out
+
+
+def _count_dev(n, cap, device):
+    import torch
+    if n is None:
+        n = cap
+    if isinstance(n, int):
+        return torch.tensor([n], dtype=torch.int64, device=device)
+    return n
+
+
+def sggx_compact(w, S, n=None, eps=1e-3, vectors=True, stream=None):
+    """Leaf eigen-fit and 6-byte SGGX code of the first n voxels (Sec. 4.1, Sec. 4.3).
+
+    w: float32 [cap]; S: float32 [6, cap]; n: int or device int64 [1] (default cap).
+    Returns (lam float32 [3, cap], vec float32 [9, cap] or None, code uint8 [cap, 6]).
+    """
+    import torch
+    cap = int(w.shape[0])
+    if S.shape != (6, cap) or w.dtype != torch.float32 or S.dtype != torch.float32:
+        raise VxError(1, "sggx_compact: w [cap] and S [6, cap] float32")
+    w, S = w.contiguous(), S.contiguous()
+    n_dev = _count_dev(n, cap, w.device)
+    lam = torch.empty((3, cap), dtype=torch.float32, device=w.device)
+    vec = torch.empty((9, cap), dtype=torch.float32, device=w.device) if vectors else None
+    code = torch.empty((cap, 6), dtype=torch.uint8, device=w.device)
+    cv = CVoxels(None, None, w.data_ptr(), S.data_ptr(), None, cap)
+    st = load().vx_sggx_compact(ctypes.byref(cv), _ptr(n_dev), float(eps), _ptr(lam), _ptr(vec), _ptr(code),
+                                _stream(stream))
+    if st != 0:
+        raise VxError(st, "sggx_compact")
+    return lam, vec, code
+
+
+def sggx_decode(code, n=None, stream=None):
+    """uint8 [cap, 6] codes -> float32 [6, cap] SGGX matrices (largest sigma about 1)."""
+    import torch
+    cap = int(code.shape[0])
+    if code.shape != (cap, 6) or code.dtype != torch.uint8:
+        raise VxError(1, "sggx_decode: code uint8 [cap, 6]")
+    code = code.contiguous()
+    n_dev = _count_dev(n, cap, code.device)
+    S = torch.empty((6, cap), dtype=torch.float32, device=code.device)
+    st = load().vx_sggx_decode(_ptr(code), _ptr(n_dev), cap, _ptr(S), _stream(stream))
+    if st != 0:
+        raise VxError(st, "sggx_decode")
+    return S
 
 
 def timing_enable(on=True):

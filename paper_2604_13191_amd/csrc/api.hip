@@ -495,4 +495,20 @@ int32_t vx_timing_collect(char names[][48], double* total_ms, int64_t* launches,
   return k;
 }
 
+vx_status vx_sggx_compact(const vx_voxels* vox, const int64_t* n_vox, float eps, float* lam, float* vec,
+                          uint8_t* code, vx_stream stream) {
+  if (!vox || !vox->w || !vox->S || vox->cap < 1 || !n_vox || !code || !(eps > 0.0f) || !(eps <= 1.0f) ||
+      reinterpret_cast<uintptr_t>(code) % 2 != 0)
+    return VX_ERR_ARG;
+  sggx_compact_run(vox->w, vox->S, n_vox, vox->cap, double(eps), lam, vec, code,
+                   reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+vx_status vx_sggx_decode(const uint8_t* code, const int64_t* n, int64_t cap, float* S, vx_stream stream) {
+  if (!code || !n || !S || cap < 1 || reinterpret_cast<uintptr_t>(code) % 2 != 0) return VX_ERR_ARG;
+  sggx_decode_run(code, n, cap, S, reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
 }  // extern "C"

@@ -340,6 +340,11 @@ vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, co
 
 // the voxelize pass by tiles (tiles.hip); tb = tile bits per axis
 size_t tile_ws_bytes(int64_t n_prims, int64_t max_rec, int64_t max_units, int64_t max_vox, bool key64);
+// leaf eigen-fit + compact SGGX code, and its decoding (compact.hip)
+void sggx_compact_run(const float* w, const float* S, const int64_t* n, int64_t cap, double eps, float* lam,
+                      float* vec, uint8_t* code, hipStream_t s);
+void sggx_decode_run(const uint8_t* code, const int64_t* n, int64_t cap, float* S, hipStream_t s);
+
 vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                         int64_t n_fib, float radius, int64_t max_rec, int64_t max_units, void* ws,
                         const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb);

@@ -99,3 +99,27 @@ def test_batch_graph_and_grid_calls_host_side(lib):
     gg(arr, 5)
     assert list(arr) == [64, 128, 256, 512, 16384]      # a rejected call changes nothing
     assert sg((ctypes.c_int32 * 5)(*default), 5) == 0
+
+
+def test_sggx_compact_argument_errors(lib):
+    class CVox(ctypes.Structure):
+        _fields_ = [("keys", ctypes.c_void_p), ("count", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                    ("S", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("cap", ctypes.c_int64)]
+    f = lib.vx_sggx_compact
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(CVox), ctypes.c_void_p, ctypes.c_float] + [ctypes.c_void_p] * 4
+    fake = 4096                                   # never dereferenced: every call below fails its checks
+    v = CVox(None, None, fake, fake, None, 8)
+    assert f(ctypes.byref(v), fake, 0.0, None, None, fake, None) == 1          # eps must be > 0
+    assert f(ctypes.byref(v), fake, 1.5, None, None, fake, None) == 1          # eps <= 1
+    assert f(ctypes.byref(v), fake, float("nan"), None, None, fake, None) == 1
+    assert f(ctypes.byref(v), fake, 1e-3, None, None, None, None) == 1         # code is required
+    assert f(ctypes.byref(v), fake, 1e-3, None, None, fake + 1, None) == 1     # code 2-byte aligned
+    assert f(ctypes.byref(v), None, 1e-3, None, None, fake, None) == 1         # count required
+    v0 = CVox(None, None, fake, fake, None, 0)
+    assert f(ctypes.byref(v0), fake, 1e-3, None, None, fake, None) == 1        # cap >= 1
+    d = lib.vx_sggx_decode
+    d.restype = ctypes.c_int
+    d.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    assert d(None, fake, 8, fake, None) == 1 and d(fake, fake, 0, fake, None) == 1
+    assert d(fake + 1, fake, 8, fake, None) == 1
