@@ -10,7 +10,7 @@
 // SGGX.
 //
 // One thread per voxel, all arithmetic in FP64: cyclic Jacobi rotations on the 3x3 matrix
-// (each zeroes one off-diagonal entry), until the off-diagonal part is below 2^-60 of the
+// (each zeroes one off-diagonal entry), until the off-diagonal part is below 2^-52 of the
 // diagonal or after 12 sweeps.  Quotients and square roots use the hardware reciprocal and
 // reciprocal-square-root estimates refined by Newton steps.  The kernel streams 28 bytes in and up to 82 bytes out per
 // voxel, so it is bound by HBM once the rotations are cheap enough.
@@ -38,10 +38,10 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 
 // rotation in the (P, Q) plane that zeroes a[P][Q]; V accumulates the rotations by columns
 template <int P, int Q>
-__device__ __forceinline__ void jacobi_rotate(double (&a)[3][3], double (&V)[3][3]) {
+__device__ __forceinline__ void jacobi_rotate(double (&a)[3][3], double (&V)[3][3], double skip) {
   constexpr int R = 3 - P - Q;
   const double apq = a[P][Q];
-  if (!(fabs(apq) > 0x1p-1000)) return;   // zero (or far below any reachable scale): nothing to rotate
+  if (!(fabs(apq) > skip)) return;        // already negligible against the diagonal
   const double theta = (a[Q][Q] - a[P][P]) * rcp_nr(2.0 * apq);
   const double at = fabs(theta);
   double t;
@@ -126,10 +126,13 @@ __global__ void __launch_bounds__(kCBlock) k_sggx_compact(const float* __restric
       for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         const double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
         const double diag = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]);
-        if (!(off > 0x1p-60 * diag)) break;
-        jacobi_rotate<0, 1>(a, V);
-        jacobi_rotate<0, 2>(a, V);
-        jacobi_rotate<1, 2>(a, V);
+        if (!(off > 0x1p-52 * diag)) break;
+        // entries below 2^-56 of the diagonal are left alone (their sum stays under the stop
+        // level); the floor 2^-1000 keeps every quotient of a rotation finite
+        const double skip = fmax(0x1p-56 * diag, 0x1p-1000);
+        jacobi_rotate<0, 1>(a, V, skip);
+        jacobi_rotate<0, 2>(a, V, skip);
+        jacobi_rotate<1, 2>(a, V, skip);
       }
       d[0] = a[0][0];
       d[1] = a[1][1];
