@@ -255,6 +255,28 @@ void launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i64, dim3(blocks), dim3(256), 0, s, p, n, v);
 }
 
+// up to four ranges cleared by one launch (ranges with n = 0 are skipped)
+struct ZeroSet {
+  int64_t* p[4];
+  int64_t n[4];
+};
+
+__global__ void k_zero_multi(ZeroSet z) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    for (int64_t i = t; i < z.n[r]; i += stride) z.p[r][i] = 0;
+}
+
+static void launch_zero_multi(const ZeroSet& z, hipStream_t s) {
+  int64_t m = 1;
+  for (int r = 0; r < 4; ++r) m = z.n[r] > m ? z.n[r] : m;
+  int blocks = int((m + 255) / 256);
+  blocks = blocks > 1024 ? 1024 : blocks;
+  hipLaunchKernelGGL(k_zero_multi, dim3(blocks), dim3(256), 0, s, z);
+}
+
 // ---------------------------------------------------------------------------------------------
 // the whole voxelize pass
 // ---------------------------------------------------------------------------------------------
@@ -281,10 +303,12 @@ void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_p
 
 void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                 int64_t n_fib, float radius, const FrontWs& w, int64_t* stats, hipStream_t s,
-                const BatchLattice* batch) {
+                const BatchLattice* batch, int64_t* zero_extra, int64_t zero_extra_n) {
   const Lat L = make_lat(g, kind, radius);
-  launch_fill_i64(stats, VX_NSTAT, 0, s);
-  launch_fill_i64(w.ctl, CTL_SIZE, 0, s);
+  // one launch clears the stats, the control block, the fiber-start bytes and the caller's range
+  ZeroSet z{{stats, w.ctl, kind == 1 ? reinterpret_cast<int64_t*>(w.fstart) : nullptr, zero_extra},
+            {VX_NSTAT, CTL_SIZE, kind == 1 ? (n_prims + 8) / 8 : 0, zero_extra ? zero_extra_n : 0}};
+  launch_zero_multi(z, s);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
   if (kind == 0) {
     VX_TIMED("prep_tri", s);
@@ -293,7 +317,6 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
   } else {
     {
       VX_TIMED("check_offsets", s);
-      launch_fill_i64(reinterpret_cast<int64_t*>(w.fstart), (n_prims + 8) / 8, 0, s);
       hipLaunchKernelGGL(k_check_offsets, dim3(int(n_fib / 256 + 1 < 256 ? n_fib / 256 + 1 : 256)), dim3(256), 0,
                          s, offsets, n_fib, n_prims, w.fstart, stats);
     }

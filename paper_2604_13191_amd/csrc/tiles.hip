@@ -832,6 +832,83 @@ struct UnitCand {
   __device__ int64_t operator()(int64_t i) const { return u[i].cand; }
 };
 
+// The three unit-level sums after the unit kernel in one two-kernel scan: totals of the pairs and
+// of the candidates (statistics) and the exclusive scan of the voxels per unit (leaf positions).
+// Same chunking as device_scan; partial holds 3 values per block.
+__global__ void __launch_bounds__(kBlock) k_unit_sums_partial(const int64_t* __restrict__ unp,
+                                                              const Unit* __restrict__ units,
+                                                              const int64_t* __restrict__ unv,
+                                                              const int64_t* __restrict__ ctl,
+                                                              int64_t* __restrict__ partial) {
+  __shared__ int64_t red[3][kWaves];
+  const int64_t n = ctl[CTL_N_UNITS];
+  const int64_t chunk = scan_chunk(n);
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  int64_t ap = 0, ac = 0, av = 0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+    ap += unp[i];
+    ac += units[i].cand;
+    av += unv[i];
+  }
+  ap = wave_sum(ap);
+  ac = wave_sum(ac);
+  av = wave_sum(av);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x >> 6] = ap;
+    red[1][threadIdx.x >> 6] = ac;
+    red[2][threadIdx.x >> 6] = av;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    int64_t t = 0;
+    for (int i = 0; i < kWaves; ++i) t += red[threadIdx.x][i];
+    partial[3 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_unit_sums_apply(const int64_t* __restrict__ unv,
+                                                            int64_t* __restrict__ ctl,
+                                                            const int64_t* __restrict__ partial,
+                                                            int64_t* __restrict__ upos, int64_t* __restrict__ stats,
+                                                            int64_t cap) {
+  __shared__ int64_t tmp[kWaves + 1];
+  const int64_t n = ctl[CTL_N_UNITS];
+  const int64_t chunk = scan_chunk(n);
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  int64_t pre = 0, tp = 0, tc = 0, tv = 0;
+  for (int i = threadIdx.x; i < kGrid; i += kBlock) {
+    const int64_t v = partial[3 * i + 2];
+    if (i < int(blockIdx.x)) pre += v;
+    if (blockIdx.x == 0) {
+      tp += partial[3 * i];
+      tc += partial[3 * i + 1];
+      tv += v;
+    }
+  }
+  int64_t base;
+  (void)block_exclusive_scan(pre, tmp, base);
+  if (blockIdx.x == 0) {
+    int64_t t;
+    (void)block_exclusive_scan(tp, tmp, t);
+    if (threadIdx.x == 0) stats[VX_STAT_PAIRS] = t;
+    (void)block_exclusive_scan(tc, tmp, t);
+    if (threadIdx.x == 0) stats[VX_STAT_CAND] = t;
+    (void)block_exclusive_scan(tv, tmp, t);
+    if (threadIdx.x == 0) VoxTotal{upos, ctl, stats, cap}(t, n);
+  }
+  if (b0 >= b1) return;
+  for (int64_t t0 = b0; t0 < b1; t0 += kBlock) {
+    const int64_t i = t0 + threadIdx.x;
+    const int64_t v = i < b1 ? unv[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(v, tmp, tot);
+    if (i < b1) upos[i] = base + ex;
+    base += tot;
+  }
+}
+
 // one block per unit: copy its staged voxels to their place in the leaf
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_unit_compact(const int64_t* __restrict__ unv,
@@ -894,7 +971,7 @@ static size_t tile_ws_layout(int64_t n_prims, int64_t max_rec, int64_t max_units
   x.rb.w = cv.take<float>(max_rec);
   x.rb.prim = cv.take<uint32_t>(max_rec);
   x.hist = cv.take<int32_t>(int64_t(kRadixBuckets) * kGrid);
-  x.partial = cv.take<int64_t>(kGrid + 1);
+  x.partial = cv.take<int64_t>(3 * kGrid + 1);     // 3 values per block for the unit sums
   x.tstart = cv.take<int64_t>(max_rec + 1);
   x.ucnt = cv.take<int64_t>(max_rec + 1);
   x.uoff = cv.take<int64_t>(max_rec + 1);
@@ -945,8 +1022,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   f.cand_cnt = w.cand_cnt;
   f.partial = w.partial;
   f.fstart = reinterpret_cast<uint8_t*>(w.roff);       // free until the record counts
-  prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch);
-  launch_fill_i64(w.stage_ctr, 1, 0, s);
+  prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch, w.stage_ctr, 1);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
   {
     VX_TIMED("tile_records", s);
@@ -1011,10 +1087,10 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   }
   {
     VX_TIMED("unit_compact", s);
-    device_scan(ArrIn64{w.unp}, NoOut{}, SumTotal{stats + VX_STAT_PAIRS}, w.ctl + CTL_N_UNITS, 0, w.partial, s);
-    device_scan(UnitCand{w.units}, NoOut{}, SumTotal{stats + VX_STAT_CAND}, w.ctl + CTL_N_UNITS, 0, w.partial, s);
-    device_scan(ArrIn64{w.unv}, ArrOut64{w.upos}, VoxTotal{w.upos, w.ctl, stats, out->cap}, w.ctl + CTL_N_UNITS, 0,
-                w.partial, s);
+    hipLaunchKernelGGL(k_unit_sums_partial, dim3(kGrid), dim3(kBlock), 0, s, w.unp, w.units, w.unv, w.ctl,
+                       w.partial);
+    hipLaunchKernelGGL(k_unit_sums_apply, dim3(kGrid), dim3(kBlock), 0, s, w.unv, w.ctl, w.partial, w.upos, stats,
+                       out->cap);
     if (key64)
       hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(tuned_grid(kTuneCompact)), dim3(kBlock), 0, s, w.unv,
                          w.usoff, w.upos, w.ctl, w.st, *out);

@@ -325,7 +325,7 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
 // its first step: clear stats and control, snap the primitives, write records and candidate counts
 void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                 int64_t n_fib, float radius, const FrontWs& w, int64_t* stats, hipStream_t s,
-                const BatchLattice* batch);
+                const BatchLattice* batch, int64_t* zero_extra = nullptr, int64_t zero_extra_n = 0);
 
 // the differentiable two-lobe fit (fit.hip)
 size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, int log2R);
