@@ -203,8 +203,7 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
   Carver cv(ws);
   int64_t* pstart = cv.take<int64_t>(leaf->cap + 1);
   int64_t* partial = cv.take<int64_t>(kGrid + 1);
-  launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
-  lod_clamp(n_leaf, leaf->cap, n_levels, s);
+  lod_init(n_leaf, leaf->cap, n_levels, int64_t(levels) + 1, s);
   int L = 1;
   for (; L < levels; ++L) {
     const vx_voxels& in = L == 1 ? *leaf : out[L - 2];
@@ -341,8 +340,7 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
                                &out[0], stats, s, &bl, std::min(kTileBits, min_log2));
   if (st != VX_OK) return st;
   // the pyramid, with the patch-preserving parent
-  launch_fill_i64(n_levels, int64_t(levels) + 1, 0, s);
-  lod_clamp(stats + VX_STAT_VOXELS, leaf_cap, n_levels, s);
+  lod_init(stats + VX_STAT_VOXELS, leaf_cap, n_levels, int64_t(levels) + 1, s);
   int L = 1;
   for (; L < levels; ++L) {
     if (K == 1 && out[L - 1].cap <= kTailMax) break;

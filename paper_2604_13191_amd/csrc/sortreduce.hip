@@ -309,15 +309,21 @@ __global__ void __launch_bounds__(kLodBlock) k_lod_tail(TailLevels T, int64_t* _
   }
 }
 
-__global__ void k_clamp_count(const int64_t* src, int64_t cap, int64_t* dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t v = *src;
-    *dst = v < 0 ? 0 : (v > cap ? cap : v);
+// level counts of a pyramid build: entry 0 is the leaf count clamped to [0, cap], the other
+// count - 1 entries (levels and the flag word) start at zero
+__global__ void k_lod_init(const int64_t* src, int64_t cap, int64_t* n_levels, int64_t count) {
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
+    if (i == 0) {
+      const int64_t v = *src;
+      n_levels[0] = v < 0 ? 0 : (v > cap ? cap : v);
+    } else {
+      n_levels[i] = 0;
+    }
   }
 }
 
-void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(64), 0, s, src, cap, dst);
+void lod_init(const int64_t* src, int64_t cap, int64_t* n_levels, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_lod_init, dim3(1), dim3(64), 0, s, src, cap, n_levels, count);
 }
 
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,

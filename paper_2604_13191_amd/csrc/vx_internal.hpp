@@ -284,7 +284,7 @@ struct HeadOut {
 // receives every parent's first child
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
                int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s, bool batch = false);
-void lod_clamp(const int64_t* src, int64_t cap, int64_t* dst, hipStream_t s);
+void lod_init(const int64_t* src, int64_t cap, int64_t* n_levels, int64_t count, hipStream_t s);
 // levels lv[1 .. count] from lv[0] in one single-block launch (small levels, no lobes):
 // n[i] the device count of lv[i]
 constexpr int64_t kTailMax = 2048;
