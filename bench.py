@@ -139,6 +139,15 @@ def compact_timing(vx, leaf, args):
     vx.timing_enable(False)
     kt = vx.timing_collect()
     out = {"workload": "leaf voxels of the plain weave", "voxels": n}
+    # storage error of the byte code (untimed): decoded SGGX against S / w scaled to a largest
+    # diagonal entry of 1, per voxel the largest entry difference (it includes the eigenvalue floor)
+    dec = vx.sggx_decode(code, n=n)[:, :n].double()
+    pos = leaf.w[:n] > 0
+    M = leaf.S[:, :n].double()[:, pos] / leaf.w[:n].double()[pos]
+    M = M / M[:3].max(dim=0).values.clamp_min(1e-30)
+    err = (dec[:, pos] - M).abs().max(dim=0).values
+    out["code_error_max"] = float(err.max())
+    out["code_error_mean"] = float(err.mean())
     # algorithmic bytes per voxel: w + S in (28), code (6) + eigenvalues (12) + eigenvectors (36) out;
     # decoding reads the code (6) and writes S (24)
     for name, per in (("sggx_compact", 82), ("sggx_decode", 30)):
