@@ -42,16 +42,11 @@ __device__ __forceinline__ void jacobi_rotate(double (&a)[3][3], double (&V)[3][
   constexpr int R = 3 - P - Q;
   const double apq = a[P][Q];
   if (!(fabs(apq) > skip)) return;        // already negligible against the diagonal
-  const double theta = (a[Q][Q] - a[P][P]) * rcp_nr(2.0 * apq);
-  const double at = fabs(theta);
-  double t;
-  if (at > 1e150) {
-    t = 0.5 * rcp_nr(at);
-  } else {
-    const double q = fma(at, at, 1.0);
-    t = rcp_nr(at + q * rsqrt_nr(q));
-  }
-  if (theta < 0.0) t = -t;
+  // tangent of the rotation angle, the smaller root of t^2 + 2 theta t - 1 = 0 with
+  // theta = d / (2 a_pq): t = 2 a_pq sgn(d) / (|d| + sqrt(d^2 + 4 a_pq^2)), one quotient
+  const double d = a[Q][Q] - a[P][P];
+  const double q = fma(d, d, 4.0 * apq * apq);
+  const double t = (d < 0.0 ? -2.0 * apq : 2.0 * apq) * rcp_nr(fabs(d) + q * rsqrt_nr(q));
   const double c = rsqrt_nr(fma(t, t, 1.0));
   const double s = t * c;
   a[P][P] -= t * apq;
@@ -128,8 +123,9 @@ __global__ void __launch_bounds__(kCBlock) k_sggx_compact(const float* __restric
         const double diag = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]);
         if (!(off > 0x1p-52 * diag)) break;
         // entries below 2^-56 of the diagonal are left alone (their sum stays under the stop
-        // level); the floor 2^-1000 keeps every quotient of a rotation finite
-        const double skip = fmax(0x1p-56 * diag, 0x1p-1000);
+        // level); the floor 2^-500 keeps 4 a_pq^2 a normal number, so every quotient of a
+        // rotation is finite
+        const double skip = fmax(0x1p-56 * diag, 0x1p-500);
         jacobi_rotate<0, 1>(a, V, skip);
         jacobi_rotate<0, 2>(a, V, skip);
         jacobi_rotate<1, 2>(a, V, skip);
