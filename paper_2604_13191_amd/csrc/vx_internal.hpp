@@ -118,6 +118,7 @@ __device__ __forceinline__ T block_exclusive_scan_n(T v, T* tmp, T& total) {
 __device__ __forceinline__ int64_t scan_n(const int64_t* n_ptr, int64_t n_const) {
   return n_ptr ? *n_ptr : n_const;
 }
+constexpr int kScanRun = 4;   // consecutive elements per thread in a round of the apply pass
 __device__ __forceinline__ int64_t scan_chunk(int64_t n) {
   int64_t c = (n + kGrid - 1) / kGrid;
   return (c + kBlock - 1) / kBlock * kBlock;
@@ -169,12 +170,23 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(In in, Out out, Total tot
     }
   }
   if (b0 >= b1) return;
-  for (int64_t t0 = b0; t0 < b1; t0 += kBlock) {
-    const int64_t i = t0 + threadIdx.x;
-    const int64_t v = i < b1 ? in(i) : 0;
+  // each thread takes kScanRun consecutive elements per round: one block scan per
+  // kBlock * kScanRun elements
+  for (int64_t t0 = b0; t0 < b1; t0 += int64_t(kBlock) * kScanRun) {
+    const int64_t i0 = t0 + int64_t(threadIdx.x) * kScanRun;
+    int64_t v[kScanRun], run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      v[j] = i0 + j < b1 ? in(i0 + j) : 0;
+      run += v[j];
+    }
     int64_t tot;
-    const int64_t ex = block_exclusive_scan(v, tmp, tot);
-    if (i < b1) out(i, base + ex, v);
+    int64_t ex = base + block_exclusive_scan(run, tmp, tot);
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      if (i0 + j < b1) out(i0 + j, ex, v[j]);
+      ex += v[j];
+    }
     base += tot;
   }
 }
