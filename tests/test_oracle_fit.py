@@ -154,3 +154,43 @@ def test_fit_directions_cover_the_sphere_evenly():
     W = oracle.fit_dirs()
     assert W.shape == (128, 3) and np.allclose(np.linalg.norm(W, axis=1), 1.0)
     assert np.allclose(W.T @ W / 128, np.eye(3) / 3, atol=2e-3)
+
+
+def test_fit_target_over_several_children_by_hand():
+    """Three children of one level-1 voxel, worked by hand: two x-directed fiber pieces of length
+    3/4 (voxels (2,2,2) and (3,2,2), normalised SGGX diag(0, 1, 1)) and one y-directed piece of
+    length 1/2 (voxel (2,3,2), diag(1, 0, 1)).  The target is the density-weighted mean of the
+    children's projected areas, tau(w) = (3/4 sqrt(1 - wx^2) + 3/4 sqrt(1 - wx^2)
+    + 1/2 sqrt(1 - wy^2)) / 2, and with both lobes zero the loss is the mean of tau^2 over the
+    direction set.  An unweighted mean over the children, a division by the child count, or the
+    square root of the summed moments all give other values."""
+    grid = synth.Grid((0.0, 0.0, 0.0), 8.0, 3)
+    pts = np.array([[2.25, 2.5, 2.5], [3.75, 2.5, 2.5],      # x-directed, crosses x = 3
+                    [2.5, 3.25, 2.5], [2.5, 3.75, 2.5]],     # y-directed, inside voxel (2, 3, 2)
+                   dtype=np.float32)
+    off = np.array([0, 2, 4])
+    v = oracle.voxelize_fibers(grid, pts, off, 0.0)
+    assert [tuple(c) for c in oracle.demorton(v.keys, 3)] == [(2, 2, 2), (3, 2, 2), (2, 3, 2)]
+    assert np.allclose(v.w, [0.75, 0.75, 0.5], rtol=0, atol=1e-15)
+    n = oracle.fit_levels(grid, pts, off, 0.0, 1)
+    assert list(n) == [3, 1]
+    W = oracle.fit_dirs()
+    tau = (0.75 * np.sqrt(1 - W[:, 0] ** 2) * 2 + 0.5 * np.sqrt(1 - W[:, 1] ** 2)) / 2.0
+    want = np.mean(tau ** 2)
+    loss, lv, dL, _ = oracle.fit_eval(grid, pts, pts.astype(np.float64), off, 0.0, 1, 1, np.zeros((1, 12)))
+    assert abs(loss - want) <= 1e-12 * want and abs(lv[0] - want) <= 1e-12 * want
+    # the plausible misreadings, for the record: each differs from the target by far more
+    unweighted = np.mean(((np.sqrt(1 - W[:, 0] ** 2) * 2 + np.sqrt(1 - W[:, 1] ** 2)) / 3.0) ** 2)
+    summed = np.mean((np.sqrt(1.5 * (1 - W[:, 0] ** 2) + 0.5 * (1 - W[:, 1] ** 2)) / 2.0) ** 2)
+    per_child = np.mean(((0.75 * np.sqrt(1 - W[:, 0] ** 2) * 2 + 0.5 * np.sqrt(1 - W[:, 1] ** 2)) / 3.0) ** 2)
+    for other in (unweighted, summed, per_child):
+        assert abs(other - want) > 1e-3 * want
+    # with a single lobe L1 = diag(a, a, a) the fit is a |w| = a everywhere: loss = mean((a - tau)^2)
+    a = 0.4
+    row = np.array([[a, 0, a, 0, 0, a] + [0.0] * 6])
+    loss2, _, dL2, _ = oracle.fit_eval(grid, pts, pts.astype(np.float64), off, 0.0, 1, 1, row)
+    assert abs(loss2 - np.mean((a - tau) ** 2)) <= 1e-12 * loss2
+    # d loss / d L00 = mean(2 (a - tau) * d|L^T w| / d L00) with |L^T w| = a |w|: y0 = a wx, so
+    # d/dL00 of |y| = y0 wx / |y| = wx^2
+    g00 = np.mean(2 * (a - tau) * W[:, 0] ** 2)
+    assert abs(dL2[0, 0] - g00) <= 1e-12 * max(1.0, abs(g00))
