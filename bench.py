@@ -1,20 +1,30 @@
-"""Benchmark: voxelize + LoD pyramid of the plain-weave fabric on one MI355X.
+"""Benchmark: voxelize + LoD pyramid with lobe clustering of the brushed-metal height field on one
+MI355X, with the plain-weave fabric, the batched patches, the differentiable fit and the compact
+SGGX code as further sections.
 
-Workload: 2,000 fibers x 256 segments (float32 polylines), sinusoidal warp/weft crimp
-(period 64 voxels, amplitude 4), helix twist U(-5, 5) deg, N(0, 0.3^2) jitter, radius 0.5
-voxel, sparse 1024^3 grid, fiber lobe S = I - t t^T, 11-level LoD with one lobe per voxel
-(synth.plain_weave, seed 1).  A step is one full pass of the hot path on that input, already
-resident in HBM: snap + candidates, exact capsule tests with ballot compaction, clipped
-lengths, radix sort by Morton key, segmented SGGX reduce, and the 10 parent levels.
+Headline workload (synth.brushed_metal, seed 2): a 4096 x 4096 vertex height field (33,538,050
+float32 triangles, two per cell) with anisotropic ridges (wavelength about 8 cells along x and
+256 along y, amplitude 2 voxels), sparse 4096^3 grid, surface lobe S = n n^T weighted by clipped
+area, 13-level pyramid with K = 4 merged lobes per coarse voxel.  A step is one full pass of the
+hot path on that input, already resident in HBM: snap + candidate boxes, primitive-tile records and
+their radix sort, exact closed-box tests, clipped areas, per-voxel SGGX sums in primitive order,
+then the 12 parent levels with Ward + Lloyd lobe clustering.
 
-Prints one JSON line.  ``value`` is primitive-voxel pairs per second of whole steps.
+Prints one JSON line.  ``value`` is primitive-voxel pairs per second of whole steps (wall clock
+between two device synchronisations around K steps).  The roofline uses the algorithmic byte
+model of the path (bytes the method must move with pair lists in HBM):
+    B = B_in + 12 N_prims + 4 rec N_pairs + sum_L out_L N_L (written once, read once by the next level)
+with rec = 12 (32-bit keys) or 16 bytes (64-bit keys) per pair, out_0 = key + 4 + 4 + 24 bytes per
+leaf voxel, out_L = key + 4 + 28 (K = 1) or key + 4 + 28 (1 + K) bytes above it.  The unit kernel
+does the work of the pair terms (emit, sort, reduce) on chip, so its share is
+12 N_prims + 4 rec N_pairs + out_0 N_0.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
@@ -23,37 +33,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "primitive-voxel pairs/s & LoD build ms; fwd+bwd SGGX fit ms vs plain path"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64
 
 
-def kernel_flops(name, c):
-    """Lower-bound FP64 operation count of the exact-test kernels: the centre-ball filter that
-    every candidate takes (45 operations: box-relative coordinates and scale bound, the
-    projection of the box centre on the segment, the clamped distance and the two comparisons) and the clipped length of every touching pair (32: two divisions and the
-    clamps per axis, the product by the length).  The exact bracketing of the candidates the
-    filter leaves undecided is not counted."""
-    if name in ("unit_fib",):
-        return 45 * c["n_cand"] + 32 * c["n_pairs"]
-    return None
+# ------------------------------------------------------------------------------------------------
+# byte model
+# ------------------------------------------------------------------------------------------------
+
+def rec_bytes(key_bytes):
+    return 12 if key_bytes == 4 else 16
+
+
+def step_bytes(c, K):
+    """Algorithmic bytes of one step (voxelize + pyramid) from the run's counts."""
+    kb = c["key_bytes"]
+    out0 = kb + 4 + 4 + 24
+    outL = kb + 4 + 28 * (1 + K) if K > 1 else kb + 4 + 28
+    return (c["input_bytes"] + 12 * c["n_prims"] + 4 * rec_bytes(kb) * c["n_pairs"] + 2 * out0 * c["levels"][0]
+            + 2 * outL * sum(c["levels"][1:]))
 
 
 def kernel_bytes(name, c):
-    """Algorithmic bytes one launch of `name` must move (counted once), from the run's counts:
-    P pairs, C candidates, N primitives, V leaf voxels, F fibers, T records, U units."""
-    kb, P, N, V, F = c["key_bytes"], c["n_pairs"], c["n_prims"], c["n_vox"], c["n_fib"]
-    T, U = c["n_records"], c["n_units"]
-    rec = 64   # per-primitive record
-    table = {
-        "prep_fib": 12 * N + 8 * (F + 1) + rec * N + 16 * N + 8 * N,
-        "check_offsets": 8 * (F + 1),
-        # per record of a unit: primitive id, record and the primitive's direction; per voxel the
-        # staged key (leaf key width), count, w and S; per unit its descriptor
-        "unit_fib": (4 + rec + 16) * T + (kb + 32) * V + 32 * U,
-        "unit_compact": 2 * (kb + 32) * V + 24 * U,
-        "radix_scatter": 2 * (kb + 8) * T,
-        "radix_hist": kb * T,
-    }
-    return table.get(name)
+    """Algorithmic bytes one launch of `name` must move (counted once)."""
+    kb, P, N, V = c["key_bytes"], c["n_pairs"], c["n_prims"], c["levels"][0]
+    if name in ("unit_tri", "unit_fib"):
+        return 12 * N + 4 * rec_bytes(kb) * P + (kb + 32) * V
+    if name == "unit_compact":
+        return 2 * (kb + 32) * V
+    return None
 
 
 def source_digest():
@@ -67,11 +73,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a plain copy of known size), or None when absent or taken from
-    other sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_plain_weave.json")
+def traffic_bytes(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of `workload`
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None when absent or
+    taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -82,32 +88,152 @@ def traffic_bytes(kernel):
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
-def cpu_baseline(wl, nthreads):
-    import oracle
-    t0 = time.perf_counter()
-    ref = oracle.voxelize_fibers(wl.grid, wl.pts, wl.offsets, wl.radius, nthreads=nthreads)
-    oracle.build_lod(ref, wl.levels)
-    dt = time.perf_counter() - t0
-    return {"value": ref.n_pairs / dt, "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"the full workload once (voxelize + {wl.levels}-level pyramid, FP64, "
-                      f"{ref.n_pairs} pairs) in {dt:.2f} s on {nthreads} host threads"}
+# ------------------------------------------------------------------------------------------------
+# one single-instance workload: plans, kernel table, timed steps, roofline
+# ------------------------------------------------------------------------------------------------
 
+def make_plans(vx, kind, grid, data, levels, K, offsets=None, radius=0.0):
+    plan = vx.VoxelizePlan(kind, grid, data, offsets=offsets, radius=radius)
+    plan.run()
+    leaf = plan.check()
+    cal = vx.LodPlan(grid, leaf, plan.stats[2:3], levels).run()
+    caps = [max(v.n, 1) for v in cal.check()[1:]]
+    del cal
+    lod = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, K=K, iters=2, caps=caps)
+    lod.run()
+    lod.check()
+    return plan, lod, leaf
+
+
+def kernel_table(vx, plan, lod, counts, steps=5):
+    """Per-kernel time per step from events around every launch (untimed steps)."""
+    vx.timing_reset()
+    vx.timing_filter(None)
+    vx.timing_enable(True)
+    for _ in range(steps):
+        plan.run()
+        lod.run()
+    vx.timing_enable(False)
+    kt = vx.timing_collect()
+    kernels = {}
+    for name, (ms, n) in sorted(kt.items(), key=lambda x: -x[1][0]):
+        avg = ms / max(n, 1)
+        b = kernel_bytes(name, counts)
+        kernels[name] = {"ms_per_step": round(ms / steps, 4), "launches_per_step": n // steps, "avg_ms": round(avg, 4),
+                         "GBps_algorithmic": round(b / (avg * 1e-3) / 1e9, 1) if b is not None and avg > 0 else None}
+    return kernels
+
+
+def timed_steps(vx, plan, lod, steps, warmup, dom):
+    """K whole steps between two synchronisations; events only around the dominant kernel."""
+    import torch
+    for _ in range(warmup):
+        plan.run()
+        lod.run()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    vx.timing_reset()
+    vx.timing_filter(dom)
+    vx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b, c in ev:
+        a.record()
+        plan.run()
+        b.record()
+        lod.run()
+        c.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vx.timing_enable(False)
+    kd = vx.timing_collect()
+    vx.timing_filter(None)
+    plan.check()
+    lod.check()
+    dom_ms, dom_n = kd.get(dom, (0.0, 0))
+    return {"ms_per_step": (t1 - t0) * 1e3 / steps,
+            "voxelize_ms": sum(a.elapsed_time(b) for a, b, _ in ev) / steps,
+            "lod_build_ms": sum(b.elapsed_time(c) for _, b, c in ev) / steps,
+            "dom_avg_ms": dom_ms / max(dom_n, 1), "dom_launches": dom_n}
+
+
+def graph_steps(vx, plan, lod, steps, warmup):
+    import torch
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = vx.capture(lambda st: (plan.run(st), lod.run(st)), side)
+    for _ in range(warmup):
+        graph.replay()
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    side.synchronize()
+    for a, b in gev:
+        a.record(side)
+        graph.replay()
+        b.record(side)
+    side.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in gev) / steps
+    del graph
+    plan.check()
+    return ms
+
+
+def roofline(name, workload, counts, t, K):
+    """HBM roofline of the dominant kernel (algorithmic bytes / its average launch) and of the step."""
+    b = kernel_bytes(name, counts)
+    B = step_bytes(counts, K)
+    step_gbs = B / (t["ms_per_step"] * 1e-3) / 1e9
+    out = {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+           "traffic": traffic_bytes(workload, name), "algorithmic_bytes_per_launch": b,
+           "avg_launch_ms": round(t["dom_avg_ms"], 5), "launches_timed": t["dom_launches"],
+           "step_algorithmic_bytes": B, "step_GBps": round(step_gbs, 1), "step_frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+    if b is not None and t["dom_avg_ms"] > 0:
+        ach = b / (t["dom_avg_ms"] * 1e-3) / 1e9
+        out["achieved"] = round(ach, 1)
+        out["frac"] = round(ach / HBM_PEAK_GBS, 4)
+    return out
+
+
+def single_section(vx, kind, grid, data, levels, K, args, workload, offsets=None, radius=0.0, input_bytes=0,
+                   graph=True):
+    plan, lod, leaf = make_plans(vx, kind, grid, data, levels, K, offsets, radius)
+    counts = {"key_bytes": 4 if grid.log2_res <= 10 else 8, "n_pairs": plan.n_pairs, "n_cand": plan.n_cand,
+              "n_prims": plan.n_prims, "levels": [leaf.n] + [v.n for v in lod.out], "n_records": plan.n_records,
+              "n_units": plan.n_units, "input_bytes": input_bytes}
+    kernels = kernel_table(vx, plan, lod, counts)
+    dom = next(iter(kernels))
+    t = timed_steps(vx, plan, lod, args.steps, args.warmup, dom)
+    out = {"n_pairs": plan.n_pairs, "n_candidates": plan.n_cand, "n_leaf_voxels": leaf.n,
+           "level_voxels": counts["levels"], "n_tile_records": plan.n_records, "n_units": plan.n_units,
+           "ms_per_step": t["ms_per_step"], "pairs_per_s": plan.n_pairs / (t["ms_per_step"] * 1e-3),
+           "voxelize_ms": t["voxelize_ms"], "lod_build_ms": t["lod_build_ms"],
+           "roofline": roofline(dom, workload, counts, t, K), "kernels": kernels}
+    if graph:
+        g = graph_steps(vx, plan, lod, args.steps, args.warmup)
+        out["graph_ms_per_step"] = g
+        out["graph_pairs_per_s"] = plan.n_pairs / (g * 1e-3)
+    return out, plan, lod, leaf
+
+
+# ------------------------------------------------------------------------------------------------
+# extension sections
+# ------------------------------------------------------------------------------------------------
 
 def fit_timing(vx, wl, pts, offs, args, plain_ms):
-    """Differentiable two-lobe fit (levels 1..6, 128 directions) on the same fabric: one forward
+    """Differentiable two-lobe fit (levels 1..6, 128 directions) on the plain weave: one forward
     (voxelize + 7-level pyramid + fit loss) plus one backward (lobe and control-point gradients)."""
     import torch
     plan = vx.FitPlan(wl.grid, pts, offs, wl.radius, 1, 6)
     params = vx.fit_init(plan, seed=4)
     one = torch.ones(1, device=pts.device)
     for _ in range(max(1, args.warmup)):
-        plan.forward(pts, params)
+        plan.forward(pts, params, check=False)
         plan.backward(one, params)
     torch.cuda.synchronize()
+    plan.check()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     for a, b, c in ev:
         a.record()
-        plan.forward(pts, params)
+        plan.forward(pts, params, check=False)
         b.record()
         plan.backward(one, params)
         c.record()
@@ -155,7 +281,7 @@ def compact_timing(vx, leaf, args):
         avg = ms / max(cnt, 1)
         gbs = per * n / (avg * 1e-3) / 1e9 if avg > 0 else None
         out[name] = {"avg_ms": avg, "launches": cnt, "bytes_per_voxel": per, "GBps": gbs,
-                     "hbm_frac": gbs / 8000.0 if gbs else None}
+                     "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None}
     return out
 
 
@@ -164,21 +290,14 @@ def _single_build(vx, wl, K):
     import torch
     pts = torch.as_tensor(wl.pts).cuda()
     offs = torch.as_tensor(wl.offsets).cuda()
-    plan = vx.VoxelizePlan(1, wl.grid, pts, offsets=offs, radius=wl.radius)
-    plan.run()
-    leaf = plan.check()
-    levels = wl.grid.log2_res + 1
-    cal = vx.LodPlan(wl.grid, leaf, plan.stats[2:3], levels).run()
-    caps = [max(v.n, 1) for v in cal.check()[1:]]
-    del cal
-    lod = vx.LodPlan(wl.grid, leaf, plan.stats[2:3], levels, K=K, iters=2, caps=caps)
+    plan, lod, _ = make_plans(vx, 1, wl.grid, pts, wl.grid.log2_res + 1, K, offs, wl.radius)
     return plan, lod
 
 
 def batch_timing(vx, args):
     """Uneven batch: 64 weave patches (fiber counts log-uniform in [100, 20000], grids 256^3 ..
     2048^3, full pyramids, K = 4): one replay of the captured batched build against the 64
-    single-instance builds of the same patches, each timed on its own."""
+    single-instance builds of the same patches, each captured as a graph and replayed."""
     import torch
     import synth
     from paper_2604_13191_amd import autotune
@@ -205,83 +324,87 @@ def batch_timing(vx, args):
     plan.check(stream)
     batch_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
     n_pairs, levels_n = plan.n_pairs, [v.n for v in plan.out]
+    n_prims = plan.n_pts
     del g, plan
     torch.cuda.empty_cache()
     single_ms, single_pairs = 0.0, 0
     for wl in wls:
         sp, sl = _single_build(vx, wl, 4)
-        sp.run()
-        sl.run()
+        side = torch.cuda.Stream()
         torch.cuda.synchronize()
+        sg = vx.capture(lambda st: (sp.run(st), sl.run(st)), side)
+        sg.replay()
+        side.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
         for a, b in ev:
-            a.record()
-            sp.run()
-            sl.run()
-            b.record()
-        torch.cuda.synchronize()
+            a.record(side)
+            sg.replay()
+            b.record(side)
+        side.synchronize()
         sp.check()
         sl.check()
         single_ms += sum(a.elapsed_time(b) for a, b in ev) / len(ev)
         single_pairs += sp.n_pairs
-        del sp, sl
+        del sg, sp, sl
     torch.cuda.empty_cache()
     vx.set_launch_grids(default)
     assert single_pairs == n_pairs, (single_pairs, n_pairs)
+    counts = {"key_bytes": 8, "n_pairs": n_pairs, "n_prims": n_prims, "levels": levels_n,
+              "input_bytes": 12 * n_prims + 8 * (sum(len(w.offsets) - 1 for w in wls) + 1)}
+    B = step_bytes(counts, 4)
     return {"workload": "64 weave patches, 100-20,000 fibers x 256 segments, 256^3-2048^3, full pyramids, K=4",
             "fibers": int(sum(len(w.offsets) - 1 for w in wls)), "pairs": n_pairs, "voxels_per_level": levels_n,
             "graph_replay_ms": batch_ms, "pairs_per_s": n_pairs / (batch_ms * 1e-3),
-            "single_instance_sum_ms": single_ms, "speedup_vs_single": single_ms / batch_ms,
-            "launch_grids": grids if grids is not None else "default (1024)"}
+            "single_instance_graphs_sum_ms": single_ms, "speedup_vs_single": single_ms / batch_ms,
+            "algorithmic_bytes": B, "hbm_frac": round(B / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch_grids": grids if grids is not None else "default"}
 
 
-def brushed_timing(vx, args):
-    """Brushed-metal height field at full size (33,538,050 triangles, 4096^3, 13 levels, K = 4):
-    voxelize (exact triangle-box test, clipped areas) and the pyramid with lobe clustering."""
-    import torch
+# ------------------------------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the headline workload
+# ------------------------------------------------------------------------------------------------
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(window=1025, repeats=3):
+    """The oracle (FP64, std::thread over primitive chunks) on the first `window` x `window`
+    vertices of the brushed-metal field (1/16 of it at 1025): voxelize + 13-level pyramid + K = 4
+    lobe clustering, single-threaded and on every host core the process may use, median of
+    `repeats` runs each."""
+    import oracle
     import synth
-    wl = synth.brushed_metal()
-    tris = torch.as_tensor(wl.tris).cuda()
-    grid, levels = wl.grid, wl.levels
-    del wl
-    plan = vx.VoxelizePlan(0, grid, tris)
-    plan.run()
-    leaf = plan.check()
-    cal = vx.LodPlan(grid, leaf, plan.stats[2:3], levels).run()
-    caps = [max(v.n, 1) for v in cal.check()[1:]]
-    del cal
-    lod = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, K=4, iters=2, caps=caps)
-    for _ in range(max(1, min(args.warmup, 2))):
-        plan.run()
-        lod.run()
-    torch.cuda.synchronize()
-    steps = max(1, min(args.steps, 5))
-    vx.timing_reset()
-    vx.timing_filter(None)
-    vx.timing_enable(True)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-    for a, b, c in ev:
-        a.record()
-        plan.run()
-        b.record()
-        lod.run()
-        c.record()
-    torch.cuda.synchronize()
-    vx.timing_enable(False)
-    kt = vx.timing_collect()
-    plan.check()
-    lod.check()
-    vox = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
-    lodm = sum(b.elapsed_time(c) for _, b, c in ev) / steps
-    top = sorted(kt.items(), key=lambda x: -x[1][0])[:6]
-    out = {"workload": "brushed metal: 4096x4096 vertices (33,538,050 triangles), 4096^3, 13 levels, K=4",
-           "pairs": plan.n_pairs, "leaf_voxels": leaf.n, "voxelize_ms": vox, "lod_build_ms": lodm,
-           "pairs_per_s": plan.n_pairs / ((vox + lodm) * 1e-3), "voxelize_pairs_per_s": plan.n_pairs / (vox * 1e-3),
-           "kernels_ms_per_step": {k: round(ms / steps, 3) for k, (ms, n) in top}}
-    del plan, lod, leaf, tris
-    torch.cuda.empty_cache()
-    return out
+    wl = synth.brushed_metal(window=window)
+    nall = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    res = {}
+    for nth in (1, nall):
+        ts, pairs = [], 0
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            ref = oracle.voxelize_triangles(wl.grid, wl.tris, nthreads=nth)
+            lod = oracle.build_lod(ref, wl.levels)
+            oracle.cluster_pyramid(lod, 4, 2, nthreads=nth)
+            ts.append(time.perf_counter() - t0)
+            pairs = ref.n_pairs
+        res[nth] = (statistics.median(ts), pairs)
+    t_all, pairs = res[nall]
+    t_one, _ = res[1]
+    return {"value": pairs / t_all, "unit": "pairs/s", "cores": nall, "kind": "oracle",
+            "sample": f"brushed metal, first {window}x{window} vertices ({wl.tris.shape[0]} triangles, {pairs} pairs): "
+                      f"voxelize + {wl.levels}-level pyramid + K=4 clustering in FP64, median of {repeats} runs: "
+                      f"{t_all:.2f} s on {nall} threads, {t_one:.2f} s on 1 thread",
+            "single_thread_value": pairs / t_one, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
+
+# ------------------------------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
@@ -291,8 +414,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
-    ap.add_argument("--no-brushed", action="store_true")
+    ap.add_argument("--no-weave", action="store_true")
     ap.add_argument("--no-compact", action="store_true")
+    ap.add_argument("--probe", action="store_true", help="end with a plain copy of known size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; sharding across GPUs is a design note only, "
@@ -305,145 +429,62 @@ def main():
 
     torch.cuda.set_device(0)
     from paper_2604_13191_amd import autotune
-    tuned = autotune.apply("plain_weave")          # launch grids chosen by the autotuner, if tuned
-    wl = synth.plain_weave()
-    pts = torch.as_tensor(wl.pts).cuda()
-    offs = torch.as_tensor(wl.offsets).cuda()
-    plan = vx.VoxelizePlan(1, wl.grid, pts, offsets=offs, radius=wl.radius)
-    plan.run()
-    leaf = plan.check()
-    n_leaf_dev = plan.stats[2:3]
-    cal = vx.LodPlan(wl.grid, leaf, n_leaf_dev, wl.levels).run()
-    caps = [v.n for v in cal.check()[1:]]
-    del cal
-    lod = vx.LodPlan(wl.grid, leaf, n_leaf_dev, wl.levels, caps=caps)
 
-    for _ in range(args.warmup):
-        plan.run()
-        lod.run()
-    torch.cuda.synchronize()
-    counts = {"key_bytes": 4 if wl.grid.log2_res <= 10 else 8, "n_pairs": plan.n_pairs, "n_cand": plan.n_cand,
-              "n_prims": plan.n_prims, "n_vox": leaf.n, "n_fib": plan.n_fib, "n_records": plan.n_records,
-              "n_units": plan.n_units}
-
-    # kernel breakdown: a few untimed steps with events around every launch
-    prof_steps = 5
-    vx.timing_reset()
-    vx.timing_filter(None)
-    vx.timing_enable(True)
-    for _ in range(prof_steps):
-        plan.run()
-        lod.run()
-    vx.timing_enable(False)
-    kt = vx.timing_collect()
-    kernels = {}
-    for name, (ms, n) in sorted(kt.items(), key=lambda x: -x[1][0]):
-        avg = ms / max(n, 1)
-        b = kernel_bytes(name, counts)
-        kernels[name] = {"ms_per_step": round(ms / prof_steps, 4), "launches_per_step": n // prof_steps,
-                         "avg_ms": round(avg, 4),
-                         "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b is not None and avg > 0 else None}
-    dom = next(iter(kernels))                       # largest share of the step
-
-    # timed region: K whole steps; events only around the dominant kernel's launches
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    vx.timing_reset()
-    vx.timing_filter(dom)
-    vx.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b, c in ev:
-        a.record()
-        plan.run()
-        b.record()
-        lod.run()
-        c.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    vx.timing_enable(False)
-    kd = vx.timing_collect()
-    vx.timing_filter(None)
-    plan.check()
-    lod.check()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    vox_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / args.steps
-    lod_ms = sum(b.elapsed_time(c) for _, b, c in ev) / args.steps
-    dom_ms, dom_n = kd[dom]
-    dom_avg = dom_ms / dom_n
-
-    # the same step captured once as a graph and replayed
-    side = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    graph = vx.capture(lambda st: (plan.run(st), lod.run(st)), side)
-    for _ in range(args.warmup):
-        graph.replay()
-    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    side.synchronize()
-    for a, b in gev:
-        a.record(side)
-        graph.replay()
-        b.record(side)
-    side.synchronize()
-    graph_ms = sum(a.elapsed_time(b) for a, b in gev) / args.steps
-    del graph
-    plan.check()
-
-    # a plain copy of known size, for scaling the HBM byte counters of a profiler run
-    probe = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
-    probe2 = torch.empty_like(probe)
-    probe2.copy_(probe)
-    torch.neg(probe.view(torch.float32), out=probe2.view(torch.float32))
-    torch.cuda.synchronize()
-    del probe, probe2
-
-    dom_b = kernel_bytes(dom, counts)
-    dom_f = kernel_flops(dom, counts)
-    if dom_f is not None:
-        ach = dom_f / (dom_avg * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": traffic_bytes(dom),
-                "algorithmic_flops_per_launch": dom_f, "algorithmic_bytes_per_launch": dom_b,
-                "hbm_GBps_at_algorithmic_bytes": round(dom_b / (dom_avg * 1e-3) / 1e9, 1) if dom_b else None,
-                "avg_launch_ms": round(dom_avg, 5), "launches_timed": dom_n}
-    elif dom_b is not None:
-        ach = dom_b / (dom_avg * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_bytes(dom),
-                "algorithmic_bytes_per_launch": dom_b, "avg_launch_ms": round(dom_avg, 5),
-                "launches_timed": dom_n}
-    else:
-        roof = {"bound": "unmodelled", "kernel": dom, "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None, "avg_launch_ms": round(dom_avg, 5)}
+    # ---- headline: brushed metal ---------------------------------------------------------------
+    default_grids = vx.get_launch_grids()
+    tuned = autotune.apply("brushed_metal")
+    wl = synth.brushed_metal()
+    tris = torch.as_tensor(wl.tris).cuda()
+    grid, levels, n_tris = wl.grid, wl.levels, wl.tris.shape[0]
+    del wl
+    head, plan, lod, leaf = single_section(vx, 0, grid, tris, levels, 4, args, "brushed_metal",
+                                           input_bytes=36 * n_tris)
+    del plan, lod, leaf, tris
+    torch.cuda.empty_cache()
+    vx.set_launch_grids(default_grids)
     out = {
-        "metric": METRIC, "value": plan.n_pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "metric": METRIC, "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
-        "config": {"workload": "plain_weave: 2000 fibers x 256 segments, radius 0.5 voxel, 1024^3, 11 levels, K=1",
-                   "n_pairs": plan.n_pairs, "n_candidates": plan.n_cand, "n_leaf_voxels": leaf.n,
-                   "n_tile_records": plan.n_records, "n_units": plan.n_units,
-                   "launch_grids": tuned if tuned is not None else vx.get_launch_grids(),
-                   "level_voxels": [leaf.n] + caps},
-        "voxelize_ms": vox_ms, "lod_build_ms": lod_ms, "graph_ms_per_step": graph_ms,
-        "graph_pairs_per_s": plan.n_pairs / (graph_ms * 1e-3),
-        "roofline": roof,
-        "kernels": kernels,
+        "config": {"workload": "brushed_metal: 4096x4096 vertex height field (33,538,050 triangles), 4096^3, "
+                               "13 levels, K=4", "n_pairs": head["n_pairs"], "n_leaf_voxels": head["n_leaf_voxels"],
+                   "level_voxels": head["level_voxels"], "launch_grids": tuned if tuned is not None else "default"},
+        "voxelize_ms": head["voxelize_ms"], "lod_build_ms": head["lod_build_ms"],
+        "graph_ms_per_step": head.get("graph_ms_per_step"), "graph_pairs_per_s": head.get("graph_pairs_per_s"),
+        "roofline": head["roofline"], "kernels": head["kernels"],
     }
-    if not args.no_fit:
-        out["fit"] = fit_timing(vx, wl, pts, offs, args, ms_step)
-    if not args.no_compact:
-        out["sggx_compact"] = compact_timing(vx, leaf, args)
-    if not args.no_batch or not args.no_brushed:
-        del plan, lod
+
+    # ---- plain weave, fit, compact -------------------------------------------------------------
+    if not args.no_weave or not args.no_fit or not args.no_compact:
+        tw = autotune.apply("plain_weave")
+        ww = synth.plain_weave()
+        pts = torch.as_tensor(ww.pts).cuda()
+        offs = torch.as_tensor(ww.offsets).cuda()
+        sec, plan, lod, leaf = single_section(vx, 1, ww.grid, pts, ww.levels, 1, args, "plain_weave", offs,
+                                              ww.radius, input_bytes=12 * ww.pts.shape[0] + 8 * len(ww.offsets))
+        sec["workload"] = "plain_weave: 2000 fibers x 256 segments, radius 0.5 voxel, 1024^3, 11 levels, K=1"
+        sec["launch_grids"] = tw if tw is not None else "default"
+        if not args.no_weave:
+            out["plain_weave"] = sec
+        if not args.no_fit:
+            out["fit"] = fit_timing(vx, ww, pts, offs, args, sec["ms_per_step"])
+        if not args.no_compact:
+            out["sggx_compact"] = compact_timing(vx, leaf, args)
+        del plan, lod, leaf, pts, offs
+        vx.set_launch_grids(default_grids)
         torch.cuda.empty_cache()
-    if not args.no_brushed:
-        out["brushed_metal"] = brushed_timing(vx, args)
     if not args.no_batch:
-        torch.cuda.empty_cache()
         out["batched"] = batch_timing(vx, args)
+        torch.cuda.empty_cache()
+    if args.probe:
+        # a plain copy of known size, for scaling the HBM byte counters of a profiler run
+        probe = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+        probe2 = torch.empty_like(probe)
+        torch.neg(probe.view(torch.float32), out=probe2.view(torch.float32))
+        torch.cuda.synchronize()
+        del probe, probe2
     if not args.no_cpu_baseline:
-        nth = max(1, min(16, os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(wl, nth)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -59,7 +59,8 @@ typedef enum {
   VX_ERR_CAPACITY = 2,   /* a device-detected count exceeded the capacity given */
   VX_ERR_HIP = 3,        /* a HIP runtime call failed */
   VX_ERR_INPUT = 4,      /* non-finite or out-of-range coordinate, or invalid fiber offsets */
-  VX_ERR_WORKSPACE = 5   /* workspace pointer NULL, misaligned (256 B) or too small */
+  VX_ERR_WORKSPACE = 5,  /* workspace pointer NULL, misaligned (256 B) or too small */
+  VX_ERR_BINDING = 6     /* fit parameters bound to other voxels than the level now holds */
 } vx_status;
 
 /* device flag bits in stats[VX_STAT_FLAGS] */
@@ -70,6 +71,8 @@ typedef enum {
 #define VX_FLAG_OFFSETS        16
 #define VX_FLAG_RECORD_CAPACITY 32
 #define VX_FLAG_UNIT_CAPACITY  64
+#define VX_FLAG_FIT_ROWS       128   /* a fitted level's voxel count differs from its parameter rows */
+#define VX_FLAG_FIT_KEYS       256   /* a fitted level's keys differ from those its parameters were made for */
 
 /* indices into the int64 stats array (device): candidates tested, touching pairs, leaf voxels,
  * flags, primitive-tile records, work units */
@@ -176,11 +179,20 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
  *   loss         = sum_{levels lo..hi} sum_u (1/ndir) sum_k (f_u(omega_k) - tau_u(omega_k))^2
  * levels: host array of hi + 1 level descriptors (leaf, then levels 1..hi of vx_build_lod with
  * K = 1); n_levels: their counts (device); params / dparams: host arrays of hi - lo + 1 device
- * pointers, level L at index L - lo, each [cap_L][12]; dirs: device float [ndir][3] unit
- * directions, 1 <= ndir <= 256; caps: host int64 [hi + 1], the capacities of levels 0..hi.
+ * pointers, level L at index L - lo, each [rows[L - lo]][12]; row r holds the lobes of the voxel at
+ * index r of level L when the parameters were made.  rows: host int64 [hi - lo + 1], the row counts
+ * of params (and dparams).  bound_keys: NULL, or a host array of hi - lo + 1 device pointers to the
+ * keys (the level's key width, rows[L - lo] entries) that the rows were made for.  Every kernel stays
+ * within the rows; a level whose device count differs from its rows sets VX_FLAG_FIT_ROWS and one
+ * whose keys differ from bound_keys sets VX_FLAG_FIT_KEYS in stats[VX_STAT_FLAGS] (the loss and
+ * gradients are then invalid; vx_check_stats reports VX_ERR_CAPACITY and VX_ERR_BINDING).
+ * dirs: device float [ndir][3] unit directions, 1 <= ndir <= 256; caps: host int64 [hi + 1], the
+ * capacities of levels 0..hi.
  * The gradient to the control points flows through the leaf sums: the clipped centreline
  * lengths (weights) and the tangents (moments I - t t^T) of the segments, evaluated at the
- * lattice-snapped points; the voxel sets are held fixed (the loss is piecewise smooth).
+ * lattice-snapped points; the voxel sets are held fixed (the loss is piecewise smooth).  The
+ * backward pass differentiates at FP64 sums of levels 0..hi-1, which it forms itself from the
+ * re-emitted (segment, voxel) pairs (each voxel's pairs added in primitive order).
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
   const float* pts;          /* device float [n_pts][3] */
@@ -193,21 +205,22 @@ typedef struct {
 size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int32_t hi,
                              int32_t log2_res);
 
-/* loss: device float [1], overwritten. */
+/* loss: device float [1], overwritten.  stats: device int64 [VX_NSTAT], overwritten (flags only). */
 vx_status vx_fit_forward(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int32_t lo,
-                         int32_t hi, const float* const* params, const float* dirs, int32_t ndir, float* loss,
-                         const int64_t* caps, void* workspace, size_t ws_bytes, vx_stream stream);
+                         int32_t hi, const float* const* params, const int64_t* rows, const void* const* bound_keys,
+                         const float* dirs, int32_t ndir, float* loss, int64_t* stats, const int64_t* caps,
+                         void* workspace, size_t ws_bytes, vx_stream stream);
 
 /* dloss: device float [1] (upstream gradient); dpts: device float [n_pts][3], overwritten;
- * stats: device int64 [VX_NSTAT] for the re-emitted pairs.  max_cand / max_pairs: capacities
- * of the candidate space and of the (primitive, voxel) pairs, which the backward pass lists
- * per primitive (at least stats[VX_STAT_CAND] / stats[VX_STAT_PAIRS] of vx_voxelize_fibers on
- * the same fibers; pairs at most 2^31 - 1). */
+ * stats: device int64 [VX_NSTAT] for the re-emitted pairs and the binding flags.  max_cand /
+ * max_pairs: capacities of the candidate space and of the (primitive, voxel) pairs, which the
+ * backward pass lists per primitive (at least stats[VX_STAT_CAND] / stats[VX_STAT_PAIRS] of
+ * vx_voxelize_fibers on the same fibers; pairs at most 2^31 - 1). */
 vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fibers, int64_t max_cand, int64_t max_pairs,
                           const vx_voxels* levels, const int64_t* n_levels, int32_t lo, int32_t hi,
-                          const float* const* params, const float* dirs, int32_t ndir, const float* dloss,
-                          float* const* dparams, float* dpts, int64_t* stats, const int64_t* caps, void* workspace,
-                          size_t ws_bytes, vx_stream stream);
+                          const float* const* params, const int64_t* rows, const void* const* bound_keys,
+                          const float* dirs, int32_t ndir, const float* dloss, float* const* dparams, float* dpts,
+                          int64_t* stats, const int64_t* caps, void* workspace, size_t ws_bytes, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
  * Batched fiber patches (extension): many patches of uneven size and resolution voxelized and
@@ -294,7 +307,7 @@ vx_status vx_set_launch_grids(const int32_t* grids, int32_t n);
 void vx_get_launch_grids(int32_t* grids, int32_t n);
 
 /* Synchronises `stream`, reads stats (VX_NSTAT int64 on the device) and maps its flags to a
- * status: VX_ERR_INPUT before VX_ERR_CAPACITY before VX_OK. */
+ * status: VX_ERR_INPUT before VX_ERR_BINDING before VX_ERR_CAPACITY before VX_OK. */
 vx_status vx_check_stats(const int64_t* stats, vx_stream stream);
 
 const char* vx_status_str(vx_status s);

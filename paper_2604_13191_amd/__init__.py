@@ -25,8 +25,10 @@ VX_NSTAT = 6
 STAT_CAND, STAT_PAIRS, STAT_VOXELS, STAT_FLAGS, STAT_RECORDS, STAT_UNITS = range(6)
 FLAG_CAND_CAPACITY, FLAG_PAIR_CAPACITY, FLAG_VOXEL_CAPACITY, FLAG_INPUT, FLAG_OFFSETS = 1, 2, 4, 8, 16
 FLAG_RECORD_CAPACITY, FLAG_UNIT_CAPACITY = 32, 64
+FLAG_FIT_ROWS, FLAG_FIT_KEYS = 128, 256
 STATUS = {0: "ok", 1: "invalid argument", 2: "capacity exceeded", 3: "HIP runtime error",
-          4: "non-finite or out-of-range input, or invalid fiber offsets", 5: "bad workspace"}
+          4: "non-finite or out-of-range input, or invalid fiber offsets", 5: "bad workspace",
+          6: "fit parameters bound to other voxels than the level holds"}
 
 
 class VxError(RuntimeError):
@@ -93,11 +95,11 @@ def load():
     L.vx_fit_workspace_size.restype = sz
     L.vx_fit_workspace_size.argtypes = [i64, i64, i64, vp, i32, i32]
     L.vx_fit_forward.restype = ctypes.c_int
-    L.vx_fit_forward.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, vp, vp, i32, vp, vp,
-                                 vp, sz, vp]
+    L.vx_fit_forward.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, vp, vp, vp, vp, i32,
+                                 vp, vp, vp, vp, sz, vp]
     L.vx_fit_backward.restype = ctypes.c_int
     L.vx_fit_backward.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CFibers), i64, i64, ctypes.POINTER(CVoxels),
-                                  vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+                                  vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.vx_batch_workspace_size.restype = sz
     L.vx_batch_workspace_size.argtypes = [i32, i64, i64, i64, i64]
     L.vx_batch_build.restype = ctypes.c_int
@@ -480,8 +482,12 @@ def fit_dirs(ndir=128, device="cuda"):
 class FitPlan:
     """Voxelize + K = 1 pyramid + two-lobe fit at levels lo..hi for one fiber set.
 
-    Buffers are sized from a calibration run with 25 % slack, so control points may move
-    during an optimisation; a run that outgrows them reports VX_ERR_CAPACITY."""
+    Buffers are sized from a calibration run with 25 % slack.  The lobe parameters are bound to
+    the calibration's voxels: row r of level L belongs to the voxel at index r of that level.  If
+    control points move so that a fitted level gains, loses or changes voxels, the library flags
+    it (the kernels never leave the parameter rows) and ``check()`` raises VxError
+    (VX_ERR_CAPACITY for a changed count, VX_ERR_BINDING for changed keys); a run that outgrows the
+    buffers also raises VX_ERR_CAPACITY."""
 
     def __init__(self, grid, pts, offsets, radius, lo=1, hi=6, ndir=128, slack=1.25):
         import torch
@@ -512,9 +518,15 @@ class FitPlan:
         self.levels = [leaf] + self.lod.out
         self._clevels = (CVoxels * (self.hi + 1))(*[v.cstruct() for v in self.levels])
         self._caps = (ctypes.c_int64 * (self.hi + 1))(*[v.cap for v in self.levels])
+        # the parameters' binding: row counts and the keys of the fitted levels at calibration
+        nfit = self.hi - self.lo + 1
+        self._rows = (ctypes.c_int64 * nfit)(*[counts[L] for L in range(self.lo, self.hi + 1)])
+        self.bound_keys = [self.levels[L].keys[:max(counts[L], 1)].clone() for L in range(self.lo, self.hi + 1)]
+        self._bound = (ctypes.c_void_p * nfit)(*[k.data_ptr() for k in self.bound_keys])
         self.dirs = fit_dirs(ndir, self.pts.device)
         self.ndir = int(ndir)
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.pts.device)
+        self.fstats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.pts.device)
         self.bstats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.pts.device)
         nb = self.L.vx_fit_workspace_size(int(self.pts.shape[0]), mc, mp, self._caps, self.hi, int(grid.log2_res))
         if nb == 0:
@@ -522,6 +534,7 @@ class FitPlan:
         self.ws = _ws(nb, self.pts.device)
         self.max_cand, self.max_pairs = mc, mp
         self.dpts = torch.zeros_like(self.pts)
+        self.run_id = 0                                         # forwards evaluated on this plan
 
     def param_shapes(self):
         return [(self.counts[L], 12) for L in range(self.lo, self.hi + 1)]
@@ -529,38 +542,61 @@ class FitPlan:
     def _ptrs(self, tensors):
         return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
 
-    def forward(self, pts, params, stream=None):
-        """Voxelize the (possibly moved) points, build the pyramid, evaluate the fit loss."""
+    def _params(self, params):
+        import torch
+        params = [p.contiguous() for p in params]
+        if len(params) != self.hi - self.lo + 1:
+            raise VxError(1, "fit: one parameter tensor per fitted level")
+        for L, p in zip(range(self.lo, self.hi + 1), params):
+            if tuple(p.shape) != (self.counts[L], 12) or p.dtype != torch.float32 or p.device != self.pts.device:
+                raise VxError(1, f"fit: level {L} parameters must be float32 [{self.counts[L]}, 12]")
+        return params
+
+    def forward(self, pts, params, stream=None, check=True):
+        """Voxelize the (possibly moved) points, build the pyramid, evaluate the fit loss.  With
+        check, synchronise and raise if the fitted levels no longer match the parameters."""
+        params = self._params(params)
         self.pts.copy_(pts.detach())
         self.vox.run(stream)
         self.lod.run(stream)
-        params = [p.contiguous() for p in params]
         st = self.L.vx_fit_forward(ctypes.byref(self.cgrid), self._clevels, _ptr(self.lod.n_levels), self.lo, self.hi,
-                                   self._ptrs(params), _ptr(self.dirs), self.ndir, _ptr(self.loss), self._caps,
-                                   _ptr(self.ws), self.ws.numel(), _stream(stream))
+                                   self._ptrs(params), self._rows, self._bound, _ptr(self.dirs), self.ndir,
+                                   _ptr(self.loss), _ptr(self.fstats), self._caps, _ptr(self.ws), self.ws.numel(),
+                                   _stream(stream))
         if st != 0:
             raise VxError(st, "vx_fit_forward")
+        self.run_id += 1
+        if check:
+            self.check_forward(stream)
         return self.loss
+
+    def check_forward(self, stream=None):
+        """Synchronise and raise if the last forward outgrew a buffer or lost the binding."""
+        self.vox.check(stream)
+        self.lod.check()
+        st = self.L.vx_check_stats(_ptr(self.fstats), _stream(stream))
+        if st != 0:
+            raise VxError(st, "vx_fit_forward")
 
     def backward(self, dloss, params, stream=None):
         import torch
-        params = [p.contiguous() for p in params]
+        params = self._params(params)
         dparams = [torch.empty_like(p) for p in params]
         fib = CFibers(self.pts.data_ptr(), int(self.pts.shape[0]), self.offsets.data_ptr(),
                       int(self.offsets.numel() - 1), self.radius)
         st = self.L.vx_fit_backward(ctypes.byref(self.cgrid), ctypes.byref(fib), self.max_cand, self.max_pairs,
                                     self._clevels, _ptr(self.lod.n_levels), self.lo, self.hi, self._ptrs(params),
-                                    _ptr(self.dirs), self.ndir, _ptr(dloss), self._ptrs(dparams), _ptr(self.dpts),
-                                    _ptr(self.bstats), self._caps, _ptr(self.ws), self.ws.numel(), _stream(stream))
+                                    self._rows, self._bound, _ptr(self.dirs), self.ndir, _ptr(dloss),
+                                    self._ptrs(dparams), _ptr(self.dpts), _ptr(self.bstats), self._caps,
+                                    _ptr(self.ws), self.ws.numel(), _stream(stream))
         if st != 0:
             raise VxError(st, "vx_fit_backward")
         return self.dpts.clone(), dparams
 
-    def check(self):
-        """Synchronise and raise if a buffer was outgrown."""
-        self.vox.check()
-        self.lod.check()
-        st = self.L.vx_check_stats(_ptr(self.bstats), _stream())
+    def check(self, stream=None):
+        """Synchronise and raise if a buffer was outgrown or the parameters lost their voxels."""
+        self.check_forward(stream)
+        st = self.L.vx_check_stats(_ptr(self.bstats), _stream(stream))
         if st != 0:
             raise VxError(st, "vx_fit_backward")
 
@@ -571,20 +607,26 @@ def _make_lobe_fit():
     class LobeFit(torch.autograd.Function):
         """loss = LobeFit.apply(plan, pts, *params): the two-lobe fit loss with hand-written
         backward kernels for the lobes (params, one [n_L, 12] tensor per level) and the control
-        points."""
+        points.  The plan holds one forward state (its points and pyramid); a backward after
+        another forward on the same plan raises instead of differentiating the wrong state."""
 
         @staticmethod
         def forward(ctx, plan, pts, *params):
             loss = plan.forward(pts, params)
             ctx.plan = plan
+            ctx.run_id = plan.run_id
             ctx.save_for_backward(*params)
             return loss[0].clone()
 
         @staticmethod
         def backward(ctx, gloss):
+            if ctx.plan.run_id != ctx.run_id:
+                raise RuntimeError("lobe_fit: the plan ran another forward after this loss; backward would "
+                                   "differentiate that later state (use one FitPlan per live loss)")
             params = ctx.saved_tensors
             g = gloss.reshape(1).to(torch.float32).contiguous()
             dpts, dparams = ctx.plan.backward(g, params)
+            ctx.plan.check()
             return (None, dpts, *dparams)
 
     return LobeFit

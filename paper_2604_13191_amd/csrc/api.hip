@@ -243,33 +243,37 @@ size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs,
 }
 
 static bool fit_args_ok(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
-                        const float* const* params, const float* dirs, int ndir, const int64_t* caps) {
+                        const float* const* params, const int64_t* rows, const void* const* bound, const float* dirs,
+                        int ndir, const int64_t* caps) {
   if (!grid_ok(grid) || !levels || !n_levels || lo < 1 || hi < lo || hi > 20 || hi > grid->log2_res || !params ||
-      !dirs || ndir < 1 || ndir > 256 || !caps)
+      !rows || !dirs || ndir < 1 || ndir > 256 || !caps)
     return false;
   for (int L = 0; L <= hi; ++L)
     if (!voxels_ok(&levels[L], false) || caps[L] < levels[L].cap) return false;
   for (int L = lo; L <= hi; ++L)
-    if (!params[L - lo]) return false;
+    if (!params[L - lo] || rows[L - lo] < 0 || rows[L - lo] > caps[L] || (bound && !bound[L - lo] && rows[L - lo] > 0))
+      return false;
   return true;
 }
 
 vx_status vx_fit_forward(const vx_grid* grid, const vx_voxels* levels, const int64_t* n_levels, int32_t lo,
-                         int32_t hi, const float* const* params, const float* dirs, int32_t ndir, float* loss,
-                         const int64_t* caps, void* ws, size_t ws_bytes, vx_stream stream) {
-  if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, dirs, ndir, caps) || !loss) return VX_ERR_ARG;
+                         int32_t hi, const float* const* params, const int64_t* rows, const void* const* bound,
+                         const float* dirs, int32_t ndir, float* loss, int64_t* stats, const int64_t* caps, void* ws,
+                         size_t ws_bytes, vx_stream stream) {
+  if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, rows, bound, dirs, ndir, caps) || !loss || !stats)
+    return VX_ERR_ARG;
   if (!ws_ok(ws, ws_bytes, fit_ws_bytes(0, 0, 0, caps, hi, grid->log2_res))) return VX_ERR_WORKSPACE;
-  return fit_forward_run(grid, levels, n_levels, lo, hi, params, dirs, ndir, loss, ws, caps,
+  return fit_forward_run(grid, levels, n_levels, lo, hi, params, rows, bound, dirs, ndir, loss, stats, ws, caps,
                          reinterpret_cast<hipStream_t>(stream));
 }
 
 vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fib, int64_t max_cand, int64_t max_pairs,
                           const vx_voxels* levels, const int64_t* n_levels, int32_t lo, int32_t hi,
-                          const float* const* params, const float* dirs, int32_t ndir, const float* dloss,
-                          float* const* dparams, float* dpts, int64_t* stats, const int64_t* caps, void* ws,
-                          size_t ws_bytes, vx_stream stream) {
-  if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, dirs, ndir, caps) || !fib || !dloss || !dparams ||
-      !dpts || !stats || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs)
+                          const float* const* params, const int64_t* rows, const void* const* bound,
+                          const float* dirs, int32_t ndir, const float* dloss, float* const* dparams, float* dpts,
+                          int64_t* stats, const int64_t* caps, void* ws, size_t ws_bytes, vx_stream stream) {
+  if (!fit_args_ok(grid, levels, n_levels, lo, hi, params, rows, bound, dirs, ndir, caps) || !fib || !dloss ||
+      !dparams || !dpts || !stats || max_cand < 0 || max_pairs < 0 || max_pairs > kMaxPairs)
     return VX_ERR_ARG;
   if (fib->n_pts < 0 || fib->n_fibers < 0 || !fib->offsets || (fib->n_pts > 0 && (!fib->pts || fib->n_fibers < 1)))
     return VX_ERR_ARG;
@@ -279,8 +283,8 @@ vx_status vx_fit_backward(const vx_grid* grid, const vx_fibers* fib, int64_t max
   if (!ws_ok(ws, ws_bytes, fit_ws_bytes(fib->n_pts, max_cand, max_pairs, caps, hi, grid->log2_res)))
     return VX_ERR_WORKSPACE;
   return fit_backward_run(grid, fib->pts, fib->n_pts, fib->offsets, fib->n_fibers, fib->radius, max_cand, max_pairs,
-                          levels, n_levels, lo, hi, params, dirs, ndir, dloss, dparams, dpts, stats, ws, caps,
-                          reinterpret_cast<hipStream_t>(stream));
+                          levels, n_levels, lo, hi, params, rows, bound, dirs, ndir, dloss, dparams, dpts, stats, ws,
+                          caps, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t vx_batch_workspace_size(int32_t n_patches, int64_t n_pts, int64_t max_records, int64_t max_units,
@@ -423,7 +427,8 @@ vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {
   if (hipMemcpy(h, stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) return VX_ERR_HIP;
   const int64_t f = h[VX_STAT_FLAGS];
   if (f & (VX_FLAG_INPUT | VX_FLAG_OFFSETS)) return VX_ERR_INPUT;
-  if (f & (VX_FLAG_CAND_CAPACITY | VX_FLAG_PAIR_CAPACITY | VX_FLAG_VOXEL_CAPACITY | VX_FLAG_RECORD_CAPACITY |
+  if (f & VX_FLAG_FIT_KEYS) return VX_ERR_BINDING;
+  if (f & (VX_FLAG_FIT_ROWS | VX_FLAG_CAND_CAPACITY | VX_FLAG_PAIR_CAPACITY | VX_FLAG_VOXEL_CAPACITY | VX_FLAG_RECORD_CAPACITY |
            VX_FLAG_UNIT_CAPACITY))
     return VX_ERR_CAPACITY;
   return VX_OK;
@@ -437,6 +442,7 @@ const char* vx_status_str(vx_status s) {
     case VX_ERR_HIP: return "HIP runtime error";
     case VX_ERR_INPUT: return "non-finite or out-of-range input, or invalid fiber offsets";
     case VX_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case VX_ERR_BINDING: return "fit parameters bound to other voxels than the level holds";
   }
   return "unknown status";
 }

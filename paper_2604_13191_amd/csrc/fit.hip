@@ -82,7 +82,7 @@ __device__ __forceinline__ int stage_children(const vx_voxels& ch, const int64_t
 // ---------------------------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_fit_fwd(vx_voxels par, const int64_t* n_par_p, vx_voxels ch,
+__global__ void __launch_bounds__(kBlock) k_fit_fwd(vx_voxels par, const int64_t* n_par_p, int64_t rows, vx_voxels ch,
                                                     const int64_t* __restrict__ cstart, const float* __restrict__ Lp,
                                                     const float* __restrict__ dirs, int ndir,
                                                     float* __restrict__ loss_vox) {
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_fwd(vx_voxels par, const int64_t
     for (int a = 0; a < 3; ++a) sdir[k][a] = dirs[3 * k + a];
   __syncthreads();
   const int grp = threadIdx.x / kGroup, gl = threadIdx.x % kGroup;
-  const int64_t n_par = *n_par_p;
+  const int64_t n_par = *n_par_p < rows ? *n_par_p : rows;   // never past the parameter rows
   // the four groups of a wave advance together (uniform trip count per wave)
   const int wgrp0 = (threadIdx.x >> 6) * (64 / kGroup);
   for (int64_t u0 = int64_t(blockIdx.x) * kGroups + wgrp0; u0 < n_par; u0 += int64_t(gridDim.x) * kGroups) {
@@ -135,6 +135,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_fwd(vx_voxels par, const int64_t
 struct LossLevels {
   const float* p[24];
   const int64_t* n[24];
+  int64_t rows[24];       // the forward wrote at most this many per-voxel losses
   int count;
 };
 
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_partial(LossLevels lv, float* __
   __shared__ float red[kWaves];
   float acc = 0.f;
   for (int i = 0; i < lv.count; ++i) {
-    const int64_t n = *lv.n[i];
+    const int64_t n = *lv.n[i] < lv.rows[i] ? *lv.n[i] : lv.rows[i];
     const int64_t chunk = (n + kGrid - 1) / kGrid;
     const int64_t b0 = int64_t(blockIdx.x) * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
     for (int64_t j = b0 + threadIdx.x; j < b1; j += kBlock) acc += lv.p[i][j];
@@ -191,12 +192,13 @@ __device__ __forceinline__ double quadd(const double* S, double x, double y, dou
 }
 
 template <int DPL>
-__global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t* n_par_p, vx_voxels ch,
+__global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t* n_par_p, int64_t rows,
+                                                    const double* __restrict__ c64, int64_t ccap,
                                                     const int64_t* __restrict__ cstart, const float* __restrict__ Lp,
                                                     const float* __restrict__ dirs, int ndir,
                                                     const float* __restrict__ dloss, float* __restrict__ dLp,
                                                     double* __restrict__ gch, int64_t gcap) {
-  // directions and the children's sums in FP64 once, not converted in the inner loops
+  // directions and the children's FP64 sums staged once, not converted in the inner loops
   __shared__ double sdir[kMaxDir][3];
   __shared__ double scw[kGroups][kMaxChild];
   __shared__ double scS[kGroups][kMaxChild][6];
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
     for (int a = 0; a < 3; ++a) sdir[k][a] = dirs[3 * k + a];
   __syncthreads();
   const int grp = threadIdx.x / kGroup, gl = threadIdx.x % kGroup;
-  const int64_t n_par = *n_par_p;
+  const int64_t n_par = *n_par_p < rows ? *n_par_p : rows;
   const double g0 = double(dloss[0]);
   const double g2 = 2.0 / double(ndir) * g0;
   const int wgrp0 = (threadIdx.x >> 6) * (64 / kGroup);
@@ -213,8 +215,16 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
     const bool in = u < n_par;
     const float Wf = in ? par.w[u] : 0.f;
     const bool active = in && Wf > 0.f;
-    int64_t first;
-    const int nc = stage_children(ch, cstart, u, active, gl, scw[grp], scS[grp], first);
+    int64_t first = 0;
+    int nc = 0;
+    if (active) nc = child_range(cstart, u, first);
+    if (active && gl < nc) {
+      const int64_t cc = first + gl;
+      scw[grp][gl] = c64[6 * ccap + cc];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) scS[grp][gl][t] = c64[int64_t(t) * ccap + cc];
+    }
+    wave_sync_lds();
     const double* cw = scw[grp];
     double l[12], gl12[12], dg[DPL], dt[DPL];
 #pragma unroll
@@ -222,7 +232,10 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
       l[t] = active ? double(Lp[u * 12 + t]) : 0.0;
       gl12[t] = 0.0;
     }
-    const double invW = active ? 1.0 / double(Wf) : 0.0;
+    // the parent's weight as the FP64 sum of its children's
+    double Wd = 0.0;
+    for (int c = 0; c < nc; ++c) Wd += cw[c];
+    const double invW = active && Wd > 0.0 ? 1.0 / Wd : 0.0;
     // pass 1 (this lane's directions): target, fit, residual; lobe gradients
 #pragma unroll
     for (int i = 0; i < DPL; ++i) {
@@ -438,6 +451,115 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// binding of the lobe parameters: row r of a level's parameters belongs to the voxel that was at
+// index r when the parameters were made.  A level whose voxel count or keys differ from that
+// binding (control points moved across voxels) is flagged, and every kernel stays within the
+// parameter rows.
+// ---------------------------------------------------------------------------------------------
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_fit_bind(const Key* __restrict__ keys, const int64_t* n_p, int64_t rows,
+                                                     const Key* __restrict__ bound, int64_t* stats) {
+  const int64_t n = *n_p;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n != rows)
+    atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)VX_FLAG_FIT_ROWS);
+  if (!bound) return;
+  const int64_t m = n < rows ? n : rows;
+  bool diff = false;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m; i += int64_t(gridDim.x) * kBlock)
+    diff = diff || keys[i] != bound[i];
+  if (__any(diff) && lane_id() == 0)
+    atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)VX_FLAG_FIT_KEYS);
+}
+
+// ---------------------------------------------------------------------------------------------
+// FP64 sums of the levels below the fitted ones, for the backward pass.  The target's square
+// roots are ill-conditioned where a child holds nearly one fiber direction and a direction of
+// the set is nearly parallel to it, so the backward differentiates at sums formed in FP64 from
+// the re-emitted pairs: sorted by key (stable, so each voxel's pairs stay in primitive order),
+// each leaf voxel adds its clipped lengths and moments in FP64, and every level above adds its
+// children.  Layout of a level: [7][cap] (S components xx yy zz xy xz yz, then w).
+// ---------------------------------------------------------------------------------------------
+struct LeafSegTotal {
+  int64_t* start;
+  const int64_t* n_leaf;
+  int64_t* stats;
+  __device__ void operator()(int64_t total, int64_t n) const {
+    start[total] = n;
+    if (total != *n_leaf)
+      atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)VX_FLAG_FIT_KEYS);
+  }
+};
+
+template <class Key>
+__global__ void __launch_bounds__(kBlock) k_fit_leaf64(const Key* __restrict__ pkeys, const uint32_t* __restrict__ pprim,
+                                                       const int64_t* __restrict__ sstart, const int32_t* __restrict__ rec,
+                                                       const Key* __restrict__ lkeys, const int64_t* n_leaf_p,
+                                                       int64_t cap, int Sb, int log2R, double* __restrict__ out,
+                                                       int64_t* stats) {
+  const int64_t n = *n_leaf_p < cap ? *n_leaf_p : cap;
+  const double inv_s = 1.0 / double(int64_t(1) << Sb);
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t a = sstart[i], b = sstart[i + 1];
+    double W = 0.0, S[6] = {0, 0, 0, 0, 0, 0};
+    if (b > a && pkeys[a] != lkeys[i])
+      atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)VX_FLAG_FIT_KEYS);
+    const uint64_t key = uint64_t(lkeys[i]);
+    double lo[3] = {0, 0, 0};
+    for (int bit = 0; bit < log2R; ++bit)
+      for (int ax = 0; ax < 3; ++ax) lo[ax] += double((key >> (3 * bit + ax)) & 1) * double(int64_t(1) << bit);
+    for (int64_t j = a; j < b; ++j) {
+      const int32_t* r = rec + int64_t(pprim[j]) * kRec;
+      double A[3], B[3], d[3], gA[3], gB[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        A[ax] = double(r[ax]) * inv_s;
+        B[ax] = double(r[3 + ax]) * inv_s;
+        d[ax] = B[ax] - A[ax];
+      }
+      const double w = seg_length_grad(A, B, lo, gA, gB);
+      if (!(w > 0.0)) continue;
+      const double l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double il2 = 1.0 / l2;
+      W += w;
+      S[0] += w * (1.0 - d[0] * d[0] * il2);
+      S[1] += w * (1.0 - d[1] * d[1] * il2);
+      S[2] += w * (1.0 - d[2] * d[2] * il2);
+      S[3] -= w * d[0] * d[1] * il2;
+      S[4] -= w * d[0] * d[2] * il2;
+      S[5] -= w * d[1] * d[2] * il2;
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) out[int64_t(t) * cap + i] = S[t];
+    out[6 * cap + i] = W;
+  }
+}
+
+// level L from level L - 1: every voxel adds its children [cstart[u], cstart[u + 1]) in order
+__global__ void __launch_bounds__(kBlock) k_fit_up64(const int64_t* __restrict__ cstart, const int64_t* n_p,
+                                                     int64_t cap, const double* __restrict__ in, int64_t icap,
+                                                     double* __restrict__ out) {
+  const int64_t n = *n_p < cap ? *n_p : cap;
+  for (int64_t u = int64_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += int64_t(gridDim.x) * kBlock) {
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t c = cstart[u]; c < cstart[u + 1]; ++c)
+#pragma unroll
+      for (int t = 0; t < 7; ++t) acc[t] += in[int64_t(t) * icap + c];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) out[int64_t(t) * cap + u] = acc[t];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy_pairs(const uint8_t* __restrict__ ksrc, const uint32_t* __restrict__ psrc,
+                                                       const int64_t* __restrict__ ctl, int kb,
+                                                       uint8_t* __restrict__ kdst, uint32_t* __restrict__ pdst) {
+  const int64_t n = ctl[CTL_N_PAIRS];
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    if (kb == 8) reinterpret_cast<uint64_t*>(kdst)[i] = reinterpret_cast<const uint64_t*>(ksrc)[i];
+    else reinterpret_cast<uint32_t*>(kdst)[i] = reinterpret_cast<const uint32_t*>(ksrc)[i];
+    pdst[i] = psrc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // orchestration
 // ---------------------------------------------------------------------------------------------
 struct FitWs {
@@ -451,6 +573,10 @@ struct FitWs {
   int64_t* partial;        // [kGrid + 1] scan partials
   float* seg_grad;         // [n_pts][6]
   FrontWs f;
+  double* s64[21];         // [7][cap_L] per level 0..hi-1: FP64 sums (S, then w)
+  int64_t* sstart;         // [cap_0 + 1] first sorted pair of every leaf voxel
+  PairBufs pb, pc;         // sort buffers of the re-emitted pairs (a copy, then ping-pong)
+  int32_t* hist;           // radix digit histograms
 };
 
 // dense table of 16^3 tiles for the leaf lookup of the backward pass (grids up to 2048^3)
@@ -474,6 +600,15 @@ static size_t fit_ws_layout(int64_t n_pts, int64_t max_cand, int64_t max_pairs, 
   x.partial = cv.take<int64_t>(kGrid + 1);
   x.seg_grad = cv.take<float>(6 * n_pts);
   front_ws_carve(cv, n_pts, max_cand, max_pairs, key64, &x.f);
+  for (int L = 0; L < hi; ++L) x.s64[L] = cv.take<double>(n_pts > 0 ? 7 * caps[L] : 0);
+  x.sstart = cv.take<int64_t>(n_pts > 0 ? caps[0] + 1 : 0);
+  const int kb = key64 ? 8 : 4;
+  for (PairBufs* pbuf : {&x.pb, &x.pc}) {
+    pbuf->keys = cv.take<uint8_t>(max_pairs * kb);
+    pbuf->w = cv.take<float>(max_pairs);
+    pbuf->prim = cv.take<uint32_t>(max_pairs);
+  }
+  x.hist = cv.take<int32_t>(max_pairs > 0 ? int64_t(kRadixBuckets) * kGrid : 0);
   if (w) *w = x;
   return cv.off + 256;
 }
@@ -515,21 +650,34 @@ static int blocks_for(int64_t n) {
   return int(b < 1 ? 1 : (b > kGrid ? kGrid : b));
 }
 
+template <class Key>
+static void bind_check(const vx_voxels* levels, const int64_t* n_levels, int lo, int hi, const int64_t* rows,
+                       const void* const* bound, int64_t* stats, hipStream_t s) {
+  for (int L = lo; L <= hi; ++L)
+    hipLaunchKernelGGL(k_fit_bind<Key>, dim3(blocks_for(rows[L - lo])), dim3(kBlock), 0, s,
+                       (const Key*)levels[L].keys, n_levels + L, rows[L - lo],
+                       bound ? (const Key*)bound[L - lo] : (const Key*)nullptr, stats);
+}
+
 vx_status fit_forward_run(const vx_grid* g, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
-                          const float* const* params, const float* dirs, int ndir, float* loss, void* ws,
-                          const int64_t* caps, hipStream_t s) {
+                          const float* const* params, const int64_t* rows, const void* const* bound, const float* dirs,
+                          int ndir, float* loss, int64_t* stats, void* ws, const int64_t* caps, hipStream_t s) {
   const bool key64 = g->log2_res > 10;
   FitWs w;
   fit_ws_layout(0, 0, 0, caps, hi, g->log2_res, ws, &w);
+  launch_fill_i64(stats, VX_NSTAT, 0, s);
+  if (key64) bind_check<uint64_t>(levels, n_levels, lo, hi, rows, bound, stats, s);
+  else bind_check<uint32_t>(levels, n_levels, lo, hi, rows, bound, stats, s);
   child_starts(key64, levels, n_levels, hi, w, s);
   LossLevels ll;
   ll.count = 0;
   for (int L = lo; L <= hi; ++L) {
     VX_TIMED("fit_fwd", s);
-    hipLaunchKernelGGL(k_fit_fwd, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],
-                       w.cstart[L], params[L - lo], dirs, ndir, w.loss_vox[L]);
+    hipLaunchKernelGGL(k_fit_fwd, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, rows[L - lo],
+                       levels[L - 1], w.cstart[L], params[L - lo], dirs, ndir, w.loss_vox[L]);
     ll.p[ll.count] = w.loss_vox[L];
     ll.n[ll.count] = n_levels + L;
+    ll.rows[ll.count] = rows[L - lo];
     ++ll.count;
   }
   VX_TIMED("fit_total", s);
@@ -538,26 +686,56 @@ vx_status fit_forward_run(const vx_grid* g, const vx_voxels* levels, const int64
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
 }
 
+// FP64 sums of levels 0..hi-1 from the re-emitted pairs (f.pa, emission order, left intact)
+template <class Key>
+static void level_sums64(const vx_grid* g, const vx_voxels* levels, const int64_t* n_levels, int hi,
+                         const FitWs& w, const int64_t* caps, int64_t* stats, hipStream_t s) {
+  VX_TIMED("fit_sums64", s);
+  const int kb = int(sizeof(Key));
+  hipLaunchKernelGGL(k_copy_pairs, dim3(kGrid), dim3(kBlock), 0, s, (const uint8_t*)w.f.pa.keys, w.f.pa.prim,
+                     w.f.ctl, kb, (uint8_t*)w.pc.keys, w.pc.prim);
+  const int res = radix_sort_pairs(kb == 8, 3 * g->log2_res, w.pc, w.pb, w.f.ctl + CTL_N_PAIRS, 0, w.hist,
+                                   w.partial, s);
+  const PairBufs P = res ? w.pb : w.pc;
+  device_scan(HeadIn<Key, 0>{(const Key*)P.keys}, HeadOut{w.sstart}, LeafSegTotal{w.sstart, n_levels, stats},
+              w.f.ctl + CTL_N_PAIRS, 0, w.partial, s);
+  const Lat lat = make_lat(g, 1, 0.0f);
+  hipLaunchKernelGGL(k_fit_leaf64<Key>, dim3(kGrid), dim3(kBlock), 0, s, (const Key*)P.keys, P.prim, w.sstart,
+                     w.f.rec, (const Key*)levels[0].keys, n_levels, caps[0], lat.Sb, g->log2_res, w.s64[0], stats);
+  for (int L = 1; L < hi; ++L)
+    hipLaunchKernelGGL(k_fit_up64, dim3(kGrid), dim3(kBlock), 0, s, w.cstart[L], n_levels + L, caps[L],
+                       w.s64[L - 1], caps[L - 1], w.s64[L]);
+}
+
 vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, const int64_t* offsets, int64_t n_fib,
                            float radius, int64_t max_cand, int64_t max_pairs, const vx_voxels* levels,
-                           const int64_t* n_levels, int lo, int hi, const float* const* params, const float* dirs,
-                           int ndir, const float* dloss, float* const* dparams, float* dpts, int64_t* stats,
-                           void* ws, const int64_t* caps, hipStream_t s) {
+                           const int64_t* n_levels, int lo, int hi, const float* const* params, const int64_t* rows,
+                           const void* const* bound, const float* dirs, int ndir, const float* dloss,
+                           float* const* dparams, float* dpts, int64_t* stats, void* ws, const int64_t* caps,
+                           hipStream_t s) {
   const bool key64 = g->log2_res > 10;
   FitWs w;
   fit_ws_layout(n_pts, max_cand, max_pairs, caps, hi, g->log2_res, ws, &w);
   for (int L = 0; L < hi; ++L)
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(7 * caps[L])), dim3(kBlock), 0, s, w.g[L], 7 * caps[L], 0.0);
+  // re-emit the pairs in primitive order (this clears stats), then check the parameters' binding
+  voxelize_front(1, g, pts, n_pts, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s, nullptr);
+  if (key64) bind_check<uint64_t>(levels, n_levels, lo, hi, rows, bound, stats, s);
+  else bind_check<uint32_t>(levels, n_levels, lo, hi, rows, bound, stats, s);
   child_starts(key64, levels, n_levels, hi, w, s);
+  if (key64) level_sums64<uint64_t>(g, levels, n_levels, hi, w, caps, stats, s);
+  else level_sums64<uint32_t>(g, levels, n_levels, hi, w, caps, stats, s);
   // lobe gradients and the children's (S, w) gradients, level by level
   for (int L = lo; L <= hi; ++L) {
     VX_TIMED("fit_bwd", s);
     if (ndir <= 128)
-      hipLaunchKernelGGL(k_fit_bwd<8>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],
-                         w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo], w.g[L - 1], caps[L - 1]);
+      hipLaunchKernelGGL(k_fit_bwd<8>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, rows[L - lo],
+                         w.s64[L - 1], caps[L - 1], w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo],
+                         w.g[L - 1], caps[L - 1]);
     else
-      hipLaunchKernelGGL(k_fit_bwd<16>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, levels[L - 1],
-                         w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo], w.g[L - 1], caps[L - 1]);
+      hipLaunchKernelGGL(k_fit_bwd<16>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, rows[L - lo],
+                         w.s64[L - 1], caps[L - 1], w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo],
+                         w.g[L - 1], caps[L - 1]);
   }
   // top-down accumulation to the leaf
   for (int L = hi - 2; L >= 0; --L) {
@@ -565,8 +743,7 @@ vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, co
     hipLaunchKernelGGL(k_fit_down, dim3(kGrid), dim3(kBlock), 0, s, w.pidx[L], n_levels + L, w.g[L], caps[L],
                        w.g[L + 1], caps[L + 1]);
   }
-  // re-emit the pairs in primitive order, then the chain rule per segment and per point
-  voxelize_front(1, g, pts, n_pts, offsets, n_fib, radius, max_cand, max_pairs, w.f, stats, s, nullptr);
+  // the chain rule per segment over its pairs (emission order) and per point
   const Lat lat = make_lat(g, 1, radius);
   const double vs = double(int64_t(1) << g->log2_res) / g->extent;
   const int64_t tiles = leaf_tiles(g->log2_res);

@@ -12,8 +12,6 @@
 
 namespace vx {
 
-constexpr int kPolyStride = 256;   // LDS stride between a thread's polygon slots (= block size)
-
 struct Lat {
   double bmin[3];
   double inv;        // lattice units per world unit, 2^23 / extent
@@ -201,55 +199,61 @@ VX_HD inline __attribute__((noinline)) bool plane_exact(int64_t n0, int64_t n1, 
   return !(base + lo > 0 || base + hi < 0);
 }
 
+// Every quantity of the edge tests is an integer below 2^53 in magnitude, so FP64 evaluates them
+// exactly (and with none of the 64-bit integer multiplies, which take several quarter-rate
+// instructions each on gfx950): vertex offsets from the box corner c lie in (-2^24, 2^24], edges
+// e in [-2^25, 2^25], the projections a . c on an edge-cross-axis direction (two products) in
+// [-2^50, 2^50], the box's projection bounds in [-2^48, 2^48], and the plane normal's
+// components (differences of two products of edges) in [-2^51, 2^51].
 VX_HD inline bool tri_touch(const int32_t* q, const int64_t v[3], int64_t s, int Sb) {
-  int64_t c[3][3];   // vertices relative to the box corner
+  double c[3][3];   // vertices relative to the box corner
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) c[i][a] = int64_t(q[3 * i + a]) - (v[a] << Sb);
-  int64_t e[3][3];
+    for (int a = 0; a < 3; ++a) c[i][a] = double(q[3 * i + a] - (int32_t(v[a]) << Sb));
+  double e[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     e[0][a] = c[1][a] - c[0][a];
     e[1][a] = c[2][a] - c[1][a];
     e[2][a] = c[0][a] - c[2][a];
   }
-  // nine edge x box-axis directions: projections of the triangle and of the box [0, s]^3
+  const double ds = double(s);
+  // nine edge x box-axis directions: projections of the triangle and of the box [0, s]^3.  On
+  // the direction of edge j the edge's two ends project alike, so the triangle projects onto
+  // the interval between vertex j and the opposite vertex.
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int u = (k + 1) % 3, w = (k + 2) % 3;     // axis = e_k x e_j -> components on u and w
-      const int64_t au = -e[j][w], aw = e[j][u];
-      int64_t p0 = au * c[0][u] + aw * c[0][w];
-      int64_t p1 = au * c[1][u] + aw * c[1][w];
-      int64_t p2 = au * c[2][u] + aw * c[2][w];
-      const int64_t pmin = imin(p0, imin(p1, p2)), pmax = imax(p0, imax(p1, p2));
-      const int64_t blo = (imin(au, 0) + imin(aw, 0)) * s;
-      const int64_t bhi = (imax(au, 0) + imax(aw, 0)) * s;
+      const double au = -e[j][w], aw = e[j][u];
+      const double p0 = fma(au, c[j][u], aw * c[j][w]);
+      const double p2 = fma(au, c[(j + 2) % 3][u], aw * c[(j + 2) % 3][w]);
+      const double pmin = fmin(p0, p2), pmax = fmax(p0, p2);
+      const double blo = (fmin(au, 0.0) + fmin(aw, 0.0)) * ds;
+      const double bhi = (fmax(au, 0.0) + fmax(aw, 0.0)) * ds;
       if (pmax < blo || pmin > bhi) return false;
     }
   }
   // plane: corner offsets n . (corner - c0) must not all share a strict sign
-  int64_t n[3];
-  n[0] = e[0][1] * (-e[2][2]) - e[0][2] * (-e[2][1]);
-  n[1] = e[0][2] * (-e[2][0]) - e[0][0] * (-e[2][2]);
-  n[2] = e[0][0] * (-e[2][1]) - e[0][1] * (-e[2][0]);
-  const double ds = double(s);
-  double base = -(double(n[0]) * double(c[0][0]) + double(n[1]) * double(c[0][1]) + double(n[2]) * double(c[0][2]));
-  double lo = base, hi = base, mag = fabs(double(n[0]) * double(c[0][0])) + fabs(double(n[1]) * double(c[0][1])) +
-                                     fabs(double(n[2]) * double(c[0][2]));
+  double n[3];
+  n[0] = fma(e[0][2], e[2][1], -(e[0][1] * e[2][2]));
+  n[1] = fma(e[0][0], e[2][2], -(e[0][2] * e[2][0]));
+  n[2] = fma(e[0][1], e[2][0], -(e[0][0] * e[2][1]));
+  double base = -(n[0] * c[0][0] + n[1] * c[0][1] + n[2] * c[0][2]);
+  double lo = base, hi = base, mag = fabs(n[0] * c[0][0]) + fabs(n[1] * c[0][1]) + fabs(n[2] * c[0][2]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double t = double(n[a]) * ds;
+    double t = n[a] * ds;
     if (n[a] > 0) hi += t; else lo += t;
     mag += fabs(t);
   }
   const double err = mag * 0x1p-48;
   if (lo > err || hi < -err) return false;           // strictly on one side
   if (lo < -err && hi > err) return true;            // strictly across
-  int64_t rel[3] = {-c[0][0], -c[0][1], -c[0][2]};
-  return plane_exact(n[0], n[1], n[2], rel[0], rel[1], rel[2], s);
+  return plane_exact(int64_t(n[0]), int64_t(n[1]), int64_t(n[2]), -int64_t(c[0][0]), -int64_t(c[0][1]),
+                     -int64_t(c[0][2]), s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -526,101 +530,104 @@ VX_HD inline Lat make_lat(const vx_grid* g, int kind, float radius) {
   return L;
 }
 
-constexpr int kPolyMax = 9;
-constexpr size_t kTriEmitLds = size_t(2 * kPolyMax * 2) * kPolyStride * sizeof(double);
-
-// area of the triangle inside [v, v+1)^3 (voxel^2): Sutherland-Hodgman clipping in the
-// triangle's own barycentric plane (l1, l2), FP64, polygons kept in this thread's LDS slots.
-// `poly` points at 2 x 9 x 2 doubles, strided by kPolyStride.
-VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float area2,
-                                          double* poly) {
-  const double inv_s = 1.0 / double(int64_t(1) << Sb);
+// Area of the triangle inside [v, v+1)^3 (voxel^2), in registers.
+//
+// In the triangle's barycentric plane (l1, l2) -- the point q0 + l1 (q1 - q0) + l2 (q2 - q0) --
+// the piece is the convex polygon cut out by nine half-planes h(l) = alpha + beta l1 + gamma l2
+// >= 0: the triangle's three (l1 >= 0, l2 >= 0, 1 - l1 - l2 >= 0) and, for every axis a, the
+// box's two (x_a >= 0, s - x_a >= 0 with x_a in lattice units relative to the voxel corner).
+// Its area is half the sum over its edges of the cross product of the edge's end points
+// (Green's theorem).  Every half-plane's line carries at most one edge: the line walked with the
+// inside on its left, entered where the last half-plane turning from outside to inside crosses
+// it and left where the first one turning from inside to outside does.  The two lines through
+// the origin (l1 = 0, l2 = 0) contribute nothing to the sum; they only clip.
+//
+// All coefficients are lattice integers below 2^25 in magnitude, so the intersection of two
+// lines, by Cramer's rule N1 / D, N2 / D, has exact numerators and denominator (two products
+// each) and one rounding; both lines of a vertex compute it alike, so the edges share their end
+// points.  Half-planes that hold on the whole triangle are dropped (they cut nothing), one that
+// no triangle point passes strictly makes the piece empty.  Parallel lines are decided exactly:
+// an outside one empties the line, a coincident one with the same inside gives the edge to the
+// lower-numbered line, one with the opposite inside flattens the piece to a segment (area 0).
+// A triangle flat on axis a has no line on a: it lies in one layer [k, k+1) of that axis or none.
+VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float area2) {
+  if (!(area2 > 0.0f)) return 0.0f;
   const int64_t s = int64_t(1) << Sb;
-  double cf[3], e0[3], e1[3];
-  bool skip[3];
+  double al[9], be[9], ga[9];
+  al[0] = 0.0; be[0] = 1.0; ga[0] = 0.0;       // l1 >= 0
+  al[1] = 0.0; be[1] = 0.0; ga[1] = 1.0;       // l2 >= 0
+  al[2] = 1.0; be[2] = -1.0; ga[2] = -1.0;     // 1 - l1 - l2 >= 0
+  unsigned act = 7u;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int64_t c0 = int64_t(q[a]) - (v[a] << Sb);
-    const int64_t d0 = int64_t(q[3 + a]) - int64_t(q[a]);
-    const int64_t d1 = int64_t(q[6 + a]) - int64_t(q[a]);
-    skip[a] = (d0 == 0 && d1 == 0);
-    if (skip[a] && !(c0 >= 0 && c0 < s)) return 0.0f;   // flat on axis a, owned by another layer
-    cf[a] = double(c0) * inv_s;
-    e0[a] = double(d0) * inv_s;
-    e1[a] = double(d1) * inv_s;
-  }
-#define PX(b, i) poly[((b) * 2 * kPolyMax + (i) * 2) * kPolyStride]
-#define PY(b, i) poly[((b) * 2 * kPolyMax + (i) * 2 + 1) * kPolyStride]
-  // A plane that leaves all three vertices strictly inside leaves every clipped piece inside
-  // too: the vertices' coordinates are multiples of the lattice step, and clipped vertices are
-  // convex combinations of them, so rounding cannot carry one across.  Such planes are skipped.
-  int cut = 0;
+    const int32_t c0 = q[a] - (int32_t(v[a]) << Sb);
+    const int32_t d0 = q[3 + a] - q[a];
+    const int32_t d1 = q[6 + a] - q[a];
+    al[3 + 2 * a] = double(c0);
+    be[3 + 2 * a] = double(d0);
+    ga[3 + 2 * a] = double(d1);
+    al[4 + 2 * a] = double(int32_t(s) - c0);
+    be[4 + 2 * a] = double(-d0);
+    ga[4 + 2 * a] = double(-d1);
+    if (d0 == 0 && d1 == 0) {
+      if (!(c0 >= 0 && c0 < int32_t(s))) return 0.0f;   // flat on axis a, owned by another layer
+      continue;
+    }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (skip[a]) continue;
-    const double x0 = cf[a], x1 = cf[a] + e0[a], x2 = cf[a] + e1[a];
-    if (!(x0 > 0.0 && x1 > 0.0 && x2 > 0.0)) cut |= 1 << (2 * a);
-    if (!(x0 < 1.0 && x1 < 1.0 && x2 < 1.0)) cut |= 2 << (2 * a);
-  }
-  if (cut == 0) return float(0.5 * double(area2));
-  int n = 3, cur = 0;
-  PX(0, 0) = 0.0; PY(0, 0) = 0.0;
-  PX(0, 1) = 1.0; PY(0, 1) = 0.0;
-  PX(0, 2) = 0.0; PY(0, 2) = 1.0;
-  for (int a = 0; a < 3; ++a) {
-    if (skip[a]) continue;
     for (int side = 0; side < 2; ++side) {
-      if (!((cut >> (2 * a + side)) & 1)) continue;
-      // f >= 0 with f = x_a (side 0) or 1 - x_a (side 1), x_a = cf + l1 e0 + l2 e1
-      bool all_in = true, all_out = true;
-      for (int i = 0; i < n; ++i) {
-        double x = cf[a] + PX(cur, i) * e0[a] + PY(cur, i) * e1[a];
-        double f = side ? 1.0 - x : x;
-        all_in = all_in && f >= 0.0;
-        all_out = all_out && f < 0.0;
-      }
-      if (all_out) return 0.0f;
-      if (all_in) continue;
-      const int nb = cur ^ 1;
-      int m = 0;
-      double xp = PX(cur, n - 1), yp = PY(cur, n - 1);
-      double fp = cf[a] + xp * e0[a] + yp * e1[a];
-      fp = side ? 1.0 - fp : fp;
-      for (int i = 0; i < n; ++i) {
-        const double xc = PX(cur, i), yc = PY(cur, i);
-        double fc = cf[a] + xc * e0[a] + yc * e1[a];
-        fc = side ? 1.0 - fc : fc;
-        // a convex polygon gains at most one vertex per plane; vertices beyond the 9 slots
-        // (possible only from rounding in degenerate slivers) are dropped
-        if ((fp >= 0.0) != (fc >= 0.0) && m < kPolyMax) {
-          const double t = fp / (fp - fc);
-          PX(nb, m) = xp + t * (xc - xp);
-          PY(nb, m) = yp + t * (yc - yp);
-          ++m;
-        }
-        if (fc >= 0.0 && m < kPolyMax) {
-          PX(nb, m) = xc;
-          PY(nb, m) = yc;
-          ++m;
-        }
-        xp = xc; yp = yc; fp = fc;
-      }
-      n = m;
-      cur = nb;
-      if (n < 3) return 0.0f;
+      const int k = 3 + 2 * a + side;
+      // h at the three vertices (0, 0), (1, 0), (0, 1)
+      const double h0 = al[k], h1 = al[k] + be[k], h2 = al[k] + ga[k];
+      if (fmax(h0, fmax(h1, h2)) <= 0.0) return 0.0f;   // no point of the triangle strictly inside
+      if (fmin(h0, fmin(h1, h2)) <= 0.0) act |= 1u << k;
     }
   }
-  double acc = 0.0;
-  const double x0 = PX(cur, 0), y0 = PY(cur, 0);
-  for (int i = 1; i + 1 < n; ++i) {
-    const double ux = PX(cur, i) - x0, uy = PY(cur, i) - y0;
-    const double wx = PX(cur, i + 1) - x0, wy = PY(cur, i + 1) - y0;
-    acc += ux * wy - uy * wx;
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 2; k < 9; ++k) {
+    if (!((act >> k) & 1u)) continue;
+    const double ak = al[k], bk = be[k], gk = ga[k];
+    const double nk = fma(bk, bk, gk * gk);              // |g_k|^2
+    // best entry (largest t) and exit (smallest t) as fractions T / D with D > 0 resp. D < 0;
+    // t = T / D is the position along the line, direction (gk, -bk); the comparisons multiply
+    // out the denominators (positive for two entries, both negative for two exits)
+    double Te = -1.0, De = 0.0, N1e = 0.0, N2e = 0.0;    // De = 0: no entry bound yet
+    double Tx = 1.0, Dx = 0.0, N1x = 0.0, N2x = 0.0;
+    bool dead = false;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      if (j == k || !((act >> j) & 1u)) continue;
+      const double D = fma(be[j], gk, -(ga[j] * bk));    // g_j . (gk, -bk), exact
+      const double N1 = fma(ak, ga[j], -(al[j] * gk));   // exact
+      const double N2 = fma(al[j], bk, -(ak * be[j]));   // exact
+      if (D == 0.0) {
+        // parallel: the sign of h_j on line k, from one nonzero component of g_k (exact)
+        const double hs = bk != 0.0 ? (bk > 0.0 ? N2 : -N2) : (gk > 0.0 ? -N1 : N1);
+        const double same = fma(be[j], bk, ga[j] * gk);   // g_j . g_k
+        if (hs < 0.0) dead = true;
+        else if (hs == 0.0) {
+          if (same < 0.0) return 0.0f;                     // the piece lies on one line
+          if (j < k) dead = true;                          // the edge belongs to line j
+        }
+        continue;
+      }
+      const double dot = fma(be[j], bk, ga[j] * gk);
+      const double T = fma(ak, dot, -(al[j] * nk));       // t = T / D
+      if (D > 0.0) {
+        if (De == 0.0 || T * De > Te * D) { Te = T; De = D; N1e = N1; N2e = N2; }
+      } else {
+        if (Dx == 0.0 || T * Dx < Tx * D) { Tx = T; Dx = D; N1x = N1; N2x = N2; }
+      }
+    }
+    // every line is bounded on both sides by the triangle's own lines, so De, Dx != 0 here
+    if (dead || De == 0.0 || Dx == 0.0) continue;
+    const double ie = 1.0 / De, ix = 1.0 / Dx;
+    const double xe = N1e * ie, ye = N2e * ie, xx = N1x * ix, yx = N2x * ix;
+    const double te = fma(gk, xe, -(bk * ye)), tx = fma(gk, xx, -(bk * yx));
+    if (!(tx > te)) continue;
+    sum += fma(xe, yx, -(ye * xx));
   }
-#undef PX
-#undef PY
-  return float(0.5 * fabs(acc) * double(area2));
+  return float(0.5 * fabs(sum) * double(area2));
 }
-
 
 }  // namespace vx

@@ -10,8 +10,6 @@
 
 namespace vx {
 
-static_assert(kPolyStride == kBlock, "polygon slots are strided by the block size");
-
 __device__ __forceinline__ void flag_or(int64_t* stats, int64_t bit) {
   atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)bit);
 }
@@ -169,7 +167,6 @@ __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec
                                                  const int64_t* __restrict__ chunk_prim,
                                                  const int64_t* __restrict__ wave_off, Key* __restrict__ keys,
                                                  float* __restrict__ wts, uint32_t* __restrict__ prim) {
-  extern __shared__ double lds_poly[];
   const int64_t n_chunks = ctl[CTL_N_CHUNKS];
   const int lane = lane_id();
   const int64_t w0 = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
@@ -187,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec
     candidate_voxel(r, ci - cand_off[p], v);
     float wgt;
     const int Sb = lats ? lats[r[15]].Sb : L.Sb;
-    if (KIND == 0) wgt = tri_area(r, v, Sb, dirs[p].w, lds_poly + threadIdx.x);
+    if (KIND == 0) wgt = tri_area(r, v, Sb, dirs[p].w);
     else wgt = seg_length(r, v, Sb, dirs[p].w);
     Key key = Key(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])));
     if (lats) key |= Key(uint64_t(uint32_t(r[15])) << kPatchShift);
@@ -361,22 +358,9 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
     device_scan(PopIn{w.masks}, ArrOut{w.wave_off}, PairTotal{w.wave_off, w.ctl, stats, max_pairs},
                 w.ctl + CTL_N_CHUNKS, 0, w.partial, s);
   }
-  const size_t lds = kind == 0 ? kTriEmitLds : 0;
-  if (kind == 0) {
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[key64]) {
-      if (key64)
-        (void)hipFuncSetAttribute((const void*)k_emit<0, uint64_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(kTriEmitLds));
-      else
-        (void)hipFuncSetAttribute((const void*)k_emit<0, uint32_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(kTriEmitLds));
-      attr_set[key64] = true;
-    }
-  }
   VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
 #define VX_EMIT(KD, K)                                                                                        \
-  hipLaunchKernelGGL((k_emit<KD, K>), dim3(kGrid), dim3(kBlock), lds, s, w.rec, w.dirs, w.cand_off, \
+  hipLaunchKernelGGL((k_emit<KD, K>), dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.dirs, w.cand_off, \
                      n_prims, w.ctl, L, lats, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim)
   if (kind == 0) {
     if (key64) VX_EMIT(0, uint64_t); else VX_EMIT(0, uint32_t);

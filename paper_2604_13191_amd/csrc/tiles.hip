@@ -476,9 +476,8 @@ __device__ __forceinline__ bool unit_test(const int32_t* r, const int64_t v[3], 
 }
 
 template <int KIND>
-__device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3], const LatQ& Lp, float len,
-                                             double* poly) {
-  if (KIND == 0) return tri_area(r, v, Lp.Sb, len, poly);
+__device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3], const LatQ& Lp, float len) {
+  if (KIND == 0) return tri_area(r, v, Lp.Sb, len);
   return seg_length(r, v, Lp.Sb, len);
 }
 
@@ -515,9 +514,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
                                                  int64_t* __restrict__ usoff, Stage st, int64_t* stage_ctr,
                                                  int64_t* stats) {
   extern __shared__ double lds_dyn[];
-  double* poly = lds_dyn;                                               // triangles: clipping slots
-  char* base = reinterpret_cast<char*>(lds_dyn) + (KIND == 0 ? kTriEmitLds : 0);
-  const UnitLds S = carve_unit_lds(base);
+  const UnitLds S = carve_unit_lds(reinterpret_cast<char*>(lds_dyn));
   const int64_t n_units = ctl[CTL_N_UNITS];
   const int tid = threadIdx.x;
   for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
@@ -548,7 +545,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
             const int32_t* r = S.brec + slot * 9;
             const LatQ Lp = lat_q(lats, S.bpatch[slot], L);
             hit = unit_test<KIND>(r, v, Lp);
-            if (hit) wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
+            if (hit) wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w);
           }
           int32_t tot;
           const int32_t pos = block_exclusive_scan(int32_t(hit), S.tmp32, tot);
@@ -684,7 +681,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       const LatQ Lp = lat_q(lats, r[15], L);
       const uint64_t m = m0 + k;
       const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
-      S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w, poly + tid);
+      S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w);
     }
     __syncthreads();
     // starts and the voxel list: thread t owns keys [16 t, 16 t + 16); one block scan of the
@@ -1067,7 +1064,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   }
   {
     VX_TIMED(kind == 0 ? "unit_tri" : "unit_fib", s);
-    const size_t lds = kUnitLdsBytes + (kind == 0 ? kTriEmitLds : 0);
+    const size_t lds = kUnitLdsBytes;
     static bool attr[2] = {false, false};
     if (!attr[kind]) {
       if (kind == 0)

@@ -342,13 +342,14 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
 // the differentiable two-lobe fit (fit.hip)
 size_t fit_ws_bytes(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int hi, int log2R);
 vx_status fit_forward_run(const vx_grid* g, const vx_voxels* levels, const int64_t* n_levels, int lo, int hi,
-                          const float* const* params, const float* dirs, int ndir, float* loss, void* ws,
-                          const int64_t* caps, hipStream_t s);
+                          const float* const* params, const int64_t* rows, const void* const* bound, const float* dirs,
+                          int ndir, float* loss, int64_t* stats, void* ws, const int64_t* caps, hipStream_t s);
 vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, const int64_t* offsets, int64_t n_fib,
                            float radius, int64_t max_cand, int64_t max_pairs, const vx_voxels* levels,
-                           const int64_t* n_levels, int lo, int hi, const float* const* params, const float* dirs,
-                           int ndir, const float* dloss, float* const* dparams, float* dpts, int64_t* stats,
-                           void* ws, const int64_t* caps, hipStream_t s);
+                           const int64_t* n_levels, int lo, int hi, const float* const* params, const int64_t* rows,
+                           const void* const* bound, const float* dirs, int ndir, const float* dloss,
+                           float* const* dparams, float* dpts, int64_t* stats, void* ws, const int64_t* caps,
+                           hipStream_t s);
 
 // the voxelize pass by tiles (tiles.hip); tb = tile bits per axis
 size_t tile_ws_bytes(int64_t n_prims, int64_t max_rec, int64_t max_units, int64_t max_vox, bool key64);

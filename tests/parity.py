@@ -125,3 +125,68 @@ def compare_lobes(g: dict, ref, lvl_w, lvl_S, K, tol=TOL, floor=FLOOR, prof_tol=
            "decided_profile_err_max": float(perr[decided].max(initial=0))}
     assert rep["near_tie_profile_err_max"] <= prof_tol, (what, rep)
     return rep
+
+
+def compare_lobes_stepwise(g_lobes: dict, child, child_start, K, iters=2, tol=TOL, floor=FLOOR, what=""):
+    """One level of the clustering checked on its own inputs: ``child`` holds the GPU's own lobes
+    of the level below (as an oracle.Lobes in FP64; the leaf's single lobes at level 1), which
+    the oracle clusters again.  Wherever this level's own decisions (Ward merges and Lloyd
+    assignments of the voxel, not of its subtree) have a clear margin, the GPU's lobes must match
+    the oracle's lobe for lobe; every voxel must keep the sums of its inputs, nl <= K and positive
+    weights.  Returns a report with the number of voxels checked lobe for lobe."""
+    import oracle
+    from scipy.optimize import linear_sum_assignment
+    n = len(child_start) - 1
+    assert len(g_lobes["nl"]) == n, what
+    c = oracle.Lobes(child.nl, child.w, child.S, child.gap_rel, child.gap_abs,
+                     np.full(len(child.nl), np.inf), np.full(len(child.nl), np.inf))
+    ref = oracle.cluster_level(c, child_start, K, iters)
+    # what every parent's lobes must add up to: its children's lobes
+    live_c = np.arange(child.w.shape[1])[None, :] < child.nl[:, None]
+    cw = np.where(live_c, child.w, 0.0).sum(1)
+    cS = np.where(live_c[:, :, None], child.S, 0.0).sum(1)
+    starts = np.asarray(child_start[:-1])
+    sum_w = np.add.reduceat(cw, starts) if n else np.zeros(0)
+    sum_S = np.add.reduceat(cS, starts, axis=0) if n else np.zeros((0, 6))
+    gw, gS = g_lobes["w"].astype(np.float64), g_lobes["S"].astype(np.float64)
+    scale = np.maximum(sum_S[:, 0] + sum_S[:, 1] + sum_S[:, 2], floor)
+    assert np.all(g_lobes["nl"] <= K), what
+    assert np.all(np.abs(gw.sum(1) - sum_w) <= tol * np.maximum(sum_w, floor)), what
+    assert np.all(np.abs(gS.sum(1) - sum_S).max(1) <= tol * scale), what
+    kk = np.arange(K)[None, :]
+    live = kk < g_lobes["nl"][:, None]
+    assert np.all(gw[live] > 0) and np.all(gw[~live] == 0), what
+    merged = ref.nl > 0
+    # voxels with more input lobes than K take decisions; the others keep their inputs as they are
+    n_in = np.add.reduceat(child.nl.astype(np.int64), starts) if n else np.zeros(0, np.int64)
+    decided = (ref.gap_rel >= DECIDED_REL) & (ref.gap_abs >= DECIDED_ABS)
+    n_exact, n_dec_merge = 0, 0
+    for i in np.flatnonzero(decided & merged):
+        assert g_lobes["nl"][i] == ref.nl[i], (what, i, g_lobes["nl"][i], ref.nl[i])
+        m = ref.nl[i]
+        cost = np.abs(gS[i, :m, None, :] - ref.S[i, None, :m, :]).max(-1) + np.abs(gw[i, :m, None] - ref.w[i, None, :m])
+        r, cc = linear_sum_assignment(cost)
+        err = max(np.abs(gw[i, r] - ref.w[i, cc]).max(), np.abs(gS[i, r] - ref.S[i, cc]).max())
+        assert err <= tol * scale[i], (what, i, err, scale[i])
+        n_exact += 1
+        n_dec_merge += int(n_in[i] > K)
+    return {"n": int(n), "merging": int(np.sum(n_in > K)), "checked_exactly": n_exact,
+            "checked_exactly_merging": n_dec_merge, "near_tie": int(np.sum(~decided & merged))}
+
+
+def gpu_lobes_as_oracle(g_lobes: dict):
+    """A GPU level's lobes (Lobes.numpy()) as an oracle.Lobes in FP64 (margins unknown: +inf)."""
+    import oracle
+    n = len(g_lobes["nl"])
+    inf = np.full(n, np.inf)
+    return oracle.Lobes(g_lobes["nl"].astype(np.int32), g_lobes["w"].astype(np.float64),
+                        g_lobes["S"].astype(np.float64), inf, inf.copy(), inf.copy(), inf.copy())
+
+
+def leaf_as_oracle_lobes(g_leaf: dict):
+    """A GPU leaf (Voxels.numpy()) as one lobe per voxel, present where w > 0."""
+    import oracle
+    n = len(g_leaf["w"])
+    inf = np.full(n, np.inf)
+    return oracle.Lobes((g_leaf["w"] > 0).astype(np.int32), g_leaf["w"].astype(np.float64).reshape(n, 1),
+                        g_leaf["S"].astype(np.float64).reshape(n, 1, 6), inf, inf.copy(), inf.copy(), inf.copy())

@@ -154,3 +154,42 @@ def test_brushed_metal_full_sampled_regions(vx):
                 gl = {k: v[sel] for k, v in lobes_gpu[L - 1].items()}
                 compare_lobes(gl, olobes[L], o.w, o.S, 4, what=f"brushed full region {lo.tolist()} L{L}")
         say("region", lo.tolist(), "ok:", rep)
+
+
+def _stepwise(pyr, lobes, lod, K, what, min_checked_from_level3=1):
+    """Every level clustered again by the oracle from the GPU's own lobes of the level below."""
+    from parity import compare_lobes_stepwise, gpu_lobes_as_oracle, leaf_as_oracle_lobes
+    child = leaf_as_oracle_lobes(pyr[0].numpy())
+    deep = 0
+    for L in range(1, len(pyr)):
+        g = lobes[L - 1].numpy()
+        rep = compare_lobes_stepwise(g, child, lod[L].child_start, K, what=f"{what} L{L}")
+        say(what, "level", L, rep)
+        if L >= 3:
+            deep += rep["checked_exactly_merging"]
+        child = gpu_lobes_as_oracle(g)
+    assert deep >= min_checked_from_level3, (what, deep)
+
+
+def test_cluster_levels_stepwise_brushed(vx):
+    """Brushed metal 256x256 window, K = 4: each level's merges checked on that level's inputs."""
+    import torch
+    wl = synth.brushed_metal(window=256)
+    say("case: brushed metal 256x256 window, stepwise clustering check, K=4")
+    leaf = vx.voxelize_triangles(torch.as_tensor(wl.tris).cuda(), wl.grid)
+    pyr, lobes = vx.build_lod(wl.grid, leaf, wl.levels, K=4, iters=2, return_lobes=True)
+    ref = oracle.voxelize_triangles(wl.grid, wl.tris)
+    lod = oracle.build_lod(ref, wl.levels)
+    _stepwise(pyr, lobes, lod, 4, "brushed256", min_checked_from_level3=100)
+
+
+@pytest.mark.parametrize("K", [2, 4, 8])
+def test_cluster_levels_stepwise_given_leaf(vx, K):
+    keys, cnt, w, S = _random_leaf(500 + K, 6, 40000, None)
+    say(f"case: given leaf, 64^3, stepwise clustering check, K={K}")
+    grid = synth.Grid((0.0, 0.0, 0.0), 64.0, 6)
+    leaf = _leaf_to_device(vx, keys, cnt, w, S, 6)
+    pyr, lobes = vx.build_lod(grid, leaf, 7, K=K, iters=2, return_lobes=True)
+    ref = oracle.Voxels(keys, cnt, w.astype(np.float64), S.astype(np.float64), int(cnt.sum()))
+    lod = oracle.build_lod(ref, 7)
+    _stepwise(pyr, lobes, lod, K, f"given K{K}", min_checked_from_level3=10)

@@ -1,5 +1,11 @@
 """GPU parity of the differentiable two-lobe fit: forward loss, lobe gradients and control-point
-gradients (hand-written backward kernels) against the FP64 oracle's analytic gradient."""
+gradients (hand-written backward kernels) against the FP64 oracle's analytic gradient, at a
+small fabric and at the full 2,000-fiber plain weave (levels 1-6, 128 directions).
+
+Tolerances: the loss to 1e-5 relative (FP32 sums and FP32 profiles); the gradients to 1e-4
+relative in norm over every lobe parameter and every control point.  The backward pass
+differentiates at FP64 level sums and in FP64 arithmetic; what remains is the FP32 directions
+(rounded once, about 6e-8 relative) and the FP32 parameters' gradient output."""
 import sys
 
 import numpy as np
@@ -32,35 +38,48 @@ def _setup(vx, n_fibers, seed, lo=1, hi=6):
     return wl, pts, pd, plan, params
 
 
-def test_fit_matches_oracle(vx):
+def _compare(vx, wl, pts, pd, plan, params, elementwise=False):
     import torch
-    wl, pts, pd, plan, params = _setup(vx, 64, 14)
-    say("case: fit on plain weave 64 fibers, levels 1..6, 128 directions")
     n_ref = oracle.fit_levels(wl.grid, pts, wl.offsets, wl.radius, 6)
     assert [int(x) for x in n_ref] == plan.counts
     loss = float(plan.forward(pd, params).item())
     L_all = np.concatenate([p.cpu().numpy() for p in params]).astype(np.float64)
     o_loss, _, o_dL, o_dp = oracle.fit_eval(wl.grid, pts, pts.astype(np.float64), wl.offsets, wl.radius, 1, 6, L_all)
     say("loss", loss, o_loss)
-    assert 1e-3 < o_loss < 1e6                      # a sane starting point, not uninitialised lobes
+    assert 1e-3 < o_loss < 1e9                      # a sane starting point, not uninitialised lobes
     assert abs(loss - o_loss) <= 1e-5 * o_loss
     dpts, dparams = plan.backward(torch.ones(1, device="cuda"), params)
     plan.check()
     g_dL = np.concatenate([d.cpu().numpy() for d in dparams]).astype(np.float64)
     g_dp = dpts.cpu().numpy().astype(np.float64)
     e_L = np.linalg.norm(g_dL - o_dL) / np.linalg.norm(o_dL)
-    e_all = np.linalg.norm(g_dp - o_dp) / np.linalg.norm(o_dp)
-    # The target's sqrt(w^T S w) is singular where a voxel holds (nearly) one fiber direction and
-    # a direction of the set is nearly parallel to it; there FP32 sums cannot carry the gradient
-    # to 1e-4.  Points touching voxels whose normalised projected area squared drops below 1e-3
-    # in some direction are held to a looser bound and counted.
-    cond = oracle.fit_conditioning(wl.grid, pts, wl.offsets, wl.radius, 6)
-    keep = cond >= 1e-3
-    e_p = np.linalg.norm((g_dp - o_dp)[keep]) / np.linalg.norm(o_dp[keep])
-    say("relative gradient errors: lobes", e_L, "points (well-conditioned, %d of %d)" % (keep.sum(), len(keep)), e_p,
-        "points (all)", e_all)
-    assert keep.sum() > 0.7 * len(keep)
-    assert e_L <= 1e-4 and e_p <= 1e-4 and e_all <= 5e-3
+    e_p = np.linalg.norm(g_dp - o_dp) / np.linalg.norm(o_dp)
+    # per point, relative to the point's own gradient (floor: 1e-3 of the largest)
+    pp = np.linalg.norm(g_dp - o_dp, axis=1) / np.maximum(np.linalg.norm(o_dp, axis=1),
+                                                           1e-3 * np.linalg.norm(o_dp, axis=1).max())
+    say("relative gradient errors: lobes %.3g, points %.3g (norm over all %d); worst point %.3g"
+        % (e_L, e_p, len(g_dp), pp.max()))
+    assert e_L <= 1e-4 and e_p <= 1e-4
+    if elementwise:
+        scale = np.abs(o_dL).max()
+        bad = np.abs(g_dL - o_dL) > 1e-4 * np.abs(o_dL) + 1e-6 * scale
+        say("lobe gradient entries outside 1e-4 relative (floor 1e-6 of the largest):", int(bad.sum()), "of",
+            bad.size)
+        assert not bad.any()
+
+
+def test_fit_matches_oracle(vx):
+    wl, pts, pd, plan, params = _setup(vx, 64, 14)
+    say("case: fit on plain weave 64 fibers, levels 1..6, 128 directions")
+    _compare(vx, wl, pts, pd, plan, params)
+
+
+def test_fit_matches_oracle_full_weave(vx):
+    """The differentiable-fit workload itself: 2,000 fibers x 256 segments at 1024^3, levels 1-6."""
+    wl, pts, pd, plan, params = _setup(vx, 2000, 1)
+    say("case: fit on the full plain weave (2000 fibers), levels 1..6, 128 directions;", sum(plan.counts[1:]),
+        "fitted voxels")
+    _compare(vx, wl, pts, pd, plan, params, elementwise=True)
 
 
 def test_autograd_function_and_descent(vx):
@@ -81,3 +100,40 @@ def test_autograd_function_and_descent(vx):
     loss2 = vx.lobe_fit(plan, X.detach(), Q)
     say("loss before/after one step", float(loss), float(loss2))
     assert float(loss2) < float(loss)
+
+
+def test_backward_after_another_forward_raises(vx):
+    """Two live losses on one plan: the first one's backward must not see the second's state."""
+    wl, pts, pd, plan, params = _setup(vx, 16, 16)
+    say("case: two forwards on one plan, then the first backward")
+    P = [p.clone().requires_grad_(True) for p in params]
+    l1 = vx.lobe_fit(plan, pd, P)
+    l2 = vx.lobe_fit(plan, pd, [p * 1.01 for p in P])
+    with pytest.raises(RuntimeError):
+        l1.backward()
+    l2.backward()                                   # the latest one is still fine
+
+
+def test_moved_points_are_reported_not_faulted(vx):
+    """Points moved so that the fitted levels gain and change voxels: the parameters are bound to
+    the calibration's voxels, so the call must report an error (never read or write past the
+    parameter rows)."""
+    import torch
+    wl, pts, pd, plan, params = _setup(vx, 32, 17)
+    say("case: fit with control points moved by 2.6 voxels after calibration")
+    plan.forward(pd, params)
+    moved = pd.clone()
+    moved[:, 2] += 2.6 * wl.grid.extent / wl.grid.res     # every fiber moves up by 2.6 voxels
+    moved[::7, 1] += 3.3 * wl.grid.extent / wl.grid.res
+    with pytest.raises(vx.VxError) as e:
+        plan.forward(moved, params)
+    say("status", e.value.status)
+    assert e.value.status in (2, 6)
+    # the backward on the moved state is bounded too and reports the same
+    with pytest.raises(vx.VxError):
+        plan.backward(torch.ones(1, device="cuda"), params)
+        plan.check()
+    # and the original points still work
+    plan.forward(pd, params)
+    plan.backward(torch.ones(1, device="cuda"), params)
+    plan.check()

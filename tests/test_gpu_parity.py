@@ -77,6 +77,21 @@ def test_weave_full_sampled_regions(vx):
     assert np.allclose(g["S"][:, :3].sum(1), 2 * g["w"], rtol=1e-5, atol=1e-6)
 
 
+def test_weave_full_every_voxel_all_levels(vx):
+    """The plain weave at full size (2,000 fibers x 256 segments, 1024^3): every voxel of the leaf
+    and of all 10 levels above it against the oracle's full build (keys, counts and masks exact,
+    w and S to the 1e-5 bar), and the pair count."""
+    wl = synth.plain_weave()
+    say("case: plain weave 2000 fibers full size, every voxel of all 11 levels")
+    leaf = vx.voxelize_fibers(_dev(wl.pts), _dev(wl.offsets), wl.radius, wl.grid)
+    pyr = _levels(vx, wl.grid, leaf, wl.levels)
+    ref = oracle.voxelize_fibers(wl.grid, wl.pts, wl.offsets, wl.radius)
+    assert leaf.plan.n_pairs == ref.n_pairs
+    reps = compare_pyramid(pyr, oracle.build_lod(ref, wl.levels), "weave full")
+    say("levels:", [r["n"] for r in reps], "worst w/S:", max(r["max_rel_w"] for r in reps),
+        max(r["max_rel_S"] for r in reps))
+
+
 def test_brushed_metal_window_64bit_keys(vx):
     wl = synth.brushed_metal(n=4096, window=96)
     say("case: brushed metal 96x96 window, 4096^3 (64-bit keys), 13 levels")
