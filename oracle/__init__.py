@@ -294,7 +294,7 @@ def _fit_lib():
         L.vxo_fit_eval.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                   ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+                                   ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.vxo_voxelize_fibers_pairs.restype = ctypes.c_void_p
         L.vxo_voxelize_fibers_pairs.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
                                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
@@ -324,23 +324,31 @@ def fit_levels(grid, pts, offsets, radius, hi, nthreads=None):
     return n
 
 
-def fit_eval(grid, pts_snap, pts_cont, offsets, radius, lo, hi, L_all, grad=True, nthreads=None):
+def fit_eval(grid, pts_snap, pts_cont, offsets, radius, lo, hi, L_all, grad=True, nthreads=None, dirs=None):
     """Loss of the two-lobe fit at levels lo..hi and, with grad, d loss / d L and d loss / d points.
 
     pts_snap (float32) fixes which segment touches which voxel; pts_cont (float64) gives the
-    weights and tangents.  L_all: float64 [sum of level sizes, 12], levels lo..hi in key order."""
+    weights and tangents.  L_all: float64 [sum of level sizes, 12], levels lo..hi in key order.
+    dirs: the 128 directions [128, 3] (any float dtype, evaluated in FP64), or None for the
+    Fibonacci set computed in FP64."""
     ps = np.ascontiguousarray(np.asarray(pts_snap, dtype=np.float32).reshape(-1, 3))
     pc = np.ascontiguousarray(np.asarray(pts_cont, dtype=np.float64).reshape(-1, 3))
     o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     La = np.ascontiguousarray(np.asarray(L_all, dtype=np.float64).reshape(-1, 12))
     lv = np.zeros(La.shape[0])
+    dd = None
+    if dirs is not None:
+        dd = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        if dd.shape[0] != 128:
+            raise OracleError("fit_eval: the direction set has 128 directions")
     dL = np.zeros_like(La) if grad else None
     dp = np.zeros_like(pc) if grad else None
     st = ctypes.c_int(0)
     bmin, ext, l2 = _grid_args(grid)
     loss = _fit_lib().vxo_fit_eval(bmin, ext, l2, _ptr(ps), _ptr(pc), ps.shape[0], _ptr(o), o.shape[0] - 1,
                                    float(np.float32(radius)), int(lo), int(hi), _ptr(La), _ptr(lv),
-                                   _ptr(dL) if grad else None, _ptr(dp) if grad else None, _nthreads(nthreads),
+                                   _ptr(dL) if grad else None, _ptr(dp) if grad else None,
+                                   _ptr(dd) if dd is not None else None, _nthreads(nthreads),
                                    ctypes.byref(st))
     if st.value:
         raise OracleError(f"fit_eval failed with status {st.value}")

@@ -68,8 +68,8 @@ double clip_len(const double* A, const double* B, const double* lo, double* gA, 
   for (int a = 0; a < 3; ++a) d[a] = B[a] - A[a];
   double t0 = 0.0, t1 = 1.0;
   int e0 = -1, e1 = -1;       // axis fixing the entry / exit parameter (-1: the segment end)
+  for (int a = 0; a < 3; ++a) gA[a] = gB[a] = 0.0;     // an empty piece has no gradient
   for (int a = 0; a < 3; ++a) {
-    gA[a] = gB[a] = 0.0;
     if (d[a] == 0.0) {
       if (!(A[a] >= lo[a] && A[a] < lo[a] + 1.0)) return 0.0;
       continue;
@@ -124,10 +124,11 @@ extern "C" {
 //          of the pair set (vxo_fit_levels gives n_L).
 //   loss_vox: double, per voxel of levels lo..hi (same layout as L_all / 12), may be NULL
 //   dL: double like L_all, may be NULL;  dpts: double [m][3] (world units), may be NULL
+//   dirs: double [128][3], the direction set, or NULL for the Fibonacci set in FP64
 // Returns the total loss; *status = 0 on success.
 double vxo_fit_eval(const double* bmin, double extent, int log2R, const float* pts_snap, const double* pts_cont,
                     i64 m, const i64* offsets, i64 F, double radius, int lo, int hi, const double* L_all,
-                    double* loss_vox, double* dL, double* dpts, int nthreads, int* status) {
+                    double* loss_vox, double* dL, double* dpts, const double* dirs, int nthreads, int* status) {
   *status = 0;
   void* pr = vxo_voxelize_fibers_pairs(bmin, extent, log2R, pts_snap, m, offsets, F, radius, nthreads, status);
   if (*status) return 0.0;
@@ -200,6 +201,7 @@ double vxo_fit_eval(const double* bmin, double extent, int log2R, const float* p
   }
   // loss and gradients w.r.t. L and w.r.t. the children's (S, w)
   static const Dirs D;
+  const double* dir0 = dirs ? dirs : &D.w[0][0];
   std::vector<std::vector<double>> gS(hi + 1), gw(hi + 1);
   for (int L = 0; L <= hi; ++L) {
     gS[L].assign(P.keys[L].size() * 6, 0.0);
@@ -217,7 +219,7 @@ double vxo_fit_eval(const double* bmin, double extent, int log2R, const float* p
         const double W = P.w[L][u];
         double gl[12] = {0};
         for (int k = 0; k < NDIR; ++k) {
-          const double* o = D.w[k];
+          const double* o = dir0 + 3 * k;
           double tau = 0.0;
           for (i64 c = c0; c < c1; ++c) {
             double wc = P.w[L - 1][c];

@@ -299,3 +299,14 @@ WORKLOADS = {
     "plain_weave": plain_weave,
     "brushed_metal": brushed_metal,
 }
+
+
+def fibonacci_dirs(n: int = 128) -> np.ndarray:
+    """The fit's direction set: n Fibonacci points on the unit sphere, z = 1 - (2k+1)/n,
+    phi = k pi (3 - sqrt 5), computed in FP64 and rounded once to float32 (the values both the
+    GPU path and the oracle then evaluate with)."""
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * k + 1.0) / n
+    phi = k * (np.pi * (3.0 - np.sqrt(5.0)))
+    r = np.sqrt(1.0 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1).astype(np.float32)

@@ -194,3 +194,65 @@ def test_fit_target_over_several_children_by_hand():
     # d/dL00 of |y| = y0 wx / |y| = wx^2
     g00 = np.mean(2 * (a - tau) * W[:, 0] ** 2)
     assert abs(dL2[0, 0] - g00) <= 1e-12 * max(1.0, abs(g00))
+
+
+def test_fit_given_direction_set_by_hand():
+    """The direction set is an input: with 128 random unit directions (float32 values) the loss
+    of the three-children case above is the mean of tau^2 over those directions, and the
+    default set equals the float32-rounded Fibonacci set up to that rounding."""
+    grid = synth.Grid((0.0, 0.0, 0.0), 8.0, 3)
+    pts = np.array([[2.25, 2.5, 2.5], [3.75, 2.5, 2.5], [2.5, 3.25, 2.5], [2.5, 3.75, 2.5]], dtype=np.float32)
+    off = np.array([0, 2, 4])
+    rng = np.random.default_rng(5)
+    D = rng.normal(size=(128, 3))
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    Dd = D.astype(np.float64)
+    n2 = (Dd ** 2).sum(1)                      # float32 directions are unit length only to ~1e-8
+    tau = (0.75 * np.sqrt(n2 - Dd[:, 0] ** 2) * 2 + 0.5 * np.sqrt(n2 - Dd[:, 1] ** 2)) / 2.0
+    loss, _, _, _ = oracle.fit_eval(grid, pts, pts.astype(np.float64), off, 0.0, 1, 1, np.zeros((1, 12)), dirs=D)
+    want = np.mean(tau ** 2)
+    assert abs(loss - want) <= 1e-12 * want
+    F = synth.fibonacci_dirs(128)
+    assert np.abs(F.astype(np.float64) - oracle.fit_dirs()).max() < 1e-7
+    l_def = oracle.fit_eval(grid, pts, pts.astype(np.float64), off, 0.0, 1, 1, np.zeros((1, 12)))[0]
+    l_f32 = oracle.fit_eval(grid, pts, pts.astype(np.float64), off, 0.0, 1, 1, np.zeros((1, 12)), dirs=F)[0]
+    assert l_def != l_f32 and abs(l_def - l_f32) <= 1e-6 * l_def
+
+
+def test_fit_gradient_of_axis_parallel_segments():
+    """Segments with a coordinate held fixed (d_x = 0 or d_z = 0) whose capsule also touches the
+    neighbouring column with no centreline inside it (weight 0): such touches carry no gradient.
+    Central differences of the loss in every coordinate of every point, none near a clip kink."""
+    grid = synth.Grid((0.0, 0.0, 0.0), 8.0, 3)
+    pts = np.array([[1.3, 1.2, 3.4], [2.75, 1.9, 3.6],       # generic
+                    [2.75, 4.3, 4.1],                        # d_x = 0 at x = 2.75: touches column x = 3
+                    [2.75, 6.6, 3.45],                       # d_x = 0 again
+                    [4.2, 5.1, 3.45], [5.6, 3.3, 3.45],      # d_z = 0 at z = 3.45: touches layer z = 4
+                    [1.6, 6.2, 5.3], [2.3, 4.4, 6.2], [3.7, 2.2, 5.9]], dtype=np.float32)
+    pts = _lattice_points(grid, pts)
+    off = np.array([0, 6, 9])
+    lo, hi = 1, 2
+    L0 = _init_L(grid, pts, off, 0.5, lo, hi, 7)
+    pc = pts.astype(np.float64)
+    _, _, _, dp = oracle.fit_eval(grid, pts, pc, off, 0.5, lo, hi, L0)
+    fd = np.zeros_like(dp)
+    checked = 0
+    for i in range(len(pts)):
+        for a in range(3):
+            delta = np.zeros(3)
+            delta[a] = 1e-3
+            if _crosses(pc, i, off, grid, delta):
+                fd[i, a] = dp[i, a]
+                continue
+            def cd(step):
+                P1, P2 = pc.copy(), pc.copy()
+                P1[i, a] += step
+                P2[i, a] -= step
+                l1 = oracle.fit_eval(grid, pts, P1, off, 0.5, lo, hi, L0, grad=False)[1]
+                l2 = oracle.fit_eval(grid, pts, P2, off, 0.5, lo, hi, L0, grad=False)[1]
+                return (l1 - l2).sum() / (2 * step)
+            fd[i, a] = (4.0 * cd(5e-4) - cd(1e-3)) / 3.0
+            checked += 1
+    assert checked >= 20
+    assert np.abs(dp).max() > 0
+    assert np.abs(fd - dp).max() <= 1e-6 * np.abs(dp).max(), np.abs(fd - dp).max(axis=1)
