@@ -489,7 +489,8 @@ class FitPlan:
     (VX_ERR_CAPACITY for a changed count, VX_ERR_BINDING for changed keys); a run that outgrows the
     buffers also raises VX_ERR_CAPACITY."""
 
-    def __init__(self, grid, pts, offsets, radius, lo=1, hi=6, ndir=128, slack=1.25):
+    def __init__(self, grid, pts, offsets, radius, lo=1, hi=6, ndir=128, slack=1.25, dirs=None):
+        """dirs: the direction set [ndir, 3] (float32 values), or None for ``fit_dirs(ndir)``."""
         import torch
         self.L = load()
         self.grid, self.cgrid, self.lo, self.hi = grid, _cgrid(grid), int(lo), int(hi)
@@ -523,7 +524,13 @@ class FitPlan:
         self._rows = (ctypes.c_int64 * nfit)(*[counts[L] for L in range(self.lo, self.hi + 1)])
         self.bound_keys = [self.levels[L].keys[:max(counts[L], 1)].clone() for L in range(self.lo, self.hi + 1)]
         self._bound = (ctypes.c_void_p * nfit)(*[k.data_ptr() for k in self.bound_keys])
-        self.dirs = fit_dirs(ndir, self.pts.device)
+        if dirs is None:
+            self.dirs = fit_dirs(ndir, self.pts.device)
+        else:
+            self.dirs = torch.as_tensor(dirs, dtype=torch.float32).to(self.pts.device).reshape(-1, 3).contiguous()
+            ndir = self.dirs.shape[0]
+            if not 1 <= ndir <= 256:
+                raise VxError(1, "fit: 1 to 256 directions")
         self.ndir = int(ndir)
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.pts.device)
         self.fstats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.pts.device)

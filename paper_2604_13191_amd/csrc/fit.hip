@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_bwd(vx_voxels par, const int64_t
     const int64_t u = u0 + (grp - wgrp0);
     const bool in = u < n_par;
     const float Wf = in ? par.w[u] : 0.f;
-    const bool active = in && Wf > 0.f;
+    const bool active = in && Wf > 0.f && c64 != nullptr;   // no FP64 sums: no points, nothing to fit
     int64_t first = 0;
     int nc = 0;
     if (active) nc = child_range(cstart, u, first);
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(kBlock) k_fit_pairs(const int32_t* __restrict_
                                                       vx_voxels leaf, const int64_t* n_leaf_p,
                                                       const double* __restrict__ gleaf, int64_t gcap, int Sb,
                                                       int log2R, double vs, const int64_t* __restrict__ tfirst,
-                                                      const int64_t* __restrict__ tend, float* __restrict__ seg_grad) {
+                                                      const int64_t* __restrict__ tend, double* __restrict__ seg_grad) {
   const int64_t n_leaf = *n_leaf_p;
   const int64_t n_cand = ctl[CTL_N_CAND];
   const int64_t n_pairs = ctl[CTL_N_PAIRS];
@@ -432,17 +432,19 @@ __global__ void __launch_bounds__(kBlock) k_fit_pairs(const int32_t* __restrict_
       }
     }
     for (int a = 0; a < 3; ++a) {
-      seg_grad[p * 6 + a] = float(gA[a] * vs);
-      seg_grad[p * 6 + 3 + a] = float(gB[a] * vs);
+      seg_grad[p * 6 + a] = gA[a] * vs;
+      seg_grad[p * 6 + 3 + a] = gB[a] * vs;
     }
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fit_points(const float* __restrict__ seg_grad, int64_t n,
+// a point's gradient: its segment's start end plus the previous segment's far end, added in FP64
+// (the two nearly cancel along a straight fiber) and rounded once
+__global__ void __launch_bounds__(kBlock) k_fit_points(const double* __restrict__ seg_grad, int64_t n,
                                                        float* __restrict__ dpts) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
     for (int a = 0; a < 3; ++a)
-      dpts[i * 3 + a] = seg_grad[i * 6 + a] + (i > 0 ? seg_grad[(i - 1) * 6 + 3 + a] : 0.f);
+      dpts[i * 3 + a] = float(seg_grad[i * 6 + a] + (i > 0 ? seg_grad[(i - 1) * 6 + 3 + a] : 0.0));
 }
 
 __global__ void k_fill_f64(double* p, int64_t n, double v) {
@@ -479,12 +481,23 @@ __global__ void __launch_bounds__(kBlock) k_fit_bind(const Key* __restrict__ key
 // each leaf voxel adds its clipped lengths and moments in FP64, and every level above adds its
 // children.  Layout of a level: [7][cap] (S components xx yy zz xy xz yz, then w).
 // ---------------------------------------------------------------------------------------------
+// start has cap + 2 entries: the first pair of every key (heads past cap are dropped), the end
+// at index min(total, cap), and the number of distinct keys at index cap + 1
+struct LeafSegOut {
+  int64_t* start;
+  int64_t cap;
+  __device__ void operator()(int64_t i, int64_t ex, int64_t v) const {
+    if (v && ex <= cap) start[ex] = i;
+  }
+};
 struct LeafSegTotal {
   int64_t* start;
+  int64_t cap;
   const int64_t* n_leaf;
   int64_t* stats;
   __device__ void operator()(int64_t total, int64_t n) const {
-    start[total] = n;
+    if (total <= cap) start[total] = n;
+    start[cap + 1] = total;
     if (total != *n_leaf)
       atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)VX_FLAG_FIT_KEYS);
   }
@@ -496,7 +509,9 @@ __global__ void __launch_bounds__(kBlock) k_fit_leaf64(const Key* __restrict__ p
                                                        const Key* __restrict__ lkeys, const int64_t* n_leaf_p,
                                                        int64_t cap, int Sb, int log2R, double* __restrict__ out,
                                                        int64_t* stats) {
-  const int64_t n = *n_leaf_p < cap ? *n_leaf_p : cap;
+  // within the leaf, its capacity and the keys the pairs hold (sstart[i + 1] is written for i < n)
+  int64_t n = *n_leaf_p < cap ? *n_leaf_p : cap;
+  n = sstart[cap + 1] < n ? sstart[cap + 1] : n;
   const double inv_s = 1.0 / double(int64_t(1) << Sb);
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     const int64_t a = sstart[i], b = sstart[i + 1];
@@ -571,10 +586,10 @@ struct FitWs {
   int64_t* tend;
   float* part;             // [kGrid] block sums of the loss
   int64_t* partial;        // [kGrid + 1] scan partials
-  float* seg_grad;         // [n_pts][6]
+  double* seg_grad;        // [n_pts][6] d loss / d (segment start, segment end), world units
   FrontWs f;
   double* s64[21];         // [7][cap_L] per level 0..hi-1: FP64 sums (S, then w)
-  int64_t* sstart;         // [cap_0 + 1] first sorted pair of every leaf voxel
+  int64_t* sstart;         // [cap_0 + 2] first sorted pair of every leaf voxel, end, key count
   PairBufs pb, pc;         // sort buffers of the re-emitted pairs (a copy, then ping-pong)
   int32_t* hist;           // radix digit histograms
 };
@@ -598,10 +613,10 @@ static size_t fit_ws_layout(int64_t n_pts, int64_t max_cand, int64_t max_pairs, 
   x.tend = cv.take<int64_t>(tiles);
   x.part = cv.take<float>(kGrid);
   x.partial = cv.take<int64_t>(kGrid + 1);
-  x.seg_grad = cv.take<float>(6 * n_pts);
+  x.seg_grad = cv.take<double>(6 * n_pts);
   front_ws_carve(cv, n_pts, max_cand, max_pairs, key64, &x.f);
   for (int L = 0; L < hi; ++L) x.s64[L] = cv.take<double>(n_pts > 0 ? 7 * caps[L] : 0);
-  x.sstart = cv.take<int64_t>(n_pts > 0 ? caps[0] + 1 : 0);
+  x.sstart = cv.take<int64_t>(n_pts > 0 ? caps[0] + 2 : 0);
   const int kb = key64 ? 8 : 4;
   for (PairBufs* pbuf : {&x.pb, &x.pc}) {
     pbuf->keys = cv.take<uint8_t>(max_pairs * kb);
@@ -697,8 +712,8 @@ static void level_sums64(const vx_grid* g, const vx_voxels* levels, const int64_
   const int res = radix_sort_pairs(kb == 8, 3 * g->log2_res, w.pc, w.pb, w.f.ctl + CTL_N_PAIRS, 0, w.hist,
                                    w.partial, s);
   const PairBufs P = res ? w.pb : w.pc;
-  device_scan(HeadIn<Key, 0>{(const Key*)P.keys}, HeadOut{w.sstart}, LeafSegTotal{w.sstart, n_levels, stats},
-              w.f.ctl + CTL_N_PAIRS, 0, w.partial, s);
+  device_scan(HeadIn<Key, 0>{(const Key*)P.keys}, LeafSegOut{w.sstart, caps[0]},
+              LeafSegTotal{w.sstart, caps[0], n_levels, stats}, w.f.ctl + CTL_N_PAIRS, 0, w.partial, s);
   const Lat lat = make_lat(g, 1, 0.0f);
   hipLaunchKernelGGL(k_fit_leaf64<Key>, dim3(kGrid), dim3(kBlock), 0, s, (const Key*)P.keys, P.prim, w.sstart,
                      w.f.rec, (const Key*)levels[0].keys, n_levels, caps[0], lat.Sb, g->log2_res, w.s64[0], stats);
@@ -723,19 +738,22 @@ vx_status fit_backward_run(const vx_grid* g, const float* pts, int64_t n_pts, co
   if (key64) bind_check<uint64_t>(levels, n_levels, lo, hi, rows, bound, stats, s);
   else bind_check<uint32_t>(levels, n_levels, lo, hi, rows, bound, stats, s);
   child_starts(key64, levels, n_levels, hi, w, s);
-  if (key64) level_sums64<uint64_t>(g, levels, n_levels, hi, w, caps, stats, s);
-  else level_sums64<uint32_t>(g, levels, n_levels, hi, w, caps, stats, s);
+  // (no points: every level is empty and the FP64 sums, sized by the points, are not read)
+  if (n_pts > 0) {
+    if (key64) level_sums64<uint64_t>(g, levels, n_levels, hi, w, caps, stats, s);
+    else level_sums64<uint32_t>(g, levels, n_levels, hi, w, caps, stats, s);
+  }
   // lobe gradients and the children's (S, w) gradients, level by level
   for (int L = lo; L <= hi; ++L) {
     VX_TIMED("fit_bwd", s);
     if (ndir <= 128)
       hipLaunchKernelGGL(k_fit_bwd<8>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, rows[L - lo],
-                         w.s64[L - 1], caps[L - 1], w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo],
-                         w.g[L - 1], caps[L - 1]);
+                         n_pts > 0 ? w.s64[L - 1] : nullptr, caps[L - 1], w.cstart[L], params[L - lo], dirs, ndir,
+                         dloss, dparams[L - lo], w.g[L - 1], caps[L - 1]);
     else
       hipLaunchKernelGGL(k_fit_bwd<16>, dim3(kGrid), dim3(kBlock), 0, s, levels[L], n_levels + L, rows[L - lo],
-                         w.s64[L - 1], caps[L - 1], w.cstart[L], params[L - lo], dirs, ndir, dloss, dparams[L - lo],
-                         w.g[L - 1], caps[L - 1]);
+                         n_pts > 0 ? w.s64[L - 1] : nullptr, caps[L - 1], w.cstart[L], params[L - lo], dirs, ndir,
+                         dloss, dparams[L - lo], w.g[L - 1], caps[L - 1]);
   }
   // top-down accumulation to the leaf
   for (int L = hi - 2; L >= 0; --L) {

@@ -11,25 +11,29 @@ import bench  # noqa: E402
 
 
 def _counts(kb=4):
-    return {"key_bytes": kb, "n_pairs": 1000, "n_cand": 1700, "n_prims": 500, "n_vox": 400, "n_fib": 10,
-            "n_records": 300, "n_units": 20}
+    return {"key_bytes": kb, "n_pairs": 1000, "n_cand": 1700, "n_prims": 500, "levels": [400, 60, 8, 1],
+            "n_records": 300, "n_units": 20, "input_bytes": 36 * 500}
 
 
 def test_byte_model_counts_each_array_once():
     c = _counts()
-    # unit kernel: per record id + record + direction, per voxel key + count + w + S, per unit 32
-    assert bench.kernel_bytes("unit_fib", c) == (4 + 64 + 16) * 300 + (4 + 32) * 400 + 32 * 20
-    assert bench.kernel_bytes("unit_fib", _counts(8)) == (4 + 64 + 16) * 300 + (8 + 32) * 400 + 32 * 20
+    # unit kernel: per primitive its direction (12), per pair emit + sort exchange + reduce read
+    # (4 x 12 bytes with 32-bit keys), per leaf voxel key + count + w + S written once
+    assert bench.kernel_bytes("unit_fib", c) == 12 * 500 + 4 * 12 * 1000 + (4 + 32) * 400
+    c8 = _counts(8)
+    assert bench.kernel_bytes("unit_tri", c8) == 12 * 500 + 4 * 16 * 1000 + (8 + 32) * 400
     # the compaction reads and writes each voxel once
-    assert bench.kernel_bytes("unit_compact", c) == 2 * (4 + 32) * 400 + 24 * 20
+    assert bench.kernel_bytes("unit_compact", c) == 2 * (4 + 32) * 400
     assert bench.kernel_bytes("no_such_kernel", c) is None
 
 
-def test_flop_model_is_linear_in_candidates_and_pairs():
+def test_step_bytes_follow_the_level_records():
     c = _counts()
-    f = bench.kernel_flops("unit_fib", c)
-    c2 = dict(c, n_cand=2 * c["n_cand"], n_pairs=2 * c["n_pairs"])
-    assert f > 0 and bench.kernel_flops("unit_fib", c2) == 2 * f
+    body = 36 * 500 + 12 * 500 + 4 * 12 * 1000
+    # leaf: key + count + w + S (4 + 4 + 4 + 24 bytes); K = 1 above it: key + mask word + w + S
+    assert bench.step_bytes(c, 1) == body + 2 * (4 + 4 + 4 + 24) * 400 + 2 * (4 + 4 + 28) * 69
+    # K = 4: the one-lobe sums plus four lobes of 28 bytes each
+    assert bench.step_bytes(c, 4) == body + 2 * (4 + 4 + 4 + 24) * 400 + 2 * (4 + 4 + 28 * 5) * 69
 
 
 def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
@@ -41,10 +45,11 @@ def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch
     # the digest covers the HIP sources of the repository; the table is read from ROOT/profiles
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "source_digest", lambda: table["source_digest"])
-    assert bench.traffic_bytes("unit_fib") == 150
-    assert bench.traffic_bytes("unit_compact") is None
+    assert bench.traffic_bytes("plain_weave", "unit_fib") == 150
+    assert bench.traffic_bytes("plain_weave", "unit_compact") is None
+    assert bench.traffic_bytes("brushed_metal", "unit_fib") is None
     monkeypatch.setattr(bench, "source_digest", lambda: "0" * 16)
-    assert bench.traffic_bytes("unit_fib") is None
+    assert bench.traffic_bytes("plain_weave", "unit_fib") is None
 
 
 def test_tuner_table_round_trip(tmp_path, monkeypatch):
