@@ -31,7 +31,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "vxo.cpp"), os.path.join(_HERE, "vxo_fit.cpp")]
-_LIB = os.path.join(_HERE, "libvxo.so")
+# VXO_SANITIZE=1: a separate build under AddressSanitizer and UndefinedBehaviorSanitizer (load it
+# with libasan preloaded; tests/test_oracle_sanitized.py does)
+_SAN = os.environ.get("VXO_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libvxo_san.so" if _SAN else "libvxo.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 _lib = None
 
 _c_i64p = ctypes.POINTER(ctypes.c_int64)
@@ -43,7 +47,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC",
-                               "-pthread"] + _SRCS + ["-o", tmp])
+                               "-pthread"] + (_SAN_FLAGS if _SAN else []) + _SRCS + ["-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
