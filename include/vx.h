@@ -167,6 +167,23 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
                        int64_t* n_levels, void* workspace, size_t ws_bytes, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
+ * vx_build_lod without a workspace, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as vx_build_lod; its scratch (the parent starts and scan partials) lives in
+ * a library-owned device array of (VX_LOD_NOALLOC_MAX_LEAF + 1026) int64 (64 MiB) that each GPU
+ * the library runs on holds until the process ends.  The call allocates nothing and frees
+ * nothing.  leaf->cap above VX_LOD_NOALLOC_MAX_LEAF returns VX_ERR_CAPACITY before any launch.
+ * Every call on one GPU shares that GPU's array and it keeps the last call's contents (nothing
+ * in it needs to start at zero): calls that overlap on one GPU (other streams or threads)
+ * race and must be serialised by the caller.
+ * ------------------------------------------------------------------------------------------ */
+#define VX_LOD_NOALLOC_MAX_LEAF 8388608
+
+vx_status vx_build_lod_noalloc(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels,
+                               int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
+                               int64_t* n_levels, vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
  * Differentiable two-lobe fit (extension; the projected area of an SGGX lobe is Sec. 4.1's
  * sigma(omega) = sqrt(omega^T S omega)).
  *

@@ -26,6 +26,7 @@ STAT_CAND, STAT_PAIRS, STAT_VOXELS, STAT_FLAGS, STAT_RECORDS, STAT_UNITS = range
 FLAG_CAND_CAPACITY, FLAG_PAIR_CAPACITY, FLAG_VOXEL_CAPACITY, FLAG_INPUT, FLAG_OFFSETS = 1, 2, 4, 8, 16
 FLAG_RECORD_CAPACITY, FLAG_UNIT_CAPACITY = 32, 64
 FLAG_FIT_ROWS, FLAG_FIT_KEYS = 128, 256
+NOALLOC_MAX_LEAF = 8388608          # leaf capacity limit of vx_build_lod_noalloc
 STATUS = {0: "ok", 1: "invalid argument", 2: "capacity exceeded", 3: "HIP runtime error",
           4: "non-finite or out-of-range input, or invalid fiber offsets", 5: "bad workspace",
           6: "fit parameters bound to other voxels than the level holds"}
@@ -88,6 +89,9 @@ def load():
     L.vx_build_lod.restype = ctypes.c_int
     L.vx_build_lod.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, i32,
                                ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp, sz, vp]
+    L.vx_build_lod_noalloc.restype = ctypes.c_int
+    L.vx_build_lod_noalloc.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, i32,
+                                       ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp]
     L.vx_check_stats.restype = ctypes.c_int
     L.vx_check_stats.argtypes = [vp, vp]
     L.vx_status_str.restype = ctypes.c_char_p
@@ -319,7 +323,9 @@ class Lobes:
 class LodPlan:
     """Per-level output buffers for build_lod; level caps default to the leaf's count."""
 
-    def __init__(self, grid, leaf: Voxels, n_leaf_dev, levels, K=1, iters=2, caps=None):
+    def __init__(self, grid, leaf: Voxels, n_leaf_dev, levels, K=1, iters=2, caps=None, noalloc=False):
+        """noalloc: run vx_build_lod_noalloc (the library's own scratch, no workspace tensor;
+        leaf caps up to NOALLOC_MAX_LEAF; calls on one GPU must not overlap)."""
         import torch
         self.L = load()
         self.grid, self.cgrid = grid, _cgrid(grid)
@@ -339,17 +345,25 @@ class LodPlan:
             self._clobes = (CLobes * max(1, len(self.lobes)))(*[lb.cstruct() for lb in self.lobes])
         self._cleaf = leaf.cstruct()
         self.n_levels = torch.zeros(self.levels + 1, dtype=torch.int64, device=dev)
-        nb = self.L.vx_lod_workspace_size(leaf.cap, self.levels, self.K)
-        if nb == 0:
-            raise VxError(1, "vx_lod_workspace_size")
-        self.ws = _ws(nb, dev)
+        self.noalloc = bool(noalloc)
+        self.ws = None
+        if not self.noalloc:
+            nb = self.L.vx_lod_workspace_size(leaf.cap, self.levels, self.K)
+            if nb == 0:
+                raise VxError(1, "vx_lod_workspace_size")
+            self.ws = _ws(nb, dev)
 
     def run(self, stream=None):
-        st = self.L.vx_build_lod(ctypes.byref(self.cgrid), ctypes.byref(self._cleaf), _ptr(self.n_leaf_dev),
-                                 self.levels, self.K, self.iters, self._cout, self._clobes, _ptr(self.n_levels),
-                                 _ptr(self.ws), self.ws.numel(), _stream(stream))
+        if self.noalloc:
+            st = self.L.vx_build_lod_noalloc(ctypes.byref(self.cgrid), ctypes.byref(self._cleaf),
+                                             _ptr(self.n_leaf_dev), self.levels, self.K, self.iters, self._cout,
+                                             self._clobes, _ptr(self.n_levels), _stream(stream))
+        else:
+            st = self.L.vx_build_lod(ctypes.byref(self.cgrid), ctypes.byref(self._cleaf), _ptr(self.n_leaf_dev),
+                                     self.levels, self.K, self.iters, self._cout, self._clobes, _ptr(self.n_levels),
+                                     _ptr(self.ws), self.ws.numel(), _stream(stream))
         if st != 0:
-            raise VxError(st, "build_lod")
+            raise VxError(st, "build_lod_noalloc" if self.noalloc else "build_lod")
         return self
 
     def check(self):

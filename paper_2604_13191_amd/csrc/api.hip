@@ -182,9 +182,12 @@ size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K) {
   return cv.off + 256;
 }
 
-vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
-                       int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, int64_t* n_levels,
-                       void* ws, size_t ws_bytes, vx_stream stream) {
+}  // extern "C"
+
+namespace {
+
+vx_status lod_args(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
+                   int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, const int64_t* n_levels) {
   if (!grid_ok(grid) || !voxels_ok(leaf, false) || !n_leaf || !n_levels || levels < 1 ||
       levels > grid->log2_res + 1 || K < 1 || K > 8 || kmeans_iters < 0)
     return VX_ERR_ARG;
@@ -197,12 +200,15 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
       if (!lb.nl || !lb.w || !lb.S || lb.cap < out[L - 1].cap) return VX_ERR_ARG;
     }
   }
-  if (!ws_ok(ws, ws_bytes, vx_lod_workspace_size(leaf->cap, levels, K))) return VX_ERR_WORKSPACE;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return VX_OK;
+}
+
+// the pyramid on the caller's stream; pstart [leaf->cap + 1] and partial [kGrid + 1] are scratch
+// that every kernel writes before it reads (no clearing needed)
+vx_status lod_run(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
+                  int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, int64_t* n_levels,
+                  int64_t* pstart, int64_t* partial, hipStream_t s) {
   const bool key64 = grid->log2_res > 10;
-  Carver cv(ws);
-  int64_t* pstart = cv.take<int64_t>(leaf->cap + 1);
-  int64_t* partial = cv.take<int64_t>(kGrid + 1);
   lod_init(n_leaf, leaf->cap, n_levels, int64_t(levels) + 1, s);
   int L = 1;
   for (; L < levels; ++L) {
@@ -230,6 +236,60 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
     lod_tail(key64, false, lv, nl, levels - L, n_levels + levels, s);
   }
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;
+}
+
+// Scratch of the allocation-free pyramid entry point: parent starts of a leaf of up to
+// VX_LOD_NOALLOC_MAX_LEAF voxels, then the scan partials.  Each GPU holds its own copy for the
+// life of the process; its device address is looked up once per device (the array's name is a
+// host-side stand-in and never reaches a kernel).
+constexpr int64_t kNoAllocWords = VX_LOD_NOALLOC_MAX_LEAF + 1 + (kGrid + 1);
+static __device__ __align__(256) int64_t scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t* g_scratch_ptr[kMaxDevices] = {};
+
+vx_status scratch_for_current_device(int64_t** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return VX_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return VX_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<int64_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return VX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
+                       int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, int64_t* n_levels,
+                       void* ws, size_t ws_bytes, vx_stream stream) {
+  const vx_status st = lod_args(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels);
+  if (st != VX_OK) return st;
+  if (!ws_ok(ws, ws_bytes, vx_lod_workspace_size(leaf->cap, levels, K))) return VX_ERR_WORKSPACE;
+  Carver cv(ws);
+  int64_t* pstart = cv.take<int64_t>(leaf->cap + 1);
+  int64_t* partial = cv.take<int64_t>(kGrid + 1);
+  return lod_run(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels, pstart, partial,
+                 reinterpret_cast<hipStream_t>(stream));
+}
+
+vx_status vx_build_lod_noalloc(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels,
+                               int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
+                               int64_t* n_levels, vx_stream stream) {
+  const vx_status st = lod_args(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels);
+  if (st != VX_OK) return st;
+  if (leaf->cap > VX_LOD_NOALLOC_MAX_LEAF) return VX_ERR_CAPACITY;
+  int64_t* base = nullptr;
+  const vx_status sst = scratch_for_current_device(&base);
+  if (sst != VX_OK) return sst;
+  return lod_run(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels, base,
+                 base + VX_LOD_NOALLOC_MAX_LEAF + 1, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int32_t hi,
