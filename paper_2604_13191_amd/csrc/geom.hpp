@@ -43,6 +43,16 @@ constexpr int kRec = 16;
 VX_HD inline int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
 VX_HD inline int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
 VX_HD inline int64_t floor_shift(int64_t a, int Sb) { return a >> Sb; }
+// 1 / x to a few ulp: the hardware estimate refined by two Newton steps on the device
+VX_HD inline double rcp_fast(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+#else
+  return 1.0 / x;
+#endif
+}
 VX_HD inline int64_t ceil_shift(int64_t a, int Sb) { return -((-a) >> Sb); }
 
 // Sec. 3.1: P_volume = (P - bmin) / extent * R, on the lattice; false for non-finite or
@@ -533,101 +543,251 @@ VX_HD inline Lat make_lat(const vx_grid* g, int kind, float radius) {
 // Area of the triangle inside [v, v+1)^3 (voxel^2), in registers.
 //
 // In the triangle's barycentric plane (l1, l2) -- the point q0 + l1 (q1 - q0) + l2 (q2 - q0) --
-// the piece is the convex polygon cut out by nine half-planes h(l) = alpha + beta l1 + gamma l2
-// >= 0: the triangle's three (l1 >= 0, l2 >= 0, 1 - l1 - l2 >= 0) and, for every axis a, the
-// box's two (x_a >= 0, s - x_a >= 0 with x_a in lattice units relative to the voxel corner).
-// Its area is half the sum over its edges of the cross product of the edge's end points
-// (Green's theorem).  Every half-plane's line carries at most one edge: the line walked with the
-// inside on its left, entered where the last half-plane turning from outside to inside crosses
-// it and left where the first one turning from inside to outside does.  The two lines through
-// the origin (l1 = 0, l2 = 0) contribute nothing to the sum; they only clip.
+// the piece is the convex polygon cut out by half-planes h(l) = a + b l1 + g l2 >= 0: the
+// triangle's three (l1 >= 0, l2 >= 0, 1 - l1 - l2 >= 0) and the box's, x >= 0 and s - x >= 0 for
+// every axis (x in lattice units from the voxel corner).  A box half-plane that holds on the
+// whole (closed) triangle clips nothing and is left out; one that no point passes strictly
+// empties the piece.  By Green's theorem the area is half the sum over the polygon's edges of
+// the cross products of their end points, and each line carries at most one edge: walked in
+// direction (g, -b), inside on the left, from the foot P = -a (b, g) / n of the origin
+// (n = b^2 + g^2), its edge runs from the last constraint turning inside (D > 0) to the first
+// turning outside (D < 0), D = g_j . (g, -b), and contributes cross(P_e, P_x) = a (t_x - t_e).
+// The two lines through the origin (l1 = 0, l2 = 0) contribute nothing; they only bound.
 //
-// All coefficients are lattice integers below 2^25 in magnitude, so the intersection of two
-// lines, by Cramer's rule N1 / D, N2 / D, has exact numerators and denominator (two products
-// each) and one rounding; both lines of a vertex compute it alike, so the edges share their end
-// points.  Half-planes that hold on the whole triangle are dropped (they cut nothing), one that
-// no triangle point passes strictly makes the piece empty.  Parallel lines are decided exactly:
-// an outside one empties the line, a coincident one with the same inside gives the edge to the
-// lower-numbered line, one with the opposite inside flattens the piece to a segment (area 0).
-// A triangle flat on axis a has no line on a: it lies in one layer [k, k+1) of that axis or none.
-VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float area2) {
-  if (!(area2 > 0.0f)) return 0.0f;
-  const int64_t s = int64_t(1) << Sb;
-  double al[9], be[9], ga[9];
-  al[0] = 0.0; be[0] = 1.0; ga[0] = 0.0;       // l1 >= 0
-  al[1] = 0.0; be[1] = 0.0; ga[1] = 1.0;       // l2 >= 0
-  al[2] = 1.0; be[2] = -1.0; ga[2] = -1.0;     // 1 - l1 - l2 >= 0
-  unsigned act = 7u;
+// Line intersections come from Cramer's rule with exact numerators and denominators (lattice
+// integers below 2^25: products below 2^52).  Each pair of lines is visited once and bounds both
+// of its lines; the best bounds are chosen on quotients from a refined reciprocal, and the
+// chosen ones are then divided exactly (one rounding, the same for every pair of lines through
+// one point), so a piece that degenerates to a point or a segment closes exactly and has area 0.
+// A line is parametrised by the coordinate (l1 or l2) that changes more along it.  Parallel
+// lines are decided exactly: an outside one removes the line, a coincident one with the same
+// inside keeps the edge on one line only, one with the opposite inside flattens the piece (area
+// 0).  A triangle flat on an axis has no lines on it: it lies in one layer [k, k+1) or in none.
+//
+// The fast form holds each axis's active lines as one primary line and, for one axis only, a
+// second: when the triangle crosses both box planes of two axes, the exact routine below takes
+// the piece.
+struct AreaLine {
+  double a, b, g;      // h(l) = a + b l1 + g l2
+  bool on;
+  bool dead;
+  bool use_x;          // parameter: l1 (else l2)
+  double sig;          // +-1: the parameter grows with t
+  double qe, ne, de;   // entry bound: approximate value, exact numerator and denominator
+  double qx, nx, dx;   // exit bound
+};
+
+VX_HD inline void area_line_init(AreaLine& L, double a, double b, double g, bool on) {
+  L.a = a;
+  L.b = b;
+  L.g = g;
+  L.on = on;
+  L.dead = false;
+  L.use_x = fabs(g) >= fabs(b);
+  L.sig = L.use_x ? (g > 0.0 ? 1.0 : -1.0) : (b > 0.0 ? -1.0 : 1.0);
+  L.qe = -INFINITY;
+  L.ne = 0.0;
+  L.de = 0.0;
+  L.qx = INFINITY;
+  L.nx = 0.0;
+  L.dx = 0.0;
+}
+
+// the sign of line j's half-plane along line k when the two are parallel (exact)
+VX_HD inline double parallel_side(const AreaLine& J, const AreaLine& K) {
+  const double N1 = fma(K.a, J.g, -(J.a * K.g));
+  const double N2 = fma(J.a, K.b, -(K.a * J.b));
+  return K.b != 0.0 ? (K.b > 0.0 ? N2 : -N2) : (K.g > 0.0 ? -N1 : N1);
+}
+
+// lines j (index ij) and k (index ik > ij) bound each other; UJ: line j contributes an edge
+template <bool UJ>
+VX_HD inline void area_pair(AreaLine& J, AreaLine& K, int ij, int ik, bool& flat) {
+  if (!(J.on && K.on)) return;
+  const double D = fma(J.b, K.g, -(J.g * K.b));           // exact
+  if (D == 0.0) {
+    const double sk = parallel_side(J, K), sj = parallel_side(K, J);
+    if (sk < 0.0) K.dead = true;
+    if (sj < 0.0) J.dead = true;
+    if (sk == 0.0) {                                      // coincident
+      if (fma(J.b, K.b, J.g * K.g) < 0.0) flat = true;
+      if (ij < ik) K.dead = true;
+    }
+    return;
+  }
+  const double N1 = fma(K.a, J.g, -(J.a * K.g));          // intersection (N1 / D, N2 / D), exact
+  const double N2 = fma(J.a, K.b, -(K.a * J.b));
+  const double r = rcp_fast(D);
+  {
+    const double n = K.use_x ? N1 : N2;
+    const double q = K.sig * n * r;
+    if (D > 0.0) {
+      if (q > K.qe) { K.qe = q; K.ne = n; K.de = D; }
+    } else {
+      if (q < K.qx) { K.qx = q; K.nx = n; K.dx = D; }
+    }
+  }
+  if (UJ) {
+    const double n = J.use_x ? N1 : N2;
+    const double q = J.sig * n * r;
+    if (D < 0.0) {
+      if (q > J.qe) { J.qe = q; J.ne = n; J.de = D; }
+    } else {
+      if (q < J.qx) { J.qx = q; J.nx = n; J.dx = D; }
+    }
+  }
+}
+
+// the edge of line L: its cross-product term a (t_x - t_e)
+VX_HD inline double area_edge(const AreaLine& L) {
+  if (!L.on || L.dead || L.de == 0.0 || L.dx == 0.0) return 0.0;
+  const double ue = L.ne / L.de, ux = L.nx / L.dx;        // exact quotients, one rounding
+  const double d = L.sig * (ux - ue);
+  if (!(d > 0.0)) return 0.0;
+  return L.a * d * rcp_fast(L.use_x ? fabs(L.g) : fabs(L.b));
+}
+
+// the piece's area in barycentric units (the whole triangle has 1/2), or -1 when the exact
+// routine must take it
+VX_HD inline double tri_area_bary(const int32_t* q, const int64_t v[3], int Sb) {
+  const int32_t s = int32_t(1) << Sb;
+  const double ds = double(s);
+  AreaLine T0, T1, T2, P0, P1, P2, SC;
+  AreaLine* P[3] = {&P0, &P1, &P2};
+  area_line_init(T0, 0.0, 1.0, 0.0, true);       // l1 >= 0
+  area_line_init(T1, 0.0, 0.0, 1.0, true);       // l2 >= 0
+  area_line_init(T2, 1.0, -1.0, -1.0, true);     // 1 - l1 - l2 >= 0
+  area_line_init(SC, 0.0, 0.0, 0.0, false);
+  bool second = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int32_t c0 = q[a] - (int32_t(v[a]) << Sb);
-    const int32_t d0 = q[3 + a] - q[a];
-    const int32_t d1 = q[6 + a] - q[a];
-    al[3 + 2 * a] = double(c0);
-    be[3 + 2 * a] = double(d0);
-    ga[3 + 2 * a] = double(d1);
-    al[4 + 2 * a] = double(int32_t(s) - c0);
-    be[4 + 2 * a] = double(-d0);
-    ga[4 + 2 * a] = double(-d1);
-    if (d0 == 0 && d1 == 0) {
-      if (!(c0 >= 0 && c0 < int32_t(s))) return 0.0f;   // flat on axis a, owned by another layer
+    const int32_t e0 = q[3 + a] - q[a];
+    const int32_t e1 = q[6 + a] - q[a];
+    const double c = double(c0), d0 = double(e0), d1 = double(e1);
+    if (e0 == 0 && e1 == 0) {
+      if (!(c0 >= 0 && c0 < s)) return 0.0;     // flat on axis a, owned by another layer
+      area_line_init(*P[a], 0.0, 0.0, 0.0, false);
       continue;
     }
-#pragma unroll
+    // the two box half-planes of this axis at the vertices (0, 0), (1, 0), (0, 1), exact
+    const double l0 = c, l1 = c + d0, l2 = c + d1;
+    const double u0 = ds - c, u1 = u0 - d0, u2 = u0 - d1;
+    if (fmax(l0, fmax(l1, l2)) <= 0.0 || fmax(u0, fmax(u1, u2)) <= 0.0) return 0.0;
+    const bool lo = fmin(l0, fmin(l1, l2)) < 0.0, hi = fmin(u0, fmin(u1, u2)) < 0.0;
+    if (lo && hi) {
+      if (second) return -1.0;                   // two axes crossed through: the exact routine
+      second = true;
+      area_line_init(SC, u0, -d0, -d1, true);
+    }
+    if (lo) area_line_init(*P[a], c, d0, d1, true);
+    else area_line_init(*P[a], u0, -d0, -d1, hi);
+  }
+  bool flat = false;
+  area_pair<false>(T0, T2, 0, 2, flat);
+  area_pair<false>(T0, P0, 0, 3, flat);
+  area_pair<false>(T0, P1, 0, 4, flat);
+  area_pair<false>(T0, P2, 0, 5, flat);
+  area_pair<false>(T0, SC, 0, 6, flat);
+  area_pair<false>(T1, T2, 1, 2, flat);
+  area_pair<false>(T1, P0, 1, 3, flat);
+  area_pair<false>(T1, P1, 1, 4, flat);
+  area_pair<false>(T1, P2, 1, 5, flat);
+  area_pair<false>(T1, SC, 1, 6, flat);
+  area_pair<true>(T2, P0, 2, 3, flat);
+  area_pair<true>(T2, P1, 2, 4, flat);
+  area_pair<true>(T2, P2, 2, 5, flat);
+  area_pair<true>(T2, SC, 2, 6, flat);
+  area_pair<true>(P0, P1, 3, 4, flat);
+  area_pair<true>(P0, P2, 3, 5, flat);
+  area_pair<true>(P1, P2, 4, 5, flat);
+  area_pair<true>(P0, SC, 3, 6, flat);
+  area_pair<true>(P1, SC, 4, 6, flat);
+  area_pair<true>(P2, SC, 5, 6, flat);
+  if (flat) return 0.0;
+  const double sum = area_edge(T2) + area_edge(P0) + area_edge(P1) + area_edge(P2) + area_edge(SC);
+  return 0.5 * fabs(sum);
+}
+
+// The same area with exactly computed line intersections (Cramer's rule with exact numerators and
+// denominators, one rounding each; both lines of a vertex compute it alike, so a degenerate
+// piece closes exactly and has area 0): one line at a time against all the others.
+VX_HD inline __attribute__((noinline)) double tri_area_exact(const int32_t* q, int64_t v0, int64_t v1, int64_t v2,
+                                                             int Sb) {
+  const int64_t v[3] = {v0, v1, v2};
+  const int32_t s = int32_t(1) << Sb;
+  const double ds = double(s);
+  double al[9], be[9], ga[9];
+  al[0] = 0.0; be[0] = 1.0; ga[0] = 0.0;
+  al[1] = 0.0; be[1] = 0.0; ga[1] = 1.0;
+  al[2] = 1.0; be[2] = -1.0; ga[2] = -1.0;
+  unsigned act = 7u;
+  for (int a = 0; a < 3; ++a) {
+    const int32_t c0 = q[a] - (int32_t(v[a]) << Sb);
+    const int32_t e0 = q[3 + a] - q[a];
+    const int32_t e1 = q[6 + a] - q[a];
+    al[3 + 2 * a] = double(c0);
+    be[3 + 2 * a] = double(e0);
+    ga[3 + 2 * a] = double(e1);
+    al[4 + 2 * a] = ds - double(c0);
+    be[4 + 2 * a] = -double(e0);
+    ga[4 + 2 * a] = -double(e1);
+    if (e0 == 0 && e1 == 0) {
+      if (!(c0 >= 0 && c0 < s)) return 0.0;
+      continue;
+    }
     for (int side = 0; side < 2; ++side) {
       const int k = 3 + 2 * a + side;
-      // h at the three vertices (0, 0), (1, 0), (0, 1)
       const double h0 = al[k], h1 = al[k] + be[k], h2 = al[k] + ga[k];
-      if (fmax(h0, fmax(h1, h2)) <= 0.0) return 0.0f;   // no point of the triangle strictly inside
+      if (fmax(h0, fmax(h1, h2)) <= 0.0) return 0.0;
       if (fmin(h0, fmin(h1, h2)) <= 0.0) act |= 1u << k;
     }
   }
   double sum = 0.0;
-#pragma unroll
   for (int k = 2; k < 9; ++k) {
     if (!((act >> k) & 1u)) continue;
     const double ak = al[k], bk = be[k], gk = ga[k];
-    const double nk = fma(bk, bk, gk * gk);              // |g_k|^2
-    // best entry (largest t) and exit (smallest t) as fractions T / D with D > 0 resp. D < 0;
-    // t = T / D is the position along the line, direction (gk, -bk); the comparisons multiply
-    // out the denominators (positive for two entries, both negative for two exits)
+    const double nk = fma(bk, bk, gk * gk);
     double Te = -1.0, De = 0.0, N1e = 0.0, N2e = 0.0;    // De = 0: no entry bound yet
     double Tx = 1.0, Dx = 0.0, N1x = 0.0, N2x = 0.0;
     bool dead = false;
-#pragma unroll
     for (int j = 0; j < 9; ++j) {
       if (j == k || !((act >> j) & 1u)) continue;
-      const double D = fma(be[j], gk, -(ga[j] * bk));    // g_j . (gk, -bk), exact
-      const double N1 = fma(ak, ga[j], -(al[j] * gk));   // exact
-      const double N2 = fma(al[j], bk, -(ak * be[j]));   // exact
+      const double D = fma(be[j], gk, -(ga[j] * bk));
+      const double N1 = fma(ak, ga[j], -(al[j] * gk));
+      const double N2 = fma(al[j], bk, -(ak * be[j]));
+      const double dot = fma(be[j], bk, ga[j] * gk);
       if (D == 0.0) {
-        // parallel: the sign of h_j on line k, from one nonzero component of g_k (exact)
         const double hs = bk != 0.0 ? (bk > 0.0 ? N2 : -N2) : (gk > 0.0 ? -N1 : N1);
-        const double same = fma(be[j], bk, ga[j] * gk);   // g_j . g_k
         if (hs < 0.0) dead = true;
         else if (hs == 0.0) {
-          if (same < 0.0) return 0.0f;                     // the piece lies on one line
-          if (j < k) dead = true;                          // the edge belongs to line j
+          if (dot < 0.0) return 0.0;
+          if (j < k) dead = true;
         }
         continue;
       }
-      const double dot = fma(be[j], bk, ga[j] * gk);
-      const double T = fma(ak, dot, -(al[j] * nk));       // t = T / D
+      const double T = fma(ak, dot, -(al[j] * nk));
       if (D > 0.0) {
         if (De == 0.0 || T * De > Te * D) { Te = T; De = D; N1e = N1; N2e = N2; }
       } else {
         if (Dx == 0.0 || T * Dx < Tx * D) { Tx = T; Dx = D; N1x = N1; N2x = N2; }
       }
     }
-    // every line is bounded on both sides by the triangle's own lines, so De, Dx != 0 here
     if (dead || De == 0.0 || Dx == 0.0) continue;
-    const double ie = 1.0 / De, ix = 1.0 / Dx;
-    const double xe = N1e * ie, ye = N2e * ie, xx = N1x * ix, yx = N2x * ix;
+    const double xe = N1e / De, ye = N2e / De, xx = N1x / Dx, yx = N2x / Dx;
     const double te = fma(gk, xe, -(bk * ye)), tx = fma(gk, xx, -(bk * yx));
     if (!(tx > te)) continue;
     sum += fma(xe, yx, -(ye * xx));
   }
-  return float(0.5 * fabs(sum) * double(area2));
+  return 0.5 * fabs(sum);
+}
+
+// area of the triangle inside [v, v+1)^3 in voxel^2 (area2: twice the triangle's area)
+VX_HD inline float tri_area(const int32_t* q, const int64_t v[3], int Sb, float area2) {
+  if (!(area2 > 0.0f)) return 0.0f;
+  double a = tri_area_bary(q, v, Sb);
+  if (a < 0.0) a = tri_area_exact(q, v[0], v[1], v[2], Sb);
+  return float(a * double(area2));
 }
 
 }  // namespace vx

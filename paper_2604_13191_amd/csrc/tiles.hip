@@ -480,6 +480,14 @@ __device__ __forceinline__ float unit_weight(const int32_t* r, const int64_t v[3
   if (KIND == 0) return tri_area(r, v, Lp.Sb, len);
   return seg_length(r, v, Lp.Sb, len);
 }
+// the same, out of line: the rare streaming path keeps no second copy of the weight code
+template <int KIND>
+__device__ __attribute__((noinline)) float unit_weight_call(const int32_t* r, int64_t v0, int64_t v1, int64_t v2,
+                                                            int Sb, float len) {
+  const int64_t v[3] = {v0, v1, v2};
+  if (KIND == 0) return tri_area(r, v, Sb, len);
+  return seg_length(r, v, Sb, len);
+}
 
 // Staging of a unit's voxels (SoA, capacity cap); units claim contiguous ranges in any order.
 struct Stage {
@@ -545,7 +553,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
             const int32_t* r = S.brec + slot * 9;
             const LatQ Lp = lat_q(lats, S.bpatch[slot], L);
             hit = unit_test<KIND>(r, v, Lp);
-            if (hit) wgt = unit_weight<KIND>(r, v, Lp, dirs[p].w);
+            if (hit) wgt = unit_weight_call<KIND>(r, v[0], v[1], v[2], Lp.Sb, dirs[p].w);
           }
           int32_t tot;
           const int32_t pos = block_exclusive_scan(int32_t(hit), S.tmp32, tot);
