@@ -570,81 +570,105 @@ VX_HD inline Lat make_lat(const vx_grid* g, int kind, float radius) {
 struct AreaLine {
   double a, b, g;      // h(l) = a + b l1 + g l2
   bool on;
-  bool dead;
-  bool use_x;          // parameter: l1 (else l2)
-  double sig;          // +-1: the parameter grows with t
-  double qe, ne, de;   // entry bound: approximate value, exact numerator and denominator
-  double qx, nx, dx;   // exit bound
 };
 
-VX_HD inline void area_line_init(AreaLine& L, double a, double b, double g, bool on) {
-  L.a = a;
-  L.b = b;
-  L.g = g;
-  L.on = on;
-  L.dead = false;
-  L.use_x = fabs(g) >= fabs(b);
-  L.sig = L.use_x ? (g > 0.0 ? 1.0 : -1.0) : (b > 0.0 ? -1.0 : 1.0);
-  L.qe = -INFINITY;
-  L.ne = 0.0;
-  L.de = 0.0;
-  L.qx = INFINITY;
-  L.nx = 0.0;
-  L.dx = 0.0;
+// the bounds of one line K: walked with the inside on its left, parametrised by the coordinate
+// (l1 or l2) that changes more along it, sig = +-1 so that sig * coordinate grows along the walk
+struct AreaEdge {
+  bool use_x, dead;
+  double sig;
+  double qe, ne, de;   // entry: approximate sig * coordinate, exact numerator and denominator
+  double qx, nx, dx;   // exit
+};
+
+VX_HD inline void area_edge_init(AreaEdge& E, const AreaLine& K) {
+  E.use_x = fabs(K.g) >= fabs(K.b);
+  E.sig = E.use_x ? (K.g > 0.0 ? 1.0 : -1.0) : (K.b > 0.0 ? -1.0 : 1.0);
+  E.dead = false;
+  E.qe = -INFINITY;
+  E.ne = 0.0;
+  E.de = 0.0;
+  E.qx = INFINITY;
+  E.nx = 0.0;
+  E.dx = 0.0;
 }
 
-// the sign of line j's half-plane along line k when the two are parallel (exact)
-VX_HD inline double parallel_side(const AreaLine& J, const AreaLine& K) {
-  const double N1 = fma(K.a, J.g, -(J.a * K.g));
-  const double N2 = fma(J.a, K.b, -(K.a * J.b));
+// K bounded where it meets another line at (N1 / D, N2 / D); the other line turns inside along
+// K where D > 0 (an entry) and outside where D < 0 (an exit)
+VX_HD inline void area_bound(AreaEdge& E, double D, double N1, double N2) {
+  const double n = E.use_x ? N1 : N2;
+  const double q = E.sig * n * rcp_fast(D);
+  if (D > 0.0) {
+    if (q > E.qe) { E.qe = q; E.ne = n; E.de = D; }
+  } else {
+    if (q < E.qx) { E.qx = q; E.nx = n; E.dx = D; }
+  }
+}
+
+// the sign along K of a parallel line's half-plane, from the exact intersection numerators
+VX_HD inline double parallel_side(const AreaLine& K, double N1, double N2) {
   return K.b != 0.0 ? (K.b > 0.0 ? N2 : -N2) : (K.g > 0.0 ? -N1 : N1);
 }
 
-// lines j (index ij) and k (index ik > ij) bound each other; UJ: line j contributes an edge
-template <bool UJ>
-VX_HD inline void area_pair(AreaLine& J, AreaLine& K, int ij, int ik, bool& flat) {
-  if (!(J.on && K.on)) return;
-  const double D = fma(J.b, K.g, -(J.g * K.b));           // exact
+// K (index ik) against the triangle's line T: 0 (l1 = 0), 1 (l2 = 0), 2 (l1 + l2 = 1), whose
+// constant coefficients fold.  A box line never coincides with a triangle line here (one through
+// a triangle edge holds on the whole triangle or empties the piece).
+template <int T>
+VX_HD inline void area_tri_bound(AreaEdge& E, const AreaLine& K) {
+  double D, N1, N2;
+  if (T == 0) { D = K.g; N1 = 0.0; N2 = -K.a; }
+  else if (T == 1) { D = -K.b; N1 = K.a; N2 = 0.0; }
+  else { D = K.b - K.g; N1 = -(K.a + K.g); N2 = K.a + K.b; }
   if (D == 0.0) {
-    const double sk = parallel_side(J, K), sj = parallel_side(K, J);
-    if (sk < 0.0) K.dead = true;
-    if (sj < 0.0) J.dead = true;
-    if (sk == 0.0) {                                      // coincident
-      if (fma(J.b, K.b, J.g * K.g) < 0.0) flat = true;
-      if (ij < ik) K.dead = true;
+    if (parallel_side(K, N1, N2) < 0.0) E.dead = true;
+    return;
+  }
+  area_bound(E, D, N1, N2);
+}
+
+// K (index ik) against another box line J (index ij)
+VX_HD inline void area_box_bound(AreaEdge& E, const AreaLine& K, int ik, const AreaLine& J, int ij, bool& flat) {
+  if (!J.on) return;
+  const double D = fma(J.b, K.g, -(J.g * K.b));           // exact
+  const double N1 = fma(K.a, J.g, -(J.a * K.g));          // intersection (N1 / D, N2 / D), exact
+  const double N2 = fma(J.a, K.b, -(K.a * J.b));
+  if (D == 0.0) {
+    const double side = parallel_side(K, N1, N2);
+    if (side < 0.0) E.dead = true;
+    if (side == 0.0) {                                    // coincident
+      if (fma(J.b, K.b, J.g * K.g) < 0.0) flat = true;    // opposite insides: a segment
+      if (ij < ik) E.dead = true;                         // the edge stays on the lower line
     }
     return;
   }
-  const double N1 = fma(K.a, J.g, -(J.a * K.g));          // intersection (N1 / D, N2 / D), exact
-  const double N2 = fma(J.a, K.b, -(K.a * J.b));
-  const double r = rcp_fast(D);
-  {
-    const double n = K.use_x ? N1 : N2;
-    const double q = K.sig * n * r;
-    if (D > 0.0) {
-      if (q > K.qe) { K.qe = q; K.ne = n; K.de = D; }
-    } else {
-      if (q < K.qx) { K.qx = q; K.nx = n; K.dx = D; }
-    }
-  }
-  if (UJ) {
-    const double n = J.use_x ? N1 : N2;
-    const double q = J.sig * n * r;
-    if (D < 0.0) {
-      if (q > J.qe) { J.qe = q; J.ne = n; J.de = D; }
-    } else {
-      if (q < J.qx) { J.qx = q; J.nx = n; J.dx = D; }
-    }
-  }
+  area_bound(E, D, N1, N2);
 }
 
-// the edge of line L: its cross-product term a (t_x - t_e)
-VX_HD inline double area_edge(const AreaLine& L) {
-  if (!L.on || L.dead || L.de == 0.0 || L.dx == 0.0) return 0.0;
-  const double ue = L.ne / L.de, ux = L.nx / L.dx;        // exact quotients, one rounding
-  const double d = L.sig * (ux - ue);
+// the edge's cross-product term a (t_x - t_e), from exact quotients (one rounding each)
+VX_HD inline double area_edge_term(const AreaEdge& E, const AreaLine& K) {
+  if (E.dead || E.de == 0.0 || E.dx == 0.0) return 0.0;
+  const double ue = E.ne / E.de, ux = E.nx / E.dx;
+  const double d = E.sig * (ux - ue);
   if (!(d > 0.0)) return 0.0;
-  return L.a * d * rcp_fast(L.use_x ? fabs(L.g) : fabs(L.b));
+  return K.a * d * rcp_fast(E.use_x ? fabs(K.g) : fabs(K.b));
+}
+
+// line ik's edge bounded by the triangle's lines and every other box line
+template <int IK>
+VX_HD inline double area_line_term(const AreaLine* L, bool& flat) {
+  const AreaLine& K = L[IK];
+  if (!K.on) return 0.0;
+  AreaEdge E;
+  area_edge_init(E, K);
+  area_tri_bound<0>(E, K);
+  area_tri_bound<1>(E, K);
+#pragma unroll
+  for (int j = 2; j < 7; ++j)
+    if (j != IK) {
+      if (j == 2) area_tri_bound<2>(E, K);
+      else area_box_bound(E, K, IK, L[j], j, flat);
+    }
+  return area_edge_term(E, K);
 }
 
 // the piece's area in barycentric units (the whole triangle has 1/2), or -1 when the exact
@@ -652,12 +676,11 @@ VX_HD inline double area_edge(const AreaLine& L) {
 VX_HD inline double tri_area_bary(const int32_t* q, const int64_t v[3], int Sb) {
   const int32_t s = int32_t(1) << Sb;
   const double ds = double(s);
-  AreaLine T0, T1, T2, P0, P1, P2, SC;
-  AreaLine* P[3] = {&P0, &P1, &P2};
-  area_line_init(T0, 0.0, 1.0, 0.0, true);       // l1 >= 0
-  area_line_init(T1, 0.0, 0.0, 1.0, true);       // l2 >= 0
-  area_line_init(T2, 1.0, -1.0, -1.0, true);     // 1 - l1 - l2 >= 0
-  area_line_init(SC, 0.0, 0.0, 0.0, false);
+  // lines 2..6: the triangle's l1 + l2 = 1 (always there), the primary box line of x, y, z and
+  // one second box line (l1 >= 0 and l2 >= 0 only bound; their coefficients are folded in)
+  AreaLine L[7];
+  L[2] = {1.0, -1.0, -1.0, true};
+  L[6] = {0.0, 0.0, 0.0, false};
   bool second = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -665,9 +688,9 @@ VX_HD inline double tri_area_bary(const int32_t* q, const int64_t v[3], int Sb) 
     const int32_t e0 = q[3 + a] - q[a];
     const int32_t e1 = q[6 + a] - q[a];
     const double c = double(c0), d0 = double(e0), d1 = double(e1);
+    L[3 + a] = {0.0, 0.0, 0.0, false};
     if (e0 == 0 && e1 == 0) {
       if (!(c0 >= 0 && c0 < s)) return 0.0;     // flat on axis a, owned by another layer
-      area_line_init(*P[a], 0.0, 0.0, 0.0, false);
       continue;
     }
     // the two box half-planes of this axis at the vertices (0, 0), (1, 0), (0, 1), exact
@@ -678,34 +701,15 @@ VX_HD inline double tri_area_bary(const int32_t* q, const int64_t v[3], int Sb) 
     if (lo && hi) {
       if (second) return -1.0;                   // two axes crossed through: the exact routine
       second = true;
-      area_line_init(SC, u0, -d0, -d1, true);
+      L[6] = {u0, -d0, -d1, true};
     }
-    if (lo) area_line_init(*P[a], c, d0, d1, true);
-    else area_line_init(*P[a], u0, -d0, -d1, hi);
+    if (lo) L[3 + a] = {c, d0, d1, true};
+    else if (hi) L[3 + a] = {u0, -d0, -d1, true};
   }
   bool flat = false;
-  area_pair<false>(T0, T2, 0, 2, flat);
-  area_pair<false>(T0, P0, 0, 3, flat);
-  area_pair<false>(T0, P1, 0, 4, flat);
-  area_pair<false>(T0, P2, 0, 5, flat);
-  area_pair<false>(T0, SC, 0, 6, flat);
-  area_pair<false>(T1, T2, 1, 2, flat);
-  area_pair<false>(T1, P0, 1, 3, flat);
-  area_pair<false>(T1, P1, 1, 4, flat);
-  area_pair<false>(T1, P2, 1, 5, flat);
-  area_pair<false>(T1, SC, 1, 6, flat);
-  area_pair<true>(T2, P0, 2, 3, flat);
-  area_pair<true>(T2, P1, 2, 4, flat);
-  area_pair<true>(T2, P2, 2, 5, flat);
-  area_pair<true>(T2, SC, 2, 6, flat);
-  area_pair<true>(P0, P1, 3, 4, flat);
-  area_pair<true>(P0, P2, 3, 5, flat);
-  area_pair<true>(P1, P2, 4, 5, flat);
-  area_pair<true>(P0, SC, 3, 6, flat);
-  area_pair<true>(P1, SC, 4, 6, flat);
-  area_pair<true>(P2, SC, 5, 6, flat);
+  const double sum = area_line_term<2>(L, flat) + area_line_term<3>(L, flat) + area_line_term<4>(L, flat) +
+                     area_line_term<5>(L, flat) + area_line_term<6>(L, flat);
   if (flat) return 0.0;
-  const double sum = area_edge(T2) + area_edge(P0) + area_edge(P1) + area_edge(P2) + area_edge(SC);
   return 0.5 * fabs(sum);
 }
 

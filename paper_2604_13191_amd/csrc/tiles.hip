@@ -361,7 +361,10 @@ struct UnitLds {
 };
 
 // above this many pairs per voxel (unit mean) the grouping places stably instead of sorting
-constexpr int32_t kStableMean = 4;
+// (triangles: a surface voxel holds a handful of pairs, sorted per voxel in parallel faster than
+// one wave places them in order; fibers: dense patches hold hundreds per voxel)
+template <int KIND>
+constexpr int32_t stable_mean() { return KIND == 0 ? 24 : 4; }
 // keys of a unit's range: at most one 16^3 tile
 constexpr int32_t kUnitKeys = 4096;
 static_assert(kBlock * 9 * 4 >= kUnitKeys * 2, "per-key counters live in the record batch's space");
@@ -742,7 +745,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     // restore primitive order per voxel by insertion sort below; dense ones place stably: one
     // wave walks the list (primitive order) and lanes holding the same key find each other by
     // ballots over the 12 key bits.
-    const bool stable = npairs > kStableMean * nv;
+    const bool stable = npairs > stable_mean<KIND>() * nv;
     if (!stable) {
       for (int32_t i = tid; i < npairs; i += kBlock) S.idx[kst[S.key[i]] + slot[i]] = uint16_t(i);
     } else if (tid < 64) {
