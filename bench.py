@@ -92,14 +92,14 @@ def traffic_bytes(workload, kernel):
 # one single-instance workload: plans, kernel table, timed steps, roofline
 # ------------------------------------------------------------------------------------------------
 
-def make_plans(vx, kind, grid, data, levels, K, offsets=None, radius=0.0):
-    plan = vx.VoxelizePlan(kind, grid, data, offsets=offsets, radius=radius)
+def make_plans(vx, kind, grid, data, levels, K, offsets=None, radius=0.0, tuning=None):
+    plan = vx.VoxelizePlan(kind, grid, data, offsets=offsets, radius=radius, tuning=tuning)
     plan.run()
     leaf = plan.check()
-    cal = vx.LodPlan(grid, leaf, plan.stats[2:3], levels).run()
+    cal = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, tuning=tuning).run()
     caps = [max(v.n, 1) for v in cal.check()[1:]]
     del cal
-    lod = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, K=K, iters=2, caps=caps)
+    lod = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, K=K, iters=2, caps=caps, tuning=tuning)
     lod.run()
     lod.check()
     return plan, lod, leaf
@@ -194,8 +194,8 @@ def roofline(name, workload, counts, t, K):
 
 
 def single_section(vx, kind, grid, data, levels, K, args, workload, offsets=None, radius=0.0, input_bytes=0,
-                   graph=True):
-    plan, lod, leaf = make_plans(vx, kind, grid, data, levels, K, offsets, radius)
+                   graph=True, tuning=None):
+    plan, lod, leaf = make_plans(vx, kind, grid, data, levels, K, offsets, radius, tuning)
     counts = {"key_bytes": 4 if grid.log2_res <= 10 else 8, "n_pairs": plan.n_pairs, "n_cand": plan.n_cand,
               "n_prims": plan.n_prims, "levels": [leaf.n] + [v.n for v in lod.out], "n_records": plan.n_records,
               "n_units": plan.n_units, "input_bytes": input_bytes}
@@ -285,12 +285,12 @@ def compact_timing(vx, leaf, args):
     return out
 
 
-def _single_build(vx, wl, K):
+def _single_build(vx, wl, K, tuning):
     """Single-instance plain path for one fiber set: voxelize + full pyramid with K lobes."""
     import torch
     pts = torch.as_tensor(wl.pts).cuda()
     offs = torch.as_tensor(wl.offsets).cuda()
-    plan, lod, _ = make_plans(vx, 1, wl.grid, pts, wl.grid.log2_res + 1, K, offs, wl.radius)
+    plan, lod, _ = make_plans(vx, 1, wl.grid, pts, wl.grid.log2_res + 1, K, offs, wl.radius, tuning)
     return plan, lod
 
 
@@ -302,11 +302,10 @@ def batch_timing(vx, args):
     import synth
     from paper_2604_13191_amd import autotune
     wls = synth.weave_patches()
-    default = vx.get_launch_grids()
-    grids = autotune.apply("weave_patches")
+    tuning = autotune.load("weave_patches")
     stream = torch.cuda.Stream()
     plan = vx.BatchPlan([vx.Patch(w.grid, torch.as_tensor(w.pts).cuda(), torch.as_tensor(w.offsets), w.radius)
-                         for w in wls], K=4, iters=2)
+                         for w in wls], K=4, iters=2, tuning=tuning)
     plan.run(stream)
     plan.check(stream)
     torch.cuda.synchronize()
@@ -329,7 +328,7 @@ def batch_timing(vx, args):
     torch.cuda.empty_cache()
     single_ms, single_pairs = 0.0, 0
     for wl in wls:
-        sp, sl = _single_build(vx, wl, 4)
+        sp, sl = _single_build(vx, wl, 4, tuning)
         side = torch.cuda.Stream()
         torch.cuda.synchronize()
         sg = vx.capture(lambda st: (sp.run(st), sl.run(st)), side)
@@ -347,7 +346,6 @@ def batch_timing(vx, args):
         single_pairs += sp.n_pairs
         del sg, sp, sl
     torch.cuda.empty_cache()
-    vx.set_launch_grids(default)
     assert single_pairs == n_pairs, (single_pairs, n_pairs)
     counts = {"key_bytes": 8, "n_pairs": n_pairs, "n_prims": n_prims, "levels": levels_n,
               "input_bytes": 12 * n_prims + 8 * (sum(len(w.offsets) - 1 for w in wls) + 1)}
@@ -357,7 +355,7 @@ def batch_timing(vx, args):
             "graph_replay_ms": batch_ms, "pairs_per_s": n_pairs / (batch_ms * 1e-3),
             "single_instance_graphs_sum_ms": single_ms, "speedup_vs_single": single_ms / batch_ms,
             "algorithmic_bytes": B, "hbm_frac": round(B / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "launch_grids": grids if grids is not None else "default"}
+            "tuning": tuning.as_dict() if tuning is not None else "default"}
 
 
 # ------------------------------------------------------------------------------------------------
@@ -431,24 +429,22 @@ def main():
     from paper_2604_13191_amd import autotune
 
     # ---- headline: brushed metal ---------------------------------------------------------------
-    default_grids = vx.get_launch_grids()
-    tuned = autotune.apply("brushed_metal")
+    tuned = autotune.load("brushed_metal")
     wl = synth.brushed_metal()
     tris = torch.as_tensor(wl.tris).cuda()
     grid, levels, n_tris = wl.grid, wl.levels, wl.tris.shape[0]
     del wl
     head, plan, lod, leaf = single_section(vx, 0, grid, tris, levels, 4, args, "brushed_metal",
-                                           input_bytes=36 * n_tris)
+                                           input_bytes=36 * n_tris, tuning=tuned)
     del plan, lod, leaf, tris
     torch.cuda.empty_cache()
-    vx.set_launch_grids(default_grids)
     out = {
         "metric": METRIC, "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
         "config": {"workload": "brushed_metal: 4096x4096 vertex height field (33,538,050 triangles), 4096^3, "
                                "13 levels, K=4", "n_pairs": head["n_pairs"], "n_leaf_voxels": head["n_leaf_voxels"],
-                   "level_voxels": head["level_voxels"], "launch_grids": tuned if tuned is not None else "default"},
+                   "level_voxels": head["level_voxels"], "tuning": tuned.as_dict() if tuned is not None else "default"},
         "voxelize_ms": head["voxelize_ms"], "lod_build_ms": head["lod_build_ms"],
         "graph_ms_per_step": head.get("graph_ms_per_step"), "graph_pairs_per_s": head.get("graph_pairs_per_s"),
         "roofline": head["roofline"], "kernels": head["kernels"],
@@ -456,14 +452,15 @@ def main():
 
     # ---- plain weave, fit, compact -------------------------------------------------------------
     if not args.no_weave or not args.no_fit or not args.no_compact:
-        tw = autotune.apply("plain_weave")
+        tw = autotune.load("plain_weave")
         ww = synth.plain_weave()
         pts = torch.as_tensor(ww.pts).cuda()
         offs = torch.as_tensor(ww.offsets).cuda()
         sec, plan, lod, leaf = single_section(vx, 1, ww.grid, pts, ww.levels, 1, args, "plain_weave", offs,
-                                              ww.radius, input_bytes=12 * ww.pts.shape[0] + 8 * len(ww.offsets))
+                                              ww.radius, input_bytes=12 * ww.pts.shape[0] + 8 * len(ww.offsets),
+                                              tuning=tw)
         sec["workload"] = "plain_weave: 2000 fibers x 256 segments, radius 0.5 voxel, 1024^3, 11 levels, K=1"
-        sec["launch_grids"] = tw if tw is not None else "default"
+        sec["tuning"] = tw.as_dict() if tw is not None else "default"
         if not args.no_weave:
             out["plain_weave"] = sec
         if not args.no_fit:
@@ -471,7 +468,6 @@ def main():
         if not args.no_compact:
             out["sggx_compact"] = compact_timing(vx, leaf, args)
         del plan, lod, leaf, pts, offs
-        vx.set_launch_grids(default_grids)
         torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = batch_timing(vx, args)

@@ -112,6 +112,26 @@ typedef struct {
 } vx_lobes;
 
 /* ------------------------------------------------------------------------------------------
+ * Tuning (chosen by the project's autotuner per workload; NULL or zero fields = defaults).  It
+ * changes the work decomposition, never a result:
+ *   tile_bits    leaf tiles of 2^tile_bits voxels per axis (2, 3 or 4; default 4), the spatial
+ *                bins the primitive-tile records are sorted by
+ *   unit_budget  candidates one work unit keeps in LDS (1024, 1536, 2048 or 3072; default 1536
+ *                for triangles, 3072 for fibers); smaller budgets split crowded tiles further and
+ *                let more units share a compute unit
+ *   grids        blocks of the persistent kernels: unit kernel, unit planner, leaf compaction,
+ *                parent reduce, lobe clustering (each 64 .. 16384; defaults 16384, 8192, 16384,
+ *                512, 8192)
+ * Invalid values return VX_ERR_ARG.  The library keeps no tuning state of its own.
+ * ------------------------------------------------------------------------------------------ */
+#define VX_TUNE_COUNT 5
+typedef struct {
+  int32_t tile_bits;
+  int32_t unit_budget;
+  int32_t grids[VX_TUNE_COUNT];
+} vx_tuning;
+
+/* ------------------------------------------------------------------------------------------
  * Voxelization (Sec. 3.1-3.4).
  *
  * The grid is cut into aligned tiles of 16^3 voxels (Sec. 3.1's blocks); every primitive is
@@ -132,7 +152,7 @@ size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_rec
  * stats: int64[VX_NSTAT] on the device, overwritten. */
 vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris,
                                 int64_t max_records, int64_t max_units, void* workspace, size_t ws_bytes,
-                                const vx_voxels* out, int64_t* stats, vx_stream stream);
+                                const vx_voxels* out, int64_t* stats, const vx_tuning* tuning, vx_stream stream);
 
 /* pts: float32 [n_pts][3] polyline nodes (Sec. 3.1 node collections); offsets: int64
  * [n_fibers + 1] (device), offsets[0] = 0, non-decreasing, offsets[n_fibers] = n_pts.  Segment
@@ -140,7 +160,7 @@ vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t 
 vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
                              int64_t n_fibers, float radius, int64_t max_records, int64_t max_units,
                              void* workspace, size_t ws_bytes, const vx_voxels* out, int64_t* stats,
-                             vx_stream stream);
+                             const vx_tuning* tuning, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
  * LoD pyramid (Sec. 4.3-4.4).
@@ -164,7 +184,8 @@ size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K);
 
 vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels,
                        int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
-                       int64_t* n_levels, void* workspace, size_t ws_bytes, vx_stream stream);
+                       int64_t* n_levels, void* workspace, size_t ws_bytes, const vx_tuning* tuning,
+                       vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
  * vx_build_lod without a workspace, for callers that cannot allocate device memory (code under
@@ -181,7 +202,7 @@ vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t
 
 vx_status vx_build_lod_noalloc(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels,
                                int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
-                               int64_t* n_levels, vx_stream stream);
+                               int64_t* n_levels, const vx_tuning* tuning, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
  * Differentiable two-lobe fit (extension; the projected area of an SGGX lobe is Sec. 4.1's
@@ -272,7 +293,7 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
                          int64_t n_pts, const int64_t* offsets, int64_t n_fibers, int32_t levels, int32_t K,
                          int32_t kmeans_iters, int64_t max_records, int64_t max_units, const vx_voxels* out,
                          const vx_lobes* lobes, int64_t* n_levels, int64_t* patch_table, int64_t* stats,
-                         void* workspace, size_t ws_bytes, vx_stream stream);
+                         void* workspace, size_t ws_bytes, const vx_tuning* tuning, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
  * Leaf eigen-fit and compact SGGX storage (Sec. 4.1 "Fitting to SGGX distribution"; Sec. 4.3
@@ -314,14 +335,6 @@ vx_status vx_graph_begin(vx_stream stream);
 vx_status vx_graph_end(vx_stream stream, vx_graph* graph);
 vx_status vx_graph_launch(vx_graph graph, vx_stream stream);
 void vx_graph_destroy(vx_graph graph);
-
-/* Launch geometry (set by the autotuner): grid sizes of the persistent kernels -- the unit kernel
- * (exact test, weights, per-voxel sums), the unit planner, the leaf compaction, the parent reduce
- * and the lobe clustering, in that order; each 64 .. 16384 blocks of 256 threads.  The grid
- * changes no result. */
-#define VX_TUNE_COUNT 5
-vx_status vx_set_launch_grids(const int32_t* grids, int32_t n);
-void vx_get_launch_grids(int32_t* grids, int32_t n);
 
 /* Synchronises `stream`, reads stats (VX_NSTAT int64 on the device) and maps its flags to a
  * status: VX_ERR_INPUT before VX_ERR_BINDING before VX_ERR_CAPACITY before VX_OK. */

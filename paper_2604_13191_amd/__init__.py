@@ -56,6 +56,43 @@ class CPatch(ctypes.Structure):
                 ("radius", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
+class CTuning(ctypes.Structure):
+    _fields_ = [("tile_bits", ctypes.c_int32), ("unit_budget", ctypes.c_int32), ("grids", ctypes.c_int32 * 5)]
+
+
+TUNE_KERNELS = ("unit", "unit_plan", "unit_compact", "lod_reduce", "lod_cluster")
+
+
+@dataclass(frozen=True)
+class Tuning:
+    """Work decomposition of one call (include/vx.h, vx_tuning); 0 = the library's default.
+    tile_bits: leaf tiles of 2^tile_bits voxels per axis (2..4); unit_budget: candidates per work
+    unit (1024, 1536, 2048, 3072); grids: blocks of the kernels in TUNE_KERNELS order."""
+    tile_bits: int = 0
+    unit_budget: int = 0
+    grids: tuple = (0, 0, 0, 0, 0)
+
+    def cstruct(self) -> "CTuning":
+        g = tuple(int(x) for x in self.grids)
+        if len(g) != 5:
+            raise ValueError("tuning: five grid sizes")
+        return CTuning(int(self.tile_bits), int(self.unit_budget), (ctypes.c_int32 * 5)(*g))
+
+    def as_dict(self):
+        return {"tile_bits": int(self.tile_bits), "unit_budget": int(self.unit_budget),
+                "grids": [int(x) for x in self.grids]}
+
+    @staticmethod
+    def from_dict(d):
+        if d is None:
+            return None
+        return Tuning(int(d.get("tile_bits", 0)), int(d.get("unit_budget", 0)), tuple(d.get("grids", (0,) * 5)))
+
+
+def _ctuning(t):
+    return ctypes.byref(t.cstruct()) if t is not None else None
+
+
 class CFibers(ctypes.Structure):
     _fields_ = [("pts", ctypes.c_void_p), ("n_pts", ctypes.c_int64), ("offsets", ctypes.c_void_p),
                 ("n_fibers", ctypes.c_int64), ("radius", ctypes.c_float)]
@@ -80,18 +117,19 @@ def load():
     L.vx_voxelize_workspace_size.argtypes = [i32, i64, i64, i64, i64, i32]
     L.vx_voxelize_triangles.restype = ctypes.c_int
     L.vx_voxelize_triangles.argtypes = [ctypes.POINTER(CGrid), vp, i64, i64, i64, vp, sz,
-                                        ctypes.POINTER(CVoxels), vp, vp]
+                                        ctypes.POINTER(CVoxels), vp, ctypes.POINTER(CTuning), vp]
     L.vx_voxelize_fibers.restype = ctypes.c_int
     L.vx_voxelize_fibers.argtypes = [ctypes.POINTER(CGrid), vp, i64, vp, i64, ctypes.c_float, i64, i64, vp, sz,
-                                     ctypes.POINTER(CVoxels), vp, vp]
+                                     ctypes.POINTER(CVoxels), vp, ctypes.POINTER(CTuning), vp]
     L.vx_lod_workspace_size.restype = sz
     L.vx_lod_workspace_size.argtypes = [i64, i32, i32]
     L.vx_build_lod.restype = ctypes.c_int
     L.vx_build_lod.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, i32,
-                               ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp, sz, vp]
+                               ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp, sz, ctypes.POINTER(CTuning), vp]
     L.vx_build_lod_noalloc.restype = ctypes.c_int
     L.vx_build_lod_noalloc.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), vp, i32, i32, i32,
-                                       ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp]
+                                       ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp,
+                                       ctypes.POINTER(CTuning), vp]
     L.vx_check_stats.restype = ctypes.c_int
     L.vx_check_stats.argtypes = [vp, vp]
     L.vx_status_str.restype = ctypes.c_char_p
@@ -108,7 +146,8 @@ def load():
     L.vx_batch_workspace_size.argtypes = [i32, i64, i64, i64, i64]
     L.vx_batch_build.restype = ctypes.c_int
     L.vx_batch_build.argtypes = [ctypes.POINTER(CPatch), vp, i32, vp, i64, vp, i64, i32, i32, i32, i64, i64,
-                                 ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp, vp, vp, sz, vp]
+                                 ctypes.POINTER(CVoxels), ctypes.POINTER(CLobes), vp, vp, vp, vp, sz,
+                                 ctypes.POINTER(CTuning), vp]
     L.vx_graph_begin.restype = ctypes.c_int
     L.vx_graph_begin.argtypes = [vp]
     L.vx_graph_end.restype = ctypes.c_int
@@ -117,10 +156,6 @@ def load():
     L.vx_graph_launch.argtypes = [vp, vp]
     L.vx_graph_destroy.restype = None
     L.vx_graph_destroy.argtypes = [vp]
-    L.vx_set_launch_grids.restype = ctypes.c_int
-    L.vx_set_launch_grids.argtypes = [ctypes.POINTER(i32), i32]
-    L.vx_get_launch_grids.restype = None
-    L.vx_get_launch_grids.argtypes = [ctypes.POINTER(i32), i32]
     L.vx_timing_filter.argtypes = [ctypes.c_char_p]
     L.vx_timing_filter.restype = None
     L.vx_timing_enable.argtypes = [i32]
@@ -208,10 +243,12 @@ class VoxelizePlan:
     once each).  ``run()`` then enqueues the whole voxelize pass with no host sync.
     """
 
-    def __init__(self, kind, grid, data, offsets=None, radius=0.0, max_records=None, max_units=None, out_cap=None):
+    def __init__(self, kind, grid, data, offsets=None, radius=0.0, max_records=None, max_units=None, out_cap=None,
+                 tuning=None):
         import torch
         self.L = load()
         self.kind = kind
+        self.tuning = tuning
         self.grid = grid
         self.cgrid = _cgrid(grid)
         self.data = data.contiguous()
@@ -249,11 +286,13 @@ class VoxelizePlan:
     def _call(self, max_records, max_units, ws, ws_bytes, cout, stream):
         if self.kind == 0:
             st = self.L.vx_voxelize_triangles(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims, max_records,
-                                              max_units, ws, ws_bytes, ctypes.byref(cout), _ptr(self.stats), stream)
+                                              max_units, ws, ws_bytes, ctypes.byref(cout), _ptr(self.stats),
+                                              _ctuning(self.tuning), stream)
         else:
             st = self.L.vx_voxelize_fibers(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims,
                                            _ptr(self.offsets), self.n_fib, self.radius, max_records, max_units, ws,
-                                           ws_bytes, ctypes.byref(cout), _ptr(self.stats), stream)
+                                           ws_bytes, ctypes.byref(cout), _ptr(self.stats), _ctuning(self.tuning),
+                                           stream)
         if st != 0:
             raise VxError(st, "voxelize")
 
@@ -323,7 +362,7 @@ class Lobes:
 class LodPlan:
     """Per-level output buffers for build_lod; level caps default to the leaf's count."""
 
-    def __init__(self, grid, leaf: Voxels, n_leaf_dev, levels, K=1, iters=2, caps=None, noalloc=False):
+    def __init__(self, grid, leaf: Voxels, n_leaf_dev, levels, K=1, iters=2, caps=None, noalloc=False, tuning=None):
         """noalloc: run vx_build_lod_noalloc (the library's own scratch, no workspace tensor;
         leaf caps up to NOALLOC_MAX_LEAF; calls on one GPU must not overlap)."""
         import torch
@@ -346,6 +385,7 @@ class LodPlan:
         self._cleaf = leaf.cstruct()
         self.n_levels = torch.zeros(self.levels + 1, dtype=torch.int64, device=dev)
         self.noalloc = bool(noalloc)
+        self.tuning = tuning
         self.ws = None
         if not self.noalloc:
             nb = self.L.vx_lod_workspace_size(leaf.cap, self.levels, self.K)
@@ -357,11 +397,12 @@ class LodPlan:
         if self.noalloc:
             st = self.L.vx_build_lod_noalloc(ctypes.byref(self.cgrid), ctypes.byref(self._cleaf),
                                              _ptr(self.n_leaf_dev), self.levels, self.K, self.iters, self._cout,
-                                             self._clobes, _ptr(self.n_levels), _stream(stream))
+                                             self._clobes, _ptr(self.n_levels), _ctuning(self.tuning),
+                                             _stream(stream))
         else:
             st = self.L.vx_build_lod(ctypes.byref(self.cgrid), ctypes.byref(self._cleaf), _ptr(self.n_leaf_dev),
                                      self.levels, self.K, self.iters, self._cout, self._clobes, _ptr(self.n_levels),
-                                     _ptr(self.ws), self.ws.numel(), _stream(stream))
+                                     _ptr(self.ws), self.ws.numel(), _ctuning(self.tuning), _stream(stream))
         if st != 0:
             raise VxError(st, "build_lod_noalloc" if self.noalloc else "build_lod")
         return self
@@ -395,13 +436,13 @@ def voxelize_fibers(pts, offsets, radius, grid, **kw):
     return v
 
 
-def build_lod(grid, leaf: Voxels, levels, K=1, iters=2, n_leaf_dev=None, caps=None, return_lobes=False):
+def build_lod(grid, leaf: Voxels, levels, K=1, iters=2, n_leaf_dev=None, caps=None, return_lobes=False, tuning=None):
     """Leaf voxels -> list [leaf, level 1, ..., level levels-1] (Sec. 4.3); with K > 1 and
     return_lobes, also the per-level lobes [level 1, ...] (Sec. 4.4)."""
     import torch
     if n_leaf_dev is None:
         n_leaf_dev = torch.tensor([leaf.n], dtype=torch.int64, device=leaf.w.device)
-    p = LodPlan(grid, leaf, n_leaf_dev, levels, K, iters, caps).run()
+    p = LodPlan(grid, leaf, n_leaf_dev, levels, K, iters, caps, tuning=tuning).run()
     out = p.check()
     if return_lobes:
         return out, p.lobes
@@ -696,24 +737,6 @@ def fit_init(plan, seed=4, noise=0.01):
 # Launch geometry and graphs
 # ------------------------------------------------------------------------------------------------
 
-TUNE_KERNELS = ("unit_fib", "unit_plan", "unit_compact", "lod_reduce", "lod_cluster")
-
-
-def get_launch_grids():
-    """Grid sizes (blocks) of the persistent kernels, in the order of TUNE_KERNELS."""
-    arr = (ctypes.c_int32 * len(TUNE_KERNELS))()
-    load().vx_get_launch_grids(arr, len(TUNE_KERNELS))
-    return list(arr)
-
-
-def set_launch_grids(grids):
-    grids = [int(g) for g in grids]
-    arr = (ctypes.c_int32 * len(grids))(*grids)
-    st = load().vx_set_launch_grids(arr, len(grids))
-    if st != 0:
-        raise VxError(st, f"vx_set_launch_grids({grids})")
-
-
 class Graph:
     """A captured sequence of library calls on one (non-null) stream, replayed as one launch."""
 
@@ -774,9 +797,10 @@ class BatchPlan:
     voxel on the levels above it.  Capacities come from counting calls of the same entry point
     (candidates, pairs, leaf voxels, then per-level counts), synchronising once per call."""
 
-    def __init__(self, patches, K=4, iters=2, levels=None, device=None):
+    def __init__(self, patches, K=4, iters=2, levels=None, device=None, tuning=None):
         import torch
         self.L = load()
+        self.tuning = tuning
         self.patches = list(patches)
         self.n_patches = len(self.patches)
         if self.n_patches < 1:
@@ -813,7 +837,7 @@ class BatchPlan:
         st = self.L.vx_batch_build(self._cp, _ptr(self.patches_dev), self.n_patches, _ptr(self.pts), self.n_pts,
                                    _ptr(self.offsets), self.n_fib, levels, K, self.iters, max_records, max_units, cout,
                                    clobes, _ptr(self.n_levels), _ptr(self.patch_table), _ptr(self.stats), _ptr(ws),
-                                   ws.numel(), stream)
+                                   ws.numel(), _ctuning(self.tuning), stream)
         if st != 0:
             raise VxError(st, "vx_batch_build")
 

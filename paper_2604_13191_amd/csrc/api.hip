@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -26,7 +27,7 @@ struct Acc {
   int64_t n = 0;
 };
 std::mutex g_mu;
-bool g_on = false;
+std::atomic<bool> g_on{false};   // read without the lock: launches pay nothing while timing is off
 std::string g_filter;            // time only launches of this name (empty: all)
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
@@ -46,8 +47,8 @@ hipEvent_t get_event() {
 }  // namespace
 
 void timing_begin(const char* name, hipStream_t s) {
+  if (!g_on.load(std::memory_order_acquire)) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_on) return;
   if (!g_filter.empty() && g_filter != name) {
     g_open.push_back(SIZE_MAX);
     return;
@@ -59,16 +60,41 @@ void timing_begin(const char* name, hipStream_t s) {
 }
 
 void timing_end(hipStream_t s) {
+  if (g_open.empty()) return;                  // this thread opened nothing (timing was off)
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_on || g_open.empty()) return;
   size_t i = g_open.back();
   g_open.pop_back();
   if (i == SIZE_MAX) return;
   (void)hipEventRecord(g_pending[i].b, s);
 }
 
-int g_grids[kTuneCount] = {kGrid, kGrid, 4 * kGrid, kGrid, kGrid};
-int tuned_grid(int which) { return g_grids[which]; }
+bool resolve_tuning(const vx_tuning* t, int kind, Tuning* out) {
+  Tuning u;
+  u.tile_bits = kTileBits;
+  u.unit_budget = kind == 0 ? 1536 : kUnitCand;
+  // persistent grids well above the resident blocks (768 to 1024 per launch), so that no tail of
+  // late blocks runs alone; the parent reduce walks children per thread and likes fewer blocks
+  const int defaults[kTuneCount] = {16384, 8192, 16384, 512, 8192};
+  for (int i = 0; i < kTuneCount; ++i) u.grids[i] = defaults[i];
+  if (t) {
+    if (t->tile_bits != 0) {
+      if (t->tile_bits < 2 || t->tile_bits > kTileBits) return false;
+      u.tile_bits = t->tile_bits;
+    }
+    if (t->unit_budget != 0) {
+      const int b = t->unit_budget;
+      if (b != 1024 && b != 1536 && b != 2048 && b != 3072) return false;
+      u.unit_budget = b;
+    }
+    for (int i = 0; i < kTuneCount; ++i)
+      if (t->grids[i] != 0) {
+        if (t->grids[i] < 64 || t->grids[i] > 16384) return false;
+        u.grids[i] = t->grids[i];
+      }
+  }
+  *out = u;
+  return true;
+}
 
 // batched patches: device lattice table and point ranges from the caller's device patch array
 __global__ void k_batch_setup(const vx_patch* __restrict__ patches, int n, Lat* __restrict__ lats,
@@ -143,7 +169,9 @@ size_t vx_voxelize_workspace_size(int32_t kind, int64_t n_prims, int64_t max_rec
 static vx_status voxelize_common(int kind, const vx_grid* grid, const float* data, int64_t n_prims,
                                  const int64_t* offsets, int64_t n_fib, float radius, int64_t max_records,
                                  int64_t max_units, void* ws, size_t ws_bytes, const vx_voxels* out,
-                                 int64_t* stats, vx_stream stream) {
+                                 int64_t* stats, const vx_tuning* tuning, vx_stream stream) {
+  Tuning tu;
+  if (!resolve_tuning(tuning, kind, &tu)) return VX_ERR_ARG;
   if (!grid_ok(grid) || n_prims < 0 || n_prims > kMaxPrims || max_records < 0 || max_units < 0 || !stats ||
       !voxels_ok(out, false) || (n_prims > 0 && !data))
     return VX_ERR_ARG;
@@ -155,23 +183,24 @@ static vx_status voxelize_common(int kind, const vx_grid* grid, const float* dat
   }
   if (!ws_ok(ws, ws_bytes, tile_ws_bytes(n_prims, max_records, max_units, out->cap, grid->log2_res > 10)))
     return VX_ERR_WORKSPACE;
-  const int tb = std::min(kTileBits, int(grid->log2_res));
+  const int tb = std::min(tu.tile_bits, int(grid->log2_res));
   return tile_voxelize(kind, grid, data, n_prims, offsets, n_fib, radius, max_records, max_units, ws, out, stats,
-                       reinterpret_cast<hipStream_t>(stream), nullptr, tb);
+                       reinterpret_cast<hipStream_t>(stream), nullptr, tb, tu);
 }
 
 vx_status vx_voxelize_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, int64_t max_records,
                                 int64_t max_units, void* ws, size_t ws_bytes, const vx_voxels* out,
-                                int64_t* stats, vx_stream stream) {
+                                int64_t* stats, const vx_tuning* tuning, vx_stream stream) {
   return voxelize_common(0, grid, tris, n_tris, nullptr, 0, 0.0f, max_records, max_units, ws, ws_bytes, out, stats,
-                         stream);
+                         tuning, stream);
 }
 
 vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
                              int64_t n_fibers, float radius, int64_t max_records, int64_t max_units, void* ws,
-                             size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream) {
+                             size_t ws_bytes, const vx_voxels* out, int64_t* stats, const vx_tuning* tuning,
+                             vx_stream stream) {
   return voxelize_common(1, grid, pts, n_pts, offsets, n_fibers, radius, max_records, max_units, ws, ws_bytes, out,
-                         stats, stream);
+                         stats, tuning, stream);
 }
 
 size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K) {
@@ -207,7 +236,7 @@ vx_status lod_args(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_
 // that every kernel writes before it reads (no clearing needed)
 vx_status lod_run(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
                   int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, int64_t* n_levels,
-                  int64_t* pstart, int64_t* partial, hipStream_t s) {
+                  int64_t* pstart, int64_t* partial, const Tuning& tu, hipStream_t s) {
   const bool key64 = grid->log2_res > 10;
   lod_init(n_leaf, leaf->cap, n_levels, int64_t(levels) + 1, s);
   int L = 1;
@@ -215,13 +244,14 @@ vx_status lod_run(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_l
     const vx_voxels& in = L == 1 ? *leaf : out[L - 2];
     if (K == 1 && in.cap <= kTailMax) break;       // the small top levels go in one launch
     lod_level(key64, in, n_levels + L - 1, out[L - 1], n_levels + L, n_levels + levels, pstart,
-              partial, s);
+              partial, tu.grids[kTuneLod], s);
     if (K > 1) {
       if (L == 1)
-        cluster_level(pstart, n_levels + 1, leaf->w, leaf->S, nullptr, 1, leaf->cap, K, kmeans_iters, lobes[0], s);
+        cluster_level(pstart, n_levels + 1, leaf->w, leaf->S, nullptr, 1, leaf->cap, K, kmeans_iters, lobes[0],
+                      tu.grids[kTuneCluster], s);
       else
         cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
-                      kmeans_iters, lobes[L - 1], s);
+                      kmeans_iters, lobes[L - 1], tu.grids[kTuneCluster], s);
     }
   }
   if (L < levels) {
@@ -268,28 +298,32 @@ extern "C" {
 
 vx_status vx_build_lod(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels, int32_t K,
                        int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes, int64_t* n_levels,
-                       void* ws, size_t ws_bytes, vx_stream stream) {
+                       void* ws, size_t ws_bytes, const vx_tuning* tuning, vx_stream stream) {
   const vx_status st = lod_args(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels);
   if (st != VX_OK) return st;
+  Tuning tu;
+  if (!resolve_tuning(tuning, 1, &tu)) return VX_ERR_ARG;
   if (!ws_ok(ws, ws_bytes, vx_lod_workspace_size(leaf->cap, levels, K))) return VX_ERR_WORKSPACE;
   Carver cv(ws);
   int64_t* pstart = cv.take<int64_t>(leaf->cap + 1);
   int64_t* partial = cv.take<int64_t>(kGrid + 1);
-  return lod_run(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels, pstart, partial,
+  return lod_run(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels, pstart, partial, tu,
                  reinterpret_cast<hipStream_t>(stream));
 }
 
 vx_status vx_build_lod_noalloc(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_leaf, int32_t levels,
                                int32_t K, int32_t kmeans_iters, const vx_voxels* out, const vx_lobes* lobes,
-                               int64_t* n_levels, vx_stream stream) {
+                               int64_t* n_levels, const vx_tuning* tuning, vx_stream stream) {
   const vx_status st = lod_args(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels);
   if (st != VX_OK) return st;
+  Tuning tu;
+  if (!resolve_tuning(tuning, 1, &tu)) return VX_ERR_ARG;
   if (leaf->cap > VX_LOD_NOALLOC_MAX_LEAF) return VX_ERR_CAPACITY;
   int64_t* base = nullptr;
   const vx_status sst = scratch_for_current_device(&base);
   if (sst != VX_OK) return sst;
   return lod_run(grid, leaf, n_leaf, levels, K, kmeans_iters, out, lobes, n_levels, base,
-                 base + VX_LOD_NOALLOC_MAX_LEAF + 1, reinterpret_cast<hipStream_t>(stream));
+                 base + VX_LOD_NOALLOC_MAX_LEAF + 1, tu, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t vx_fit_workspace_size(int64_t n_pts, int64_t max_cand, int64_t max_pairs, const int64_t* caps, int32_t hi,
@@ -365,7 +399,9 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
                          int64_t n_pts, const int64_t* offsets, int64_t n_fibers, int32_t levels, int32_t K,
                          int32_t kmeans_iters, int64_t max_records, int64_t max_units, const vx_voxels* out,
                          const vx_lobes* lobes, int64_t* n_levels, int64_t* patch_table, int64_t* stats, void* ws,
-                         size_t ws_bytes, vx_stream stream) {
+                         size_t ws_bytes, const vx_tuning* tuning, vx_stream stream) {
+  Tuning tu;
+  if (!resolve_tuning(tuning, 1, &tu)) return VX_ERR_ARG;
   if (!patches || !patches_dev || n_patches < 1 || n_patches > 65536 || n_pts < 0 || n_pts > kMaxPrims || !offsets ||
       n_fibers < 0 || (n_pts > 0 && (!pts || n_fibers < 1)) || levels < 1 || K < 1 || K > 8 || kmeans_iters < 0 ||
       max_records < 0 || max_units < 0 || !out || !n_levels || !patch_table || !stats)
@@ -401,7 +437,7 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
                      pt_begin);
   BatchLattice bl{lats, pt_begin, n_patches};
   vx_status st = tile_voxelize(1, &patches[0].grid, pts, n_pts, offsets, n_fibers, 0.0f, max_records, max_units, vws,
-                               &out[0], stats, s, &bl, std::min(kTileBits, min_log2));
+                               &out[0], stats, s, &bl, std::min(tu.tile_bits, min_log2), tu);
   if (st != VX_OK) return st;
   // the pyramid, with the patch-preserving parent
   lod_init(stats + VX_STAT_VOXELS, leaf_cap, n_levels, int64_t(levels) + 1, s);
@@ -409,13 +445,14 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
   for (; L < levels; ++L) {
     if (K == 1 && out[L - 1].cap <= kTailMax) break;
     lod_level(true, out[L - 1], n_levels + L - 1, out[L], n_levels + L, n_levels + levels, pstart,
-              partial, s, true);
+              partial, tu.grids[kTuneLod], s, true);
     if (K > 1) {
       if (L == 1)
-        cluster_level(pstart, n_levels + 1, out[0].w, out[0].S, nullptr, 1, out[0].cap, K, kmeans_iters, lobes[0], s);
+        cluster_level(pstart, n_levels + 1, out[0].w, out[0].S, nullptr, 1, out[0].cap, K, kmeans_iters, lobes[0],
+                      tu.grids[kTuneCluster], s);
       else
         cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
-                      kmeans_iters, lobes[L - 1], s);
+                      kmeans_iters, lobes[L - 1], tu.grids[kTuneCluster], s);
     }
   }
   if (L < levels) {
@@ -468,17 +505,6 @@ void vx_graph_destroy(vx_graph graph) {
   delete graph;
 }
 
-vx_status vx_set_launch_grids(const int32_t* grids, int32_t n) {
-  if (!grids || n < 1 || n > kTuneCount) return VX_ERR_ARG;
-  for (int i = 0; i < n; ++i)
-    if (grids[i] < 64 || grids[i] > 16384) return VX_ERR_ARG;
-  for (int i = 0; i < n; ++i) g_grids[i] = grids[i];
-  return VX_OK;
-}
-
-void vx_get_launch_grids(int32_t* grids, int32_t n) {
-  for (int i = 0; i < n && i < kTuneCount; ++i) grids[i] = g_grids[i];
-}
 
 vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {
   if (!stats) return VX_ERR_ARG;

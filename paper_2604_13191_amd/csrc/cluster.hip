@@ -491,21 +491,21 @@ __global__ void __launch_bounds__(kBlock) k_cluster_adapt(const int64_t* __restr
 }
 
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
-                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, hipStream_t s) {
+                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s) {
   const int need = 8 * Kc;
   // timing names by group width: the first level (one lobe per child) and the levels above
   VX_TIMED(need <= 8 ? "lod_cluster" : "lod_cluster_up", s);
   if (need <= 8)
-    hipLaunchKernelGGL(k_cluster<8>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+    hipLaunchKernelGGL(k_cluster<8>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
   else if (need <= 16)
-    hipLaunchKernelGGL(k_cluster<16>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+    hipLaunchKernelGGL(k_cluster<16>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
                        iters, out);
   else if (need <= 32)
-    hipLaunchKernelGGL(k_cluster_adapt<32>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
+    hipLaunchKernelGGL(k_cluster_adapt<32>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
                        Kc, cap_c, K, iters, out);
   else
-    hipLaunchKernelGGL(k_cluster_adapt<64>, dim3(tuned_grid(kTuneCluster)), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
+    hipLaunchKernelGGL(k_cluster_adapt<64>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
                        Kc, cap_c, K, iters, out);
 }
 

@@ -327,7 +327,7 @@ void lod_init(const int64_t* src, int64_t cap, int64_t* n_levels, int64_t count,
 }
 
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
-               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s, bool batch) {
+               int64_t* flags, int64_t* pstart, int64_t* partial, int grid_blocks, hipStream_t s, bool batch) {
   {
     VX_TIMED("lod_heads", s);
     if (batch)
@@ -341,7 +341,7 @@ void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_vo
                   LodTotal{pstart, n_out, flags, out.cap}, n_in, 0, partial, s);
   }
   VX_TIMED("lod_reduce", s);
-  const dim3 grid(tuned_grid(kTuneLod));
+  const dim3 grid(grid_blocks);
   if (batch)
     hipLaunchKernelGGL((k_lod_reduce<uint64_t, true>), grid, dim3(kBlock), 0, s, in, pstart, n_out, out);
   else if (key64)

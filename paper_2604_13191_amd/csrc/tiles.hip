@@ -148,10 +148,10 @@ __device__ __forceinline__ void unit_box(int lev, int ncell, int32_t sz[3]) {
 }
 
 // Per tile (one block each): walk the octant tree depth first in Morton order and count (PASS 0)
-// or write (PASS 1) the units.  A cell whose candidates exceed kUnitCand is split; among its
+// or write (PASS 1) the units.  A cell whose candidates exceed the unit budget is split; among its
 // eight children, aligned groups of four or two siblings whose candidates fit together become
 // one unit, the others single-cell units or further splits.  A single voxel is always a unit
-// (summed in streaming order when it holds more than kUnitCand candidates).
+// (summed in streaming order when it holds more than the budget).
 namespace {
 enum { kEntUnit = 0, kEntSplit = 1 };
 struct PlanEntry {
@@ -167,8 +167,8 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
                                                       const uint32_t* __restrict__ rprim,
                                                       const int64_t* __restrict__ tstart,
                                                       const int64_t* __restrict__ ctl, int tb, int batch,
-                                                      int64_t* __restrict__ ucnt, const int64_t* __restrict__ uoff,
-                                                      Unit* __restrict__ units) {
+                                                      int64_t budget, int64_t* __restrict__ ucnt,
+                                                      const int64_t* __restrict__ uoff, Unit* __restrict__ units) {
   __shared__ PlanEntry stk[48];
   __shared__ PlanEntry g[8];                         // one split's groups, before they are pushed
   __shared__ int64_t csum[8];
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
       r.o[2] = to[2];
       r.lev = int16_t(tb);
       r.ncell = 1;
-      r.kind = (c <= kUnitCand || tb == 0) ? kEntUnit : kEntSplit;
+      r.kind = (c <= budget || tb == 0) ? kEntUnit : kEntSplit;
       r.cand = c;
       stk[0] = r;
       s_top = 1;
@@ -293,18 +293,18 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
         };
         for (int q = 0; q < 8; q += 4) {
           const int64_t s4 = csum[q] + csum[q + 1] + csum[q + 2] + csum[q + 3];
-          if (s4 <= kUnitCand) {
+          if (s4 <= budget) {
             child(q, 4, s4, kEntUnit);
             continue;
           }
           for (int pp = q; pp < q + 4; pp += 2) {
             const int64_t s2 = csum[pp] + csum[pp + 1];
-            if (s2 <= kUnitCand) {
+            if (s2 <= budget) {
               child(pp, 2, s2, kEntUnit);
               continue;
             }
             for (int k = pp; k < pp + 2; ++k)
-              child(k, 1, csum[k], (csum[k] <= kUnitCand || E.lev - 1 == 0) ? kEntUnit : kEntSplit);
+              child(k, 1, csum[k], (csum[k] <= budget || E.lev - 1 == 0) ? kEntUnit : kEntSplit);
           }
         }
         for (int i = ng - 1; i >= 0; --i) stk[top++] = g[i];
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
     // units per tile (low half); a tile that is one unit as a whole also keeps its candidate
     // count plus one (high half), so that the writing pass skips it
     if (PASS == 0 && threadIdx.x == 0)
-      ucnt[t] = nu | ((c <= kUnitCand || tb == 0) && c < (int64_t(1) << 30) ? (c + 1) << 32 : 0);
+      ucnt[t] = nu | ((c <= budget || tb == 0) && c < (int64_t(1) << 30) ? (c + 1) << 32 : 0);
     __syncthreads();
   }
 }
@@ -338,12 +338,12 @@ struct UnitTotal {
 // the unit kernel: test, weigh, group by voxel and sum in LDS
 // ---------------------------------------------------------------------------------------------
 struct UnitLds {
-  uint32_t* start;    // [kUnitCand] after the batches: the voxels' keys and range ends (2 x u16)
-  uint16_t* key;      // [kUnitCand] unit-local Morton code of each pair
-  uint16_t* idx;      // [kUnitCand] grouped order -> pair
-  float* w;           // [kUnitCand] (before the weights: the queue of undecided candidates)
-  uint32_t* prim;     // [kUnitCand]
-  uint16_t* ckey;     // [kUnitCand] per candidate of the batch: kTouch | its unit-local key,
+  uint32_t* start;    // [budget]   after the batches: the voxels' keys and range ends (2 x u16)
+  uint16_t* key;      // [budget]   unit-local Morton code of each pair
+  uint16_t* idx;      // [budget]   grouped order -> pair
+  float* w;           // [budget]   (before the weights: the queue of undecided candidates)
+  uint32_t* prim;     // [budget]  
+  uint16_t* ckey;     // [budget]   per candidate of the batch: kTouch | its unit-local key,
                       // kUndecided, or 0 for a miss (after the batches: each pair's arrival
                       // slot among its voxel's pairs)
   uint64_t* sbm;      // [64] batch: bit c set where a slot's first candidate is c
@@ -369,16 +369,24 @@ constexpr int32_t stable_mean() { return KIND == 0 ? 24 : 4; }
 constexpr int32_t kUnitKeys = 4096;
 static_assert(kBlock * 9 * 4 >= kUnitKeys * 2, "per-key counters live in the record batch's space");
 static_assert(kBlock * 16 == kUnitKeys, "each thread owns 16 keys in the scan of the counters");
-static_assert(kUnitCand <= 0xffff, "pair positions are 16-bit");
-static_assert(kUnitCand % (kWaves * 64) == 0, "each wave's queue holds all of its candidates");
+
 // a candidate's outcome and key in one 16-bit word (keys below 4096)
 constexpr uint16_t kTouch = 0x8000, kUndecided = 0x4000;
 static_assert(kUnitKeys <= kUndecided, "keys fit below the flags");
 
-constexpr size_t kUnitLdsBytes = kUnitCand * (4 + 2 + 2 + 4 + 4 + 2) + 64 * 8 + 64 * 4 +
-                                 kBlock * 4 * (8 + 9 + 1) + kBlock * 8 + (kWaves + 1) * 4 + 8 * 4 + 256;
-static_assert(2 * kUnitLdsBytes <= 160 * 1024, "two fiber units per CU");
+// LDS of a unit with a budget of CAND candidates; the budgets and the unit kernel's waves per
+// SIMD that the LDS then allows (160 KB per CU: 2 blocks at 3072 and 2048, 3 at 1536, 4 at 1024)
+template <int CAND>
+constexpr size_t unit_lds_bytes() {
+  return size_t(CAND) * (4 + 2 + 2 + 4 + 4 + 2) + 64 * 8 + 64 * 4 + kBlock * 4 * (8 + 9 + 1) + kBlock * 8 +
+         (kWaves + 1) * 4 + 8 * 4 + 256;
+}
+constexpr int unit_waves(int cand) { return cand <= 1024 ? 4 : (cand <= 1536 ? 3 : 2); }
+static_assert(2 * unit_lds_bytes<3072>() <= 160 * 1024, "two units per CU at the largest budget");
+static_assert(3 * unit_lds_bytes<1536>() <= 160 * 1024, "three units per CU at 1536");
+static_assert(4 * unit_lds_bytes<1024>() <= 160 * 1024, "four units per CU at 1024");
 
+template <int CAND>
 __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
   UnitLds L;
   size_t off = 0;
@@ -388,12 +396,12 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
     return p;
   };
   L.sbm = reinterpret_cast<uint64_t*>(take(64 * 8));
-  L.start = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
-  L.w = reinterpret_cast<float*>(take(kUnitCand * 4));
-  L.prim = reinterpret_cast<uint32_t*>(take(kUnitCand * 4));
-  L.key = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
-  L.idx = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
-  L.ckey = reinterpret_cast<uint16_t*>(take(kUnitCand * 2));
+  L.start = reinterpret_cast<uint32_t*>(take(CAND * 4));
+  L.w = reinterpret_cast<float*>(take(CAND * 4));
+  L.prim = reinterpret_cast<uint32_t*>(take(CAND * 4));
+  L.key = reinterpret_cast<uint16_t*>(take(CAND * 2));
+  L.idx = reinterpret_cast<uint16_t*>(take(CAND * 2));
+  L.ckey = reinterpret_cast<uint16_t*>(take(CAND * 2));
   L.spre = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.bprim = reinterpret_cast<int32_t*>(take(kBlock * 4));
   L.blo = reinterpret_cast<int32_t*>(take(3 * kBlock * 4));
@@ -516,8 +524,8 @@ __device__ __forceinline__ void write_voxel(const Stage& st, int64_t i, uint64_t
   st.S[5 * st.cap + i] = m.yz;
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec, const float4* __restrict__ dirs,
+template <int KIND, int CAND>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(unit_waves(CAND)))) k_unit(const int32_t* __restrict__ rec, const float4* __restrict__ dirs,
                                                  const uint32_t* __restrict__ rprim,
                                                  const int64_t* __restrict__ tstart, const Unit* __restrict__ units,
                                                  const int64_t* __restrict__ ctl, Lat L, const Lat* __restrict__ lats,
@@ -525,7 +533,9 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
                                                  int64_t* __restrict__ usoff, Stage st, int64_t* stage_ctr,
                                                  int64_t* stats) {
   extern __shared__ double lds_dyn[];
-  const UnitLds S = carve_unit_lds(reinterpret_cast<char*>(lds_dyn));
+  static_assert(CAND <= 0xffff, "pair positions are 16-bit");
+  static_assert(CAND % (kWaves * 64) == 0, "each wave's queue holds all of its candidates");
+  const UnitLds S = carve_unit_lds<CAND>(reinterpret_cast<char*>(lds_dyn));
   const int64_t n_units = ctl[CTL_N_UNITS];
   const int tid = threadIdx.x;
   for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
@@ -534,7 +544,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     int32_t usz[3];
     unit_box(U.lev, U.ncell, usz);
     const uint64_t m0 = morton3(uint32_t(U.o[0]), uint32_t(U.o[1]), uint32_t(U.o[2]));   // the unit's first key
-    const bool stream = U.cand > kUnitCand;          // a single voxel holding too many candidates
+    const bool stream = U.cand > CAND;          // a single voxel holding too many candidates
     int32_t np = 0;                                   // pairs so far (uniform)
     Moment acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // streaming sums (thread 0)
     uint32_t acc_n = 0;
@@ -583,7 +593,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       // which is primitive order.
       const int wv = tid >> 6, lane = tid & 63;
       const uint64_t lt = (uint64_t(1) << lane) - 1;
-      uint32_t* wq = reinterpret_cast<uint32_t*>(S.w) + wv * (kUnitCand / kWaves);
+      uint32_t* wq = reinterpret_cast<uint32_t*>(S.w) + wv * (CAND / kWaves);
       int32_t nq = 0;                                  // this wave's queue (uniform)
       for (int32_t c0 = wv * 64; c0 < cb; c0 += kBlock) {
         const int32_t c = c0 + lane;
@@ -642,7 +652,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
           const uint64_t mh = __ballot(hit);
           if (hit) {
             const int32_t q = base + int32_t(__popcll(mh & lt));
-            if (q < kUnitCand) {
+            if (q < CAND) {
               S.key[q] = uint16_t(S.ckey[c] & (kTouch - 1));
               S.prim[q] = uint32_t(S.bprim[find_slot(S, c)]);
             } else {
@@ -673,7 +683,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
       __syncthreads();
       continue;
     }
-    const int32_t npairs = np < kUnitCand ? np : kUnitCand;
+    const int32_t npairs = np < CAND ? np : CAND;
     // Group the pairs by voxel with one counter per key of the unit's range (at most 4096 keys;
     // 16-bit counts packed two to a word, in the record batch's space, dead now); the weights
     // are computed in the same pass.  Each pair keeps its arrival slot among its voxel's pairs.
@@ -681,7 +691,7 @@ __global__ void __launch_bounds__(kBlock) k_unit(const int32_t* __restrict__ rec
     uint16_t* kst = reinterpret_cast<uint16_t*>(S.brec);                 // [4096] then starts
     uint16_t* slot = S.ckey;                                              // [npairs]
     uint16_t* vkey = reinterpret_cast<uint16_t*>(S.start);               // [nv] key of voxel v
-    uint16_t* vend = reinterpret_cast<uint16_t*>(S.start) + kUnitCand;   // [nv] end of its pairs
+    uint16_t* vend = reinterpret_cast<uint16_t*>(S.start) + CAND;   // [nv] end of its pairs
     for (int32_t j = tid; j < kUnitKeys / 2; j += kBlock) kcw[j] = 0u;
     __syncthreads();
     for (int32_t i = tid; i < npairs; i += kBlock) {
@@ -1018,7 +1028,8 @@ struct ArrOut64 {
 
 vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                         int64_t n_fib, float radius, int64_t max_rec, int64_t max_units, void* ws_ptr,
-                        const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb) {
+                        const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb,
+                        const Tuning& tu) {
   const bool key64 = batch || g->log2_res > 10;
   TileWs w;
   tile_ws_layout(n_prims, max_rec, max_units, out->cap, key64, ws_ptr, &w);
@@ -1063,10 +1074,11 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   }
   {
     VX_TIMED("unit_plan", s);
-    const int grid = tuned_grid(kTunePlan);
+    const int grid = tu.grids[kTunePlan];
+    const int64_t budget = tu.unit_budget;
 #define VX_PLAN(P, K)                                                                                        \
   hipLaunchKernelGGL((k_unit_plan<P, K>), dim3(grid), dim3(kBlock), 0, s, w.rec, (const K*)R.keys, R.prim, w.tstart, \
-                     w.ctl, tb, batch ? 1 : 0, w.ucnt, w.uoff, w.units)
+                     w.ctl, tb, batch ? 1 : 0, budget, w.ucnt, w.uoff, w.units)
     if (key64) VX_PLAN(0, uint64_t); else VX_PLAN(0, uint32_t);
     device_scan(UnitCountIn{w.ucnt}, ArrOut64{w.uoff}, UnitTotal{w.uoff, w.ctl, stats, max_units}, w.ctl + CTL_N_TILES,
                 0, w.partial, s);
@@ -1075,23 +1087,34 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   }
   {
     VX_TIMED(kind == 0 ? "unit_tri" : "unit_fib", s);
-    const size_t lds = kUnitLdsBytes;
-    static bool attr[2] = {false, false};
-    if (!attr[kind]) {
-      if (kind == 0)
-        (void)hipFuncSetAttribute((const void*)k_unit<0>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-      else
-        (void)hipFuncSetAttribute((const void*)k_unit<1>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-      attr[kind] = true;
-    }
     const Lat L = make_lat(g, kind, radius);
     const Lat* lats = batch ? batch->lats : nullptr;
-    if (kind == 0)
-      hipLaunchKernelGGL(k_unit<0>, dim3(tuned_grid(kTuneUnit)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
-                         w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);
-    else
-      hipLaunchKernelGGL(k_unit<1>, dim3(tuned_grid(kTuneUnit)), dim3(kBlock), lds, s, w.rec, w.dirs, R.prim,
-                         w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);
+    const int ugrid = tu.grids[kTuneUnit];
+#define VX_UNIT(KD, C)                                                                                           \
+  do {                                                                                                          \
+    static bool attr_ = false;                                                                                  \
+    if (!attr_) {                                                                                               \
+      (void)hipFuncSetAttribute((const void*)k_unit<KD, C>, hipFuncAttributeMaxDynamicSharedMemorySize,        \
+                                int(unit_lds_bytes<C>()));                                                      \
+      attr_ = true;                                                                                             \
+    }                                                                                                           \
+    hipLaunchKernelGGL((k_unit<KD, C>), dim3(ugrid), dim3(kBlock), unit_lds_bytes<C>(), s, w.rec, w.dirs, R.prim, \
+                       w.tstart, w.units, w.ctl, L, lats, w.unv, w.unp, w.usoff, w.st, w.stage_ctr, stats);    \
+  } while (0)
+#define VX_UNIT_KIND(KD)                                        \
+  switch (tu.unit_budget) {                                     \
+    case 1024: VX_UNIT(KD, 1024); break;                        \
+    case 1536: VX_UNIT(KD, 1536); break;                        \
+    case 2048: VX_UNIT(KD, 2048); break;                        \
+    default: VX_UNIT(KD, 3072); break;                          \
+  }
+    if (kind == 0) {
+      VX_UNIT_KIND(0);
+    } else {
+      VX_UNIT_KIND(1);
+    }
+#undef VX_UNIT_KIND
+#undef VX_UNIT
   }
   {
     VX_TIMED("unit_compact", s);
@@ -1100,10 +1123,10 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     hipLaunchKernelGGL(k_unit_sums_apply, dim3(kGrid), dim3(kBlock), 0, s, w.unv, w.ctl, w.partial, w.upos, stats,
                        out->cap);
     if (key64)
-      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(tuned_grid(kTuneCompact)), dim3(kBlock), 0, s, w.unv,
+      hipLaunchKernelGGL(k_unit_compact<uint64_t>, dim3(tu.grids[kTuneCompact]), dim3(kBlock), 0, s, w.unv,
                          w.usoff, w.upos, w.ctl, w.st, *out);
     else
-      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(tuned_grid(kTuneCompact)), dim3(kBlock), 0, s, w.unv,
+      hipLaunchKernelGGL(k_unit_compact<uint32_t>, dim3(tu.grids[kTuneCompact]), dim3(kBlock), 0, s, w.unv,
                          w.usoff, w.upos, w.ctl, w.st, *out);
   }
   return hipGetLastError() == hipSuccess ? VX_OK : VX_ERR_HIP;

@@ -13,7 +13,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kGrid = 1024;          // persistent grid of the streaming kernels: 4 blocks per CU
 constexpr int kPatchShift = 33;      // batched keys: patch id above a 33-bit Morton code (R <= 2048)
 constexpr int kTileBits = 4;         // leaf tiles of 16^3 voxels
-constexpr int kUnitCand = 3072;      // candidates (so pairs) one work unit keeps in LDS
+constexpr int kUnitCand = 3072;      // the largest unit budget: candidates (so pairs) a unit keeps in LDS
 
 // ---------------------------------------------------------------------------------------------
 // Kernel timing (measurement only): events around every launch when enabled.
@@ -200,10 +200,18 @@ inline void device_scan(In in, Out out, Total total, const int64_t* n_ptr, int64
 }
 
 // ---------------------------------------------------------------------------------------------
-// Launch geometry chosen by the autotuner: grid sizes of the persistent streaming kernels.
+// The tuning of one call (vx_tuning resolved): tile edge, unit budget and the grid sizes of the
+// persistent streaming kernels.  It changes the decomposition of the work, never a result.
 // ---------------------------------------------------------------------------------------------
 enum { kTuneUnit = 0, kTunePlan, kTuneCompact, kTuneLod, kTuneCluster, kTuneCount };
-int tuned_grid(int which);
+static_assert(kTuneCount == VX_TUNE_COUNT, "one grid per tuned kernel");
+struct Tuning {
+  int tile_bits;      // 2..4
+  int unit_budget;    // 1024, 1536, 2048 or 3072 candidates
+  int grids[kTuneCount];
+};
+// defaults for NULL or zero fields (kind 0 triangles, 1 fibers); false on an invalid value
+bool resolve_tuning(const vx_tuning* t, int kind, Tuning* out);
 
 // ---------------------------------------------------------------------------------------------
 // Workspace carving (256-byte aligned sub-buffers).
@@ -295,7 +303,7 @@ struct HeadOut {
 // new count clamped to out.cap, and flags the capacity bit when it had to be clamped; pstart
 // receives every parent's first child
 void lod_level(bool key64, const vx_voxels& in, const int64_t* n_in, const vx_voxels& out, int64_t* n_out,
-               int64_t* flags, int64_t* pstart, int64_t* partial, hipStream_t s, bool batch = false);
+               int64_t* flags, int64_t* pstart, int64_t* partial, int grid, hipStream_t s, bool batch = false);
 void lod_init(const int64_t* src, int64_t cap, int64_t* n_levels, int64_t count, hipStream_t s);
 // levels lv[1 .. count] from lv[0] in one single-block launch (small levels, no lobes):
 // n[i] the device count of lv[i]
@@ -306,7 +314,7 @@ void lod_tail(bool key64, bool batch, const vx_voxels* lv, int64_t* const* n, in
 // lobe clustering of one level (cluster.hip): parents [0, *n_par) with children
 // [pstart[p], pstart[p+1]) whose lobes are cw[k * cap_c + c], cS[(j * Kc + k) * cap_c + c]
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
-                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, hipStream_t s);
+                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s);
 
 // the front half of voxelize (prims.hip): pairs in emission order (by primitive, then candidate)
 struct FrontWs {
@@ -358,8 +366,10 @@ void sggx_compact_run(const float* w, const float* S, const int64_t* n, int64_t 
                       float* vec, uint8_t* code, hipStream_t s);
 void sggx_decode_run(const uint8_t* code, const int64_t* n, int64_t cap, float* S, hipStream_t s);
 
+// tb: tile bits of this call (the tuning's, at most log2 of the grid)
 vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                         int64_t n_fib, float radius, int64_t max_rec, int64_t max_units, void* ws,
-                        const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb);
+                        const vx_voxels* out, int64_t* stats, hipStream_t s, const BatchLattice* batch, int tb,
+                        const Tuning& tu);
 
 }  // namespace vx

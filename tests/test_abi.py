@@ -57,14 +57,15 @@ def test_argument_errors_before_any_launch(lib):
     f = lib.vx_voxelize_triangles
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.POINTER(CGrid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
-                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p]
     bad = CGrid((ctypes.c_double * 3)(0, 0, 0), 0.0, 4)
-    assert f(ctypes.byref(bad), None, 0, 0, 0, None, 0, None, None, None) == 1
+    assert f(ctypes.byref(bad), None, 0, 0, 0, None, 0, None, None, None, None) == 1
     good = CGrid((ctypes.c_double * 3)(0, 0, 0), 1.0, 4)
-    assert f(ctypes.byref(good), None, 0, 0, 0, None, 0, None, None, None) == 1     # no outputs
+    assert f(ctypes.byref(good), None, 0, 0, 0, None, 0, None, None, None, None) == 1     # no outputs
 
 
-def test_batch_graph_and_grid_calls_host_side(lib):
+def test_batch_and_graph_calls_host_side(lib):
     ws = lib.vx_batch_workspace_size
     ws.restype = ctypes.c_size_t
     ws.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
@@ -73,7 +74,7 @@ def test_batch_graph_and_grid_calls_host_side(lib):
     assert ws(2, 1, 1, 1, 0) == 0
     b = lib.vx_batch_build
     b.restype = ctypes.c_int
-    assert b(None, None, 1, None, 0, None, 0, 1, 1, 0, 0, 0, None, None, None, None, None, None, 0, None) == 1
+    assert b(None, None, 1, None, 0, None, 0, 1, 1, 0, 0, 0, None, None, None, None, None, None, 0, None, None) == 1
     gb = lib.vx_graph_begin
     gb.restype = ctypes.c_int
     gb.argtypes = [ctypes.c_void_p]
@@ -84,21 +85,26 @@ def test_batch_graph_and_grid_calls_host_side(lib):
     assert gl(None, None) == 1
     lib.vx_graph_destroy.argtypes = [ctypes.c_void_p]
     lib.vx_graph_destroy(None)
-    sg, gg = lib.vx_set_launch_grids, lib.vx_get_launch_grids
-    sg.restype = ctypes.c_int
-    arr = (ctypes.c_int32 * 5)()
-    gg(arr, 5)
-    default = list(arr)
-    assert default == [1024, 1024, 4096, 1024, 1024]
-    assert sg((ctypes.c_int32 * 5)(64, 128, 256, 512, 16384), 5) == 0
-    gg(arr, 5)
-    assert list(arr) == [64, 128, 256, 512, 16384]
-    assert sg((ctypes.c_int32 * 5)(63, 128, 256, 512, 1024), 5) == 1
-    assert sg((ctypes.c_int32 * 5)(64, 128, 256, 512, 16385), 5) == 1
-    assert sg((ctypes.c_int32 * 6)(*([1024] * 6)), 6) == 1
-    gg(arr, 5)
-    assert list(arr) == [64, 128, 256, 512, 16384]      # a rejected call changes nothing
-    assert sg((ctypes.c_int32 * 5)(*default), 5) == 0
+
+
+class CTuning(ctypes.Structure):
+    _fields_ = [("tile_bits", ctypes.c_int32), ("unit_budget", ctypes.c_int32), ("grids", ctypes.c_int32 * 5)]
+
+
+def test_tuning_values_are_checked_before_any_launch(lib):
+    class CGrid(ctypes.Structure):
+        _fields_ = [("bmin", ctypes.c_double * 3), ("extent", ctypes.c_double), ("log2_res", ctypes.c_int32)]
+    f = lib.vx_voxelize_triangles
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(CGrid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(CTuning),
+                  ctypes.c_void_p]
+    good = CGrid((ctypes.c_double * 3)(0, 0, 0), 1.0, 4)
+    grids = (ctypes.c_int32 * 5)(0, 0, 0, 0, 0)
+    for bad in (CTuning(5, 0, grids), CTuning(1, 0, grids), CTuning(0, 1000, grids), CTuning(0, 4096, grids),
+                CTuning(0, 0, (ctypes.c_int32 * 5)(63, 0, 0, 0, 0)), CTuning(0, 0, (ctypes.c_int32 * 5)(0, 0, 0, 0, 16385))):
+        assert f(ctypes.byref(good), None, 0, 0, 0, None, 0, None, None, ctypes.byref(bad), None) == 1
+    assert not hasattr(lib, "vx_set_launch_grids")           # no tuning state in the library
 
 
 def test_sggx_compact_argument_errors(lib):

@@ -6,7 +6,8 @@
 * Each patch of a small batch agrees with the FP64 oracle (keys/counts/masks exact, w and S
   to the bar of tests/parity.py, lobes as in the clustering tests).
 * A captured graph replays to the eager result, replay after replay, with eager work between.
-* Other launch grids (the autotuner's knob) do not change a bit of the result.
+* Other tunings (tile edge, unit budget, launch grids: the autotuner's knobs) do not change a bit
+  of the result.
 * At the full uneven workload (64 patches, 100 .. 20,000 fibers, 256^3 .. 2048^3, K = 4) the
   batched build equals the 64 single-instance builds, and its two smallest patches match the
   oracle.
@@ -195,32 +196,47 @@ def test_graph_replay_matches_eager(vx):
     del g
 
 
-def test_launch_grids_do_not_change_results(vx):
+def test_tunings_do_not_change_results(vx):
+    """Tile edge, unit budget and launch grids change the decomposition, never a bit of the result:
+    a small uneven batch (fibers) and a brushed-metal window (triangles, 64-bit keys, K = 4)."""
     import torch
+    import synth
     wls = _small_batch(8)
-    say("case: small uneven batch under other launch grids")
+    say("case: small uneven batch and a brushed-metal window under other tunings")
+    tunings = [vx.Tuning(3, 1024, (64, 64, 64, 64, 64)), vx.Tuning(4, 1536, (4096, 256, 16384, 512, 2048)),
+               vx.Tuning(2, 2048, (0, 0, 0, 0, 0)), vx.Tuning(4, 3072, (128, 8192, 256, 16384, 64))]
     plan = vx.BatchPlan(_patches(vx, wls), K=4, iters=2)
     plan.run()
     plan.check()
     ref = [(v.keys[:v.n].clone(), v.w[:v.n].clone(), v.S[:, :v.n].clone()) for v in plan.out]
     ref_l = [lb.S[:, :, :lb.n].clone() for lb in plan.lobes]
-    default = vx.get_launch_grids()
-    try:
-        for grids in ([64, 64, 64, 64, 64], [4096, 256, 16384, 512, 2048]):
-            vx.set_launch_grids(grids)
-            assert vx.get_launch_grids() == grids
-            plan.run()
-            plan.check()
-            for v, r in zip(plan.out, ref):
-                assert torch.equal(v.keys[:v.n], r[0]) and torch.equal(v.w[:v.n], r[1])
-                assert torch.equal(v.S[:, :v.n], r[2])
-            for lb, r in zip(plan.lobes, ref_l):
-                assert torch.equal(lb.S[:, :, :lb.n], r)
-            say("grids", grids, "ok")
-        with pytest.raises(vx.VxError):
-            vx.set_launch_grids([32, 1024, 1024, 1024, 1024])
-    finally:
-        vx.set_launch_grids(default)
+    for t in tunings:
+        p2 = vx.BatchPlan(_patches(vx, wls), K=4, iters=2, tuning=t)
+        p2.run()
+        p2.check()
+        for v, r in zip(p2.out, ref):
+            assert torch.equal(v.keys[:v.n], r[0]) and torch.equal(v.w[:v.n], r[1])
+            assert torch.equal(v.S[:, :v.n], r[2])
+        for lb, r in zip(p2.lobes, ref_l):
+            assert torch.equal(lb.S[:, :, :lb.n], r)
+        say("batch", t, "ok")
+    wl = synth.brushed_metal(window=96)
+    tris = torch.as_tensor(wl.tris).cuda()
+    base = vx.voxelize_triangles(tris, wl.grid)
+    lod0, lobes0 = vx.build_lod(wl.grid, base, 6, K=4, return_lobes=True)
+    for t in tunings:
+        v = vx.voxelize_triangles(tris, wl.grid, tuning=t)
+        assert v.n == base.n
+        for name in ("keys", "count", "w", "S"):
+            assert torch.equal(getattr(v, name)[..., :v.n], getattr(base, name)[..., :v.n]), (t, name)
+        lod, lobes = vx.build_lod(wl.grid, v, 6, K=4, return_lobes=True, tuning=t)
+        for a, b in zip(lod[1:], lod0[1:]):
+            assert torch.equal(a.w[:a.n], b.w[:b.n]) and torch.equal(a.S[:, :a.n], b.S[:, :b.n])
+        for a, b in zip(lobes, lobes0):
+            assert torch.equal(a.S[:, :, :a.n], b.S[:, :, :b.n])
+        say("triangles", t, "ok")
+    with pytest.raises(vx.VxError):
+        vx.voxelize_triangles(tris, wl.grid, tuning=vx.Tuning(0, 1000))
 
 
 def test_batch_errors(vx):

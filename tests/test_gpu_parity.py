@@ -289,7 +289,8 @@ def test_errors(vx):
     assert L.vx_voxelize_workspace_size(0, 1 << 32, 10, 10, 10, 4) == 0
     assert L.vx_voxelize_workspace_size(2, 10, 10, 10, 10, 4) == 0
     bad = vx.CGrid((vx.ctypes.c_double * 3)(0, 0, 0), -1.0, 4)
-    st = L.vx_voxelize_triangles(vx.ctypes.byref(bad), vx._ptr(t), 1, 0, 0, None, 0, None, vx._ptr(plan.stats), None)
+    st = L.vx_voxelize_triangles(vx.ctypes.byref(bad), vx._ptr(t), 1, 0, 0, None, 0, None, vx._ptr(plan.stats), None,
+                                 None)
     assert st == 1
     torch.cuda.synchronize()
 

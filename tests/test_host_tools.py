@@ -52,31 +52,30 @@ def test_traffic_is_reported_only_for_the_measured_sources(tmp_path, monkeypatch
     assert bench.traffic_bytes("plain_weave", "unit_fib") is None
 
 
-def test_tuner_table_round_trip(tmp_path, monkeypatch):
+def test_tuner_table_round_trip(tmp_path):
     from paper_2604_13191_amd import autotune
-
-    calls = []
-
-    class FakeVx:
-        TUNE_KERNELS = ("unit_fib", "unit_plan", "unit_compact", "lod_reduce", "lod_cluster")
-
-        @staticmethod
-        def set_launch_grids(g):
-            calls.append(list(g))
-
-    path = tmp_path / "grids.json"
-    path.write_text(json.dumps({"device": "test", "tables": {"w": {"grids": [512, 1024, 2048, 256, 8192]}}}))
-    monkeypatch.setattr(autotune, "vx", FakeVx)
-    assert autotune.apply("w", str(path)) == [512, 1024, 2048, 256, 8192]
-    assert calls == [[512, 1024, 2048, 256, 8192]]
-    assert autotune.apply("missing", str(path)) is None
-    assert autotune.apply("w", str(tmp_path / "absent.json")) is None
+    import paper_2604_13191_amd as vx
+    path = tmp_path / "tunings.json"
+    t = vx.Tuning(3, 1536, (512, 1024, 2048, 256, 8192))
+    path.write_text(json.dumps({"device": "test", "tables": {"w": {"tuning": t.as_dict()}}}))
+    assert autotune.load("w", str(path)) == t
+    assert autotune.load("missing", str(path)) is None
+    assert autotune.load("w", str(tmp_path / "absent.json")) is None
+    c = t.cstruct()
+    assert (c.tile_bits, c.unit_budget, list(c.grids)) == (3, 1536, [512, 1024, 2048, 256, 8192])
+    assert vx.Tuning.from_dict(t.as_dict()) == t and vx.Tuning.from_dict(None) is None
 
 
-def test_committed_tables_are_well_formed():
+def test_committed_tunings_are_well_formed():
+    import os
     from paper_2604_13191_amd import autotune
+    if not os.path.exists(autotune.TABLE):
+        return
     with open(autotune.TABLE) as f:
         t = json.load(f)
     for name, tab in t["tables"].items():
-        assert len(tab["grids"]) == 5, name
-        assert all(64 <= g <= 16384 for g in tab["grids"]), name
+        tu = tab["tuning"]
+        assert tu["tile_bits"] in (0, 2, 3, 4), name
+        assert tu["unit_budget"] in (0, 1024, 1536, 2048, 3072), name
+        assert len(tu["grids"]) == 5 and all(g == 0 or 64 <= g <= 16384 for g in tu["grids"]), name
+        assert tab["step_ms"]["tuned"] > 0 and tab["step_ms"]["default"] > 0, name
