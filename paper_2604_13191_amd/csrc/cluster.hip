@@ -96,7 +96,7 @@ struct ClusterLds {
 // [pstart[p], pstart[p+1]) in the level below carry lobes cw[k * cap_c + c] and
 // cS[(j * Kc + k) * cap_c + c] (cnl == nullptr: one lobe per child, present when its weight is
 // positive).
-template <int G>
+template <int G, bool NARROW_ONLY = false>
 __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const int64_t* __restrict__ pstart,
                                               const float* __restrict__ cw, const float* __restrict__ cS,
                                               const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
@@ -105,7 +105,7 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
   const int g = lane % G, gi = lane / G;
   const int64_t cap = out.cap;
   const int64_t p = base + gi;
-  const bool live = p < n_par;
+  bool live = p < n_par;
   // ---- gather the children's lobes in canonical order (child, then lobe), compacted to lanes
   // 0..n-1.  Lane g takes slots g, g + G, ... of the 8 Kc (child, lobe) slots; n <= G is the
   // caller's guarantee (G >= 8 Kc, or a parent known to gather at most G lobes).
@@ -139,6 +139,10 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
       for (int j = 0; j < 6; ++j) L.lS[gi][j][m] = S[j];
     }
     n += __popcll(vm);
+  }
+  if (NARROW_ONLY && n > G) {
+    live = false;                                  // more lobes than the group holds: the wide pass
+    n = 0;
   }
   n = n < G ? n : G;
   __builtin_amdgcn_wave_barrier();
@@ -334,11 +338,24 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
         if (rescan) {
           best = INFINITY;
           bjr = G;
-          for (int j = 0; j < n; ++j) {
-            const float c = L.mat[gi][j][g];
-            if (c < best) {
-              best = c;
-              bjr = j;
+          if constexpr (G <= 16) {
+            // the whole row, its loads issued together (unrolled over the group width)
+            float c[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) c[j] = j < n ? L.mat[gi][j][g] : INFINITY;
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+              if (c[j] < best) {
+                best = c[j];
+                bjr = j;
+              }
+          } else {
+            for (int j = 0; j < n; ++j) {
+              const float c = L.mat[gi][j][g];
+              if (c < best) {
+                best = c;
+                bjr = j;
+              }
             }
           }
         }
@@ -359,9 +376,10 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
     for (int it = 0; it < iters; ++it) {
       int assign = -1;
       if (mine) {
+        // nearest active centroid (ties to the lowest index), walking the active set
         float bestd = INFINITY;
-        for (int k = 0; k < n; ++k) {
-          if (!((act >> k) & 1)) continue;
+        for (uint64_t m = act; m; m &= m - 1) {
+          const int k = __ffsll((unsigned long long)m) - 1;
           float b[6];
 #pragma unroll
           for (int t = 0; t < 6; ++t) b[t] = L.nS[gi][t][k];
@@ -380,9 +398,23 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
         uint64_t m = act;
         for (int i = 0; i < r; ++i) m &= m - 1;
         const int k = __ffsll((unsigned long long)m) - 1;
+        // the members in lobe order (narrow groups: every member's load issued before the sum)
         float sum = 0.f;
-        for (int mm = 0; mm < n; ++mm)
-          if (L.asg[gi][mm] == k) sum += t == 6 ? L.lw[gi][mm] : L.lS[gi][t][mm];
+        if constexpr (G <= 16) {
+          float v[G];
+          bool in[G];
+#pragma unroll
+          for (int mm = 0; mm < G; ++mm) {
+            in[mm] = mm < n && L.asg[gi][mm] == k;
+            v[mm] = in[mm] ? (t == 6 ? L.lw[gi][mm] : L.lS[gi][t][mm]) : 0.f;
+          }
+#pragma unroll
+          for (int mm = 0; mm < G; ++mm)
+            if (in[mm]) sum += v[mm];
+        } else {
+          for (int mm = 0; mm < n; ++mm)
+            if (L.asg[gi][mm] == k) sum += t == 6 ? L.lw[gi][mm] : L.lS[gi][t][mm];
+        }
         if (t == 6) L.cw[gi][k] = sum;
         else L.cS[gi][t][k] = sum;
       }
@@ -435,8 +467,9 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
-// One level with a fixed group width G (G lanes per parent, 64 / G parents per wave).
-template <int G>
+// One level with a fixed group width G (G lanes per parent, 64 / G parents per wave).  With
+// NARROW_ONLY, parents that gather more than G lobes are left to k_cluster_wide.
+template <int G, bool NARROW_ONLY>
 __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
                                                     const float* __restrict__ cw, const float* __restrict__ cS,
                                                     const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
@@ -448,45 +481,36 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
   const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per_wave;
   const int64_t stride = int64_t(gridDim.x) * kWaves * per_wave;
   for (int64_t base = w0; base < n_par; base += stride)
-    cluster_round<G>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
+    cluster_round<G, NARROW_ONLY>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
 }
 
-// Levels whose parents may gather up to GM lobes: a wave takes four parents at a time and
-// serves them with 16 lanes each when none of them gathers more than 16 lobes, else two (or one)
-// at a time with GM lanes.  The group width changes no result.
+// The parents of a level that gather more than 16 lobes (the narrow pass left them), one at a
+// time with GM lanes: a wave counts 64 parents' lobes (one per lane), then serves the wide ones
+// in order.  Few parents are wide, so this pass is mostly the count.  The group width changes no
+// result.
 template <int GM>
-__global__ void __launch_bounds__(kBlock) k_cluster_adapt(const int64_t* __restrict__ pstart,
-                                                          const int64_t* n_par_ptr, const float* __restrict__ cw,
-                                                          const float* __restrict__ cS,
-                                                          const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c,
-                                                          int K, int iters, vx_lobes out) {
-  struct PerWave {
-    union {
-      ClusterLds<16> narrow;
-      ClusterLds<GM> wide;
-    };
-  };
-  __shared__ PerWave sm[kWaves];
-  PerWave& W = sm[threadIdx.x >> 6];
+__global__ void __launch_bounds__(kBlock) k_cluster_wide(const int64_t* __restrict__ pstart,
+                                                         const int64_t* n_par_ptr, const float* __restrict__ cw,
+                                                         const float* __restrict__ cS,
+                                                         const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c,
+                                                         int K, int iters, vx_lobes out) {
+  __shared__ ClusterLds<GM> sm[kWaves];
+  ClusterLds<GM>& L = sm[threadIdx.x >> 6];
   const int lane = lane_id();
   const int64_t n_par = *n_par_ptr;
-  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * 4;
-  const int64_t stride = int64_t(gridDim.x) * kWaves * 4;
+  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * 64;
+  const int64_t stride = int64_t(gridDim.x) * kWaves * 64;
   for (int64_t base = w0; base < n_par; base += stride) {
-    // lanes 0..3: how many lobes parent base + lane gathers (the children's lobe counts)
     int nq = 0;
-    if (lane < 4 && base + lane < n_par) {
-      const int64_t cs = pstart[base + lane], ce = pstart[base + lane + 1];
+    const int64_t p = base + lane;
+    if (p < n_par) {
+      const int64_t cs = pstart[p], ce = pstart[p + 1];
       for (int64_t c = cs; c < ce; ++c) nq += cnl ? (int(cnl[c]) < Kc ? int(cnl[c]) : Kc) : 1;
     }
-    if (__ballot(nq > 16) == 0) {
-      cluster_round<16>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, W.narrow);
-    } else {
-      for (int h = 0; h < 4; h += 64 / GM)
-        cluster_round<GM>(base + h, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, W.wide);
+    for (uint64_t m = __ballot(nq > 16); m; m &= m - 1) {
+      const int64_t q = base + (__ffsll((unsigned long long)m) - 1);
+      cluster_round<GM>(q, q + 1, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
 }
 
@@ -496,17 +520,22 @@ void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw,
   // timing names by group width: the first level (one lobe per child) and the levels above
   VX_TIMED(need <= 8 ? "lod_cluster" : "lod_cluster_up", s);
   if (need <= 8)
-    hipLaunchKernelGGL(k_cluster<8>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
-                       iters, out);
+    hipLaunchKernelGGL((k_cluster<8, false>), dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c,
+                       K, iters, out);
   else if (need <= 16)
-    hipLaunchKernelGGL(k_cluster<16>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
-                       iters, out);
-  else if (need <= 32)
-    hipLaunchKernelGGL(k_cluster_adapt<32>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
-                       Kc, cap_c, K, iters, out);
-  else
-    hipLaunchKernelGGL(k_cluster_adapt<64>, dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl,
-                       Kc, cap_c, K, iters, out);
+    hipLaunchKernelGGL((k_cluster<16, false>), dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
+                       cap_c, K, iters, out);
+  else {
+    // most parents gather at most 16 lobes: a narrow pass at four parents per wave, then the rest
+    hipLaunchKernelGGL((k_cluster<16, true>), dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c,
+                       K, iters, out);
+    if (need <= 32)
+      hipLaunchKernelGGL(k_cluster_wide<32>, dim3(grid / 4 > 64 ? grid / 4 : 64), dim3(kBlock), 0, s, pstart, n_par,
+                         cw, cS, cnl, Kc, cap_c, K, iters, out);
+    else
+      hipLaunchKernelGGL(k_cluster_wide<64>, dim3(grid / 4 > 64 ? grid / 4 : 64), dim3(kBlock), 0, s, pstart, n_par,
+                         cw, cS, cnl, Kc, cap_c, K, iters, out);
+  }
 }
 
 }  // namespace vx
