@@ -15,6 +15,9 @@ Functions and the passages they follow:
   cap of K per voxel, with the deterministic distance and Lloyd refinement in ``vxo.cpp``.
 * ``oracle.compact`` (a module of its own, numpy) -- Sec. 4.1 leaf eigen-fit with an
   eigenvalue floor, and Sec. 4.3's 6-byte compact SGGX code and its decoding.
+* ``sample_fibers`` / ``sample_triangles`` -- Sec. 3.2 sampling voxelizer: Catmull-Rom spans
+  subdivided into chords with equally spaced samples, and Heitz's low-distortion triangle map
+  with sample counts in proportion to the triangle's area (``vxo_sample.cpp``).
 
 Pins (tests/test_oracle_*.py): exact-rational brute force (``oracle/brute.py``) on tiny
 grids; conservation of area / length / moment; closed forms for axis-aligned fibers and
@@ -30,7 +33,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "vxo.cpp"), os.path.join(_HERE, "vxo_fit.cpp")]
+_SRCS = [os.path.join(_HERE, "vxo.cpp"), os.path.join(_HERE, "vxo_fit.cpp"), os.path.join(_HERE, "vxo_sample.cpp")]
 # VXO_SANITIZE=1: a separate build under AddressSanitizer and UndefinedBehaviorSanitizer (load it
 # with libasan preloaded; tests/test_oracle_sanitized.py does)
 _SAN = os.environ.get("VXO_SANITIZE") == "1"
@@ -408,3 +411,77 @@ def fit_conditioning(grid, pts, offsets, radius, hi):
     np.minimum.at(cond, pp, cond_leaf[vi])
     np.minimum.at(cond, pp + 1, cond_leaf[vi])
     return cond
+
+# ------------------------------------------------------------------------------------------------
+# the paper's sampling voxelizer (Sec. 3.2)
+# ------------------------------------------------------------------------------------------------
+
+def _sample_lib():
+    L = lib()
+    if not hasattr(L, "_sample_ready"):
+        L.vxo_sample_fibers.restype = ctypes.c_void_p
+        L.vxo_sample_fibers.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]
+        L.vxo_sample_triangles.restype = ctypes.c_void_p
+        L.vxo_sample_triangles.argtypes = [_c_dp, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.vxo_sresult_size.restype = ctypes.c_int64
+        L.vxo_sresult_size.argtypes = [ctypes.c_void_p]
+        L.vxo_sresult_nsamples.restype = ctypes.c_int64
+        L.vxo_sresult_nsamples.argtypes = [ctypes.c_void_p]
+        L.vxo_sresult_copy.argtypes = [ctypes.c_void_p] * 5
+        L.vxo_sresult_free.argtypes = [ctypes.c_void_p]
+        L.vxo_heitz_map.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+        L.vxo_tri_sample_count.restype = ctypes.c_int64
+        L.vxo_tri_sample_count.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L._sample_ready = True
+    return L
+
+
+def _take_samples(res) -> Voxels:
+    L = _sample_lib()
+    n = L.vxo_sresult_size(res)
+    v = Voxels(np.empty(n, np.uint64), np.empty(n, np.uint32), np.empty(n, np.float64),
+               np.empty((n, 6), np.float64), int(L.vxo_sresult_nsamples(res)))
+    L.vxo_sresult_copy(res, _ptr(v.keys), _ptr(v.count), _ptr(v.w), _ptr(v.S))
+    L.vxo_sresult_free(res)
+    return v
+
+
+def sample_fibers(grid, pts, offsets, sub, per) -> Voxels:
+    """Sampling voxelizer for fibers (Sec. 3.2): per segment the Catmull-Rom span cut into `sub`
+    chords, `per` samples per chord; count = samples per voxel, w = summed chord length / per,
+    S = sum w (I - t t^T).  n_pairs holds the number of samples inside the grid."""
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float32).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    bmin, ext, l2 = _grid_args(grid)
+    st = ctypes.c_int(0)
+    res = _sample_lib().vxo_sample_fibers(bmin, ext, l2, _ptr(p), p.shape[0], _ptr(o), o.shape[0] - 1, int(sub),
+                                          int(per), ctypes.byref(st))
+    if st.value:
+        raise OracleError(f"sample_fibers failed with status {st.value}")
+    return _take_samples(res)
+
+
+def sample_triangles(grid, tris, max_samples) -> Voxels:
+    """Sampling voxelizer for triangles (Sec. 3.2): Heitz's triangle map of stratified points,
+    max(1, floor(N A / A_max)) samples per triangle; w = summed A / n_T, S = sum w n n^T."""
+    t = np.ascontiguousarray(np.asarray(tris, dtype=np.float32).reshape(-1, 3, 3))
+    bmin, ext, l2 = _grid_args(grid)
+    st = ctypes.c_int(0)
+    res = _sample_lib().vxo_sample_triangles(bmin, ext, l2, _ptr(t), t.shape[0], int(max_samples),
+                                             ctypes.byref(st))
+    if st.value:
+        raise OracleError(f"sample_triangles failed with status {st.value}")
+    return _take_samples(res)
+
+
+def heitz_map(u1, u2):
+    b = np.zeros(2)
+    _sample_lib().vxo_heitz_map(float(u1), float(u2), _ptr(b))
+    return b
+
+
+def tri_sample_count(q, qmax, N) -> int:
+    return int(_sample_lib().vxo_tri_sample_count(float(q), float(qmax), int(N)))
