@@ -163,6 +163,48 @@ vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pt
                              const vx_tuning* tuning, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Sampling voxelizer (Sec. 3.2 sparse data sampling, Sec. 3.3 gathering): the paper's own
+ * method, kept as the baseline of the exact path above.  Points are placed on the primitives
+ * from their indices (no random numbers) and every point is stored in the voxel containing it:
+ *   fibers     every segment (i, i+1) of a fiber is the uniform Catmull-Rom span through points
+ *              i-1, i, i+1, i+2 (a fiber's end points repeated), cut at t = j / m (j = 0 .. m)
+ *              into m chords; each chord carries n samples at fractions (k + 1/2) / n of it, each
+ *              weighing chord length / n, moment I - t t^T of the chord's tangent;
+ *   triangles  triangle T gets n_T = max(1, floor(N * area_T / area_max)) samples (the area
+ *              relative to the largest triangle's), sample k at (u1, u2) = ((k + 1/2) / n_T,
+ *              radical inverse of k in base 2), mapped to barycentric coordinates by Heitz's
+ *              low-distortion square-to-triangle map, each weighing area_T / n_T, moment n n^T.
+ * Positions are FP64 grid units g = (P - bmin) * 2^log2_res / extent, every operation in a fixed
+ * order (the fused multiply-adds are explicit); the sample's voxel is floor(g), samples outside
+ * [0, R)^3 are dropped, and n_T's floor is decided on squares (k^2 area_max^2 <= N^2 area_T^2).
+ * Per voxel: count = samples, w = summed weight, S = summed weight * moment, summed in sample
+ * order (primitive, chord, sample), so the result is reproducible bit for bit.
+ * Capacities: max_samples = samples generated (stats[VX_STAT_CAND] of a call with 0 reports it);
+ * stats[VX_STAT_PAIRS] = samples inside the grid, stats[VX_STAT_VOXELS] = voxels.
+ * Workspace: about 2 * (key + 8) bytes per sample plus 16 bytes per chord or triangle.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t chords_per_segment;    /* fibers: m, 1 .. 1024 */
+  int32_t samples_per_chord;     /* fibers: n, 1 .. 65536 */
+  int32_t max_triangle_samples;  /* triangles: N, the largest triangle's samples, 1 .. 2^20 */
+} vx_sampling;
+
+/* kind: 0 = triangles, 1 = fibers; n_prims as for vx_voxelize_workspace_size; 0 on bad
+ * arguments. */
+size_t vx_sample_workspace_size(int32_t kind, int64_t n_prims, int64_t max_samples, int64_t max_voxels,
+                                int32_t log2_res, const vx_sampling* sampling);
+
+/* tris: float32 [n_tris][3][3] on the device.  out: voxels sorted by key (out->mask unused). */
+vx_status vx_sample_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, const vx_sampling* sampling,
+                              int64_t max_samples, void* workspace, size_t ws_bytes, const vx_voxels* out,
+                              int64_t* stats, vx_stream stream);
+
+/* pts, offsets: as for vx_voxelize_fibers (n_pts * chords_per_segment <= 2^32). */
+vx_status vx_sample_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
+                           int64_t n_fibers, const vx_sampling* sampling, int64_t max_samples, void* workspace,
+                           size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
  * LoD pyramid (Sec. 4.3-4.4).
  *
  * leaf: the voxelize output, with its count at n_leaf (device int64, e.g. &stats[VX_STAT_VOXELS]).

@@ -93,6 +93,11 @@ def _ctuning(t):
     return ctypes.byref(t.cstruct()) if t is not None else None
 
 
+class CSampling(ctypes.Structure):
+    _fields_ = [("chords_per_segment", ctypes.c_int32), ("samples_per_chord", ctypes.c_int32),
+                ("max_triangle_samples", ctypes.c_int32)]
+
+
 class CFibers(ctypes.Structure):
     _fields_ = [("pts", ctypes.c_void_p), ("n_pts", ctypes.c_int64), ("offsets", ctypes.c_void_p),
                 ("n_fibers", ctypes.c_int64), ("radius", ctypes.c_float)]
@@ -121,6 +126,14 @@ def load():
     L.vx_voxelize_fibers.restype = ctypes.c_int
     L.vx_voxelize_fibers.argtypes = [ctypes.POINTER(CGrid), vp, i64, vp, i64, ctypes.c_float, i64, i64, vp, sz,
                                      ctypes.POINTER(CVoxels), vp, ctypes.POINTER(CTuning), vp]
+    L.vx_sample_workspace_size.restype = sz
+    L.vx_sample_workspace_size.argtypes = [i32, i64, i64, i64, i32, ctypes.POINTER(CSampling)]
+    L.vx_sample_triangles.restype = ctypes.c_int
+    L.vx_sample_triangles.argtypes = [ctypes.POINTER(CGrid), vp, i64, ctypes.POINTER(CSampling), i64, vp, sz,
+                                      ctypes.POINTER(CVoxels), vp, vp]
+    L.vx_sample_fibers.restype = ctypes.c_int
+    L.vx_sample_fibers.argtypes = [ctypes.POINTER(CGrid), vp, i64, vp, i64, ctypes.POINTER(CSampling), i64, vp, sz,
+                                   ctypes.POINTER(CVoxels), vp, vp]
     L.vx_lod_workspace_size.restype = sz
     L.vx_lod_workspace_size.argtypes = [i64, i32, i32]
     L.vx_build_lod.restype = ctypes.c_int
@@ -339,6 +352,94 @@ class VoxelizePlan:
         self.n_cand = int(h[STAT_CAND])
         self.n_records = int(h[STAT_RECORDS])
         self.n_units = int(h[STAT_UNITS])
+        return self.out
+
+
+class SamplePlan:
+    """The sampling voxelizer (Sec. 3.2-3.3) for one set of primitives, reusable across runs.
+
+    kind 0: triangles float32 [n, 3, 3], ``N`` samples for the largest triangle (the others in
+    proportion to their area); kind 1: fibers float32 [m, 3] + int64 offsets, ``chords`` chords
+    per Catmull-Rom span and ``per_chord`` samples per chord.  The sample and voxel capacities
+    come from two counting calls (device stats read back once each); ``run()`` then enqueues the
+    whole pass with no host sync.
+    """
+
+    def __init__(self, kind, grid, data, offsets=None, N=16, chords=4, per_chord=4, max_samples=None, out_cap=None):
+        import torch
+        self.L = load()
+        self.kind = kind
+        self.grid = grid
+        self.cgrid = _cgrid(grid)
+        self.sampling = CSampling(int(chords), int(per_chord), int(N))
+        self.data = data.contiguous()
+        if self.data.dtype != torch.float32 or not self.data.is_cuda:
+            raise TypeError("primitives must be a float32 CUDA tensor")
+        self.device = self.data.device
+        if kind == 0:
+            self.n_prims = int(self.data.numel() // 9)
+            self.offsets, self.n_fib = None, 0
+        else:
+            self.n_prims = int(self.data.numel() // 3)
+            self.offsets = offsets.to(device=self.device, dtype=torch.int64).contiguous()
+            self.n_fib = int(self.offsets.numel() - 1)
+        self.stats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.device)
+        if max_samples is None or out_cap is None:
+            s = _stream()
+            tmp = alloc_voxels(1, grid.log2_res, self.device, False)
+            ms = 0 if max_samples is None else int(max_samples)
+            for step in range(2):
+                if step == 0 and max_samples is not None:
+                    continue
+                ws = self._ws_for(ms, 1)
+                self._call(ms, ws, tmp.cstruct(), s)
+                self.L.vx_check_stats(_ptr(self.stats), s)
+                h = self.stats.cpu().numpy()
+                if h[STAT_FLAGS] & (FLAG_INPUT | FLAG_OFFSETS):
+                    raise VxError(4, "sample")
+                if step == 0:
+                    ms = int(h[STAT_CAND])
+                else:
+                    v = int(h[STAT_VOXELS])
+                del ws
+            max_samples = ms if max_samples is None else max_samples
+            out_cap = v if out_cap is None else out_cap
+        self.max_samples = int(max_samples)
+        self.out = alloc_voxels(max(int(out_cap), 1), grid.log2_res, self.device, False)
+        self.ws = self._ws_for(self.max_samples, self.out.cap)
+        self._cout = self.out.cstruct()
+
+    def _ws_for(self, max_samples, max_voxels):
+        nb = self.L.vx_sample_workspace_size(self.kind, self.n_prims, max_samples, max(max_voxels, 1),
+                                             int(self.grid.log2_res), ctypes.byref(self.sampling))
+        if nb == 0:
+            raise VxError(1, "vx_sample_workspace_size")
+        return _ws(nb, self.device)
+
+    def _call(self, max_samples, ws, cout, stream):
+        if self.kind == 0:
+            st = self.L.vx_sample_triangles(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims,
+                                            ctypes.byref(self.sampling), max_samples, _ptr(ws), ws.numel(),
+                                            ctypes.byref(cout), _ptr(self.stats), stream)
+        else:
+            st = self.L.vx_sample_fibers(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims,
+                                         _ptr(self.offsets), self.n_fib, ctypes.byref(self.sampling), max_samples,
+                                         _ptr(ws), ws.numel(), ctypes.byref(cout), _ptr(self.stats), stream)
+        if st != 0:
+            raise VxError(st, "sample")
+
+    def run(self, stream=None):
+        self._call(self.max_samples, self.ws, self._cout, _stream(stream))
+        return self
+
+    def check(self, stream=None):
+        st = self.L.vx_check_stats(_ptr(self.stats), _stream(stream))
+        h = self.stats.cpu().numpy()
+        if st != 0:
+            raise VxError(st, f"sample (stats {h.tolist()})")
+        self.out.n = int(h[STAT_VOXELS])
+        self.n_samples = int(h[STAT_CAND])
+        self.n_inside = int(h[STAT_PAIRS])
         return self.out
 
 

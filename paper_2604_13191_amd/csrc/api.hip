@@ -203,6 +203,53 @@ vx_status vx_voxelize_fibers(const vx_grid* grid, const float* pts, int64_t n_pt
                          stats, tuning, stream);
 }
 
+static bool sampling_ok(int kind, const vx_sampling* sp) {
+  if (!sp) return false;
+  if (kind == 0) return sp->max_triangle_samples >= 1 && sp->max_triangle_samples <= (1 << 20);
+  return sp->chords_per_segment >= 1 && sp->chords_per_segment <= 1024 && sp->samples_per_chord >= 1 &&
+         sp->samples_per_chord <= 65536;
+}
+
+size_t vx_sample_workspace_size(int32_t kind, int64_t n_prims, int64_t max_samples, int64_t max_voxels,
+                                int32_t log2_res, const vx_sampling* sampling) {
+  if ((kind != 0 && kind != 1) || n_prims < 0 || n_prims > kMaxPrims || max_samples < 0 ||
+      max_samples > kMaxPairs || max_voxels < 1 || log2_res < 1 || log2_res > 20 || !sampling_ok(kind, sampling))
+    return 0;
+  if (kind == 1 && n_prims * int64_t(sampling->chords_per_segment) > kMaxPrims + 1) return 0;
+  return sample_ws_bytes(kind, n_prims, max_samples, max_voxels, log2_res, sampling->chords_per_segment);
+}
+
+static vx_status sample_common(int kind, const vx_grid* grid, const float* data, int64_t n_prims,
+                               const int64_t* offsets, int64_t n_fib, const vx_sampling* sp, int64_t max_samples,
+                               void* ws, size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream) {
+  if (!grid_ok(grid) || n_prims < 0 || n_prims > kMaxPrims || max_samples < 0 || max_samples > kMaxPairs ||
+      !stats || !voxels_ok(out, false) || (n_prims > 0 && !data) || !sampling_ok(kind, sp))
+    return VX_ERR_ARG;
+  if (kind == 1) {
+    if (n_fib < 0 || !offsets || (n_prims > 0 && n_fib < 1)) return VX_ERR_ARG;
+    if (n_prims * int64_t(sp->chords_per_segment) > kMaxPrims + 1) return VX_ERR_ARG;
+  }
+  if (!ws_ok(ws, ws_bytes, sample_ws_bytes(kind, n_prims, max_samples, out->cap, grid->log2_res,
+                                           sp->chords_per_segment)))
+    return VX_ERR_WORKSPACE;
+  return sample_voxelize(kind, grid, data, n_prims, offsets, n_fib, sp, max_samples, ws, out, stats,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+vx_status vx_sample_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, const vx_sampling* sampling,
+                              int64_t max_samples, void* workspace, size_t ws_bytes, const vx_voxels* out,
+                              int64_t* stats, vx_stream stream) {
+  return sample_common(0, grid, tris, n_tris, nullptr, 0, sampling, max_samples, workspace, ws_bytes, out, stats,
+                       stream);
+}
+
+vx_status vx_sample_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
+                           int64_t n_fibers, const vx_sampling* sampling, int64_t max_samples, void* workspace,
+                           size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream) {
+  return sample_common(1, grid, pts, n_pts, offsets, n_fibers, sampling, max_samples, workspace, ws_bytes, out,
+                       stats, stream);
+}
+
 size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K) {
   if (cap < 1 || levels < 1 || K < 1 || K > 8) return 0;
   Carver cv(nullptr);

@@ -299,6 +299,12 @@ struct HeadOut {
   }
 };
 
+// the sampling voxelizer (kind 0 triangles, 1 fibers; arguments checked by the caller)
+size_t sample_ws_bytes(int kind, int64_t n_prims, int64_t max_samples, int64_t max_vox, int log2R, int sub);
+vx_status sample_voxelize(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                          int64_t n_fib, const vx_sampling* sp, int64_t max_samples, void* ws, const vx_voxels* out,
+                          int64_t* stats, hipStream_t s);
+
 // one LoD level: parent reduce of `in` (n_in on the device) into `out`; n_out receives the
 // new count clamped to out.cap, and flags the capacity bit when it had to be clamped; pstart
 // receives every parent's first child
