@@ -358,6 +358,87 @@ def batch_timing(vx, args):
             "tuning": tuning.as_dict() if tuning is not None else "default"}
 
 
+def _leaf_error(exact, ex_n, samp, s_n):
+    """Relative L1 distance of the sampled leaf from the exact one (weights and moments, summed
+    over the union of their voxels) and the share of the exact voxels of positive area that the
+    sampler reached."""
+    import torch
+    ek, sk = exact.keys[:ex_n].long(), samp.keys[:s_n].long()
+    ew, sw = exact.w[:ex_n].double(), samp.w[:s_n].double()
+    eS, sS = exact.S[:, :ex_n].double(), samp.S[:, :s_n].double()
+    idx = torch.searchsorted(ek, sk).clamp_max(max(ex_n - 1, 0))
+    hit = ek[idx] == sk
+    m = torch.zeros(ex_n, dtype=torch.bool, device=ek.device)
+    m[idx[hit]] = True
+    dw = (sw[hit] - ew[idx[hit]]).abs().sum() + sw[~hit].sum() + ew[~m].sum()
+    dS = ((sS[:, hit] - eS[:, idx[hit]]).abs().sum() + sS[:, ~hit].abs().sum() + eS[:, ~m].abs().sum())
+    pos = ew > 0
+    return {"w_rel_l1": float(dw / ew.sum()), "S_rel_l1": float(dS / eS.abs().sum()),
+            "exact_area_voxels_reached": float((m & pos).sum() / pos.sum()), "voxels": int(s_n)}
+
+
+def sampling_timing(vx, args, exact_ms):
+    """The paper's sampling voxelizer (Sec. 3.2-3.3) on the headline surface, feeding the same
+    13-level pyramid with K = 4 lobes: whole steps (sample + pyramid) for N = 4, 16 and 64 samples
+    on the largest triangle, against the exact step, with the sampled leaf's distance from the
+    exact one."""
+    import torch
+    import synth
+    from paper_2604_13191_amd import autotune
+    wl = synth.brushed_metal()
+    tris = torch.as_tensor(wl.tris).cuda()
+    grid, levels = wl.grid, wl.levels
+    del wl
+    tuned = autotune.load("brushed_metal")
+    ex = vx.VoxelizePlan(0, grid, tris, tuning=tuned).run()
+    exact = ex.check()
+    out = {"workload": "brushed_metal, sampled voxelizer + 13-level pyramid, K=4", "exact_step_ms": exact_ms,
+           "runs": {}}
+    steps = max(1, min(args.steps, 5))
+    for N in (4, 16, 64):
+        sp = vx.SamplePlan(0, grid, tris, N=N)
+        sp.run()
+        leaf = sp.check()
+        cal = vx.LodPlan(grid, leaf, sp.stats[2:3], levels, tuning=tuned).run()
+        caps = [max(v.n, 1) for v in cal.check()[1:]]
+        del cal
+        lod = vx.LodPlan(grid, leaf, sp.stats[2:3], levels, K=4, iters=2, caps=caps, tuning=tuned)
+        for _ in range(max(1, args.warmup)):
+            sp.run()
+            lod.run()
+        torch.cuda.synchronize()
+        vx.timing_reset()
+        vx.timing_filter(None)
+        vx.timing_enable(True)
+        sp.run()
+        lod.run()
+        vx.timing_enable(False)
+        kt = vx.timing_collect()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for a, b, c in ev:
+            a.record()
+            sp.run()
+            b.record()
+            lod.run()
+            c.record()
+        torch.cuda.synchronize()
+        sp.check()
+        lod.check()
+        smp = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+        lb = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+        r = {"samples": sp.n_samples, "sample_ms": smp, "lod_build_ms": lb, "step_ms": smp + lb,
+             "samples_per_s": sp.n_samples / (smp * 1e-3), "step_over_exact": (smp + lb) / exact_ms,
+             "kernels_ms": {k: round(v[0], 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])
+                            if k.startswith("sample") or k.startswith("radix")}}
+        r.update(_leaf_error(exact, exact.n, leaf, leaf.n))
+        out["runs"][str(N)] = r
+        del sp, lod, leaf
+        torch.cuda.empty_cache()
+    del ex, exact, tris
+    torch.cuda.empty_cache()
+    return out
+
+
 # ------------------------------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the headline workload
 # ------------------------------------------------------------------------------------------------
@@ -414,6 +495,7 @@ def main():
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--no-weave", action="store_true")
     ap.add_argument("--no-compact", action="store_true")
+    ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--probe", action="store_true", help="end with a plain copy of known size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -449,6 +531,10 @@ def main():
         "graph_ms_per_step": head.get("graph_ms_per_step"), "graph_pairs_per_s": head.get("graph_pairs_per_s"),
         "roofline": head["roofline"], "kernels": head["kernels"],
     }
+
+    if not args.no_sampling:
+        out["sampling"] = sampling_timing(vx, args, head["ms_per_step"])
+        torch.cuda.empty_cache()
 
     # ---- plain weave, fit, compact -------------------------------------------------------------
     if not args.no_weave or not args.no_fit or not args.no_compact:
