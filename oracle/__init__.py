@@ -15,6 +15,9 @@ Functions and the passages they follow:
   cap of K per voxel, with the deterministic distance and Lloyd refinement in ``vxo.cpp``.
 * ``oracle.compact`` (a module of its own, numpy) -- Sec. 4.1 leaf eigen-fit with an
   eigenvalue floor, and Sec. 4.3's 6-byte compact SGGX code and its decoding.
+* ``oracle.occupancy`` (numpy over the voxelizer) -- Sec. 3.5 occupancy of 8^3 sub-cells per
+  voxel and its XY / XZ / YZ projections, Sec. 4.2 the same for the coarser levels: the
+  sub-cells are the voxels of the voxelizer run at 8x the resolution.
 * ``sample_fibers`` / ``sample_triangles`` -- Sec. 3.2 sampling voxelizer: Catmull-Rom spans
   subdivided into chords with equally spaced samples, and Heitz's low-distortion triangle map
   with sample counts in proportion to the triangle's area (``vxo_sample.cpp``).
