@@ -60,7 +60,8 @@ typedef enum {
   VX_ERR_HIP = 3,        /* a HIP runtime call failed */
   VX_ERR_INPUT = 4,      /* non-finite or out-of-range coordinate, or invalid fiber offsets */
   VX_ERR_WORKSPACE = 5,  /* workspace pointer NULL, misaligned (256 B) or too small */
-  VX_ERR_BINDING = 6     /* fit parameters bound to other voxels than the level now holds */
+  VX_ERR_BINDING = 6     /* arguments bound to other voxels than the level holds (fit parameters,
+                            an occupancy leaf from other primitives) */
 } vx_status;
 
 /* device flag bits in stats[VX_STAT_FLAGS] */
@@ -73,6 +74,7 @@ typedef enum {
 #define VX_FLAG_UNIT_CAPACITY  64
 #define VX_FLAG_FIT_ROWS       128   /* a fitted level's voxel count differs from its parameter rows */
 #define VX_FLAG_FIT_KEYS       256   /* a fitted level's keys differ from those its parameters were made for */
+#define VX_FLAG_OCC_LEAF       512   /* a primitive touches a voxel missing from the leaf given for occupancy */
 
 /* indices into the int64 stats array (device): candidates tested, touching pairs, leaf voxels,
  * flags, primitive-tile records, work units */
@@ -203,6 +205,48 @@ vx_status vx_sample_triangles(const vx_grid* grid, const float* tris, int64_t n_
 vx_status vx_sample_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
                            int64_t n_fibers, const vx_sampling* sampling, int64_t max_samples, void* workspace,
                            size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Sub-voxel occupancy and projected densities (Sec. 3.5 occupancy equation and XY / XZ / YZ
+ * projections, Sec. 4.2 the projections at the coarser levels).
+ *
+ * Every voxel of every level holds 8^3 sub-cells of its edge / 8.  A leaf sub-cell is hit when a
+ * primitive touches its closed box (the voxel-level predicate on the same lattice); a coarser
+ * voxel's sub-cell, the union of 2 x 2 x 2 sub-cells of one child, is hit when one of those is.
+ * Per voxel:
+ *   mask   512 bits, sub-cell (i, j, k) in [0, 8)^3 at Morton index m (i bit b at 3b, j at 3b+1,
+ *          k at 3b+2): bit m & 63 of word m >> 6 -- word c is octant c of the voxel;
+ *   hits   hit sub-cells (occupancy O = hits / 512), and the cells of the XY, XZ and YZ planes
+ *          whose column (along z, y, x) holds a hit (the per-axis densities are those / 64).
+ * Inputs: the primitives, and the pyramid they were voxelized into: leaf (vx_voxelize_*), out and
+ * n_levels (vx_build_lod's, levels as there; n_levels[0] the leaf's count).  log2_res <= 17.
+ * The pairs are regenerated by the candidate pipeline (max_cand / max_pairs as reported in
+ * stats[VX_STAT_CAND] / stats[VX_STAT_PAIRS] of a call with 0).  A pair whose voxel the leaf lacks
+ * sets VX_FLAG_OCC_LEAF (VX_ERR_BINDING); a level over its occupancy capacity sets
+ * VX_FLAG_VOXEL_CAPACITY.  The result is exact and independent of scheduling.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t* mask;     /* [8 * cap]: word w of voxel i at mask[w * cap + i] */
+  uint16_t* hits;     /* [4 * cap]: hits[i] = hit sub-cells, hits[cap + i] = XY cells,
+                         hits[2 cap + i] = XZ cells, hits[3 cap + i] = YZ cells */
+  int64_t cap;        /* >= the level's voxel count */
+} vx_occupancy;
+
+/* kind 0 triangles, 1 fibers; 0 on bad arguments */
+size_t vx_occupancy_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
+                                   int32_t log2_res);
+
+/* occ: host array of `levels` device descriptors (level 0 = leaf). */
+vx_status vx_occupancy_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, const vx_voxels* leaf,
+                                 const vx_voxels* out, const int64_t* n_levels, int32_t levels, int64_t max_cand,
+                                 int64_t max_pairs, const vx_occupancy* occ, void* workspace, size_t ws_bytes,
+                                 int64_t* stats, vx_stream stream);
+
+vx_status vx_occupancy_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
+                              int64_t n_fibers, float radius, const vx_voxels* leaf, const vx_voxels* out,
+                              const int64_t* n_levels, int32_t levels, int64_t max_cand, int64_t max_pairs,
+                              const vx_occupancy* occ, void* workspace, size_t ws_bytes, int64_t* stats,
+                              vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
  * LoD pyramid (Sec. 4.3-4.4).

@@ -25,7 +25,7 @@ VX_NSTAT = 6
 STAT_CAND, STAT_PAIRS, STAT_VOXELS, STAT_FLAGS, STAT_RECORDS, STAT_UNITS = range(6)
 FLAG_CAND_CAPACITY, FLAG_PAIR_CAPACITY, FLAG_VOXEL_CAPACITY, FLAG_INPUT, FLAG_OFFSETS = 1, 2, 4, 8, 16
 FLAG_RECORD_CAPACITY, FLAG_UNIT_CAPACITY = 32, 64
-FLAG_FIT_ROWS, FLAG_FIT_KEYS = 128, 256
+FLAG_FIT_ROWS, FLAG_FIT_KEYS, FLAG_OCC_LEAF = 128, 256, 512
 NOALLOC_MAX_LEAF = 8388608          # leaf capacity limit of vx_build_lod_noalloc
 STATUS = {0: "ok", 1: "invalid argument", 2: "capacity exceeded", 3: "HIP runtime error",
           4: "non-finite or out-of-range input, or invalid fiber offsets", 5: "bad workspace",
@@ -98,6 +98,10 @@ class CSampling(ctypes.Structure):
                 ("max_triangle_samples", ctypes.c_int32)]
 
 
+class COccupancy(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_void_p), ("hits", ctypes.c_void_p), ("cap", ctypes.c_int64)]
+
+
 class CFibers(ctypes.Structure):
     _fields_ = [("pts", ctypes.c_void_p), ("n_pts", ctypes.c_int64), ("offsets", ctypes.c_void_p),
                 ("n_fibers", ctypes.c_int64), ("radius", ctypes.c_float)]
@@ -134,6 +138,16 @@ def load():
     L.vx_sample_fibers.restype = ctypes.c_int
     L.vx_sample_fibers.argtypes = [ctypes.POINTER(CGrid), vp, i64, vp, i64, ctypes.POINTER(CSampling), i64, vp, sz,
                                    ctypes.POINTER(CVoxels), vp, vp]
+    L.vx_occupancy_workspace_size.restype = sz
+    L.vx_occupancy_workspace_size.argtypes = [i32, i64, i64, i64, i32]
+    L.vx_occupancy_triangles.restype = ctypes.c_int
+    L.vx_occupancy_triangles.argtypes = [ctypes.POINTER(CGrid), vp, i64, ctypes.POINTER(CVoxels),
+                                         ctypes.POINTER(CVoxels), vp, i32, i64, i64, ctypes.POINTER(COccupancy), vp,
+                                         sz, vp, vp]
+    L.vx_occupancy_fibers.restype = ctypes.c_int
+    L.vx_occupancy_fibers.argtypes = [ctypes.POINTER(CGrid), vp, i64, vp, i64, ctypes.c_float,
+                                      ctypes.POINTER(CVoxels), ctypes.POINTER(CVoxels), vp, i32, i64, i64,
+                                      ctypes.POINTER(COccupancy), vp, sz, vp, vp]
     L.vx_lod_workspace_size.restype = sz
     L.vx_lod_workspace_size.argtypes = [i64, i32, i32]
     L.vx_build_lod.restype = ctypes.c_int
@@ -519,6 +533,112 @@ class LodPlan:
             if self.lobes:
                 self.lobes[L - 1].n = int(h[L])
         return [self.leaf] + self.out
+
+
+@dataclass
+class Occupancy:
+    """Sub-cell occupancy of one level: mask int64 [8, cap] (uint64 bit patterns; word w of voxel
+    i at mask[w, i]), hits int16 [4, cap] (hit sub-cells, XY, XZ, YZ cells)."""
+    mask: object
+    hits: object
+    n: int = -1
+
+    @property
+    def cap(self):
+        return int(self.mask.shape[1])
+
+    def cstruct(self) -> COccupancy:
+        return COccupancy(self.mask.data_ptr(), self.hits.data_ptr(), self.cap)
+
+    def numpy(self, n=None):
+        n = self.n if n is None else n
+        m = self.mask[:, :n].cpu().numpy().view(np.uint64).T.copy()
+        h = self.hits[:, :n].cpu().numpy().astype(np.int64)
+        return {"mask": m, "hits": h[0], "xy": h[1], "xz": h[2], "yz": h[3]}
+
+
+class OccupancyPlan:
+    """Sub-voxel occupancy (Sec. 3.5, Sec. 4.2) of the pyramid `lod` (a LodPlan, run and
+    checked) built from these primitives.  Candidate and pair capacities come from two counting
+    calls; ``run()`` then enqueues the pass with no host sync."""
+
+    def __init__(self, kind, grid, data, lod, offsets=None, radius=0.0, max_cand=None, max_pairs=None):
+        import torch
+        self.L = load()
+        self.kind, self.grid, self.cgrid = kind, grid, _cgrid(grid)
+        self.data = data.contiguous()
+        self.device = self.data.device
+        if kind == 0:
+            self.n_prims, self.offsets, self.n_fib = int(self.data.numel() // 9), None, 0
+        else:
+            self.n_prims = int(self.data.numel() // 3)
+            self.offsets = offsets.to(device=self.device, dtype=torch.int64).contiguous()
+            self.n_fib = int(self.offsets.numel() - 1)
+        self.radius = float(radius)
+        self.lod = lod
+        self.levels = lod.levels
+        self.stats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=self.device)
+        caps = [lod.leaf.cap] + [v.cap for v in lod.out]
+        self.occ = [Occupancy(torch.empty((8, c), dtype=torch.int64, device=self.device),
+                              torch.empty((4, c), dtype=torch.int16, device=self.device)) for c in caps]
+        self._cocc = (COccupancy * len(self.occ))(*[o.cstruct() for o in self.occ])
+        self._cleaf = lod.leaf.cstruct()
+        self._cout = (CVoxels * max(1, len(lod.out)))(*[v.cstruct() for v in lod.out])
+        if max_cand is None or max_pairs is None:
+            mc, mp = 0 if max_cand is None else int(max_cand), 0
+            for step in range(2):
+                if step == 0 and max_cand is not None:
+                    continue
+                ws = self._ws_for(mc, mp)
+                self._call(mc, mp, ws, _stream())
+                self.L.vx_check_stats(_ptr(self.stats), _stream())
+                h = self.stats.cpu().numpy()
+                if h[STAT_FLAGS] & (FLAG_INPUT | FLAG_OFFSETS):
+                    raise VxError(4, "occupancy")
+                if step == 0:
+                    mc = int(h[STAT_CAND])
+                else:
+                    mp = int(h[STAT_PAIRS])
+                del ws
+            max_cand = mc if max_cand is None else max_cand
+            max_pairs = mp if max_pairs is None else max_pairs
+        self.max_cand, self.max_pairs = int(max_cand), int(max_pairs)
+        self.ws = self._ws_for(self.max_cand, self.max_pairs)
+
+    def _ws_for(self, max_cand, max_pairs):
+        nb = self.L.vx_occupancy_workspace_size(self.kind, self.n_prims, max_cand, max_pairs, int(self.grid.log2_res))
+        if nb == 0:
+            raise VxError(1, "vx_occupancy_workspace_size")
+        return _ws(nb, self.device)
+
+    def _call(self, max_cand, max_pairs, ws, stream):
+        if self.kind == 0:
+            st = self.L.vx_occupancy_triangles(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims,
+                                               ctypes.byref(self._cleaf), self._cout, _ptr(self.lod.n_levels),
+                                               self.levels, max_cand, max_pairs, self._cocc, _ptr(ws), ws.numel(),
+                                               _ptr(self.stats), stream)
+        else:
+            st = self.L.vx_occupancy_fibers(ctypes.byref(self.cgrid), _ptr(self.data), self.n_prims,
+                                            _ptr(self.offsets), self.n_fib, self.radius, ctypes.byref(self._cleaf),
+                                            self._cout, _ptr(self.lod.n_levels), self.levels, max_cand, max_pairs,
+                                            self._cocc, _ptr(ws), ws.numel(), _ptr(self.stats), stream)
+        if st != 0:
+            raise VxError(st, "occupancy")
+
+    def run(self, stream=None):
+        self._call(self.max_cand, self.max_pairs, self.ws, _stream(stream))
+        return self
+
+    def check(self, stream=None):
+        st = self.L.vx_check_stats(_ptr(self.stats), _stream(stream))
+        h = self.stats.cpu().numpy()
+        if st != 0:
+            raise VxError(st, f"occupancy (stats {h.tolist()})")
+        n = self.lod.n_levels.cpu().numpy()
+        for L, o in enumerate(self.occ):
+            o.n = int(n[L])
+        self.n_pairs = int(h[STAT_PAIRS])
+        return self.occ
 
 
 def voxelize_triangles(tris, grid, **kw):

@@ -250,6 +250,56 @@ vx_status vx_sample_fibers(const vx_grid* grid, const float* pts, int64_t n_pts,
                        stats, stream);
 }
 
+size_t vx_occupancy_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
+                                   int32_t log2_res) {
+  if ((kind != 0 && kind != 1) || n_prims < 0 || n_prims > kMaxPrims || max_cand < 0 || max_pairs < 0 ||
+      max_pairs > kMaxPairs || log2_res < 1 || log2_res > 17)
+    return 0;
+  return occupancy_ws_bytes(n_prims, max_cand, max_pairs, log2_res > 10);
+}
+
+static vx_status occupancy_common(int kind, const vx_grid* grid, const float* data, int64_t n_prims,
+                                  const int64_t* offsets, int64_t n_fib, float radius, const vx_voxels* leaf,
+                                  const vx_voxels* out, const int64_t* n_levels, int32_t levels, int64_t max_cand,
+                                  int64_t max_pairs, const vx_occupancy* occ, void* ws, size_t ws_bytes,
+                                  int64_t* stats, vx_stream stream) {
+  if (!grid_ok(grid) || grid->log2_res > 17 || n_prims < 0 || n_prims > kMaxPrims || max_cand < 0 ||
+      max_pairs < 0 || max_pairs > kMaxPairs || !stats || !n_levels || (n_prims > 0 && !data) ||
+      !voxels_ok(leaf, false) || levels < 1 || levels > grid->log2_res + 1 || (levels > 1 && !out) || !occ)
+    return VX_ERR_ARG;
+  for (int l = 1; l < levels; ++l)
+    if (!out[l - 1].keys || out[l - 1].cap < 1) return VX_ERR_ARG;
+  for (int l = 0; l < levels; ++l)
+    if (!occ[l].mask || !occ[l].hits || occ[l].cap < 1) return VX_ERR_ARG;
+  if (kind == 1) {
+    if (n_fib < 0 || !offsets || (n_prims > 0 && n_fib < 1)) return VX_ERR_ARG;
+    if (!(radius >= 0.0f) || !std::isfinite(radius)) return VX_ERR_ARG;
+    const double rho = std::rint(double(radius) * (std::ldexp(1.0, 23) / grid->extent));
+    if (rho > 8388608.0) return VX_ERR_ARG;
+  }
+  if (!ws_ok(ws, ws_bytes, occupancy_ws_bytes(n_prims, max_cand, max_pairs, grid->log2_res > 10)))
+    return VX_ERR_WORKSPACE;
+  return occupancy_run(kind, grid, data, n_prims, offsets, n_fib, radius, leaf, out, n_levels, levels, max_cand,
+                       max_pairs, occ, ws, stats, reinterpret_cast<hipStream_t>(stream));
+}
+
+vx_status vx_occupancy_triangles(const vx_grid* grid, const float* tris, int64_t n_tris, const vx_voxels* leaf,
+                                 const vx_voxels* out, const int64_t* n_levels, int32_t levels, int64_t max_cand,
+                                 int64_t max_pairs, const vx_occupancy* occ, void* workspace, size_t ws_bytes,
+                                 int64_t* stats, vx_stream stream) {
+  return occupancy_common(0, grid, tris, n_tris, nullptr, 0, 0.0f, leaf, out, n_levels, levels, max_cand, max_pairs,
+                          occ, workspace, ws_bytes, stats, stream);
+}
+
+vx_status vx_occupancy_fibers(const vx_grid* grid, const float* pts, int64_t n_pts, const int64_t* offsets,
+                              int64_t n_fibers, float radius, const vx_voxels* leaf, const vx_voxels* out,
+                              const int64_t* n_levels, int32_t levels, int64_t max_cand, int64_t max_pairs,
+                              const vx_occupancy* occ, void* workspace, size_t ws_bytes, int64_t* stats,
+                              vx_stream stream) {
+  return occupancy_common(1, grid, pts, n_pts, offsets, n_fibers, radius, leaf, out, n_levels, levels, max_cand,
+                          max_pairs, occ, workspace, ws_bytes, stats, stream);
+}
+
 size_t vx_lod_workspace_size(int64_t cap, int32_t levels, int32_t K) {
   if (cap < 1 || levels < 1 || K < 1 || K > 8) return 0;
   Carver cv(nullptr);
@@ -560,7 +610,7 @@ vx_status vx_check_stats(const int64_t* stats, vx_stream stream) {
   if (hipMemcpy(h, stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) return VX_ERR_HIP;
   const int64_t f = h[VX_STAT_FLAGS];
   if (f & (VX_FLAG_INPUT | VX_FLAG_OFFSETS)) return VX_ERR_INPUT;
-  if (f & VX_FLAG_FIT_KEYS) return VX_ERR_BINDING;
+  if (f & (VX_FLAG_FIT_KEYS | VX_FLAG_OCC_LEAF)) return VX_ERR_BINDING;
   if (f & (VX_FLAG_FIT_ROWS | VX_FLAG_CAND_CAPACITY | VX_FLAG_PAIR_CAPACITY | VX_FLAG_VOXEL_CAPACITY | VX_FLAG_RECORD_CAPACITY |
            VX_FLAG_UNIT_CAPACITY))
     return VX_ERR_CAPACITY;
@@ -575,7 +625,7 @@ const char* vx_status_str(vx_status s) {
     case VX_ERR_HIP: return "HIP runtime error";
     case VX_ERR_INPUT: return "non-finite or out-of-range input, or invalid fiber offsets";
     case VX_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
-    case VX_ERR_BINDING: return "fit parameters bound to other voxels than the level holds";
+    case VX_ERR_BINDING: return "arguments bound to other voxels than the level holds";
   }
   return "unknown status";
 }

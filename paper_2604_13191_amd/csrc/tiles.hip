@@ -19,16 +19,6 @@ __device__ __forceinline__ void flag_set(int64_t* stats, int64_t bit) {
   atomicOr(reinterpret_cast<unsigned long long*>(stats + VX_STAT_FLAGS), (unsigned long long)bit);
 }
 
-// inverse of the Morton spread: every third bit of x, from bit 0
-__device__ __forceinline__ uint32_t compact3(uint64_t x) {
-  x &= 0x1249249249249249ull;
-  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
-  x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
-  x = (x | (x >> 16)) & 0x1f00000000ffffull;
-  x = (x | (x >> 32)) & 0x1fffffull;
-  return uint32_t(x);
-}
 
 // a block-wide sum (all threads get it); tmp: kWaves + 1 entries
 template <class T>

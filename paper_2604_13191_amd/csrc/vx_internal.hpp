@@ -45,6 +45,16 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
 __device__ __forceinline__ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
 }
+// inverse of the Morton spread: every third bit of x, from bit 0
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x | (x >> 16)) & 0x1f00000000ffffull;
+  x = (x | (x >> 32)) & 0x1fffffull;
+  return uint32_t(x);
+}
 
 // ---------------------------------------------------------------------------------------------
 // Wave and block scans (wave64).
@@ -298,6 +308,13 @@ struct HeadOut {
     if (v) start[ex] = i;
   }
 };
+
+// sub-voxel occupancy (occupancy.hip; arguments checked by the caller)
+size_t occupancy_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64);
+vx_status occupancy_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
+                        int64_t n_fib, float radius, const vx_voxels* leaf, const vx_voxels* out,
+                        const int64_t* n_levels, int levels, int64_t max_cand, int64_t max_pairs,
+                        const vx_occupancy* occ, void* ws, int64_t* stats, hipStream_t s);
 
 // the sampling voxelizer (kind 0 triangles, 1 fibers; arguments checked by the caller)
 size_t sample_ws_bytes(int kind, int64_t n_prims, int64_t max_samples, int64_t max_vox, int log2R, int sub);
