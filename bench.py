@@ -358,6 +358,56 @@ def batch_timing(vx, args):
             "tuning": tuning.as_dict() if tuning is not None else "default"}
 
 
+def occupancy_timing(vx, args):
+    """Sub-voxel occupancy (Sec. 3.5, Sec. 4.2) of the full pyramids of the brushed-metal surface
+    (13 levels) and of the plain weave (11 levels): the pass regenerates the pairs, builds every
+    pair's 512-bit sub-cell mask and the masks and counts of all levels."""
+    import torch
+    import synth
+    out = {}
+    for name in ("brushed_metal", "plain_weave"):
+        wl = synth.brushed_metal() if name == "brushed_metal" else synth.plain_weave()
+        kind = 0 if name == "brushed_metal" else 1
+        data = torch.as_tensor(wl.tris if kind == 0 else wl.pts).cuda()
+        offs = None if kind == 0 else torch.as_tensor(wl.offsets).cuda()
+        radius = 0.0 if kind == 0 else wl.radius
+        plan = vx.VoxelizePlan(kind, wl.grid, data, offsets=offs, radius=radius).run()
+        leaf = plan.check()
+        cal = vx.LodPlan(wl.grid, leaf, plan.stats[2:3], wl.levels).run()
+        caps = [max(v.n, 1) for v in cal.check()[1:]]
+        del cal
+        lod = vx.LodPlan(wl.grid, leaf, plan.stats[2:3], wl.levels, caps=caps).run()
+        lod.check()
+        occ = vx.OccupancyPlan(kind, wl.grid, data, lod, offsets=offs, radius=radius)
+        for _ in range(max(1, args.warmup)):
+            occ.run()
+        torch.cuda.synchronize()
+        vx.timing_reset()
+        vx.timing_filter(None)
+        vx.timing_enable(True)
+        occ.run()
+        vx.timing_enable(False)
+        kt = vx.timing_collect()
+        steps = max(1, min(args.steps, 5))
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record()
+            occ.run()
+            b.record()
+        torch.cuda.synchronize()
+        levels = occ.check()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        lv0 = levels[0].numpy()
+        out[name] = {"pass_ms": ms, "pairs": occ.n_pairs, "leaf_voxels": leaf.n,
+                     "pairs_per_s": occ.n_pairs / (ms * 1e-3),
+                     "leaf_mean_occupancy": float(lv0["hits"].mean() / 512.0),
+                     "leaf_mean_density_xy_xz_yz": [float(lv0[f].mean() / 64.0) for f in ("xy", "xz", "yz")],
+                     "kernels_ms": {k: round(v[0], 4) for k, v in sorted(kt.items(), key=lambda x: -x[1][0])}}
+        del occ, lod, plan, leaf, data, offs
+        torch.cuda.empty_cache()
+    return out
+
+
 def _leaf_error(exact, ex_n, samp, s_n):
     """Relative L1 distance of the sampled leaf from the exact one (weights and moments, summed
     over the union of their voxels) and the share of the exact voxels of positive area that the
@@ -496,6 +546,7 @@ def main():
     ap.add_argument("--no-weave", action="store_true")
     ap.add_argument("--no-compact", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
+    ap.add_argument("--no-occupancy", action="store_true")
     ap.add_argument("--probe", action="store_true", help="end with a plain copy of known size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -534,6 +585,9 @@ def main():
 
     if not args.no_sampling:
         out["sampling"] = sampling_timing(vx, args, head["ms_per_step"])
+        torch.cuda.empty_cache()
+    if not args.no_occupancy:
+        out["occupancy"] = occupancy_timing(vx, args)
         torch.cuda.empty_cache()
 
     # ---- plain weave, fit, compact -------------------------------------------------------------

@@ -4,9 +4,10 @@
 // Every voxel of every level holds 8^3 sub-cells.  At the leaf a sub-cell is hit when a primitive
 // touches its closed box (the voxel level's exact predicate on the same lattice, with boxes of
 // s / 8 lattice units).  The pairs (primitive, voxel) come from the candidate pipeline; for each
-// pair the sub-cells are found by descending the voxel's octree three times (halves, quarters,
-// eighths), testing only the children of touched boxes, and the pair's 512-bit mask is OR-ed into
-// its voxel's mask.  OR is order-free, so the result does not depend on the order of the atomics.
+// pair the sub-cells inside the primitive's bounding box are tested (triangles through their three
+// axis projections and the plane, capsules by the distance from each sub-cell's centre), and the
+// pair's 512-bit mask is OR-ed into its voxel's mask.  OR is order-free, so the result does not
+// depend on the order of the atomics.
 // A coarser voxel's sub-cell is the union of 2 x 2 x 2 sub-cells of one child, so its mask is its
 // children's masks with every byte OR-reduced to one bit.
 //
@@ -24,35 +25,44 @@ __device__ __forceinline__ void occ_flag(int64_t* stats, int64_t bit) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// triangles: the sub-box test with the triangle's figures computed once per pair
+// triangles
 // ---------------------------------------------------------------------------------------------
-// All coordinates are lattice units relative to the voxel's corner.  The edge-axis projections
-// and every box bound are integers below 2^53 (see tri_touch), so FP64 holds them exactly; the
-// plane test uses the same error bound and exact fallback as tri_touch.
-struct TriSub {
-  double c0[3];              // vertex 0
-  double e[3][3];            // edges
-  double pmin[9], pmax[9];   // the triangle's projections on the nine edge x axis directions
-  double amin[3], amax[3];   // its bounding box
-  double n[3];               // plane normal
+// The closed-box test is the separating-axis test on the box axes, the plane normal and the nine
+// edge x box-axis directions.  The three edge directions perpendicular to axis k and the two box
+// axes other than k are the separating-axis test of the triangle and the box projected along k, so
+// a sub-cell (i, j, k) is touched exactly when
+//     P_z(i, j)  and  P_y(i, k)  and  P_x(j, k)  and  the plane meets the box,
+// with P_z, P_y, P_x the 8 x 8 masks of the squares the projected triangle meets (each 64 bits,
+// first coordinate * 8 + second).  Coordinates are lattice units from the voxel's corner.  The
+// projections and every box bound of the edge tests are integers below 2^53 (see tri_touch), so
+// FP64 holds them exactly; the plane test takes tri_touch's error bound and exact fallback.
+struct TriOcc {
+  double c0[3];
+  double e[3][3];
+  double pmin[9], pmax[9];   // the triangle on the nine edge x axis directions (edge j, axis k: 3j + k)
+  double n[3], nlo, nhi;     // plane normal, sums of its negative and positive parts
   double base;               // -n . c0
-  double mag0;               // sum |n_a c0_a|
+  double err;                // bound on the rounding of every plane evaluation in this voxel
+  int lo[3], hi[3];          // sub-cells the bounding box meets, per axis
 };
 
-__device__ __forceinline__ void tri_sub_setup(const int32_t* q, const int64_t v[3], int Sb, TriSub& T) {
+__device__ __forceinline__ void tri_occ_setup(const int32_t* q, const int64_t v[3], int Sb, TriOcc& T) {
   double c[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int a = 0; a < 3; ++a) c[i][a] = double(q[3 * i + a] - (int32_t(v[a]) << Sb));
+  const double sl = double(int64_t(1) << (Sb - 3)), isl = 1.0 / sl;    // exact: powers of two
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     T.c0[a] = c[0][a];
     T.e[0][a] = c[1][a] - c[0][a];
     T.e[1][a] = c[2][a] - c[1][a];
     T.e[2][a] = c[0][a] - c[2][a];
-    T.amin[a] = fmin(fmin(c[0][a], c[1][a]), c[2][a]);
-    T.amax[a] = fmax(fmax(c[0][a], c[1][a]), c[2][a]);
+    const double mn = fmin(fmin(c[0][a], c[1][a]), c[2][a]), mx = fmax(fmax(c[0][a], c[1][a]), c[2][a]);
+    // box [i sl, (i+1) sl] meets [mn, mx] for ceil(mn / sl) - 1 <= i <= floor(mx / sl)
+    T.lo[a] = int(fmax(ceil(mn * isl) - 1.0, 0.0));
+    T.hi[a] = int(fmin(floor(mx * isl), 7.0));
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -69,70 +79,121 @@ __device__ __forceinline__ void tri_sub_setup(const int32_t* q, const int64_t v[
   T.n[0] = fma(T.e[0][2], T.e[2][1], -(T.e[0][1] * T.e[2][2]));
   T.n[1] = fma(T.e[0][0], T.e[2][2], -(T.e[0][2] * T.e[2][0]));
   T.n[2] = fma(T.e[0][1], T.e[2][0], -(T.e[0][0] * T.e[2][1]));
+  T.nlo = (fmin(T.n[0], 0.0) + fmin(T.n[1], 0.0) + fmin(T.n[2], 0.0)) * sl;
+  T.nhi = (fmax(T.n[0], 0.0) + fmax(T.n[1], 0.0) + fmax(T.n[2], 0.0)) * sl;
   T.base = -(T.n[0] * c[0][0] + T.n[1] * c[0][1] + T.n[2] * c[0][2]);
-  T.mag0 = fabs(T.n[0] * c[0][0]) + fabs(T.n[1] * c[0][1]) + fabs(T.n[2] * c[0][2]);
+  const double mag0 = fabs(T.n[0] * c[0][0]) + fabs(T.n[1] * c[0][1]) + fabs(T.n[2] * c[0][2]);
+  // every sub-box corner offset is at most 8 sl per axis, and its bounds add sl more
+  T.err = (mag0 + 9.0 * sl * (fabs(T.n[0]) + fabs(T.n[1]) + fabs(T.n[2]))) * 0x1p-48;
 }
 
-// does the triangle meet the closed box [o, o + sl]^3?
-__device__ __forceinline__ bool tri_sub_touch(const TriSub& T, double o0, double o1, double o2, double sl) {
-  const double o[3] = {o0, o1, o2};
+// the squares (a, b) of the plane perpendicular to axis k (a along (k+1) % 3, b along (k+2) % 3)
+// that the projected triangle meets: bit a * 8 + b
+__device__ __forceinline__ uint64_t tri_occ_proj(const TriOcc& T, int k, double sl) {
+  const int u = (k + 1) % 3, w = (k + 2) % 3;
+  uint64_t m = 0;
+  for (int a = T.lo[u]; a <= T.hi[u]; ++a) {
+    for (int b = T.lo[w]; b <= T.hi[w]; ++b) {
+      const double ou = a * sl, ow = b * sl;
+      bool in = true;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-    if (o[a] > T.amax[a] || o[a] + sl < T.amin[a]) return false;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int u = (k + 1) % 3, w = (k + 2) % 3;
-      const double au = -T.e[j][w], aw = T.e[j][u];
-      const double ao = fma(au, o[u], aw * o[w]);
-      const double blo = ao + (fmin(au, 0.0) + fmin(aw, 0.0)) * sl;
-      const double bhi = ao + (fmax(au, 0.0) + fmax(aw, 0.0)) * sl;
-      if (T.pmax[3 * j + k] < blo || T.pmin[3 * j + k] > bhi) return false;
+      for (int j = 0; j < 3; ++j) {
+        const double au = -T.e[j][w], aw = T.e[j][u];
+        const double ao = fma(au, ou, aw * ow);
+        const double blo = ao + (fmin(au, 0.0) + fmin(aw, 0.0)) * sl;
+        const double bhi = ao + (fmax(au, 0.0) + fmax(aw, 0.0)) * sl;
+        in = in && !(T.pmax[3 * j + k] < blo || T.pmin[3 * j + k] > bhi);
+      }
+      if (in) m |= 1ull << (a * 8 + b);
     }
   }
-  // plane: n . (corner - c0) over the box's corners must not keep one strict sign
-  const double no = T.n[0] * o[0] + T.n[1] * o[1] + T.n[2] * o[2];
-  const double b = T.base + no;
-  double lo = b, hi = b;
-  double mag = T.mag0 + fabs(T.n[0] * o[0]) + fabs(T.n[1] * o[1]) + fabs(T.n[2] * o[2]);
+  return m;
+}
+
+// does the plane meet the closed box at sub-cell (i, j, k)?
+__device__ __forceinline__ bool tri_occ_plane(const TriOcc& T, int i, int j, int k, double sl) {
+  const double o0 = i * sl, o1 = j * sl, o2 = k * sl;
+  const double b = T.base + (T.n[0] * o0 + T.n[1] * o1 + T.n[2] * o2);
+  const double lo = b + T.nlo, hi = b + T.nhi;
+  if (lo > T.err || hi < -T.err) return false;
+  if (lo < -T.err && hi > T.err) return true;
+  return plane_exact(int64_t(T.n[0]), int64_t(T.n[1]), int64_t(T.n[2]), int64_t(o0 - T.c0[0]), int64_t(o1 - T.c0[1]),
+                     int64_t(o2 - T.c0[2]), int64_t(sl));
+}
+
+// ---------------------------------------------------------------------------------------------
+// capsules: per sub-cell the distance from its centre to the segment decides (the box holds the
+// ball of radius h around its centre and lies in the one of radius h sqrt(3)); the rest take the
+// exact voxel-level test on the sub-box.
+// ---------------------------------------------------------------------------------------------
+struct CapOcc {
+  double c[3], d[3];         // segment start from the voxel's corner, direction (lattice units)
+  double inv_dd;             // 1 / |d|^2 (0 for a point)
+  double err;                // rounding bound of a squared distance, as in cap_ball
+  double rin2, rout2;        // touch below (h + rho)^2, none above (h sqrt 3 + rho)^2
+  int lo[3], hi[3];
+};
+
+__device__ __forceinline__ void cap_occ_setup(const int32_t* r, const int64_t v[3], int Sb, int64_t rho, CapOcc& C) {
+  const double s = double(int64_t(1) << Sb), sl = 0.125 * s, isl = 1.0 / sl;
+  double M = s;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double t = T.n[a] * sl;
-    if (T.n[a] > 0) hi += t; else lo += t;
-    mag += fabs(t);
+    const int32_t ci = r[a] - (int32_t(v[a]) << Sb);
+    const int32_t di = r[3 + a] - r[a];
+    C.c[a] = double(ci);
+    C.d[a] = double(di);
+    M = fmax(M, fabs(C.c[a]) + fabs(C.d[a]) + s);
+    const double mn = fmin(C.c[a], C.c[a] + C.d[a]) - double(rho), mx = fmax(C.c[a], C.c[a] + C.d[a]) + double(rho);
+    C.lo[a] = int(fmax(ceil(mn * isl) - 1.0, 0.0));
+    C.hi[a] = int(fmin(floor(mx * isl), 7.0));
   }
-  const double err = mag * 0x1p-48;
-  if (lo > err || hi < -err) return false;
-  if (lo < -err && hi > err) return true;
-  return plane_exact(int64_t(T.n[0]), int64_t(T.n[1]), int64_t(T.n[2]), int64_t(o[0] - T.c0[0]),
-                     int64_t(o[1] - T.c0[1]), int64_t(o[2] - T.c0[2]), int64_t(sl));
+  C.inv_dd = cap_inv_len2(r);
+  C.err = M * M * 0x1p-44;
+  const double h = 0.5 * sl, rh = double(rho);
+  C.rin2 = (h + rh) * (h + rh);
+  C.rout2 = (h * 1.7320508075688772 + rh) * (h * 1.7320508075688772 + rh) * (1.0 + 0x1p-40);
 }
 
-// ---------------------------------------------------------------------------------------------
-// capsules: the voxel level's test on the sub-boxes (absolute sub-box indices), plus a
-// conservative containment test that settles whole subtrees
-// ---------------------------------------------------------------------------------------------
-// Is the closed box (index u, size 2^Sb) inside the capsule?  Its farthest point from the
-// segment is within dist(centre, segment) + h sqrt(3); a true answer is certain (the margins
-// cover every rounding), a false one only means "not known".
-__device__ __forceinline__ bool cap_contains(const int32_t* r, const int64_t u[3], int64_t s, int Sb, int64_t rho,
-                                             double inv_dd) {
-  CapIn q;
-  cap_setup(r, u, s, Sb, q);
-  const double h = 0.5 * double(s);
-  double wx = h - q.c[0], wy = h - q.c[1], wz = h - q.c[2];
-  double tc = (wx * q.d[0] + wy * q.d[1] + wz * q.d[2]) * inv_dd;
+__device__ __attribute__((noinline)) bool cap_occ_exact(const int32_t* r, int64_t u0, int64_t u1, int64_t u2,
+                                                        int64_t sl, int Sbl, int64_t rho) {
+  const int64_t u[3] = {u0, u1, u2};
+  return cap_touch(r, u, sl, Sbl, rho);
+}
+
+// A sub-cell whose centre lies between the two balls.  P, the segment's point nearest the centre
+// X, and u = (X - P) / |X - P|: the segment projects onto u at or below u . P (P is its nearest
+// point to X) and the box at or above u . X - h (|u_x| + |u_y| + |u_z|), so the box lies farther
+// than |X - P| - h sum |u_a| from the segment; and the box lies within the distance from P to the
+// box.  Either settles most; the margins (2 err on squared lengths) cover every rounding.  The
+// rest take the exact test.
+__device__ __forceinline__ bool cap_occ_band(const CapOcc& C, const int32_t* r, const int64_t v[3], int a, int b,
+                                             int c, double sl, int Sb, int64_t rho) {
+  const double h = 0.5 * sl, rh = double(rho);
+  const double o[3] = {a * sl, b * sl, c * sl};
+  double w[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) w[x] = (o[x] + h) - C.c[x];
+  double tc = (w[0] * C.d[0] + w[1] * C.d[1] + w[2] * C.d[2]) * C.inv_dd;
   tc = fmin(fmax(tc, 0.0), 1.0);
-  wx = fma(-tc, q.d[0], wx);
-  wy = fma(-tc, q.d[1], wy);
-  wz = fma(-tc, q.d[2], wz);
-  const double dc = sqrt(wx * wx + wy * wy + wz * wz + q.err);
-  return (dc + h * 1.7320508075688772 * (1.0 + 0x1p-40)) * (1.0 + 0x1p-40) <= double(rho);
+  double dc2 = 0.0, s1 = 0.0, f = 0.0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    const double wx = fma(-tc, C.d[x], w[x]);
+    dc2 = fma(wx, wx, dc2);
+    s1 += fabs(wx);
+    const double p = fma(tc, C.d[x], C.c[x]) - o[x];          // P from the box's corner
+    const double e = p < 0 ? p : (p > sl ? p - sl : 0.0);
+    f = fma(e, e, f);
+  }
+  if (f + C.err <= rh * rh) return true;
+  const double lhs = dc2 - h * s1 - 2.0 * C.err;
+  if (lhs > 0.0 && lhs > rh * sqrt(dc2 + C.err) * (1.0 + 0x1p-40)) return false;
+  return cap_occ_exact(r, 8 * v[0] + a, 8 * v[1] + b, 8 * v[2] + c, int64_t(sl), Sb - 3, rho);
 }
 
 // ---------------------------------------------------------------------------------------------
-// per pair: find the voxel in the leaf, descend, OR the words in
+// per pair: find the voxel in the leaf, build each octant's word, OR it in
 // ---------------------------------------------------------------------------------------------
 template <class Key>
 __device__ __forceinline__ int64_t find_key(const Key* __restrict__ keys, int64_t n, Key k) {
@@ -142,6 +203,11 @@ __device__ __forceinline__ int64_t find_key(const Key* __restrict__ keys, int64_
     if (keys[mid] < k) lo = mid + 1; else hi = mid;
   }
   return lo < n && keys[lo] == k ? lo : -1;
+}
+
+// Morton bit of sub-cell (i, j, k) inside its octant's word: the low bits of the coordinates
+__device__ __forceinline__ int oct_bit(int i, int j, int k) {
+  return (i & 1) | ((j & 1) << 1) | ((k & 1) << 2) | ((i & 2) << 2) | ((j & 2) << 3) | ((k & 2) << 4);
 }
 
 template <int KIND, class Key>
@@ -157,6 +223,7 @@ __global__ void __launch_bounds__(kBlock) k_occ_pairs(const int32_t* __restrict_
   // access in bounds
   const int64_t nl = imin(imin(*n_leaf, leaf_cap), cap);
   const int Sb = L.Sb;
+  const double sl = double(int64_t(1) << (Sb - 3));
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     const Key key = pkeys[i];
     const int64_t idx = find_key<Key>(leaf_keys, nl, key);
@@ -168,50 +235,61 @@ __global__ void __launch_bounds__(kBlock) k_occ_pairs(const int32_t* __restrict_
                           int64_t(compact3(uint64_t(key) >> 2))};
     const int32_t* r = rec + int64_t(prim[i]) * kRec;
     if (KIND == 0) {
-      TriSub T;
-      tri_sub_setup(r, v, Sb, T);
-      const double s1 = double(int64_t(1) << (Sb - 1)), s2 = 0.5 * s1, s3 = 0.25 * s1;
-      for (int c1 = 0; c1 < 8; ++c1) {
-        const double a0 = (c1 & 1) * s1, a1 = ((c1 >> 1) & 1) * s1, a2 = (c1 >> 2) * s1;
-        if (!tri_sub_touch(T, a0, a1, a2, s1)) continue;
+      TriOcc T;
+      tri_occ_setup(r, v, Sb, T);
+      const uint64_t pz = tri_occ_proj(T, 2, sl);     // (x, y)
+      const uint64_t py = tri_occ_proj(T, 1, sl);     // (z, x)
+      const uint64_t px = tri_occ_proj(T, 0, sl);     // (y, z)
+      for (int oct = 0; oct < 8; ++oct) {
+        const int i0 = (oct & 1) * 4, j0 = ((oct >> 1) & 1) * 4, k0 = (oct >> 2) * 4;
+        const int ia = max(T.lo[0], i0), ib = min(T.hi[0], i0 + 3);
+        const int ja = max(T.lo[1], j0), jb = min(T.hi[1], j0 + 3);
+        const int ka = max(T.lo[2], k0), kb = min(T.hi[2], k0 + 3);
         uint64_t word = 0;
-        for (int c2 = 0; c2 < 8; ++c2) {
-          const double b0 = a0 + (c2 & 1) * s2, b1 = a1 + ((c2 >> 1) & 1) * s2, b2 = a2 + (c2 >> 2) * s2;
-          if (!tri_sub_touch(T, b0, b1, b2, s2)) continue;
-          uint32_t bits = 0;
-          for (int c3 = 0; c3 < 8; ++c3)
-            if (tri_sub_touch(T, b0 + (c3 & 1) * s3, b1 + ((c3 >> 1) & 1) * s3, b2 + (c3 >> 2) * s3, s3))
-              bits |= 1u << c3;
-          word |= uint64_t(bits) << (8 * c2);
-        }
-        if (word) atomicOr(mask + int64_t(c1) * cap + idx, (unsigned long long)word);
+        for (int a = ia; a <= ib; ++a)
+          for (int b = ja; b <= jb; ++b) {
+            if (!((pz >> (a * 8 + b)) & 1)) continue;
+            for (int c = ka; c <= kb; ++c)
+              if (((py >> (c * 8 + a)) & 1) && ((px >> (b * 8 + c)) & 1) && tri_occ_plane(T, a, b, c, sl))
+                word |= 1ull << oct_bit(a, b, c);
+          }
+        if (word) atomicOr(mask + int64_t(oct) * cap + idx, (unsigned long long)word);
       }
     } else {
-      const double inv_dd = cap_inv_len2(r);
-      const int64_t rho = L.rho;
-      for (int c1 = 0; c1 < 8; ++c1) {
-        const int64_t u1[3] = {2 * v[0] + (c1 & 1), 2 * v[1] + ((c1 >> 1) & 1), 2 * v[2] + (c1 >> 2)};
-        const int64_t s1 = int64_t(1) << (Sb - 1);
-        if (!cap_touch(r, u1, s1, Sb - 1, rho)) continue;
-        uint64_t word = ~0ull;
-        if (!cap_contains(r, u1, s1, Sb - 1, rho, inv_dd)) {
-          word = 0;
-          for (int c2 = 0; c2 < 8; ++c2) {
-            const int64_t u2[3] = {2 * u1[0] + (c2 & 1), 2 * u1[1] + ((c2 >> 1) & 1), 2 * u1[2] + (c2 >> 2)};
-            const int64_t s2 = s1 >> 1;
-            if (!cap_touch(r, u2, s2, Sb - 2, rho)) continue;
-            uint32_t bits = 0xffu;
-            if (!cap_contains(r, u2, s2, Sb - 2, rho, inv_dd)) {
-              bits = 0;
-              for (int c3 = 0; c3 < 8; ++c3) {
-                const int64_t u3[3] = {2 * u2[0] + (c3 & 1), 2 * u2[1] + ((c3 >> 1) & 1), 2 * u2[2] + (c3 >> 2)};
-                if (cap_touch(r, u3, s2 >> 1, Sb - 3, rho)) bits |= 1u << c3;
-              }
+      CapOcc C;
+      cap_occ_setup(r, v, Sb, L.rho, C);
+      const double h = 0.5 * sl;
+      for (int oct = 0; oct < 8; ++oct) {
+        const int i0 = (oct & 1) * 4, j0 = ((oct >> 1) & 1) * 4, k0 = (oct >> 2) * 4;
+        const int ia = max(C.lo[0], i0), ib = min(C.hi[0], i0 + 3);
+        const int ja = max(C.lo[1], j0), jb = min(C.hi[1], j0 + 3);
+        const int ka = max(C.lo[2], k0), kb = min(C.hi[2], k0 + 3);
+        // the centre test decides most sub-cells; the few near the capsule's surface wait for the
+        // exact test until the octant's loop is done, so that one lane's slow path does not stall
+        // the wave at every step
+        uint64_t word = 0, band = 0;
+        for (int a = ia; a <= ib; ++a)
+          for (int b = ja; b <= jb; ++b)
+            for (int c = ka; c <= kb; ++c) {
+              double wx = fma(a, sl, h) - C.c[0], wy = fma(b, sl, h) - C.c[1], wz = fma(c, sl, h) - C.c[2];
+              double tc = (wx * C.d[0] + wy * C.d[1] + wz * C.d[2]) * C.inv_dd;
+              tc = fmin(fmax(tc, 0.0), 1.0);
+              wx = fma(-tc, C.d[0], wx);
+              wy = fma(-tc, C.d[1], wy);
+              wz = fma(-tc, C.d[2], wz);
+              const double dc2 = wx * wx + wy * wy + wz * wz;
+              const uint64_t bit = 1ull << oct_bit(a, b, c);
+              if (dc2 + C.err <= C.rin2) word |= bit;
+              else if (!(dc2 - C.err > C.rout2)) band |= bit;
             }
-            word |= uint64_t(bits) << (8 * c2);
-          }
+        while (band) {
+          const int t = __builtin_ctzll(band);
+          band &= band - 1;
+          const int a = i0 + ((t & 1) | ((t >> 2) & 2)), b = j0 + (((t >> 1) & 1) | ((t >> 3) & 2)),
+                    c = k0 + (((t >> 2) & 1) | ((t >> 4) & 2));
+          if (cap_occ_band(C, r, v, a, b, c, sl, Sb, L.rho)) word |= 1ull << t;
         }
-        if (word) atomicOr(mask + int64_t(c1) * cap + idx, (unsigned long long)word);
+        if (word) atomicOr(mask + int64_t(oct) * cap + idx, (unsigned long long)word);
       }
     }
   }
@@ -358,7 +436,7 @@ vx_status occupancy_run(int kind, const vx_grid* g, const float* data, int64_t n
   Carver cv(ws);
   FrontWs w;
   front_ws_carve(cv, n_prims, max_cand, max_pairs, key64, &w);
-  voxelize_front(kind, g, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, w, stats, s, nullptr);
+  voxelize_front(kind, g, data, n_prims, offsets, n_fib, radius, max_cand, max_pairs, w, stats, s, nullptr, false);
   const Lat L = make_lat(g, kind, radius);
   hipLaunchKernelGGL(k_occ_check, dim3(1), dim3(64), 0, s, n_levels, leaf->cap, occ[0].cap, stats);
   hipLaunchKernelGGL(k_occ_zero, dim3(occ_blocks(occ[0].cap)), dim3(kBlock), 0, s,

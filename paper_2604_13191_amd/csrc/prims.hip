@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec
                                                  const uint64_t* __restrict__ masks,
                                                  const int64_t* __restrict__ chunk_prim,
                                                  const int64_t* __restrict__ wave_off, Key* __restrict__ keys,
-                                                 float* __restrict__ wts, uint32_t* __restrict__ prim) {
+                                                 float* __restrict__ wts, uint32_t* __restrict__ prim, bool weights) {
   const int64_t n_chunks = ctl[CTL_N_CHUNKS];
   const int lane = lane_id();
   const int64_t w0 = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
@@ -182,10 +182,12 @@ __global__ void __launch_bounds__(kBlock) k_emit(const int32_t* __restrict__ rec
     const int32_t* r = rec + p * kRec;
     int64_t v[3];
     candidate_voxel(r, ci - cand_off[p], v);
-    float wgt;
+    float wgt = 0.0f;
     const int Sb = lats ? lats[r[15]].Sb : L.Sb;
-    if (KIND == 0) wgt = tri_area(r, v, Sb, dirs[p].w);
-    else wgt = seg_length(r, v, Sb, dirs[p].w);
+    if (weights) {
+      if (KIND == 0) wgt = tri_area(r, v, Sb, dirs[p].w);
+      else wgt = seg_length(r, v, Sb, dirs[p].w);
+    }
     Key key = Key(morton3(uint32_t(v[0]), uint32_t(v[1]), uint32_t(v[2])));
     if (lats) key |= Key(uint64_t(uint32_t(r[15])) << kPatchShift);
     keys[pos] = key;
@@ -330,7 +332,7 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
 // prep -> candidate scan -> exact test -> pair scan -> emit: pairs in emission order in f.pa
 void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                     int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
-                    int64_t* stats, hipStream_t s, const BatchLattice* batch) {
+                    int64_t* stats, hipStream_t s, const BatchLattice* batch, bool weights) {
   const bool key64 = batch || g->log2_res > 10;
   const Lat L = make_lat(g, kind, radius);
   const Lat* lats = batch ? batch->lats : nullptr;
@@ -361,7 +363,8 @@ void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_pri
   VX_TIMED(kind == 0 ? "emit_tri" : "emit_fib", s);
 #define VX_EMIT(KD, K)                                                                                        \
   hipLaunchKernelGGL((k_emit<KD, K>), dim3(kGrid), dim3(kBlock), 0, s, w.rec, w.dirs, w.cand_off, \
-                     n_prims, w.ctl, L, lats, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim)
+                     n_prims, w.ctl, L, lats, w.masks, w.chunk_prim, w.wave_off, (K*)w.pa.keys, w.pa.w, w.pa.prim, \
+                     weights)
   if (kind == 0) {
     if (key64) VX_EMIT(0, uint64_t); else VX_EMIT(0, uint32_t);
   } else {

@@ -362,9 +362,10 @@ struct BatchLattice {
   const int64_t* pt_begin;   // [n_patches + 1]
   int n_patches;
 };
+// weights = false: the pairs' weights are left 0 (for callers that need only keys and primitives)
 void voxelize_front(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                     int64_t n_fib, float radius, int64_t max_cand, int64_t max_pairs, const FrontWs& w,
-                    int64_t* stats, hipStream_t s, const BatchLattice* batch);
+                    int64_t* stats, hipStream_t s, const BatchLattice* batch, bool weights = true);
 // its first step: clear stats and control, snap the primitives, write records and candidate counts
 void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
                 int64_t n_fib, float radius, const FrontWs& w, int64_t* stats, hipStream_t s,
