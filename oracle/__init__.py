@@ -18,6 +18,9 @@ Functions and the passages they follow:
 * ``oracle.occupancy`` (numpy over the voxelizer) -- Sec. 3.5 occupancy of 8^3 sub-cells per
   voxel and its XY / XZ / YZ projections, Sec. 4.2 the same for the coarser levels: the
   sub-cells are the voxels of the voxelizer run at 8x the resolution.
+* ``sggxh_level`` / ``sggxh_pyramid`` -- Sec. 4.4 SGGX-H: lobes compared through histograms
+  of samples drawn from them (counter-based SplitMix64), a Wasserstein distance, and merges of
+  the closest pair by pooling samples (``vxo_sggxh.cpp``).
 * ``sample_fibers`` / ``sample_triangles`` -- Sec. 3.2 sampling voxelizer: Catmull-Rom spans
   subdivided into chords with equally spaced samples, and Heitz's low-distortion triangle map
   with sample counts in proportion to the triangle's area (``vxo_sample.cpp``).
@@ -36,7 +39,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "vxo.cpp"), os.path.join(_HERE, "vxo_fit.cpp"), os.path.join(_HERE, "vxo_sample.cpp")]
+_SRCS = [os.path.join(_HERE, "vxo.cpp"), os.path.join(_HERE, "vxo_fit.cpp"), os.path.join(_HERE, "vxo_sample.cpp"),
+         os.path.join(_HERE, "vxo_sggxh.cpp")]
 # VXO_SANITIZE=1: a separate build under AddressSanitizer and UndefinedBehaviorSanitizer (load it
 # with libasan preloaded; tests/test_oracle_sanitized.py does)
 _SAN = os.environ.get("VXO_SANITIZE") == "1"
@@ -488,3 +492,96 @@ def heitz_map(u1, u2):
 
 def tri_sample_count(q, qmax, N) -> int:
     return int(_sample_lib().vxo_tri_sample_count(float(q), float(qmax), int(N)))
+
+
+# ------------------------------------------------------------------------------------------------
+# the paper's SGGX-H lobe reduction (Sec. 4.4)
+# ------------------------------------------------------------------------------------------------
+
+SGGXH_SAMPLES = 5000
+
+
+def _sggxh_lib():
+    L = lib()
+    if not hasattr(L, "_sggxh_ready"):
+        u64 = ctypes.c_uint64
+        L.vxo_splitmix_at.restype = u64
+        L.vxo_splitmix_at.argtypes = [u64, u64]
+        L.vxo_sggxh_lobe_key.restype = u64
+        L.vxo_sggxh_lobe_key.argtypes = [ctypes.c_int, u64, ctypes.c_int]
+        L.vxo_sggxh_hist.argtypes = [ctypes.c_void_p, ctypes.c_double, u64, ctypes.c_int, ctypes.c_void_p]
+        L.vxo_sggxh_samples.restype = ctypes.c_int
+        L.vxo_sggxh_samples.argtypes = [ctypes.c_void_p, ctypes.c_double, u64, ctypes.c_int, ctypes.c_void_p]
+        L.vxo_sggxh_reduce.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.vxo_sggxh_level.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L._sggxh_ready = True
+    return L
+
+
+def splitmix_at(key, c) -> int:
+    """SplitMix64 output number c of seed key."""
+    return int(_sggxh_lib().vxo_splitmix_at(int(key) & (2**64 - 1), int(c)))
+
+
+def sggxh_lobe_key(level, voxel_key, slot) -> int:
+    return int(_sggxh_lib().vxo_sggxh_lobe_key(int(level), int(voxel_key), int(slot)))
+
+
+def sggxh_hist(S, w, key, N=SGGXH_SAMPLES) -> np.ndarray:
+    """Counts [5, 5, 5] (bins of x, y, z) of N normals sampled from the lobe (w, S)."""
+    S6 = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(6))
+    h = np.zeros(125, np.int32)
+    _sggxh_lib().vxo_sggxh_hist(_ptr(S6), float(w), int(key), int(N), _ptr(h))
+    return h.reshape(5, 5, 5)
+
+
+def sggxh_samples(S, w, key, N=SGGXH_SAMPLES) -> np.ndarray:
+    """The unit normals [N, 3] drawn for the lobe (w, S), in sample order."""
+    S6 = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(6))
+    out = np.zeros((int(N), 3))
+    m = _sggxh_lib().vxo_sggxh_samples(_ptr(S6), float(w), int(key), int(N), _ptr(out))
+    return out[:m]
+
+
+def sggxh_reduce(w, S, counts, K):
+    """Merge lobes with the given histograms down to K: (nl, w [K], S [K, 6], out_of [n])."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n = len(w)
+    S = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(n, 6))
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.int32).reshape(n, 125))
+    nl = ctypes.c_int(0)
+    ow, oS, of = np.zeros(max(K, 1)), np.zeros((max(K, 1), 6)), np.zeros(n, np.int32)
+    _sggxh_lib().vxo_sggxh_reduce(n, _ptr(w), _ptr(S), _ptr(c), int(K), ctypes.byref(nl), _ptr(ow), _ptr(oS),
+                                  _ptr(of))
+    return nl.value, ow[:nl.value], oS[:nl.value], of
+
+
+def sggxh_level(child: Lobes, child_start, parent_keys, level: int, K: int, N=SGGXH_SAMPLES) -> Lobes:
+    n_par = len(child_start) - 1
+    Kc = child.w.shape[1]
+    out = Lobes(np.zeros(n_par, np.int32), np.zeros((n_par, K)), np.zeros((n_par, K, 6)),
+                np.zeros(n_par), np.zeros(n_par))
+    pk = np.ascontiguousarray(parent_keys, dtype=np.uint64)
+    cs = np.ascontiguousarray(child_start, dtype=np.int64)
+    cnl = np.ascontiguousarray(child.nl, dtype=np.int32)
+    cw = np.ascontiguousarray(child.w, dtype=np.float64)
+    cS = np.ascontiguousarray(child.S, dtype=np.float64)
+    _sggxh_lib().vxo_sggxh_level(n_par, _ptr(pk), _ptr(cs), _ptr(cnl), _ptr(cw), _ptr(cS), Kc, int(level), int(K),
+                                 int(N), _ptr(out.nl), _ptr(out.w), _ptr(out.S))
+    return out
+
+
+def sggxh_pyramid(lod, K: int, N=SGGXH_SAMPLES):
+    """SGGX-H lobes of levels 1 .. len(lod)-1 (index 0 holds the leaf as one lobe per voxel)."""
+    leaf = lod[0]
+    n0 = len(leaf.keys)
+    cur = Lobes((leaf.w > 0).astype(np.int32), leaf.w.reshape(n0, 1).copy(), leaf.S.reshape(n0, 1, 6).copy(),
+                np.zeros(n0), np.zeros(n0))
+    out = [cur]
+    for L in range(1, len(lod)):
+        cur = sggxh_level(cur, lod[L].child_start, lod[L].keys, L, K, N)
+        out.append(cur)
+    return out

@@ -28,7 +28,8 @@ def test_oracle_pins_clean_under_asan_ubsan():
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
     subprocess.run([sys.executable, "-c", "import oracle; oracle.build(force=True)"], cwd=ROOT, env=env, check=True)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py", "tests/test_oracle_fit.py", "tests/test_oracle_compact.py"],
+                        "tests/test_oracle_pins.py", "tests/test_oracle_fit.py", "tests/test_oracle_compact.py",
+                        "tests/test_oracle_sample.py", "tests/test_oracle_occupancy.py", "tests/test_oracle_sggxh.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     tail = (r.stdout + r.stderr)[-3000:]
     assert r.returncode == 0, tail
