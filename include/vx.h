@@ -207,6 +207,31 @@ vx_status vx_sample_fibers(const vx_grid* grid, const float* pts, int64_t n_pts,
                            size_t ws_bytes, const vx_voxels* out, int64_t* stats, vx_stream stream);
 
 /* ------------------------------------------------------------------------------------------
+ * SGGX-H lobes (Sec. 4.4, the paper's own reduction; vx_build_lod's K > 1 lobes use the
+ * deterministic moment metric instead).
+ *
+ * Level L voxel gathers its children's lobes (level 1: one per leaf voxel; level L > 1: the
+ * SGGX-H lobes of level L - 1), drops zero weights, and while more than K remain merges the two
+ * closest (w and S added).  Closeness: each lobe's normals are sampled `samples` times -- the
+ * SGGX of S / w with 1e-3 of its trace added to the diagonal, n = L u / |L u| for S = L L^T and
+ * u uniform on the sphere (rejection from the cube), accepted with probability |L u| /
+ * sqrt(tr S); draw d of sample k is SplitMix64 output k 2^32 + d of the seed
+ * mix(mix(key + g (L + 1)) + g (slot + 1)), g = 0x9E3779B97F4A7C15, mix = SplitMix64's output
+ * function, key the voxel's Morton key, slot the lobe's index among the voxel's positive input
+ * lobes -- into 5 bins per axis (floor((n_a + 1) 2.5)); the distance is the Wasserstein-1
+ * distance between the per-axis marginals, summed over the axes; a merged lobe pools the samples
+ * of its parts.  Closest pair ties go to the first (i, j) in slot order; the survivors are
+ * sorted by descending weight.  The sampling is bit-reproducible (integer counts of IEEE double
+ * decisions), so the partition is deterministic; w and S are FP32 sums.
+ * leaf, out, n_levels: the pyramid of vx_build_lod (levels as there); lobes: levels - 1 outputs
+ * (K 1 .. 8, caps at least the levels' counts); samples 1 .. 65536 (the paper uses 5000).
+ * stats: int64[VX_NSTAT] (flags only: VX_FLAG_VOXEL_CAPACITY when a level exceeds a cap).
+ * ------------------------------------------------------------------------------------------ */
+vx_status vx_build_sggxh(const vx_grid* grid, const vx_voxels* leaf, const vx_voxels* out, const int64_t* n_levels,
+                         int32_t levels, int32_t K, int32_t samples, const vx_lobes* lobes, int64_t* stats,
+                         vx_stream stream);
+
+/* ------------------------------------------------------------------------------------------
  * Sub-voxel occupancy and projected densities (Sec. 3.5 occupancy equation and XY / XZ / YZ
  * projections, Sec. 4.2 the projections at the coarser levels).
  *

@@ -102,7 +102,7 @@ void lobe_hist(const double* S, double w, u64 key, int N, int32_t* counts) {
     int b[3];
     for (int c = 0; c < 3; ++c) {
       const double f = std::floor((n[c] + 1.0) * 2.5);
-      b[c] = f < 0.0 ? 0 : (f > 4.0 ? 4 : int(f));
+      b[c] = !(f >= 0.0) ? 0 : (f > 4.0 ? 4 : int(f));     // a non-finite lobe lands in bin 0
     }
     counts[b[0] * 25 + b[1] * 5 + b[2]] += 1;
   });

@@ -138,6 +138,9 @@ def load():
     L.vx_sample_fibers.restype = ctypes.c_int
     L.vx_sample_fibers.argtypes = [ctypes.POINTER(CGrid), vp, i64, vp, i64, ctypes.POINTER(CSampling), i64, vp, sz,
                                    ctypes.POINTER(CVoxels), vp, vp]
+    L.vx_build_sggxh.restype = ctypes.c_int
+    L.vx_build_sggxh.argtypes = [ctypes.POINTER(CGrid), ctypes.POINTER(CVoxels), ctypes.POINTER(CVoxels), vp, i32,
+                                 i32, i32, ctypes.POINTER(CLobes), vp, vp]
     L.vx_occupancy_workspace_size.restype = sz
     L.vx_occupancy_workspace_size.argtypes = [i32, i64, i64, i64, i32]
     L.vx_occupancy_triangles.restype = ctypes.c_int
@@ -533,6 +536,45 @@ class LodPlan:
             if self.lobes:
                 self.lobes[L - 1].n = int(h[L])
         return [self.leaf] + self.out
+
+
+SGGXH_SAMPLES = 5000
+
+
+class SggxhPlan:
+    """The paper's SGGX-H lobes (Sec. 4.4) over the pyramid `lod` (a LodPlan, run and checked):
+    up to K lobes per voxel of levels 1 .. levels-1, merged by the histogram distance.  ``run()``
+    enqueues all levels with no host sync; ``check()`` returns the Lobes of levels 1 ..."""
+
+    def __init__(self, lod, K=4, samples=SGGXH_SAMPLES):
+        import torch
+        self.L = load()
+        self.lod, self.K, self.samples = lod, int(K), int(samples)
+        dev = lod.leaf.w.device
+        self.lobes = [Lobes(torch.zeros(v.cap, dtype=torch.uint8, device=dev),
+                            torch.zeros((self.K, v.cap), dtype=torch.float32, device=dev),
+                            torch.zeros((6, self.K, v.cap), dtype=torch.float32, device=dev)) for v in lod.out]
+        self._clobes = (CLobes * max(1, len(self.lobes)))(*[lb.cstruct() for lb in self.lobes])
+        self._cleaf = lod.leaf.cstruct()
+        self._cout = (CVoxels * max(1, len(lod.out)))(*[v.cstruct() for v in lod.out])
+        self.stats = torch.zeros(VX_NSTAT, dtype=torch.int64, device=dev)
+
+    def run(self, stream=None):
+        st = self.L.vx_build_sggxh(ctypes.byref(self.lod.cgrid), ctypes.byref(self._cleaf), self._cout,
+                                   _ptr(self.lod.n_levels), self.lod.levels, self.K, self.samples, self._clobes,
+                                   _ptr(self.stats), _stream(stream))
+        if st != 0:
+            raise VxError(st, "build_sggxh")
+        return self
+
+    def check(self, stream=None):
+        st = self.L.vx_check_stats(_ptr(self.stats), _stream(stream))
+        if st != 0:
+            raise VxError(st, "build_sggxh")
+        n = self.lod.n_levels.cpu().numpy()
+        for L, lb in enumerate(self.lobes, start=1):
+            lb.n = int(n[L])
+        return self.lobes
 
 
 @dataclass

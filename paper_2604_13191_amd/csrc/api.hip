@@ -250,6 +250,20 @@ vx_status vx_sample_fibers(const vx_grid* grid, const float* pts, int64_t n_pts,
                        stats, stream);
 }
 
+vx_status vx_build_sggxh(const vx_grid* grid, const vx_voxels* leaf, const vx_voxels* out, const int64_t* n_levels,
+                         int32_t levels, int32_t K, int32_t samples, const vx_lobes* lobes, int64_t* stats,
+                         vx_stream stream) {
+  if (!grid_ok(grid) || !voxels_ok(leaf, false) || !n_levels || levels < 2 || levels > grid->log2_res + 1 ||
+      !out || !lobes || K < 1 || K > 8 || samples < 1 || samples > 65536 || !stats)
+    return VX_ERR_ARG;
+  for (int l = 1; l < levels; ++l) {
+    if (!out[l - 1].keys || out[l - 1].cap < 1) return VX_ERR_ARG;
+    const vx_lobes& b = lobes[l - 1];
+    if (!b.nl || !b.w || !b.S || b.cap < 1) return VX_ERR_ARG;
+  }
+  return sggxh_run(grid, leaf, out, n_levels, levels, K, samples, lobes, stats, reinterpret_cast<hipStream_t>(stream));
+}
+
 size_t vx_occupancy_workspace_size(int32_t kind, int64_t n_prims, int64_t max_cand, int64_t max_pairs,
                                    int32_t log2_res) {
   if ((kind != 0 && kind != 1) || n_prims < 0 || n_prims > kMaxPrims || max_cand < 0 || max_pairs < 0 ||

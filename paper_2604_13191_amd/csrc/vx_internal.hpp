@@ -309,6 +309,10 @@ struct HeadOut {
   }
 };
 
+// SGGX-H lobes (sggxh.hip; arguments checked by the caller)
+vx_status sggxh_run(const vx_grid* g, const vx_voxels* leaf, const vx_voxels* out, const int64_t* n_levels,
+                    int levels, int K, int N, const vx_lobes* lobes, int64_t* stats, hipStream_t s);
+
 // sub-voxel occupancy (occupancy.hip; arguments checked by the caller)
 size_t occupancy_ws_bytes(int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64);
 vx_status occupancy_run(int kind, const vx_grid* g, const float* data, int64_t n_prims, const int64_t* offsets,
