@@ -408,6 +408,87 @@ def occupancy_timing(vx, args):
     return out
 
 
+def sggxh_timing(vx, args, d_lod_ms):
+    """The paper's SGGX-H reduction (Sec. 4.4: 5000 samples per lobe, 5^3 histograms, Wasserstein
+    merges) over the 13-level pyramid of the brushed-metal surface with K = 4, against the moment
+    metric's Ward + Lloyd clustering of the same pyramid: time, and at level 1 (both reduce the
+    same leaf lobes) the share of voxels merged alike and the projected-area error of the K lobes
+    against the unmerged children (64 directions)."""
+    import torch
+    import synth
+    from paper_2604_13191_amd import autotune
+    wl = synth.brushed_metal()
+    tris = torch.as_tensor(wl.tris).cuda()
+    grid, levels = wl.grid, wl.levels
+    del wl
+    tuned = autotune.load("brushed_metal")
+    plan = vx.VoxelizePlan(0, grid, tris, tuning=tuned).run()
+    leaf = plan.check()
+    cal = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, tuning=tuned).run()
+    caps = [max(v.n, 1) for v in cal.check()[1:]]
+    del cal
+    lod = vx.LodPlan(grid, leaf, plan.stats[2:3], levels, K=4, iters=2, caps=caps, tuning=tuned).run()
+    lod.check()
+    sh = vx.SggxhPlan(lod, K=4, samples=5000)
+    sh.run()
+    sh.check()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    vx.timing_reset()
+    vx.timing_filter(None)
+    vx.timing_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        sh.run()
+        b.record()
+    torch.cuda.synchronize()
+    vx.timing_enable(False)
+    kt = vx.timing_collect()
+    hl = sh.check()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    # level 1: both methods reduce the same leaf lobes
+    n0, n1 = leaf.n, lod.out[0].n
+    lk = leaf.keys[:n0].long()
+    pk = lod.out[0].keys[:n1].long()
+    parent = torch.searchsorted(pk, lk >> 3)
+    inputs = torch.zeros(n1, dtype=torch.int64, device=lk.device).index_add_(
+        0, parent, (leaf.w[:n0] > 0).long())
+    from synth import fibonacci_dirs
+    dirs = torch.as_tensor(fibonacci_dirs(64), dtype=torch.float64, device=lk.device)
+    S0 = leaf.S[:, :n0].double()
+    x, y, z = dirs[:, 0], dirs[:, 1], dirs[:, 2]
+    q0 = (S0[0][:, None] * x * x + S0[1][:, None] * y * y + S0[2][:, None] * z * z
+          + 2 * (S0[3][:, None] * x * y + S0[4][:, None] * x * z + S0[5][:, None] * y * z))
+    # a lobe's projected area along v: w sqrt(v^T (S / w) v) = sqrt(w v^T S v)
+    w0 = leaf.w[:n0].double()[:, None]
+    ref = torch.zeros(n1, 64, dtype=torch.float64, device=lk.device).index_add_(
+        0, parent, torch.sqrt((w0 * q0).clamp_min(0)))
+    reduced = inputs > 4
+    out = {"workload": "brushed_metal 13-level pyramid, K=4, 5000 samples per lobe", "build_ms": ms,
+           "moment_metric_lod_ms": d_lod_ms,
+           "kernels_ms": {k: round(v[0] / steps, 3) for k, v in kt.items()},
+           "level1_voxels": n1, "level1_reduced": int(reduced.sum())}
+    errs = {}
+    for name, lb in (("sggx_h", hl[0]), ("moment_ward_lloyd", lod.lobes[0])):
+        Sk = lb.S[:, :, :n1].double()                           # [6, K, n]
+        x2 = (Sk[0][..., None] * x * x + Sk[1][..., None] * y * y + Sk[2][..., None] * z * z
+              + 2 * (Sk[3][..., None] * x * y + Sk[4][..., None] * x * z + Sk[5][..., None] * y * z))
+        wk = lb.w[:, :n1].double()[..., None]                   # [K, n, 1]
+        prof = torch.sqrt((wk * x2).clamp_min(0)).sum(0)        # [n, 64]
+        e = (prof - ref).abs().max(1).values / ref.max(1).values.clamp_min(1e-30)
+        errs[name] = e[reduced]
+        out[name + "_level1_profile_error"] = {"mean": float(errs[name].mean()), "p99": float(errs[name].quantile(0.99)),
+                                               "max": float(errs[name].max())}
+    wa = torch.sort(hl[0].w[:, :n1].double(), dim=0).values
+    wb = torch.sort(lod.lobes[0].w[:, :n1].double(), dim=0).values
+    same = ((wa - wb).abs() <= 1e-5 * wa.sum(0).clamp_min(1e-30)).all(0)
+    out["level1_same_partition_share"] = float(same[reduced].double().mean())
+    del sh, lod, plan, leaf, tris
+    torch.cuda.empty_cache()
+    return out
+
+
 def _leaf_error(exact, ex_n, samp, s_n):
     """Relative L1 distance of the sampled leaf from the exact one (weights and moments, summed
     over the union of their voxels) and the share of the exact voxels of positive area that the
@@ -547,6 +628,7 @@ def main():
     ap.add_argument("--no-compact", action="store_true")
     ap.add_argument("--no-sampling", action="store_true")
     ap.add_argument("--no-occupancy", action="store_true")
+    ap.add_argument("--no-sggxh", action="store_true")
     ap.add_argument("--probe", action="store_true", help="end with a plain copy of known size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -588,6 +670,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_occupancy:
         out["occupancy"] = occupancy_timing(vx, args)
+        torch.cuda.empty_cache()
+    if not args.no_sggxh:
+        out["sggx_h"] = sggxh_timing(vx, args, head["lod_build_ms"])
         torch.cuda.empty_cache()
 
     # ---- plain weave, fit, compact -------------------------------------------------------------
