@@ -78,28 +78,25 @@ __device__ __forceinline__ int bin_of(double n) {
   return !(f >= 0.0) ? 0 : (f > 4.0 ? 4 : int(f));
 }
 
-// sample k of the lobe: its three bins, or false when it ran out of attempts
-__device__ __forceinline__ bool lobe_sample(const Chol& c, uint64_t key, uint64_t k, int b[3]) {
-  for (int at = 0; at < kMaxAttempts; ++at) {
-    const uint64_t d = 4 * uint64_t(at);
-    const double x = 2.0 * unit(draw(key, k, d)) - 1.0;
-    const double y = 2.0 * unit(draw(key, k, d + 1)) - 1.0;
-    const double z = 2.0 * unit(draw(key, k, d + 2)) - 1.0;
-    const double r2 = (x * x + y * y) + z * z;
-    if (r2 > 1.0 || r2 == 0.0) continue;
-    const double p0 = c.l00 * x;
-    const double p1 = c.l10 * x + c.l11 * y;
-    const double p2 = (c.l20 * x + c.l21 * y) + c.l22 * z;
-    const double q = (p0 * p0 + p1 * p1) + p2 * p2;
-    const double U = unit(draw(key, k, d + 3));
-    if (((U * U) * c.tr) * r2 > q) continue;
-    const double len = sqrt(q);
-    b[0] = bin_of(p0 / len);
-    b[1] = bin_of(p1 / len);
-    b[2] = bin_of(p2 / len);
-    return true;
-  }
-  return false;
+// attempt `at` of sample k of the lobe: true (and the three bins) when it is accepted
+__device__ __forceinline__ bool lobe_attempt(const Chol& c, uint64_t key, uint64_t k, int at, int b[3]) {
+  const uint64_t d = 4 * uint64_t(at);
+  const double x = 2.0 * unit(draw(key, k, d)) - 1.0;
+  const double y = 2.0 * unit(draw(key, k, d + 1)) - 1.0;
+  const double z = 2.0 * unit(draw(key, k, d + 2)) - 1.0;
+  const double r2 = (x * x + y * y) + z * z;
+  if (r2 > 1.0 || r2 == 0.0) return false;
+  const double p0 = c.l00 * x;
+  const double p1 = c.l10 * x + c.l11 * y;
+  const double p2 = (c.l20 * x + c.l21 * y) + c.l22 * z;
+  const double q = (p0 * p0 + p1 * p1) + p2 * p2;
+  const double U = unit(draw(key, k, d + 3));
+  if (((U * U) * c.tr) * r2 > q) return false;
+  const double len = sqrt(q);
+  b[0] = bin_of(p0 / len);
+  b[1] = bin_of(p1 / len);
+  b[2] = bin_of(p2 / len);
+  return true;
 }
 
 // (num, den, i, j): is a strictly closer than b, or as close and earlier in (i, j) order?
@@ -180,15 +177,33 @@ __global__ void __launch_bounds__(64) k_sggxh_level(const Key* __restrict__ ckey
       // marginal counts of N samples per lobe (integer atomics: exact and order-free)
       for (int i = lane; i < kMaxLobes * 15; i += 64) smg[i / 15][i % 15] = 0;
       __syncthreads();
-      for (int j = 0; j < n; ++j) {
-        const Chol c = lobe_chol(sw[j], sS[0][j], sS[1][j], sS[2][j], sS[3][j], sS[4][j], sS[5][j]);
-        const uint64_t key = lobe_key(level, uint64_t(pk), j);
-        for (int k = lane; k < N; k += 64) {
+      // The n N samples are dealt to the lanes in turn, and a lane moves to its next sample as
+      // soon as one is accepted, so the lanes' attempts do not wait for one another sample by
+      // sample (acceptance runs from about a quarter to a half per attempt).
+      {
+        const int total = n * N;
+        int t = lane, at = 0, cj = -1;
+        Chol c{};
+        uint64_t key = 0;
+        while (t < total) {
+          const int j = t / N, k = t - j * N;
+          if (j != cj) {
+            c = lobe_chol(sw[j], sS[0][j], sS[1][j], sS[2][j], sS[3][j], sS[4][j], sS[5][j]);
+            key = lobe_key(level, uint64_t(pk), j);
+            cj = j;
+          }
           int b[3];
-          if (lobe_sample(c, key, uint64_t(k), b)) {
+          const bool ok = lobe_attempt(c, key, uint64_t(k), at, b);
+          if (ok) {
             atomicAdd(&smg[j][b[0]], 1);
             atomicAdd(&smg[j][5 + b[1]], 1);
             atomicAdd(&smg[j][10 + b[2]], 1);
+          }
+          if (ok || at + 1 >= kMaxAttempts) {
+            t += 64;
+            at = 0;
+          } else {
+            ++at;
           }
         }
       }
