@@ -96,7 +96,10 @@ struct ClusterLds {
 // [pstart[p], pstart[p+1]) in the level below carry lobes cw[k * cap_c + c] and
 // cS[(j * Kc + k) * cap_c + c] (cnl == nullptr: one lobe per child, present when its weight is
 // positive).
-template <int G, bool NARROW_ONLY = false>
+// BAND: parents that gather more than G lobes are left to a wider pass, and (LO > 0) those that
+// gather at most LO to an earlier, narrower one; with LO = 0 this pass also writes the parents
+// that gather no lobe.
+template <int G, bool BAND = false, int LO = 0, int SLOTS = 64>
 __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const int64_t* __restrict__ pstart,
                                               const float* __restrict__ cw, const float* __restrict__ cS,
                                               const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
@@ -109,39 +112,51 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
   // ---- gather the children's lobes in canonical order (child, then lobe), compacted to lanes
   // 0..n-1.  Lane g takes slots g, g + G, ... of the 8 Kc (child, lobe) slots; n <= G is the
   // caller's guarantee (G >= 8 Kc, or a parent known to gather at most G lobes).
+  // All of this lane's slots are loaded first (the weight and moment together with the lobe
+  // count, all in bounds whatever the count), then compacted in slot order: one round of
+  // dependent loads after the parent's child range instead of one chain per slot.
   const int slots = 8 * Kc;
-  int n = 0;
-  for (int s0 = 0; s0 < slots; s0 += G) {
-    float w = 0.f, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    bool valid = false;
-    const int slot = s0 + g;
-    if (live && slot < slots) {
-      const int64_t cs = pstart[p], ce = pstart[p + 1];
-      const int ch = slot / Kc, k = slot % Kc;
-      if (cs + ch < ce) {
-        const int64_t c = cs + ch;
-        const int nl = cnl ? int(cnl[c]) : 1;
-        if (k < nl) {
-          w = cw[int64_t(k) * cap_c + c];
-          if (w > 0.f) {
-            valid = true;
+  constexpr int R = (SLOTS + G - 1) / G;           // slots per lane at most (8 Kc <= SLOTS)
+  int64_t cs = 0, ce = 0;
+  if (live) {
+    cs = pstart[p];
+    ce = pstart[p + 1];
+  }
+  float rw[R], rS[R][6];
+  bool rv[R];
 #pragma unroll
-            for (int j = 0; j < 6; ++j) S[j] = cS[(int64_t(j) * Kc + k) * cap_c + c];
-          }
-        }
+  for (int r = 0; r < R; ++r) {
+    const int slot = r * G + g;
+    rw[r] = 0.f;
+    rv[r] = false;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) rS[r][j] = 0.f;
+    if (live && slot < slots) {
+      const int ch = slot / Kc, k = slot % Kc;
+      const int64_t c = cs + ch;
+      if (c < ce) {
+        const int nl = cnl ? int(cnl[c]) : 1;
+        rw[r] = cw[int64_t(k) * cap_c + c];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) rS[r][j] = cS[(int64_t(j) * Kc + k) * cap_c + c];
+        rv[r] = k < nl && rw[r] > 0.f;
       }
     }
-    const uint64_t vm = group_bits<G>(__ballot(valid), gi);
-    const int m = n + __popcll(vm & ((uint64_t(1) << g) - 1));
-    if (valid && m < G) {
-      L.lw[gi][m] = w;
+  }
+  int n = 0;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) L.lS[gi][j][m] = S[j];
+  for (int r = 0; r < R; ++r) {
+    const uint64_t vm = group_bits<G>(__ballot(rv[r]), gi);
+    const int m = n + __popcll(vm & ((uint64_t(1) << g) - 1));
+    if (rv[r] && m < G) {
+      L.lw[gi][m] = rw[r];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) L.lS[gi][j][m] = rS[r][j];
     }
     n += __popcll(vm);
   }
-  if (NARROW_ONLY && n > G) {
-    live = false;                                  // more lobes than the group holds: the wide pass
+  if (BAND && (n > G || (LO > 0 && n <= LO))) {
+    live = false;                                  // another pass takes this parent
     n = 0;
   }
   n = n < G ? n : G;
@@ -468,8 +483,8 @@ __device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const
 }
 
 // One level with a fixed group width G (G lanes per parent, 64 / G parents per wave).  With
-// NARROW_ONLY, parents that gather more than G lobes are left to k_cluster_wide.
-template <int G, bool NARROW_ONLY>
+// BAND, only the parents that gather more than LO and at most G lobes are taken.
+template <int G, bool BAND, int LO = 0, int SLOTS = 64>
 __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
                                                     const float* __restrict__ cw, const float* __restrict__ cS,
                                                     const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
@@ -481,7 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
   const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per_wave;
   const int64_t stride = int64_t(gridDim.x) * kWaves * per_wave;
   for (int64_t base = w0; base < n_par; base += stride)
-    cluster_round<G, NARROW_ONLY>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
+    cluster_round<G, BAND, LO, SLOTS>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
 }
 
 // The parents of a level that gather more than 16 lobes (the narrow pass left them), one at a
@@ -509,7 +524,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster_wide(const int64_t* __restri
     }
     for (uint64_t m = __ballot(nq > 16); m; m &= m - 1) {
       const int64_t q = base + (__ffsll((unsigned long long)m) - 1);
-      cluster_round<GM>(q, q + 1, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
+      cluster_round<GM, false, 0, GM>(q, q + 1, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
     }
   }
 }
@@ -517,24 +532,36 @@ __global__ void __launch_bounds__(kBlock) k_cluster_wide(const int64_t* __restri
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
                    int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s) {
   const int need = 8 * Kc;
+  // no more blocks than the level's capacity of parents can use (the upper levels are small)
+  auto blocks = [&](int per_block) {
+    const int64_t b = (out.cap + per_block - 1) / per_block;
+    return int(b < grid ? (b < 1 ? 1 : b) : grid);
+  };
   // timing names by group width: the first level (one lobe per child) and the levels above
   VX_TIMED(need <= 8 ? "lod_cluster" : "lod_cluster_up", s);
   if (need <= 8)
-    hipLaunchKernelGGL((k_cluster<8, false>), dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c,
-                       K, iters, out);
+    hipLaunchKernelGGL((k_cluster<8, false, 0, 8>), dim3(blocks(kWaves * 8)), dim3(kBlock), 0, s, pstart, n_par, cw,
+                       cS, cnl, Kc, cap_c, K, iters, out);
   else if (need <= 16)
-    hipLaunchKernelGGL((k_cluster<16, false>), dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
-                       cap_c, K, iters, out);
+    hipLaunchKernelGGL((k_cluster<16, false, 0, 16>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
+                       cS, cnl, Kc, cap_c, K, iters, out);
   else {
-    // most parents gather at most 16 lobes: a narrow pass at four parents per wave, then the rest
-    hipLaunchKernelGGL((k_cluster<16, true>), dim3(grid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c,
-                       K, iters, out);
+    // most parents gather at most 16 lobes: a narrow pass at four parents per wave, then the
+    // few above one at a time
     if (need <= 32)
-      hipLaunchKernelGGL(k_cluster_wide<32>, dim3(grid / 4 > 64 ? grid / 4 : 64), dim3(kBlock), 0, s, pstart, n_par,
-                         cw, cS, cnl, Kc, cap_c, K, iters, out);
+      hipLaunchKernelGGL((k_cluster<16, true, 0, 32>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
+                         cS, cnl, Kc, cap_c, K, iters, out);
     else
-      hipLaunchKernelGGL(k_cluster_wide<64>, dim3(grid / 4 > 64 ? grid / 4 : 64), dim3(kBlock), 0, s, pstart, n_par,
-                         cw, cS, cnl, Kc, cap_c, K, iters, out);
+      hipLaunchKernelGGL((k_cluster<16, true, 0, 64>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
+                         cS, cnl, Kc, cap_c, K, iters, out);
+    const int wgrid = blocks(kWaves * 64) < (grid / 4 > 64 ? grid / 4 : 64) ? blocks(kWaves * 64)
+                                                                            : (grid / 4 > 64 ? grid / 4 : 64);
+    if (need <= 32)
+      hipLaunchKernelGGL(k_cluster_wide<32>, dim3(wgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+                         iters, out);
+    else
+      hipLaunchKernelGGL(k_cluster_wide<64>, dim3(wgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
+                         iters, out);
   }
 }
 
