@@ -92,7 +92,7 @@ struct ClusterLds {
   int asg[64 / G][G];
 };
 
-// One round of one wave: parents base + gi (gi < 64 / G) of a level whose children
+// One round of one wave: group gi (gi < 64 / G) takes parent p (when live) of a level whose children
 // [pstart[p], pstart[p+1]) in the level below carry lobes cw[k * cap_c + c] and
 // cS[(j * Kc + k) * cap_c + c] (cnl == nullptr: one lobe per child, present when its weight is
 // positive).
@@ -100,15 +100,13 @@ struct ClusterLds {
 // gather at most LO to an earlier, narrower one; with LO = 0 this pass also writes the parents
 // that gather no lobe.
 template <int G, bool BAND = false, int LO = 0, int SLOTS = 64>
-__device__ __forceinline__ void cluster_round(int64_t base, int64_t n_par, const int64_t* __restrict__ pstart,
+__device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_t* __restrict__ pstart,
                                               const float* __restrict__ cw, const float* __restrict__ cS,
                                               const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
                                               int iters, const vx_lobes& out, ClusterLds<G>& L) {
   const int lane = lane_id();
   const int g = lane % G, gi = lane / G;
   const int64_t cap = out.cap;
-  const int64_t p = base + gi;
-  bool live = p < n_par;
   // ---- gather the children's lobes in canonical order (child, then lobe), compacted to lanes
   // 0..n-1.  Lane g takes slots g, g + G, ... of the 8 Kc (child, lobe) slots; n <= G is the
   // caller's guarantee (G >= 8 Kc, or a parent known to gather at most G lobes).
@@ -496,22 +494,26 @@ __global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ 
   const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per_wave;
   const int64_t stride = int64_t(gridDim.x) * kWaves * per_wave;
   for (int64_t base = w0; base < n_par; base += stride)
-    cluster_round<G, BAND, LO, SLOTS>(base, n_par, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
+    cluster_round<G, BAND, LO, SLOTS>(base + threadIdx.x % 64 / G, base + threadIdx.x % 64 / G < n_par, pstart, cw,
+                                      cS, cnl, Kc, cap_c, K, iters, out, L);
 }
 
-// The parents of a level that gather more than 16 lobes (the narrow pass left them), one at a
-// time with GM lanes: a wave counts 64 parents' lobes (one per lane), then serves the wide ones
-// in order.  Few parents are wide, so this pass is mostly the count.  The group width changes no
+// The parents of a level that gather more than LO and at most GB positive lobes, GB lanes each: a
+// wave counts 64 parents' lobes (one per lane), then serves the ones that may fall in the band,
+// 64 / GB at a time.
+// When few parents are in the band this pass is mostly the count.  The group width changes no
 // result.
-template <int GM>
-__global__ void __launch_bounds__(kBlock) k_cluster_wide(const int64_t* __restrict__ pstart,
+template <int GB, int LO, int SLOTS>
+__global__ void __launch_bounds__(kBlock) k_cluster_pick(const int64_t* __restrict__ pstart,
                                                          const int64_t* n_par_ptr, const float* __restrict__ cw,
                                                          const float* __restrict__ cS,
                                                          const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c,
                                                          int K, int iters, vx_lobes out) {
-  __shared__ ClusterLds<GM> sm[kWaves];
-  ClusterLds<GM>& L = sm[threadIdx.x >> 6];
+  __shared__ ClusterLds<GB> sm[kWaves];
+  ClusterLds<GB>& L = sm[threadIdx.x >> 6];
   const int lane = lane_id();
+  constexpr int per = 64 / GB;
+  const int gi = lane / GB;
   const int64_t n_par = *n_par_ptr;
   const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * 64;
   const int64_t stride = int64_t(gridDim.x) * kWaves * 64;
@@ -522,9 +524,20 @@ __global__ void __launch_bounds__(kBlock) k_cluster_wide(const int64_t* __restri
       const int64_t cs = pstart[p], ce = pstart[p + 1];
       for (int64_t c = cs; c < ce; ++c) nq += cnl ? (int(cnl[c]) < Kc ? int(cnl[c]) : Kc) : 1;
     }
-    for (uint64_t m = __ballot(nq > 16); m; m &= m - 1) {
-      const int64_t q = base + (__ffsll((unsigned long long)m) - 1);
-      cluster_round<GM, false, 0, GM>(q, q + 1, pstart, cw, cS, cnl, Kc, cap_c, K, iters, out, L);
+    uint64_t m = __ballot(nq > LO);              // every parent that may hold more than LO positive lobes
+    while (m) {
+      int64_t mine = -1;
+#pragma unroll
+      for (int k = 0; k < per; ++k) {
+        if (m) {
+          if (k == gi) mine = base + (__ffsll((unsigned long long)m) - 1);
+          m &= m - 1;
+        }
+      }
+      // the count includes lobes of zero weight: the round takes a parent only when its positive
+      // lobes fall in the band (a narrower pass took fewer, a wider one takes more)
+      cluster_round<GB, true, LO, SLOTS>(mine < 0 ? 0 : mine, mine >= 0, pstart, cw, cS, cnl, Kc, cap_c, K, iters,
+                                         out, L);
     }
   }
 }
@@ -546,22 +559,25 @@ void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw,
     hipLaunchKernelGGL((k_cluster<16, false, 0, 16>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
                        cS, cnl, Kc, cap_c, K, iters, out);
   else {
-    // most parents gather at most 16 lobes: a narrow pass at four parents per wave, then the
-    // few above one at a time
+    // parents by the lobes they gather: at most 16 at four parents per wave (all parents
+    // gathered), 17 to 32 at two and the few above at one (picked after a count)
+    const int pgrid = blocks(kWaves * 64) < (grid / 4 > 64 ? grid / 4 : 64) ? blocks(kWaves * 64)
+                                                                            : (grid / 4 > 64 ? grid / 4 : 64);
     if (need <= 32)
       hipLaunchKernelGGL((k_cluster<16, true, 0, 32>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
                          cS, cnl, Kc, cap_c, K, iters, out);
     else
       hipLaunchKernelGGL((k_cluster<16, true, 0, 64>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
                          cS, cnl, Kc, cap_c, K, iters, out);
-    const int wgrid = blocks(kWaves * 64) < (grid / 4 > 64 ? grid / 4 : 64) ? blocks(kWaves * 64)
-                                                                            : (grid / 4 > 64 ? grid / 4 : 64);
-    if (need <= 32)
-      hipLaunchKernelGGL(k_cluster_wide<32>, dim3(wgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
-                         iters, out);
-    else
-      hipLaunchKernelGGL(k_cluster_wide<64>, dim3(wgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc, cap_c, K,
-                         iters, out);
+    if (need <= 32) {
+      hipLaunchKernelGGL((k_cluster_pick<32, 16, 32>), dim3(pgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
+                         cap_c, K, iters, out);
+    } else {
+      hipLaunchKernelGGL((k_cluster_pick<32, 16, 64>), dim3(pgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
+                         cap_c, K, iters, out);
+      hipLaunchKernelGGL((k_cluster_pick<64, 32, 64>), dim3(pgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
+                         cap_c, K, iters, out);
+    }
   }
 }
 
