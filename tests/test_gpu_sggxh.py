@@ -117,3 +117,34 @@ def test_errors(vx):
     for K, N in ((0, 10), (9, 10), (4, 0), (4, 70000)):
         with pytest.raises(vx.VxError):
             vx.SggxhPlan(lodp, K=K, samples=N).run()
+
+
+def test_brushed_metal_full_sampled_parents(vx):
+    """The bench's configuration (the full 33.5 M-triangle surface, 13 levels, K = 4, 5000 samples
+    per lobe): at every level, 200 sampled parents reduced again by the oracle from the GPU's own
+    lobes of the level below."""
+    import torch
+    wl = synth.brushed_metal()
+    say("case: SGGX-H, brushed metal full size, K = 4, 5000 samples, 200 sampled parents per level")
+    leaf = vx.voxelize_triangles(torch.as_tensor(wl.tris).cuda(), wl.grid)
+    lodp = vx.LodPlan(wl.grid, leaf, leaf.plan.stats[2:3], wl.levels).run()
+    lodp.check()
+    lobes = vx.SggxhPlan(lodp, K=4, samples=5000).run().check()
+    pyr = [lodp.leaf] + lodp.out
+    rng = np.random.default_rng(21)
+    child = leaf_as_oracle_lobes(pyr[0].numpy())
+    ck = pyr[0].numpy()["keys"].astype(np.uint64)
+    for L in range(1, len(pyr)):
+        pk = pyr[L].numpy()["keys"].astype(np.uint64)
+        g = lobes[L - 1].numpy()
+        sel = np.sort(rng.choice(len(pk), size=min(200, len(pk)), replace=False))
+        lo = np.searchsorted(ck >> np.uint64(3), pk[sel])
+        hi = np.searchsorted(ck >> np.uint64(3), pk[sel], side="right")
+        rows = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+        cs = np.concatenate([[0], np.cumsum(hi - lo)]).astype(np.int64)
+        sub = oracle.Lobes(child.nl[rows], child.w[rows], child.S[rows], np.zeros(len(rows)), np.zeros(len(rows)))
+        ref = oracle.sggxh_level(sub, cs, pk[sel], L, 4, 5000)
+        gs = {k: v[sel] for k, v in g.items()}
+        say("level", L, _compare(gs, ref, f"full L{L}"))
+        child = gpu_lobes_as_oracle(g)
+        ck = pk
