@@ -55,61 +55,113 @@ struct NoTotal {
   __device__ void operator()(int64_t, int64_t) const {}
 };
 
+// One pass of the stable scatter.  A block takes its chunk in tiles of kTileN elements; a tile
+// is ranked by digit (wave ballots within each row of 256, counts per row and wave, one scan over
+// the digits), placed digit by digit in LDS, and written out in that order, so each digit's run
+// of the tile lands contiguously (coalesced) at the digit's next position.  Order within a digit
+// is row, wave, lane = input order: the sort is stable.  w may be null (not carried).
+constexpr int kTileE = 4;                      // rows of 256 elements per tile
+constexpr int kTileN = kBlock * kTileE;
+static_assert(kBuckets == 2 * kBlock, "the digit scan takes two digits per thread");
+
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict__ kin, const float* __restrict__ win,
                                                           const uint32_t* __restrict__ pin, Key* __restrict__ kout,
                                                           float* __restrict__ wout, uint32_t* __restrict__ pout,
                                                           const int64_t* n_ptr, int shift,
                                                           const int32_t* __restrict__ hist_off) {
-  __shared__ int32_t run[kBuckets];
-  __shared__ int32_t cnt[kWaves][kBuckets];
-  __shared__ int32_t pre[kWaves][kBuckets];
+  __shared__ int32_t run[kBuckets];                    // next output position of each digit
+  __shared__ int32_t cnt[kTileE][kWaves][kBuckets];    // per row and wave; then their prefixes
+  __shared__ int32_t toff[kBuckets];                   // each digit's first slot in the sorted tile
+  __shared__ int32_t ttot[kBuckets];
+  __shared__ Key sk[kTileN];
+  __shared__ float sw[kTileN];
+  __shared__ uint32_t sp[kTileN];
+  __shared__ int32_t stmp[kWaves + 1];
   const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+  const bool has_w = win != nullptr;
   for (int d = t; d < kBuckets; d += kBlock) run[d] = hist_off[int64_t(d) * kSortGrid + blockIdx.x];
   const int64_t n = *n_ptr;
   const int64_t chunk = sort_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   const uint64_t lt = (uint64_t(1) << lane) - 1;
-  for (int64_t t0 = b0; t0 < b1; t0 += kBlock) {
-    const int64_t i = t0 + t;
-    const bool valid = i < b1;
-    Key k = 0;
-    float wv = 0.f;
-    uint32_t pv = 0;
-    if (valid) { k = kin[i]; wv = win[i]; pv = pin[i]; }
-    const int d = int((k >> shift) & (kBuckets - 1));
-    // lanes of this wave holding the same digit
-    uint64_t peers = __ballot(valid);
+  for (int64_t t0 = b0; t0 < b1; t0 += kTileN) {
+    const int ntile = int(b1 - t0 < kTileN ? b1 - t0 : kTileN);
+    for (int q = t; q < kTileE * kWaves * kBuckets; q += kBlock) (&cnt[0][0][0])[q] = 0;
+    Key k[kTileE];
+    float wv[kTileE];
+    uint32_t pv[kTileE];
+    int dg[kTileE], rk[kTileE];
 #pragma unroll
-    for (int b = 0; b < kDigitBits; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1);
-      peers &= ((d >> b) & 1) ? m : ~m;
-    }
-    const int rank = __popcll(peers & lt);
-    for (int dd = t; dd < kBuckets; dd += kBlock) {
-#pragma unroll
-      for (int ww = 0; ww < kWaves; ++ww) cnt[ww][dd] = 0;
+    for (int j = 0; j < kTileE; ++j) {
+      const int64_t i = t0 + j * kBlock + t;
+      const bool valid = i < b1;
+      k[j] = valid ? kin[i] : Key(0);
+      wv[j] = valid && has_w ? win[i] : 0.f;
+      pv[j] = valid ? pin[i] : 0u;
+      dg[j] = int((k[j] >> shift) & (kBuckets - 1));
     }
     __syncthreads();
-    if (valid && rank == 0) cnt[w][d] = __popcll(peers);
-    __syncthreads();
-    for (int dd = t; dd < kBuckets; dd += kBlock) {
-      int32_t acc = run[dd];
 #pragma unroll
-      for (int ww = 0; ww < kWaves; ++ww) {
-        pre[ww][dd] = acc;
-        acc += cnt[ww][dd];
+    for (int j = 0; j < kTileE; ++j) {
+      const bool valid = t0 + j * kBlock + t < b1;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kDigitBits; ++b) {
+        const uint64_t m = __ballot((dg[j] >> b) & 1);
+        peers &= ((dg[j] >> b) & 1) ? m : ~m;
       }
-      run[dd] = acc;
+      rk[j] = valid ? __popcll(peers & lt) : -1;
+      if (valid && rk[j] == 0) cnt[j][w][dg[j]] = __popcll(peers);
     }
     __syncthreads();
-    if (valid) {
-      const int32_t pos = pre[w][d] + rank;
-      kout[pos] = k;
-      wout[pos] = wv;
-      pout[pos] = pv;
+    // per digit: prefixes over (row, wave) in input order, and the tile's count
+    int32_t dsum = 0;
+    for (int d = t; d < kBuckets; d += kBlock) {
+      int32_t acc = 0;
+#pragma unroll
+      for (int j = 0; j < kTileE; ++j)
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+          const int32_t c = cnt[j][ww][d];
+          cnt[j][ww][d] = acc;
+          acc += c;
+        }
+      ttot[d] = acc;
     }
+    __syncthreads();
+    // tile offsets of the digits: thread t scans digits 2t and 2t + 1
+    {
+      const int32_t a = ttot[2 * t], b = ttot[2 * t + 1];
+      int32_t total;
+      const int32_t ex = block_exclusive_scan<int32_t>(a + b, stmp, total);
+      toff[2 * t] = ex;
+      toff[2 * t + 1] = ex + a;
+      (void)dsum;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kTileE; ++j) {
+      if (rk[j] >= 0) {
+        const int slot = toff[dg[j]] + cnt[j][w][dg[j]] + rk[j];
+        sk[slot] = k[j];
+        sw[slot] = wv[j];
+        sp[slot] = pv[j];
+      }
+    }
+    __syncthreads();
+    for (int q = t; q < ntile; q += kBlock) {
+      const Key kk = sk[q];
+      const int d = int((kk >> shift) & (kBuckets - 1));
+      const int32_t pos = run[d] + (q - toff[d]);
+      kout[pos] = kk;
+      if (has_w) wout[pos] = sw[q];
+      pout[pos] = sp[q];
+    }
+    __syncthreads();
+    for (int d = t; d < kBuckets; d += kBlock) run[d] += ttot[d];
+    __syncthreads();
   }
 }
 

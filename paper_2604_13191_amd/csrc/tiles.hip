@@ -1051,7 +1051,9 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     while ((1 << pb) < batch->n_patches) ++pb;
     key_bits = kPatchShift - 3 * tb + pb;
   }
-  const int res = radix_sort_pairs(key64, key_bits, w.ra, w.rb, w.ctl + CTL_N_REC, max_rec, w.hist, w.partial, s);
+  // the records carry no weight: the sort moves keys and primitive ids only
+  const PairBufs ra{w.ra.keys, nullptr, w.ra.prim}, rb{w.rb.keys, nullptr, w.rb.prim};
+  const int res = radix_sort_pairs(key64, key_bits, ra, rb, w.ctl + CTL_N_REC, max_rec, w.hist, w.partial, s);
   const PairBufs R = res ? w.rb : w.ra;
   {
     VX_TIMED("tile_heads", s);
