@@ -60,9 +60,10 @@ struct NoTotal {
 // the digits), placed digit by digit in LDS, and written out in that order, so each digit's run
 // of the tile lands contiguously (coalesced) at the digit's next position.  Order within a digit
 // is row, wave, lane = input order: the sort is stable.  w may be null (not carried).
-constexpr int kTileE = 4;                      // rows of 256 elements per tile
+constexpr int kTileE = 8;                      // rows of 256 elements per tile
 constexpr int kTileN = kBlock * kTileE;
 static_assert(kBuckets == 2 * kBlock, "the digit scan takes two digits per thread");
+static_assert(kTileN <= 32767, "16-bit tile positions");
 
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict__ kin, const float* __restrict__ win,
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
                                                           const int64_t* n_ptr, int shift,
                                                           const int32_t* __restrict__ hist_off) {
   __shared__ int32_t run[kBuckets];                    // next output position of each digit
-  __shared__ int32_t cnt[kTileE][kWaves][kBuckets];    // per row and wave; then their prefixes
+  __shared__ int16_t cnt[kTileE][kWaves][kBuckets];    // per row and wave; then their prefixes (< kTileN)
   __shared__ int32_t toff[kBuckets];                   // each digit's first slot in the sorted tile
   __shared__ int32_t ttot[kBuckets];
   __shared__ Key sk[kTileN];
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
         peers &= ((dg[j] >> b) & 1) ? m : ~m;
       }
       rk[j] = valid ? __popcll(peers & lt) : -1;
-      if (valid && rk[j] == 0) cnt[j][w][dg[j]] = __popcll(peers);
+      if (valid && rk[j] == 0) cnt[j][w][dg[j]] = int16_t(__popcll(peers));
     }
     __syncthreads();
     // per digit: prefixes over (row, wave) in input order, and the tile's count
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const Key* __restrict_
 #pragma unroll
         for (int ww = 0; ww < kWaves; ++ww) {
           const int32_t c = cnt[j][ww][d];
-          cnt[j][ww][d] = acc;
+          cnt[j][ww][d] = int16_t(acc);
           acc += c;
         }
       ttot[d] = acc;
