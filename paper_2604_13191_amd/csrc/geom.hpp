@@ -556,9 +556,10 @@ VX_HD inline Lat make_lat(const vx_grid* g, int kind, float radius) {
 //
 // Line intersections come from Cramer's rule with exact numerators and denominators (lattice
 // integers below 2^25: products below 2^52).  Each pair of lines is visited once and bounds both
-// of its lines; the best bounds are chosen on quotients from a refined reciprocal, and the
-// chosen ones are then divided exactly (one rounding, the same for every pair of lines through
-// one point), so a piece that degenerates to a point or a segment closes exactly and has area 0.
+// of its lines; the best bounds are chosen by comparing cross products of numerators and
+// denominators (no division), and the chosen ones are then divided exactly (one rounding, the
+// same for every pair of lines through one point), so a piece that degenerates to a point or a
+// segment closes exactly and has area 0.
 // A line is parametrised by the coordinate (l1 or l2) that changes more along it.  Parallel
 // lines are decided exactly: an outside one removes the line, a coincident one with the same
 // inside keeps the edge on one line only, one with the opposite inside flattens the piece (area
@@ -577,31 +578,32 @@ struct AreaLine {
 struct AreaEdge {
   bool use_x, dead;
   double sig;
-  double qe, ne, de;   // entry: approximate sig * coordinate, exact numerator and denominator
-  double qx, nx, dx;   // exit
+  double ne, de;       // entry: exact numerator and denominator of the coordinate (de = 0: none yet)
+  double nx, dx;       // exit
 };
 
 VX_HD inline void area_edge_init(AreaEdge& E, const AreaLine& K) {
   E.use_x = fabs(K.g) >= fabs(K.b);
   E.sig = E.use_x ? (K.g > 0.0 ? 1.0 : -1.0) : (K.b > 0.0 ? -1.0 : 1.0);
   E.dead = false;
-  E.qe = -INFINITY;
   E.ne = 0.0;
   E.de = 0.0;
-  E.qx = INFINITY;
   E.nx = 0.0;
   E.dx = 0.0;
 }
 
 // K bounded where it meets another line at (N1 / D, N2 / D); the other line turns inside along
-// K where D > 0 (an entry) and outside where D < 0 (an exit)
+// K where D > 0 (an entry) and outside where D < 0 (an exit).  The latest entry and the earliest
+// exit along the walk are kept: sig n / D against sig ne / de with both sides multiplied by the
+// positive D de (D dx for exits); the first of equal bounds stays.
 VX_HD inline void area_bound(AreaEdge& E, double D, double N1, double N2) {
   const double n = E.use_x ? N1 : N2;
-  const double q = E.sig * n * rcp_fast(D);
   if (D > 0.0) {
-    if (q > E.qe) { E.qe = q; E.ne = n; E.de = D; }
+    const double l = n * E.de, r = E.ne * D;
+    if (E.de == 0.0 || (E.sig > 0.0 ? l > r : l < r)) { E.ne = n; E.de = D; }
   } else {
-    if (q < E.qx) { E.qx = q; E.nx = n; E.dx = D; }
+    const double l = n * E.dx, r = E.nx * D;
+    if (E.dx == 0.0 || (E.sig > 0.0 ? l < r : l > r)) { E.nx = n; E.dx = D; }
   }
 }
 

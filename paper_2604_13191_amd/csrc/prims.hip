@@ -24,14 +24,27 @@ __device__ __forceinline__ void store_record(int32_t* __restrict__ dst, const in
   for (int k = 0; k < kRec / 4; ++k) d[k] = make_int4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
 }
 
+// rcnt (optional): the number of aligned tiles of 2^tb voxels per axis that the candidate box
+// overlaps (0 without candidates), for the tiled path's primitive-tile records
 __global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ tris, int64_t n, Lat L,
                                                      int32_t* __restrict__ rec, float4* __restrict__ dirs,
-                                                     int64_t* __restrict__ cand_cnt, int64_t* stats) {
+                                                     int64_t* __restrict__ cand_cnt, int64_t* __restrict__ rcnt,
+                                                     int tb, int64_t* stats) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     bool ok;
     int32_t r[kRec];                                 // built in registers, stored as 4 x 16 bytes
-    cand_cnt[i] = prep_triangle(tris + i * 9, L, r, dirs + i, ok);
+    const int64_t cc = prep_triangle(tris + i * 9, L, r, dirs + i, ok);
+    cand_cnt[i] = cc;
     store_record(rec + i * kRec, r);
+    if (rcnt) {
+      int64_t c = 0;
+      if (cc > 0) {
+        c = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c *= int64_t(((r[9 + a] + r[12 + a] - 1) >> tb) - (r[9 + a] >> tb) + 1);
+      }
+      rcnt[i] = c;
+    }
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
   }
 }
@@ -312,7 +325,7 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
   if (kind == 0) {
     VX_TIMED("prep_tri", s);
     hipLaunchKernelGGL(k_prep_tri, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, L, w.rec, w.dirs, w.cand_cnt,
-                       stats);
+                       w.rcnt, w.tb, stats);
   } else {
     {
       VX_TIMED("check_offsets", s);

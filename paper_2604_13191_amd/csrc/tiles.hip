@@ -79,17 +79,16 @@ struct RecTotal {
 };
 
 // record (tile key, primitive) for every tile a primitive's candidate box overlaps; the tile key
-// is the Morton code of the tile coordinates (batched: with the patch id above it)
+// is the Morton code of the tile coordinates (batched: with the patch id above it).  roff: the
+// scanned record counts (n_prims + 1 entries); a primitive without candidates has none.
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_rec_emit(const int32_t* __restrict__ rec,
-                                                     const int64_t* __restrict__ cand_cnt,
                                                      const int64_t* __restrict__ roff, int64_t n_prims,
                                                      const int64_t* __restrict__ ctl, int tb, int batch,
-                                                     Key* __restrict__ rkeys, float* __restrict__ rw,
-                                                     uint32_t* __restrict__ rprim) {
+                                                     Key* __restrict__ rkeys, uint32_t* __restrict__ rprim) {
   if (ctl[CTL_N_REC] == 0) return;
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n_prims; p += int64_t(gridDim.x) * kBlock) {
-    if (cand_cnt[p] <= 0) continue;
+    if (roff[p + 1] == roff[p]) continue;
     const int32_t* r = rec + p * kRec;
     int32_t t0[3], t1[3];
 #pragma unroll
@@ -103,7 +102,6 @@ __global__ void __launch_bounds__(kBlock) k_rec_emit(const int32_t* __restrict__
       for (int32_t y = t0[1]; y <= t1[1]; ++y)
         for (int32_t x = t0[0]; x <= t1[0]; ++x) {
           rkeys[o] = hi | Key(morton3(uint32_t(x), uint32_t(y), uint32_t(z)));
-          rw[o] = 0.f;
           rprim[o] = uint32_t(p);
           ++o;
         }
@@ -345,7 +343,8 @@ struct UnitLds {
   int32_t* brec;      // [kBlock][9] the slot's primitive vertices (record words 0..8; after
                       // the batches: the per-key counters, then starts)
   int32_t* bpatch;    // [kBlock] the slot's patch (batched)
-  double* binv;       // [kBlock] fibers: the slot's 1 / |B - A|^2 (lattice units)
+  double* binv;       // [kBlock] fibers: the slot's 1 / |B - A|^2 (lattice units); triangles:
+                      // twice the slot's area (voxel^2)
   int32_t* tmp32;     // [kWaves + 1]
   int32_t* misc;      // [8]
 };
@@ -410,7 +409,8 @@ __device__ __forceinline__ UnitLds carve_unit_lds(char* base) {
 // batch's candidate total and the number of slots kept.  Contains __syncthreads().
 template <int KIND>
 __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* __restrict__ rec,
-                                              const uint32_t* __restrict__ rprim, int64_t j0, int64_t e,
+                                              const uint32_t* __restrict__ rprim, const float4* __restrict__ dirs,
+                                              int64_t j0, int64_t e,
                                               const int32_t o[3], const int32_t sz[3], int& nslot) {
   const int64_t j = j0 + threadIdx.x;
   int32_t c = 0, lo[3], n[3];
@@ -439,6 +439,7 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
     for (int k = 0; k < 9; ++k) S.brec[q * 9 + k] = r[k];
     S.bpatch[q] = r[15];
     if (KIND == 1) S.binv[q] = cap_inv_len2(r);
+    else S.binv[q] = double(dirs[p].w);
     atomicOr(reinterpret_cast<unsigned long long*>(&S.sbm[off >> 6]), 1ull << (off & 63));
   }
   nslot = tot >> 21;
@@ -540,7 +541,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(uni
     uint32_t acc_n = 0;
     for (int64_t j0 = s; j0 < e; j0 += kBlock) {
       int nb;
-      const int32_t cb = load_batch<KIND>(S, rec, rprim, j0, e, U.o, usz, nb);
+      const int32_t cb = load_batch<KIND>(S, rec, rprim, dirs, j0, e, U.o, usz, nb);
       (void)nb;
       if (stream) {
         for (int32_t c0 = 0; c0 < cb; c0 += kBlock) {
@@ -643,13 +644,27 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(uni
           if (hit) {
             const int32_t q = base + int32_t(__popcll(mh & lt));
             if (q < CAND) {
+              const int sl = find_slot(S, c);
               S.key[q] = uint16_t(S.ckey[c] & (kTouch - 1));
-              S.prim[q] = uint32_t(S.bprim[find_slot(S, c)]);
+              S.prim[q] = uint32_t(S.bprim[sl]);
+              if (KIND == 0) S.idx[q] = uint16_t(sl);
             } else {
               flag_set(stats, VX_FLAG_UNIT_CAPACITY);   // planning and test disagree: never expected
             }
           }
           base += int32_t(__popcll(mh));
+        }
+        // triangles: the batch's pairs are weighed now, from the records still in LDS
+        if (KIND == 0) {
+          __syncthreads();
+          const int32_t q1 = np + tot < CAND ? np + tot : CAND;
+          for (int32_t q = np + tid; q < q1; q += kBlock) {
+            const int sl = S.idx[q];
+            const uint64_t m = m0 + S.key[q];
+            const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
+            const LatQ Lp = lat_q(lats, S.bpatch[sl], L);
+            S.w[q] = unit_weight<KIND>(S.brec + sl * 9, v, Lp, float(S.binv[sl]));
+          }
         }
         np += tot;
         __syncthreads();
@@ -675,8 +690,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(uni
     }
     const int32_t npairs = np < CAND ? np : CAND;
     // Group the pairs by voxel with one counter per key of the unit's range (at most 4096 keys;
-    // 16-bit counts packed two to a word, in the record batch's space, dead now); the weights
-    // are computed in the same pass.  Each pair keeps its arrival slot among its voxel's pairs.
+    // 16-bit counts packed two to a word, in the record batch's space, dead now); the fibers'
+    // weights are computed in the same pass.  Each pair keeps its arrival slot among its voxel's
+    // pairs.
     uint32_t* kcw = reinterpret_cast<uint32_t*>(S.brec);                 // [2048] packed counts
     uint16_t* kst = reinterpret_cast<uint16_t*>(S.brec);                 // [4096] then starts
     uint16_t* slot = S.ckey;                                              // [npairs]
@@ -688,11 +704,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(uni
       const uint32_t p = S.prim[i], k = S.key[i];
       const uint32_t sh = 16u * (k & 1u);
       slot[i] = uint16_t(atomicAdd(&kcw[k >> 1], 1u << sh) >> sh);
-      const int32_t* r = rec + int64_t(p) * kRec;
-      const LatQ Lp = lat_q(lats, r[15], L);
-      const uint64_t m = m0 + k;
-      const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
-      S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w);
+      if (KIND == 1) {                            // (triangles were weighed batch by batch)
+        const int32_t* r = rec + int64_t(p) * kRec;
+        const LatQ Lp = lat_q(lats, r[15], L);
+        const uint64_t m = m0 + k;
+        const int64_t v[3] = {int64_t(compact3(m)), int64_t(compact3(m >> 1)), int64_t(compact3(m >> 2))};
+        S.w[i] = unit_weight<KIND>(r, v, Lp, dirs[p].w);
+      }
     }
     __syncthreads();
     // starts and the voxel list: thread t owns keys [16 t, 16 t + 16); one block scan of the
@@ -947,7 +965,7 @@ struct TileWs {
   float4* dirs;
   int64_t* cand_cnt;
   int64_t* roff;          // [n_prims + 1]
-  PairBufs ra, rb;        // records (tile key, unused weight, primitive), ping-pong
+  PairBufs ra, rb;        // records (tile key, primitive; no weight), ping-pong
   int32_t* hist;
   int64_t* partial;
   int64_t* tstart;        // [max_records + 1]
@@ -973,10 +991,10 @@ static size_t tile_ws_layout(int64_t n_prims, int64_t max_rec, int64_t max_units
   x.cand_cnt = cv.take<int64_t>(n_prims);
   x.roff = cv.take<int64_t>(n_prims + 1);
   x.ra.keys = cv.take<uint8_t>(max_rec * kb);
-  x.ra.w = cv.take<float>(max_rec);
+  x.ra.w = nullptr;
   x.ra.prim = cv.take<uint32_t>(max_rec);
   x.rb.keys = cv.take<uint8_t>(max_rec * kb);
-  x.rb.w = cv.take<float>(max_rec);
+  x.rb.w = nullptr;
   x.rb.prim = cv.take<uint32_t>(max_rec);
   x.hist = cv.take<int32_t>(int64_t(kRadixBuckets) * kGrid);
   x.partial = cv.take<int64_t>(3 * kGrid + 1);     // 3 values per block for the unit sums
@@ -1031,19 +1049,25 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   f.cand_cnt = w.cand_cnt;
   f.partial = w.partial;
   f.fstart = reinterpret_cast<uint8_t*>(w.roff);       // free until the record counts
+  if (kind == 0) {                                      // triangles: the prep counts the records
+    f.rcnt = w.roff;
+    f.tb = tb;
+  }
   prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch, w.stage_ctr, 1);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
   {
     VX_TIMED("tile_records", s);
-    hipLaunchKernelGGL(k_rec_count, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, n_prims, tb, w.roff);
+    // fibers: their fiber-start bytes share the counts' space, so the count is a pass of its own
+    if (kind != 0)
+      hipLaunchKernelGGL(k_rec_count, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, n_prims, tb, w.roff);
     device_scan(ArrIn64{w.roff}, ArrOut64{w.roff}, RecTotal{w.roff, w.ctl, stats, max_rec}, nullptr, n_prims,
                 w.partial, s);
     if (key64)
-      hipLaunchKernelGGL(k_rec_emit<uint64_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, w.roff, n_prims,
-                         w.ctl, tb, batch ? 1 : 0, (uint64_t*)w.ra.keys, w.ra.w, w.ra.prim);
+      hipLaunchKernelGGL(k_rec_emit<uint64_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.roff, n_prims, w.ctl, tb,
+                         batch ? 1 : 0, (uint64_t*)w.ra.keys, w.ra.prim);
     else
-      hipLaunchKernelGGL(k_rec_emit<uint32_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, w.roff, n_prims,
-                         w.ctl, tb, 0, (uint32_t*)w.ra.keys, w.ra.w, w.ra.prim);
+      hipLaunchKernelGGL(k_rec_emit<uint32_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.roff, n_prims, w.ctl, tb, 0,
+                         (uint32_t*)w.ra.keys, w.ra.prim);
   }
   int key_bits = 3 * (g->log2_res - tb);
   if (batch) {
@@ -1052,8 +1076,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     key_bits = kPatchShift - 3 * tb + pb;
   }
   // the records carry no weight: the sort moves keys and primitive ids only
-  const PairBufs ra{w.ra.keys, nullptr, w.ra.prim}, rb{w.rb.keys, nullptr, w.rb.prim};
-  const int res = radix_sort_pairs(key64, key_bits, ra, rb, w.ctl + CTL_N_REC, max_rec, w.hist, w.partial, s);
+  const int res = radix_sort_pairs(key64, key_bits, w.ra, w.rb, w.ctl + CTL_N_REC, max_rec, w.hist, w.partial, s);
   const PairBufs R = res ? w.rb : w.ra;
   {
     VX_TIMED("tile_heads", s);

@@ -356,6 +356,8 @@ struct FrontWs {
   int64_t* wave_off;
   PairBufs pa;
   int64_t* partial;
+  int64_t* rcnt = nullptr;   // triangles, tiled path: tiles of 2^tb voxels each candidate box overlaps
+  int tb = 0;
 };
 void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, FrontWs* f);
 struct Lat;
