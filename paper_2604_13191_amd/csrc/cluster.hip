@@ -178,6 +178,7 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
     }
   }
   uint64_t act = n == 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+  int cl = g;                                      // the cluster that input lobe g belongs to
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   if (n > K) {
@@ -217,6 +218,7 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
                              uint64_t(bjr);
         const uint64_t kmin = group_min_u64<G>(key);
         const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
+        if (bj < G && cl == bj) cl = bi;
         // merge cluster bj into bi
         if (g == bi && bj < G) {
           const float nw = L.cw[gi][bi] + L.cw[gi][bj];
@@ -293,6 +295,7 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
         const uint64_t kmin = group_min_u64<G>(key);
         const int bi = int((kmin >> 16) & 0xffff), bj = int(kmin & 0xffff);
         const bool merge = bj < G;
+        if (merge && cl == bj) cl = bi;
         // the merged cluster (bi absorbs bj), computed by every lane from the two lanes' registers
         const int si = base + (merge ? bi : 0), sj = base + (merge ? bj : 0);
         const float mw = __shfl(cw, si, 64) + __shfl(cw, sj, 64);
@@ -385,7 +388,9 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
-    // ---- weighted Lloyd passes over the original lobes
+    // ---- weighted Lloyd passes over the original lobes.  A pass that moves no lobe to another
+    // cluster leaves every cluster as it is, and so does every later one: the group stops there.
+    bool conv = false;                             // uniform over the group
     for (int it = 0; it < iters; ++it) {
       int assign = -1;
       if (mine) {
@@ -400,6 +405,10 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
           if (d < bestd) { bestd = d; assign = k; }
         }
       }
+      conv = group_bits<G>(__ballot(mine && assign != cl), gi) == 0;
+      if (__ballot(!conv) == 0) break;             // every group of the wave has converged
+      if (conv) continue;
+      cl = assign;
       if (mine) L.asg[gi][g] = assign;
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -483,7 +492,7 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
 // One level with a fixed group width G (G lanes per parent, 64 / G parents per wave).  With
 // BAND, only the parents that gather more than LO and at most G lobes are taken.
 template <int G, bool BAND, int LO = 0, int SLOTS = 64>
-__global__ void __launch_bounds__(kBlock) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SLOTS <= 32 ? 4 : 3))) k_cluster(const int64_t* __restrict__ pstart, const int64_t* n_par_ptr,
                                                     const float* __restrict__ cw, const float* __restrict__ cS,
                                                     const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c, int K,
                                                     int iters, vx_lobes out) {
