@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ t
     bool ok;
     int32_t r[kRec];                                 // built in registers, stored as 4 x 16 bytes
     const int64_t cc = prep_triangle(tris + i * 9, L, r, dirs + i, ok);
-    cand_cnt[i] = cc;
+    if (!rcnt) cand_cnt[i] = cc;                   // (the tiled path reads only the record counts)
     store_record(rec + i * kRec, r);
     if (rcnt) {
       int64_t c = 0;

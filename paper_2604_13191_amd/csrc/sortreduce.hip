@@ -19,8 +19,9 @@ __device__ __forceinline__ void flag_or_s(int64_t* p, int64_t bit) {
 constexpr int kDigitBits = 9;                 // 18-bit tile keys (1024^3 grids) sort in two passes
 constexpr int kBuckets = 1 << kDigitBits;
 static_assert(kBuckets == kRadixBuckets, "histogram workspace");
-// blocks of the sort kernels: fewer, longer blocks keep the digit histograms (and their scan) small
-constexpr int kSortGrid = 512;
+// blocks of the sort kernels: four per CU, all resident at once with the scatter's LDS (the digit
+// histograms, kBuckets per block, and their scan stay small)
+constexpr int kSortGrid = 1024;
 static_assert(kSortGrid <= kGrid, "histogram workspace");
 
 __device__ __forceinline__ int64_t sort_chunk(int64_t n) {
@@ -38,7 +39,32 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const Key* __restrict__ k
   const int64_t chunk = sort_chunk(n);
   const int64_t b0 = int64_t(blockIdx.x) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&h[int((keys[i] >> shift) & (kBuckets - 1))], 1);
+  // Four rows of 256 keys per step, loaded together.  Lanes of a wave holding the same digit find
+  // each other by ballots over its bits and the first of them adds the group's count: one LDS
+  // atomic per distinct digit and wave (runs of equal digits are common in the record lists).
+  constexpr int kRows = 4;
+  const int lane = lane_id();
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  for (int64_t t0 = b0; t0 < b1; t0 += int64_t(kRows) * kBlock) {
+    int dg[kRows];
+    bool ok[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const int64_t i = t0 + j * kBlock + threadIdx.x;
+      ok[j] = i < b1;
+      dg[j] = ok[j] ? int((keys[i] >> shift) & (kBuckets - 1)) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      uint64_t peers = __ballot(ok[j]);
+#pragma unroll
+      for (int b = 0; b < kDigitBits; ++b) {
+        const uint64_t m = __ballot((dg[j] >> b) & 1);
+        peers &= ((dg[j] >> b) & 1) ? m : ~m;
+      }
+      if (ok[j] && (peers & lt) == 0) atomicAdd(&h[dg[j]], int32_t(__popcll(peers)));
+    }
+  }
   __syncthreads();
   for (int d = threadIdx.x; d < kBuckets; d += kBlock) hist[int64_t(d) * kSortGrid + blockIdx.x] = h[d];
 }
@@ -60,7 +86,7 @@ struct NoTotal {
 // the digits), placed digit by digit in LDS, and written out in that order, so each digit's run
 // of the tile lands contiguously (coalesced) at the digit's next position.  Order within a digit
 // is row, wave, lane = input order: the sort is stable.  w may be null (not carried).
-constexpr int kTileE = 8;                      // rows of 256 elements per tile
+constexpr int kTileE = 4;                      // rows of 256 elements per tile (38 KB of LDS per block)
 constexpr int kTileN = kBlock * kTileE;
 static_assert(kBuckets == 2 * kBlock, "the digit scan takes two digits per thread");
 static_assert(kTileN <= 32767, "16-bit tile positions");
