@@ -362,7 +362,7 @@ vx_status lod_run(const vx_grid* grid, const vx_voxels* leaf, const int64_t* n_l
                       tu.grids[kTuneCluster], s);
       else
         cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
-                      kmeans_iters, lobes[L - 1], tu.grids[kTuneCluster], s);
+                      kmeans_iters, lobes[L - 1], tu.grids[kTuneCluster], s, L == 2);
     }
   }
   if (L < levels) {
@@ -563,7 +563,7 @@ vx_status vx_batch_build(const vx_patch* patches, const vx_patch* patches_dev, i
                       tu.grids[kTuneCluster], s);
       else
         cluster_level(pstart, n_levels + L, lobes[L - 2].w, lobes[L - 2].S, lobes[L - 2].nl, K, lobes[L - 2].cap, K,
-                      kmeans_iters, lobes[L - 1], tu.grids[kTuneCluster], s);
+                      kmeans_iters, lobes[L - 1], tu.grids[kTuneCluster], s, L == 2);
     }
   }
   if (L < levels) {

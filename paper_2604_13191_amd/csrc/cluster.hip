@@ -507,13 +507,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SLO
                                       cS, cnl, Kc, cap_c, K, iters, out, L);
 }
 
-// The parents of a level that gather more than LO and at most GB positive lobes, GB lanes each: a
-// wave counts 64 parents' lobes (one per lane), then serves the ones that may fall in the band,
-// 64 / GB at a time.
+// Parents picked by a count, GB lanes each: a wave counts up to 64 parents' (child, lobe) slots
+// in use (one parent per lane), then serves those whose count lies in (QLO, QHI], 64 / GB at a
+// time.  A wave counts as many parents as spread the level over the grid, at least one round's
+// worth: a small level runs one round per wave, all in parallel.
+// Without BAND the count bounds the lobes (QHI <= GB); with BAND the round takes a parent only
+// when its positive lobes are more than LO and at most GB (the other picks take the rest).
 // When few parents are in the band this pass is mostly the count.  The group width changes no
 // result.
-template <int GB, int LO, int SLOTS>
-__global__ void __launch_bounds__(kBlock) k_cluster_pick(const int64_t* __restrict__ pstart,
+constexpr int kAnyCount = 1 << 30;
+template <int GB, bool BAND, int LO, int QLO, int QHI, int SLOTS>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GB <= 16 && SLOTS <= 32 ? 4 : 1))) k_cluster_pick(const int64_t* __restrict__ pstart,
                                                          const int64_t* n_par_ptr, const float* __restrict__ cw,
                                                          const float* __restrict__ cS,
                                                          const uint8_t* __restrict__ cnl, int Kc, int64_t cap_c,
@@ -521,23 +525,28 @@ __global__ void __launch_bounds__(kBlock) k_cluster_pick(const int64_t* __restri
   __shared__ ClusterLds<GB> sm[kWaves];
   ClusterLds<GB>& L = sm[threadIdx.x >> 6];
   const int lane = lane_id();
-  constexpr int per = 64 / GB;
+  constexpr int per_r = 64 / GB;                  // parents served per round
   const int gi = lane / GB;
   const int64_t n_par = *n_par_ptr;
-  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * 64;
-  const int64_t stride = int64_t(gridDim.x) * kWaves * 64;
+  const int64_t waves = int64_t(gridDim.x) * kWaves;
+  int64_t per = (n_par + waves - 1) / waves;      // parents counted per wave (uniform)
+  per = per < per_r ? per_r : (per > 64 ? 64 : per);
+  const int64_t w0 = (int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6)) * per;
+  const int64_t stride = waves * per;
   for (int64_t base = w0; base < n_par; base += stride) {
     int nq = 0;
     const int64_t p = base + lane;
-    if (p < n_par) {
+    const bool counted = lane < per && p < n_par;
+    if (counted) {
       const int64_t cs = pstart[p], ce = pstart[p + 1];
       for (int64_t c = cs; c < ce; ++c) nq += cnl ? (int(cnl[c]) < Kc ? int(cnl[c]) : Kc) : 1;
     }
-    uint64_t m = __ballot(nq > LO);              // every parent that may hold more than LO positive lobes
+    static_assert(BAND || QHI <= GB, "without the band check the count must bound the lobes");
+    uint64_t m = __ballot(counted && nq > QLO && nq <= QHI);
     while (m) {
       int64_t mine = -1;
 #pragma unroll
-      for (int k = 0; k < per; ++k) {
+      for (int k = 0; k < per_r; ++k) {
         if (m) {
           if (k == gi) mine = base + (__ffsll((unsigned long long)m) - 1);
           m &= m - 1;
@@ -545,14 +554,15 @@ __global__ void __launch_bounds__(kBlock) k_cluster_pick(const int64_t* __restri
       }
       // the count includes lobes of zero weight: the round takes a parent only when its positive
       // lobes fall in the band (a narrower pass took fewer, a wider one takes more)
-      cluster_round<GB, true, LO, SLOTS>(mine < 0 ? 0 : mine, mine >= 0, pstart, cw, cS, cnl, Kc, cap_c, K, iters,
+      cluster_round<GB, BAND, LO, SLOTS>(mine < 0 ? 0 : mine, mine >= 0, pstart, cw, cS, cnl, Kc, cap_c, K, iters,
                                          out, L);
     }
   }
 }
 
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
-                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s) {
+                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s,
+                   bool narrow_first) {
   const int need = 8 * Kc;
   // no more blocks than the level's capacity of parents can use (the upper levels are small)
   auto blocks = [&](int per_block) {
@@ -568,25 +578,38 @@ void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw,
     hipLaunchKernelGGL((k_cluster<16, false, 0, 16>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
                        cS, cnl, Kc, cap_c, K, iters, out);
   else {
-    // parents by the lobes they gather: at most 16 at four parents per wave (all parents
-    // gathered), 17 to 32 at two and the few above at one (picked after a count)
+    // parents by the lobes they gather: at most 16 positive lobes at four parents per wave (all
+    // parents gathered), 17 to 32 at two and the few above at one (picked after a count).  With
+    // narrow_first (the level above the first, whose children hold few lobes: many parents gather
+    // at most 8) those with at most 8 slots filled go first at eight per wave, then the others
+    // with at most 16 positive lobes at four, each picked after a count.
     const int pgrid = blocks(kWaves * 64) < (grid / 4 > 64 ? grid / 4 : 64) ? blocks(kWaves * 64)
                                                                             : (grid / 4 > 64 ? grid / 4 : 64);
-    if (need <= 32)
-      hipLaunchKernelGGL((k_cluster<16, true, 0, 32>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
-                         cS, cnl, Kc, cap_c, K, iters, out);
-    else
-      hipLaunchKernelGGL((k_cluster<16, true, 0, 64>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par, cw,
-                         cS, cnl, Kc, cap_c, K, iters, out);
+    const int mgrid = blocks(kWaves * 64 / 4);
+#define VX_PICK(GRID, GB, BAND, LO, QLO, QHI, SL)                                                                  \
+  hipLaunchKernelGGL((k_cluster_pick<GB, BAND, LO, QLO, QHI, SL>), dim3(GRID), dim3(kBlock), 0, s, pstart, n_par, cw, \
+                     cS, cnl, Kc, cap_c, K, iters, out)
     if (need <= 32) {
-      hipLaunchKernelGGL((k_cluster_pick<32, 16, 32>), dim3(pgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
-                         cap_c, K, iters, out);
+      if (narrow_first) {
+        VX_PICK(mgrid, 8, false, 0, -1, 8, 32);
+        VX_PICK(mgrid, 16, true, 0, 8, kAnyCount, 32);
+      } else {
+        hipLaunchKernelGGL((k_cluster<16, true, 0, 32>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par,
+                           cw, cS, cnl, Kc, cap_c, K, iters, out);
+      }
+      VX_PICK(pgrid, 32, true, 16, 16, kAnyCount, 32);
     } else {
-      hipLaunchKernelGGL((k_cluster_pick<32, 16, 64>), dim3(pgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
-                         cap_c, K, iters, out);
-      hipLaunchKernelGGL((k_cluster_pick<64, 32, 64>), dim3(pgrid), dim3(kBlock), 0, s, pstart, n_par, cw, cS, cnl, Kc,
-                         cap_c, K, iters, out);
+      if (narrow_first) {
+        VX_PICK(mgrid, 8, false, 0, -1, 8, 64);
+        VX_PICK(mgrid, 16, true, 0, 8, kAnyCount, 64);
+      } else {
+        hipLaunchKernelGGL((k_cluster<16, true, 0, 64>), dim3(blocks(kWaves * 4)), dim3(kBlock), 0, s, pstart, n_par,
+                           cw, cS, cnl, Kc, cap_c, K, iters, out);
+      }
+      VX_PICK(pgrid, 32, true, 16, 16, kAnyCount, 64);
+      VX_PICK(pgrid, 64, true, 32, 32, kAnyCount, 64);
     }
+#undef VX_PICK
   }
 }
 

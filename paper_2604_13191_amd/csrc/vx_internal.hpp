@@ -339,9 +339,11 @@ void lod_tail(bool key64, bool batch, const vx_voxels* lv, int64_t* const* n, in
               hipStream_t s);
 
 // lobe clustering of one level (cluster.hip): parents [0, *n_par) with children
-// [pstart[p], pstart[p+1]) whose lobes are cw[k * cap_c + c], cS[(j * Kc + k) * cap_c + c]
+// [pstart[p], pstart[p+1]) whose lobes are cw[k * cap_c + c], cS[(j * Kc + k) * cap_c + c];
+// narrow_first: many parents are expected to gather at most 8 lobes (a launch choice only)
 void cluster_level(const int64_t* pstart, const int64_t* n_par, const float* cw, const float* cS, const uint8_t* cnl,
-                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s);
+                   int Kc, int64_t cap_c, int K, int iters, const vx_lobes& out, int grid, hipStream_t s,
+                   bool narrow_first = false);
 
 // the front half of voxelize (prims.hip): pairs in emission order (by primitive, then candidate)
 struct FrontWs {
