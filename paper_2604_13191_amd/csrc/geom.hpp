@@ -646,13 +646,18 @@ VX_HD inline void area_box_bound(AreaEdge& E, const AreaLine& K, int ik, const A
   area_bound(E, D, N1, N2);
 }
 
-// the edge's cross-product term a (t_x - t_e), from exact quotients (one rounding each)
+// the edge's cross-product term a (t_x - t_e).  t_x - t_e = nx / dx - ne / de =
+// (nx de - ne dx) / (dx de); the numerator is formed exactly up to its final rounding (each
+// product split into its rounded value and exact error by an FMA), so it is exactly 0 when the
+// two bounds meet in one point: a piece that closes to a point or a segment adds nothing.
 VX_HD inline double area_edge_term(const AreaEdge& E, const AreaLine& K) {
   if (E.dead || E.de == 0.0 || E.dx == 0.0) return 0.0;
-  const double ue = E.ne / E.de, ux = E.nx / E.dx;
-  const double d = E.sig * (ux - ue);
-  if (!(d > 0.0)) return 0.0;
-  return K.a * d * rcp_fast(E.use_x ? fabs(K.g) : fabs(K.b));
+  const double p1 = E.nx * E.de, p2 = E.ne * E.dx;
+  const double num = (p1 - p2) + (fma(E.nx, E.de, -p1) - fma(E.ne, E.dx, -p2));
+  // sig (t_x - t_e) > 0 with dx de < 0 (de > 0 > dx): sig num < 0
+  const double sn = E.sig * num;
+  if (!(sn < 0.0)) return 0.0;
+  return K.a * sn * rcp_fast(E.dx * E.de * (E.use_x ? fabs(K.g) : fabs(K.b)));
 }
 
 // line ik's edge bounded by the triangle's lines and every other box line
