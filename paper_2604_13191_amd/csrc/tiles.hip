@@ -415,11 +415,23 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
   const int64_t j = j0 + threadIdx.x;
   int32_t c = 0, lo[3], n[3];
   uint32_t p = 0;
-  const int32_t* r = nullptr;
+  // the whole record (and the triangle's doubled area) in registers at once: one round of loads
+  // after the primitive id, none after the scan below
+  int32_t r[kRec];
+  float a2 = 0.f;
   if (threadIdx.x < 64) S.sbm[threadIdx.x] = 0;
   if (j < e) {
     p = rprim[j];
-    r = rec + int64_t(p) * kRec;
+    const int4* r4 = reinterpret_cast<const int4*>(rec + int64_t(p) * kRec);
+#pragma unroll
+    for (int k = 0; k < kRec / 4; ++k) {
+      const int4 v = r4[k];
+      r[4 * k] = v.x;
+      r[4 * k + 1] = v.y;
+      r[4 * k + 2] = v.z;
+      r[4 * k + 3] = v.w;
+    }
+    if (KIND == 0) a2 = dirs[p].w;
     c = int32_t(clip_box(r, o, sz, lo, n));
   }
   // candidates (below 2^21 per batch) and kept slots (bits 21 and up) in one scan
@@ -439,7 +451,7 @@ __device__ __forceinline__ int32_t load_batch(const UnitLds& S, const int32_t* _
     for (int k = 0; k < 9; ++k) S.brec[q * 9 + k] = r[k];
     S.bpatch[q] = r[15];
     if (KIND == 1) S.binv[q] = cap_inv_len2(r);
-    else S.binv[q] = double(dirs[p].w);
+    else S.binv[q] = double(a2);
     atomicOr(reinterpret_cast<unsigned long long*>(&S.sbm[off >> 6]), 1ull << (off & 63));
   }
   nslot = tot >> 21;
