@@ -29,13 +29,14 @@ __device__ __forceinline__ void store_record(int32_t* __restrict__ dst, const in
 __global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ tris, int64_t n, Lat L,
                                                      int32_t* __restrict__ rec, float4* __restrict__ dirs,
                                                      int64_t* __restrict__ cand_cnt, int64_t* __restrict__ rcnt,
-                                                     int tb, int64_t* stats) {
+                                                     int tb, ulonglong2* __restrict__ box, int64_t* stats) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     bool ok;
     int32_t r[kRec];                                 // built in registers, stored as 4 x 16 bytes
     const int64_t cc = prep_triangle(tris + i * 9, L, r, dirs + i, ok);
     if (!rcnt) cand_cnt[i] = cc;                   // (the tiled path reads only the record counts)
     store_record(rec + i * kRec, r);
+    if (box) box[i] = pack_box(r);
     if (rcnt) {
       int64_t c = 0;
       if (cc > 0) {
@@ -53,7 +54,8 @@ __global__ void __launch_bounds__(kBlock) k_prep_tri(const float* __restrict__ t
 __global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ pts, int64_t n_pts,
                                                      const uint8_t* __restrict__ fstart, Lat L,
                                                      int32_t* __restrict__ rec, float4* __restrict__ dirs,
-                                                     int64_t* __restrict__ cand_cnt, int64_t* stats) {
+                                                     int64_t* __restrict__ cand_cnt, ulonglong2* __restrict__ box,
+                                                     int64_t* stats) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_pts; i += int64_t(gridDim.x) * kBlock) {
     // point i and the next make a segment unless the next starts a fiber (offsets are
     // non-decreasing, so a later point of the same fiber starts none)
@@ -62,6 +64,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib(const float* __restrict__ p
     int32_t r[kRec];
     cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, L, r, dirs + i, ok);
     store_record(rec + i * kRec, r);
+    if (box) box[i] = pack_box(r);
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
   }
 }
@@ -73,7 +76,8 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restri
                                                            const Lat* __restrict__ lats,
                                                            const int64_t* __restrict__ pt_begin, int n_patches,
                                                            int32_t* __restrict__ rec, float4* __restrict__ dirs,
-                                                           int64_t* __restrict__ cand_cnt, int64_t* stats) {
+                                                           int64_t* __restrict__ cand_cnt,
+                                                           ulonglong2* __restrict__ box, int64_t* stats) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_pts; i += int64_t(gridDim.x) * kBlock) {
     int lo = 0, hi = n_patches;
     while (hi - lo > 1) {
@@ -87,6 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_fib_batch(const float* __restri
     cand_cnt[i] = prep_segment(pts + i * 3, seg ? pts + (i + 1) * 3 : nullptr, lats[patch], r, dirs + i, ok);
     r[15] = patch;
     store_record(rec + i * kRec, r);
+    if (box) box[i] = pack_box(r);
     if (!ok) flag_or(stats, VX_FLAG_INPUT);
   }
 }
@@ -325,7 +330,7 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
   if (kind == 0) {
     VX_TIMED("prep_tri", s);
     hipLaunchKernelGGL(k_prep_tri, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, L, w.rec, w.dirs, w.cand_cnt,
-                       w.rcnt, w.tb, stats);
+                       w.rcnt, w.tb, w.box, stats);
   } else {
     {
       VX_TIMED("check_offsets", s);
@@ -335,10 +340,10 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
     VX_TIMED("prep_fib", s);
     if (batch)
       hipLaunchKernelGGL(k_prep_fib_batch, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, w.fstart, batch->lats,
-                         batch->pt_begin, batch->n_patches, w.rec, w.dirs, w.cand_cnt, stats);
+                         batch->pt_begin, batch->n_patches, w.rec, w.dirs, w.cand_cnt, w.box, stats);
     else
       hipLaunchKernelGGL(k_prep_fib, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, w.fstart, L, w.rec, w.dirs,
-                         w.cand_cnt, stats);
+                         w.cand_cnt, w.box, stats);
   }
 }
 

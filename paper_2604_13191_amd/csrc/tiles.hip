@@ -44,21 +44,37 @@ __device__ __forceinline__ int64_t clip_box(const int32_t* r, const int32_t o[3]
   return c;
 }
 
+// the same from a packed box
+__device__ __forceinline__ int64_t clip_packed(const ulonglong2& b, const int32_t o[3], const int32_t sz[3]) {
+  int32_t bl[3], bh[3];
+  unpack_box(b, bl, bh);
+  int64_t c = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int32_t l = bl[a] > o[a] ? bl[a] : o[a];
+    const int32_t h1 = o[a] + sz[a] - 1;
+    const int32_t h = bh[a] < h1 ? bh[a] : h1;
+    c *= h >= l ? h - l + 1 : 0;
+  }
+  return c;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
 // primitive-tile records
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_rec_count(const int32_t* __restrict__ rec,
+__global__ void __launch_bounds__(kBlock) k_rec_count(const ulonglong2* __restrict__ box,
                                                       const int64_t* __restrict__ cand_cnt, int64_t n_prims, int tb,
                                                       int64_t* __restrict__ rcnt) {
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n_prims; p += int64_t(gridDim.x) * kBlock) {
     int64_t c = 0;
     if (cand_cnt[p] > 0) {
-      const int32_t* r = rec + p * kRec;
+      int32_t lo[3], hi[3];
+      unpack_box(box[p], lo, hi);
       c = 1;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) c *= int64_t(((r[9 + a] + r[12 + a] - 1) >> tb) - (r[9 + a] >> tb) + 1);
+      for (int a = 0; a < 3; ++a) c *= int64_t((hi[a] >> tb) - (lo[a] >> tb) + 1);
     }
     rcnt[p] = c;
   }
@@ -83,20 +99,21 @@ struct RecTotal {
 // scanned record counts (n_prims + 1 entries); a primitive without candidates has none.
 template <class Key>
 __global__ void __launch_bounds__(kBlock) k_rec_emit(const int32_t* __restrict__ rec,
+                                                     const ulonglong2* __restrict__ box,
                                                      const int64_t* __restrict__ roff, int64_t n_prims,
                                                      const int64_t* __restrict__ ctl, int tb, int batch,
                                                      Key* __restrict__ rkeys, uint32_t* __restrict__ rprim) {
   if (ctl[CTL_N_REC] == 0) return;
   for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < n_prims; p += int64_t(gridDim.x) * kBlock) {
     if (roff[p + 1] == roff[p]) continue;
-    const int32_t* r = rec + p * kRec;
     int32_t t0[3], t1[3];
+    unpack_box(box[p], t0, t1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      t0[a] = r[9 + a] >> tb;
-      t1[a] = (r[9 + a] + r[12 + a] - 1) >> tb;
+      t0[a] >>= tb;
+      t1[a] >>= tb;
     }
-    const Key hi = batch ? Key(uint64_t(uint32_t(r[15])) << (kPatchShift - 3 * tb)) : Key(0);
+    const Key hi = batch ? Key(uint64_t(uint32_t(rec[p * kRec + 15])) << (kPatchShift - 3 * tb)) : Key(0);
     int64_t o = roff[p];
     for (int32_t z = t0[2]; z <= t1[2]; ++z)
       for (int32_t y = t0[1]; y <= t1[1]; ++y)
@@ -150,7 +167,7 @@ struct PlanEntry {
 }  // namespace
 
 template <int PASS, class Key>
-__global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict__ rec,
+__global__ void __launch_bounds__(kBlock) k_unit_plan(const ulonglong2* __restrict__ box,
                                                       const Key* __restrict__ rkeys,
                                                       const uint32_t* __restrict__ rprim,
                                                       const int64_t* __restrict__ tstart,
@@ -192,9 +209,8 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
     // the whole tile
     int64_t c = 0;
     for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
-      int32_t lo[3], n[3];
       const int32_t sz[3] = {1 << tb, 1 << tb, 1 << tb};
-      c += clip_box(rec + int64_t(rprim[j]) * kRec, to, sz, lo, n);
+      c += clip_packed(box[rprim[j]], to, sz);
     }
     c = block_sum(c, tmp);
     if (threadIdx.x == 0) {
@@ -243,11 +259,12 @@ __global__ void __launch_bounds__(kBlock) k_unit_plan(const int32_t* __restrict_
       __syncthreads();
       int64_t cc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int64_t j = s + threadIdx.x; j < e; j += kBlock) {
-        const int32_t* r = rec + int64_t(rprim[j]) * kRec;
+        int32_t bl[3], bh[3];
+        unpack_box(box[rprim[j]], bl, bh);
         int64_t nh[3][2];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int32_t l = r[9 + a], hh = r[9 + a] + r[12 + a] - 1;
+          const int32_t l = bl[a], hh = bh[a];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int32_t c0 = E.o[a] + q * h, c1 = c0 + h - 1;
@@ -977,6 +994,7 @@ struct TileWs {
   float4* dirs;
   int64_t* cand_cnt;
   int64_t* roff;          // [n_prims + 1]
+  ulonglong2* box;        // [n_prims] packed candidate boxes
   PairBufs ra, rb;        // records (tile key, primitive; no weight), ping-pong
   int32_t* hist;
   int64_t* partial;
@@ -1002,6 +1020,7 @@ static size_t tile_ws_layout(int64_t n_prims, int64_t max_rec, int64_t max_units
   x.dirs = cv.take<float4>(n_prims);
   x.cand_cnt = cv.take<int64_t>(n_prims);
   x.roff = cv.take<int64_t>(n_prims + 1);
+  x.box = cv.take<ulonglong2>(n_prims);
   x.ra.keys = cv.take<uint8_t>(max_rec * kb);
   x.ra.w = nullptr;
   x.ra.prim = cv.take<uint32_t>(max_rec);
@@ -1065,20 +1084,21 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     f.rcnt = w.roff;
     f.tb = tb;
   }
+  f.box = w.box;
   prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch, w.stage_ctr, 1);
   const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
   {
     VX_TIMED("tile_records", s);
     // fibers: their fiber-start bytes share the counts' space, so the count is a pass of its own
     if (kind != 0)
-      hipLaunchKernelGGL(k_rec_count, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.cand_cnt, n_prims, tb, w.roff);
+      hipLaunchKernelGGL(k_rec_count, dim3(pgrid), dim3(kBlock), 0, s, w.box, w.cand_cnt, n_prims, tb, w.roff);
     device_scan(ArrIn64{w.roff}, ArrOut64{w.roff}, RecTotal{w.roff, w.ctl, stats, max_rec}, nullptr, n_prims,
                 w.partial, s);
     if (key64)
-      hipLaunchKernelGGL(k_rec_emit<uint64_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.roff, n_prims, w.ctl, tb,
+      hipLaunchKernelGGL(k_rec_emit<uint64_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.box, w.roff, n_prims, w.ctl, tb,
                          batch ? 1 : 0, (uint64_t*)w.ra.keys, w.ra.prim);
     else
-      hipLaunchKernelGGL(k_rec_emit<uint32_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.roff, n_prims, w.ctl, tb, 0,
+      hipLaunchKernelGGL(k_rec_emit<uint32_t>, dim3(pgrid), dim3(kBlock), 0, s, w.rec, w.box, w.roff, n_prims, w.ctl, tb, 0,
                          (uint32_t*)w.ra.keys, w.ra.prim);
   }
   int key_bits = 3 * (g->log2_res - tb);
@@ -1104,7 +1124,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
     const int grid = tu.grids[kTunePlan];
     const int64_t budget = tu.unit_budget;
 #define VX_PLAN(P, K)                                                                                        \
-  hipLaunchKernelGGL((k_unit_plan<P, K>), dim3(grid), dim3(kBlock), 0, s, w.rec, (const K*)R.keys, R.prim, w.tstart, \
+  hipLaunchKernelGGL((k_unit_plan<P, K>), dim3(grid), dim3(kBlock), 0, s, w.box, (const K*)R.keys, R.prim, w.tstart, \
                      w.ctl, tb, batch ? 1 : 0, budget, w.ucnt, w.uoff, w.units)
     if (key64) VX_PLAN(0, uint64_t); else VX_PLAN(0, uint32_t);
     device_scan(UnitCountIn{w.ucnt}, ArrOut64{w.uoff}, UnitTotal{w.uoff, w.ctl, stats, max_units}, w.ctl + CTL_N_TILES,

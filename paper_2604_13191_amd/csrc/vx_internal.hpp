@@ -360,7 +360,29 @@ struct FrontWs {
   int64_t* partial;
   int64_t* rcnt = nullptr;   // triangles, tiled path: tiles of 2^tb voxels each candidate box overlaps
   int tb = 0;
+  ulonglong2* box = nullptr; // tiled path: each primitive's candidate box, packed (pack_box)
 };
+
+// A primitive's candidate box for the passes that need only the box: first (x) and last (y)
+// voxel per axis, 21 bits each (grids up to 2^20 voxels per axis), from record words 9..14.  An
+// empty box packs its first voxel twice (it has no records, so no pass reads it).
+__host__ __device__ inline ulonglong2 pack_box(const int32_t* r) {
+  uint64_t lo = 0, hi = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int32_t l = r[9 + a], h = r[12 + a] > 0 ? r[9 + a] + r[12 + a] - 1 : r[9 + a];
+    lo |= uint64_t(uint32_t(l) & 0x1fffffu) << (21 * a);
+    hi |= uint64_t(uint32_t(h) & 0x1fffffu) << (21 * a);
+  }
+  return make_ulonglong2(lo, hi);
+}
+__host__ __device__ inline void unpack_box(const ulonglong2& b, int32_t lo[3], int32_t hi[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = int32_t((b.x >> (21 * a)) & 0x1fffffu);
+    hi[a] = int32_t((b.y >> (21 * a)) & 0x1fffffu);
+  }
+}
 void front_ws_carve(Carver& cv, int64_t n_prims, int64_t max_cand, int64_t max_pairs, bool key64, FrontWs* f);
 struct Lat;
 // batched patches: per-patch lattices and point ranges (device), keys carry the patch id above
