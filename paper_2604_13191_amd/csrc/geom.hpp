@@ -598,13 +598,17 @@ VX_HD inline void area_edge_init(AreaEdge& E, const AreaLine& K) {
 // positive D de (D dx for exits); the first of equal bounds stays.
 VX_HD inline void area_bound(AreaEdge& E, double D, double N1, double N2) {
   const double n = E.use_x ? N1 : N2;
-  if (D > 0.0) {
-    const double l = n * E.de, r = E.ne * D;
-    if (E.de == 0.0 || (E.sig > 0.0 ? l > r : l < r)) { E.ne = n; E.de = D; }
-  } else {
-    const double l = n * E.dx, r = E.nx * D;
-    if (E.dx == 0.0 || (E.sig > 0.0 ? l < r : l > r)) { E.nx = n; E.dx = D; }
-  }
+  // one comparison for either side (no branch per side): an entry is later when sig n / D is
+  // larger, an exit earlier when it is smaller
+  const bool ent = D > 0.0;
+  const double dc = ent ? E.de : E.dx, nc = ent ? E.ne : E.nx;
+  const double l = n * dc, r = nc * D;
+  const bool take = dc == 0.0 || (((E.sig > 0.0) == ent) ? l > r : l < r);
+  const bool te = take && ent, tx = take && !ent;
+  E.ne = te ? n : E.ne;
+  E.de = te ? D : E.de;
+  E.nx = tx ? n : E.nx;
+  E.dx = tx ? D : E.dx;
 }
 
 // the sign along K of a parallel line's half-plane, from the exact intersection numerators
