@@ -596,14 +596,14 @@ VX_HD inline void area_edge_init(AreaEdge& E, const AreaLine& K) {
 // K where D > 0 (an entry) and outside where D < 0 (an exit).  The latest entry and the earliest
 // exit along the walk are kept: sig n / D against sig ne / de with both sides multiplied by the
 // positive D de (D dx for exits); the first of equal bounds stays.
-VX_HD inline void area_bound(AreaEdge& E, double D, double N1, double N2) {
+VX_HD inline void area_bound(AreaEdge& E, double D, double N1, double N2, bool valid = true) {
   const double n = E.use_x ? N1 : N2;
   // one comparison for either side (no branch per side): an entry is later when sig n / D is
   // larger, an exit earlier when it is smaller
   const bool ent = D > 0.0;
   const double dc = ent ? E.de : E.dx, nc = ent ? E.ne : E.nx;
   const double l = n * dc, r = nc * D;
-  const bool take = dc == 0.0 || (((E.sig > 0.0) == ent) ? l > r : l < r);
+  const bool take = valid && (dc == 0.0 || (((E.sig > 0.0) == ent) ? l > r : l < r));
   const bool te = take && ent, tx = take && !ent;
   E.ne = te ? n : E.ne;
   E.de = te ? D : E.de;
@@ -625,11 +625,9 @@ VX_HD inline void area_tri_bound(AreaEdge& E, const AreaLine& K) {
   if (T == 0) { D = K.g; N1 = 0.0; N2 = -K.a; }
   else if (T == 1) { D = -K.b; N1 = K.a; N2 = 0.0; }
   else { D = K.b - K.g; N1 = -(K.a + K.g); N2 = K.a + K.b; }
-  if (D == 0.0) {
-    if (parallel_side(K, N1, N2) < 0.0) E.dead = true;
-    return;
-  }
-  area_bound(E, D, N1, N2);
+  const bool par = D == 0.0;
+  if (par && parallel_side(K, N1, N2) < 0.0) E.dead = true;
+  area_bound(E, D, N1, N2, !par);
 }
 
 // K (index ik) against another box line J (index ij)
@@ -655,13 +653,14 @@ VX_HD inline void area_box_bound(AreaEdge& E, const AreaLine& K, int ik, const A
 // product split into its rounded value and exact error by an FMA), so it is exactly 0 when the
 // two bounds meet in one point: a piece that closes to a point or a segment adds nothing.
 VX_HD inline double area_edge_term(const AreaEdge& E, const AreaLine& K) {
-  if (E.dead || E.de == 0.0 || E.dx == 0.0) return 0.0;
   const double p1 = E.nx * E.de, p2 = E.ne * E.dx;
   const double num = (p1 - p2) + (fma(E.nx, E.de, -p1) - fma(E.ne, E.dx, -p2));
-  // sig (t_x - t_e) > 0 with dx de < 0 (de > 0 > dx): sig num < 0
+  // sig (t_x - t_e) > 0 with dx de < 0 (de > 0 > dx): sig num < 0.  Without both bounds (or on a
+  // dead line) there is no edge; the term is computed regardless and dropped.
   const double sn = E.sig * num;
-  if (!(sn < 0.0)) return 0.0;
-  return K.a * sn * rcp_fast(E.dx * E.de * (E.use_x ? fabs(K.g) : fabs(K.b)));
+  const bool edge = !E.dead && E.de != 0.0 && E.dx != 0.0 && sn < 0.0;
+  const double t = K.a * sn * rcp_fast(E.dx * E.de * (E.use_x ? fabs(K.g) : fabs(K.b)));
+  return edge ? t : 0.0;
 }
 
 // line ik's edge bounded by the triangle's lines and every other box line
