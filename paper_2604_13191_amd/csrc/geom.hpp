@@ -231,7 +231,9 @@ VX_HD inline bool tri_touch(const int32_t* q, const int64_t v[3], int64_t s, int
   const double ds = double(s);
   // nine edge x box-axis directions: projections of the triangle and of the box [0, s]^3.  On
   // the direction of edge j the edge's two ends project alike, so the triangle projects onto
-  // the interval between vertex j and the opposite vertex.
+  // the interval between vertex j and the opposite vertex.  (Most candidates pass all nine:
+  // the separations are gathered and decided once, without a branch per direction.)
+  bool sep = false;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
 #pragma unroll
@@ -243,9 +245,10 @@ VX_HD inline bool tri_touch(const int32_t* q, const int64_t v[3], int64_t s, int
       const double pmin = fmin(p0, p2), pmax = fmax(p0, p2);
       const double blo = (fmin(au, 0.0) + fmin(aw, 0.0)) * ds;
       const double bhi = (fmax(au, 0.0) + fmax(aw, 0.0)) * ds;
-      if (pmax < blo || pmin > bhi) return false;
+      sep = sep | (pmax < blo) | (pmin > bhi);
     }
   }
+  if (sep) return false;
   // plane: corner offsets n . (corner - c0) must not all share a strict sign
   double n[3];
   n[0] = fma(e[0][2], e[2][1], -(e[0][1] * e[2][2]));
