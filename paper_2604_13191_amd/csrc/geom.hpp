@@ -695,30 +695,30 @@ VX_HD inline double tri_area_bary(const int32_t* q, const int64_t v[3], int Sb) 
   L[2] = {1.0, -1.0, -1.0, true};
   L[6] = {0.0, 0.0, 0.0, false};
   bool second = false;
+  // the first deciding case over the axes, in axis order: 1 an empty piece (area 0), 2 two axes
+  // crossed through (the exact routine); the axes are set up without a branch each
+  int ev = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int32_t c0 = q[a] - (int32_t(v[a]) << Sb);
     const int32_t e0 = q[3 + a] - q[a];
     const int32_t e1 = q[6 + a] - q[a];
     const double c = double(c0), d0 = double(e0), d1 = double(e1);
-    L[3 + a] = {0.0, 0.0, 0.0, false};
-    if (e0 == 0 && e1 == 0) {
-      if (!(c0 >= 0 && c0 < s)) return 0.0;     // flat on axis a, owned by another layer
-      continue;
-    }
+    const bool flat = e0 == 0 && e1 == 0;
+    const bool flat_out = flat && !(c0 >= 0 && c0 < s);   // flat on axis a, owned by another layer
     // the two box half-planes of this axis at the vertices (0, 0), (1, 0), (0, 1), exact
     const double l0 = c, l1 = c + d0, l2 = c + d1;
     const double u0 = ds - c, u1 = u0 - d0, u2 = u0 - d1;
-    if (fmax(l0, fmax(l1, l2)) <= 0.0 || fmax(u0, fmax(u1, u2)) <= 0.0) return 0.0;
-    const bool lo = fmin(l0, fmin(l1, l2)) < 0.0, hi = fmin(u0, fmin(u1, u2)) < 0.0;
-    if (lo && hi) {
-      if (second) return -1.0;                   // two axes crossed through: the exact routine
-      second = true;
-      L[6] = {u0, -d0, -d1, true};
-    }
-    if (lo) L[3 + a] = {c, d0, d1, true};
-    else if (hi) L[3 + a] = {u0, -d0, -d1, true};
+    const bool empty = !flat && (fmax(l0, fmax(l1, l2)) <= 0.0 || fmax(u0, fmax(u1, u2)) <= 0.0);
+    const bool lo = !flat && fmin(l0, fmin(l1, l2)) < 0.0, hi = !flat && fmin(u0, fmin(u1, u2)) < 0.0;
+    const bool both = lo && hi;
+    ev = ev != 0 ? ev : (flat_out || empty ? 1 : (both && second ? 2 : 0));
+    if (both && !second) L[6] = {u0, -d0, -d1, true};
+    second = second || both;
+    L[3 + a] = lo ? AreaLine{c, d0, d1, true} : (hi ? AreaLine{u0, -d0, -d1, true} : AreaLine{0.0, 0.0, 0.0, false});
   }
+  if (ev == 1) return 0.0;
+  if (ev == 2) return -1.0;
   bool flat = false;
   const double sum = area_line_term<2>(L, flat) + area_line_term<3>(L, flat) + area_line_term<4>(L, flat) +
                      area_line_term<5>(L, flat) + area_line_term<6>(L, flat);
