@@ -330,35 +330,33 @@ __device__ __forceinline__ void cluster_round(int64_t p, bool live, const int64_
         // the merged row's minimum over the new costs (least cost, then least column)
         const uint64_t k2 = (uint64_t(__float_as_uint(cnew)) << 32) | uint64_t(g);
         const uint64_t m2 = group_min_u64<G>(k2);
-        // refresh the cached row minima: only column bi changed (to cnew) and column bj died
-        bool rescan = false;
-        if (merge) {
-          if (g == bj) {
-            best = INFINITY;
-            bjr = G;
-          } else if (g == bi) {
-            best = __uint_as_float(uint32_t(m2 >> 32));
-            bjr = best < INFINITY ? int(m2 & 0xffff) : G;
-          } else if (alive) {
-            if (bjr == bi) {
-              if (cnew <= best) best = cnew;
-              else rescan = true;
-            } else if (bjr == bj) {
-              rescan = true;
-            } else if (cnew < best || (cnew == best && bi < bjr)) {
-              best = cnew;
-              bjr = bi;
-            }
-          }
-        }
+        // refresh the cached row minima: only column bi changed (to cnew) and column bj died.
+        // Row bj dies, row bi takes the merged row's minimum; a row whose minimum sat in column bi
+        // keeps it if the new cost is no larger, else (or if it sat in column bj) is rescanned;
+        // any other row compares the new cost with its minimum (ties to the lower column).  All
+        // decided with selects, no branch per case.
+        const bool isj = merge && g == bj;
+        const bool isi = merge && !isj && g == bi;
+        const bool oth = merge && !isj && !isi && alive;
+        const bool onbi = oth && bjr == bi, onbj = oth && !onbi && bjr == bj;
+        const bool keep_bi = onbi && cnew <= best;
+        const bool rescan = (onbi && !(cnew <= best)) || onbj;
+        const bool take_new = oth && !onbi && !onbj && (cnew < best || (cnew == best && bi < bjr));
+        const float mb = __uint_as_float(uint32_t(m2 >> 32));
+        const int mj = mb < INFINITY ? int(m2 & 0xffff) : G;
+        best = isj ? INFINITY : (isi ? mb : ((keep_bi || take_new) ? cnew : best));
+        bjr = isj ? G : (isi ? mj : (take_new ? bi : bjr));
         if (rescan) {
           best = INFINITY;
           bjr = G;
           if constexpr (G <= 16) {
-            // the whole row, its loads issued together (unrolled over the group width)
+            // the whole row, its loads issued together (unrolled over the group width; every
+            // column is in bounds, those at or past n are replaced by +inf)
             float c[G];
 #pragma unroll
-            for (int j = 0; j < G; ++j) c[j] = j < n ? L.mat[gi][j][g] : INFINITY;
+            for (int j = 0; j < G; ++j) c[j] = L.mat[gi][j][g];
+#pragma unroll
+            for (int j = 0; j < G; ++j) c[j] = j < n ? c[j] : INFINITY;
 #pragma unroll
             for (int j = 0; j < G; ++j)
               if (c[j] < best) {
