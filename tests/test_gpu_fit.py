@@ -101,8 +101,9 @@ def test_autograd_function_and_descent(vx):
     with torch.no_grad():
         Q = [p - 0.05 * p.grad for p in P]
     loss2 = vx.lobe_fit(plan, X.detach(), Q)
-    say("loss before/after one step", float(loss), float(loss2))
-    assert float(loss2) < float(loss)
+    l1, l2 = float(loss.detach()), float(loss2.detach())
+    say("loss before/after one step", l1, l2)
+    assert l2 < l1
 
 
 def test_backward_after_another_forward_raises(vx):
