@@ -326,7 +326,7 @@ void prep_prims(int kind, const vx_grid* g, const float* data, int64_t n_prims, 
   ZeroSet z{{stats, w.ctl, kind == 1 ? reinterpret_cast<int64_t*>(w.fstart) : nullptr, zero_extra},
             {VX_NSTAT, CTL_SIZE, kind == 1 ? (n_prims + 8) / 8 : 0, zero_extra ? zero_extra_n : 0}};
   launch_zero_multi(z, s);
-  const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
+  const int pgrid = int(n_prims / kBlock + 1 < kPrimGrid ? n_prims / kBlock + 1 : kPrimGrid);
   if (kind == 0) {
     VX_TIMED("prep_tri", s);
     hipLaunchKernelGGL(k_prep_tri, dim3(pgrid), dim3(kBlock), 0, s, data, n_prims, L, w.rec, w.dirs, w.cand_cnt,

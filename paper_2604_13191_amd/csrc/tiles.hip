@@ -1086,7 +1086,7 @@ vx_status tile_voxelize(int kind, const vx_grid* g, const float* data, int64_t n
   }
   f.box = w.box;
   prep_prims(kind, g, data, n_prims, offsets, n_fib, radius, f, stats, s, batch, w.stage_ctr, 1);
-  const int pgrid = int(n_prims / kBlock + 1 < kGrid ? n_prims / kBlock + 1 : kGrid);
+  const int pgrid = int(n_prims / kBlock + 1 < kPrimGrid ? n_prims / kBlock + 1 : kPrimGrid);
   {
     VX_TIMED("tile_records", s);
     // fibers: their fiber-start bytes share the counts' space, so the count is a pass of its own

@@ -11,6 +11,8 @@ namespace vx {
 constexpr int kBlock = 256;          // threads per block: 4 waves of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kGrid = 1024;          // persistent grid of the streaming kernels: 4 blocks per CU
+constexpr int kPrimGrid = 4096;      // per-primitive streaming passes (prep, record count and emission):
+                                     // enough blocks to fill every SIMD with the waves its registers allow
 constexpr int kPatchShift = 33;      // batched keys: patch id above a 33-bit Morton code (R <= 2048)
 constexpr int kTileBits = 4;         // leaf tiles of 16^3 voxels
 constexpr int kUnitCand = 3072;      // the largest unit budget: candidates (so pairs) a unit keeps in LDS
