@@ -24,7 +24,9 @@ def test_oracle_pins_clean_under_asan_ubsan():
     asan, ubsan = _runtime("libasan.so"), _runtime("libubsan.so")
     if not asan or not ubsan:
         pytest.skip("gcc sanitizer runtimes not installed")
-    env = dict(os.environ, VXO_SANITIZE="1", LD_PRELOAD=f"{asan}:{ubsan}",
+    # the sanitizer runtimes go first in the child's preload list; anything already listed stays
+    pre = os.environ.get("LD_PRELOAD", "")
+    env = dict(os.environ, VXO_SANITIZE="1", LD_PRELOAD=f"{asan}:{ubsan}" + (f":{pre}" if pre else ""),
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
     subprocess.run([sys.executable, "-c", "import oracle; oracle.build(force=True)"], cwd=ROOT, env=env, check=True)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
